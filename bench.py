@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: homogenized designs/s at 128^3 through the served mixed-precision
+path, with p50/p99 latency, the FP64 GPU path beside it, the C^H error of
+mixed versus FP64, the HBM roofline fraction of the CG stencil kernel and the
+FP64 CPU oracle timed on the host as a baseline.
+
+One step = one batch of the 128^3 designs (48 charges, magnitudes U[-1,1]
+shifted to zero net charge, volume fraction U[0.05, 0.15], void E = 1e-6)
+submitted together to the continuous-batching engine and run to completion:
+field -> threshold -> six-case PCG -> C^H for every design.
+
+    python bench.py [--gpus 1] [--steps 2] [--warmup 1]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--designs", type=int, default=8)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--fp64-designs", type=int, default=2, help="designs also run on the FP64 GPU path")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--iters-per-step", type=int, default=16)
+    ap.add_argument("--max-iter", type=int, default=20000,
+                    help="CG iteration cap (lower it only for hardware-counter runs)")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="run a plain 1 GiB device-to-device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: 1 GiB read + 1 GiB written, 3 times.
+    Its FETCH_SIZE / WRITE_SIZE readings calibrate the HBM traffic counters."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4, "repeats": 3}))
+
+
+def stencil_bytes(results, n, prec_bytes):
+    """Algorithmic HBM bytes moved by the CG stencil kernel over the given
+    results: per active load case and node it reads r and p_old and writes p
+    and q (4 x 3 values); per node and launch it reads E_e and D^-1 once."""
+    nn = n ** 3
+    total = 0
+    launches = 0
+    for r in results:
+        it = r["iters"]
+        total += int(it.sum()) * nn * 12 * prec_bytes + int(it.max()) * nn * 2 * prec_bytes
+        launches += int(it.max())
+    return total, launches
+
+
+def cpu_baseline(design, gpu_iters, budget_s):
+    """Time the oracle on a bounded sample and scale it to designs/s at n^3:
+    field + assembly + a bounded number of CG iterations at 48^3 for the same
+    design, extrapolated by n^3 and by the iteration count the GPU needed."""
+    import numpy as np
+    from oracle import fem, field as fld, solve as slv
+    m = 48
+    t0 = time.perf_counter()
+    F, G = fld.field_and_gradient(design.pos, design.q, m)
+    dist = fld.distance(F, G)
+    t = fld.thickness_for_volume(dist, design.target_vf, 0.0)
+    Ee = fld.stiffness_field(fld.occupancy(dist, t, 0.0), design.E, design.E_void)
+    K = fem.assemble(Ee, design.nu, m)
+    f = fem.load_vectors(Ee, design.nu, m)
+    Kp, fp = slv.pin_node0(K, f)
+    t_setup = time.perf_counter() - t0
+    # CG iterations until the budget is used (the oracle's own loop, capped)
+    left = max(budget_s - t_setup, 2.0)
+    t1 = time.perf_counter()
+    probe = 5
+    slv.pcg_jacobi(Kp, fp, rtol=1e-300, maxiter=probe)
+    t_probe = (time.perf_counter() - t1) / probe
+    k = max(probe, min(400, int(left / max(t_probe, 1e-6))))
+    t2 = time.perf_counter()
+    slv.pcg_jacobi(Kp, fp, rtol=1e-300, maxiter=k)
+    t_it = (time.perf_counter() - t2) / k
+    scale = (design.n / m) ** 3
+    est = t_setup * scale + gpu_iters * t_it * scale
+    return {
+        "value": 1.0 / est,
+        "unit": "designs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle (NumPy/SciPy FP64) on config-2 design seed {design.seed} at {m}^3: field+threshold+"
+                   f"assembly {t_setup:.2f} s, {k} Jacobi-PCG iterations {t_it * 1e3:.1f} ms each; scaled by "
+                   f"({design.n}/{m})^3 and the GPU's {gpu_iters} iterations to one {design.n}^3 design; "
+                   f"host os.cpu_count()={os.cpu_count()}, single-threaded SciPy/NumPy"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.copy_only:
+        copy_calibration()
+        return
+    import numpy as np
+    import torch
+
+    from paper_2511_04025_amd import api, binding as B, serving, workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    designs = wl.config2_designs(n=args.n, count=args.designs)
+    eng_opts = dict(precision="mixed", rtol=args.rtol, max_iter=args.max_iter)
+    probe = serving.Engine(1 << 20, max_slots=1, **eng_opts)
+    fp = probe.footprint(designs[0])
+    probe.close()
+    del probe
+    engine = serving.Engine(fp * args.designs + (64 << 20), max_slots=args.designs, **eng_opts)
+
+    def one_step():
+        t0 = time.perf_counter()
+        for i, d in enumerate(designs):
+            engine.submit(d, i)
+        res, lat = {}, {}
+        while len(res) < len(designs):
+            engine.step(args.iters_per_step)
+            now = time.perf_counter() - t0
+            for rid, r in engine.poll():
+                res[rid] = r
+                lat[rid] = now
+                print(f"bench: design {rid} done at {now:.2f} s, iters {r['iters'].tolist()}, "
+                      f"status {r['status']}", file=sys.stderr, flush=True)
+        return [res[i] for i in range(len(designs))], [lat[i] for i in range(len(designs))]
+
+    for _ in range(args.warmup):
+        one_step()
+    lib = B.lib()
+    lib.shh_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_res, all_lat = [], []
+    for _ in range(args.steps):
+        res, lat = one_step()
+        all_res += res
+        all_lat += lat
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches = ctypes_int64()
+    ms_total = ctypes_double()
+    lib.shh_profile_read(launches, ms_total)
+    lib.shh_profile_enable(0)
+    ndes = args.steps * len(designs)
+    value = ndes / wall
+    ms_per_step = wall / args.steps * 1e3
+    bad = [r["status"] for r in all_res if r["status"] != 0]
+
+    # roofline of the CG stencil kernel: algorithmic bytes / event-timed duration
+    nbytes, _ = stencil_bytes(all_res, args.n, 4)
+    n_launch = launches.value
+    t_stencil = ms_total.value / 1e3
+    achieved = nbytes / t_stencil / 1e9 if t_stencil > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": "stencil_kernel<float,float,PCG>", "launches": n_launch,
+        "avg_launch_ms": round(ms_total.value / max(n_launch, 1), 4),
+        "algorithmic_bytes_per_launch": int(nbytes / max(n_launch, 1)),
+    }
+
+    # FP64 GPU path on a subset, and the C^H error of mixed vs FP64
+    fp64 = {}
+    if args.fp64_designs > 0:
+        sub = designs[: args.fp64_designs]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r64 = api.homogenize_batch(sub, precision="fp64", rtol=1e-10)
+        torch.cuda.synchronize()
+        w64 = time.perf_counter() - t1
+        errs = []
+        for k, r in enumerate(r64):
+            C, Cm = r["C"], all_res[k]["C"]
+            s = np.abs(C).max()
+            big = np.abs(C) >= 1e-3 * s
+            errs.append(float(np.max(np.abs(Cm - C)[big] / np.abs(C)[big])))
+        fp64 = {"fp64_designs_per_s": round(len(sub) / w64, 4), "ch_max_rel_err_vs_fp64": max(errs),
+                "fp64_iters_mean": float(np.mean([r["iters"].max() for r in r64]))}
+
+    iters = [int(r["iters"].max()) for r in all_res]
+    out = {
+        "metric": "homogenized designs/sec at 128^3 (C^H rel err <=1e-4 vs FP64) + p50/p99 latency",
+        "value": round(value, 4),
+        "unit": "designs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 stencil/vectors, f64 dots/recompute/reduction",
+        "data": "synthetic",
+        "config": {"workload": f"config2: {len(designs)} designs/step at {args.n}^3, 48 charges, "
+                               f"vf U[0.05,0.15], void E 1e-6, mixed precision, rtol {args.rtol}, "
+                               f"continuous-batching engine",
+                   "n": args.n, "designs_per_step": len(designs)},
+        "latency_p50_s": round(float(np.percentile(all_lat, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(all_lat, 99)), 4),
+        "cg_iters_mean": float(np.mean(iters)),
+        "status_failures": len(bad),
+        "roofline": roofline,
+    }
+    out.update(fp64)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(designs[0], int(np.mean(iters)), args.cpu_seconds)
+    engine.close()
+    print(json.dumps(out))
+
+
+def ctypes_int64():
+    import ctypes
+    return ctypes.c_int64(0)
+
+
+def ctypes_double():
+    import ctypes
+    return ctypes.c_double(0.0)
+
+
+if __name__ == "__main__":
+    main()

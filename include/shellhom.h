@@ -1,0 +1,225 @@
+/*
+ * shellhom.h -- C ABI of libshellhom: periodic voxel homogenization of a
+ * charge-parametrized shellular unit cell on one AMD MI355X (gfx950) GPU.
+ *
+ * The path (Huang, Liu, Wang, "Shellular Metamaterial Design via Compact
+ * Electric Potential Parametrization", arXiv 2511.04025):
+ *   1. field      F and grad F of the truncated periodic charge series, Eq. (6),
+ *                 at the n^3 voxel centers p_e = ((i+1/2)/n, (j+1/2)/n, (k+1/2)/n);
+ *   2. threshold  d_e = |F - c| / ||grad F|| (Eq. (7)), beta_e = h(d_e) with the
+ *                 hard step [d < t] or the logistic 1/(1+exp(-kappa (t - d)))
+ *                 of Sec. 4.1, E_e = E_void + (E - E_void) beta_e;
+ *   3. solve      the six periodic unit-strain cell problems K u^(k) = f^(k)
+ *                 of Eq. (8) with a matrix-free 8-node-hex stiffness stencil
+ *                 inside Jacobi-preconditioned CG;
+ *   4. reduce     C^H_ij = (1/n^3) sum_e E_e (chi^i + u^i_e)^T K_0 (chi^j + u^j_e)
+ *                 (energy form of Eq. (8)) and V = mean beta.
+ *   The adjoint (Eq. (9)) gives dL/d(charge positions, charge values).
+ *
+ * Conventions shared by every entry point
+ *   - Grids are x-fastest: voxel/node (i, j, k) has linear index (k n + j) n + i.
+ *     Node (i, j, k) is the lower corner of voxel (i, j, k); the grid is periodic.
+ *   - A 6-load-case nodal field is stored [case][component][k][j][i]
+ *     (6 * 3 * n^3 values); load cases in Voigt order (11, 22, 33, 23, 13, 12)
+ *     with engineering shear; displacements in units of the voxel edge.
+ *   - C^H is returned as 36 doubles, row-major, same Voigt order.
+ *   - Pointers prefixed d_ are device memory (hipMalloc'd or PyTorch CUDA
+ *     tensors); all others are host memory, read during the call only.
+ *   - `hip_stream` is a hipStream_t (may be NULL for the default stream).
+ *     Calls are blocking: they return after the stream work is complete.
+ *   - Every call returns 0 (SHH_OK) or a status below; negative codes leave
+ *     outputs undefined.  No exception crosses the ABI.  The library never
+ *     allocates device memory: the caller passes workspaces and arenas.
+ */
+#ifndef SHELLHOM_H
+#define SHELLHOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SHH_OK                   0
+#define SHH_NOT_CONVERGED        1   /* output valid; rel_res above rtol after max_iter */
+#define SHH_INVALID_ARG         (-1) /* n < 2, N < 1, NaN/Inf input, nu outside (-1, 0.5),
+                                        E <= 0, E_void outside [0, E], K outside [1, 6],
+                                        kappa < 0, target_vf outside (0, 1), ...        */
+#define SHH_WORKSPACE_TOO_SMALL (-2)
+#define SHH_HIP_ERROR           (-3)
+#define SHH_OVER_BUDGET         (-4) /* engine: request footprint exceeds the arena      */
+#define SHH_UNSUPPORTED         (-5) /* e.g. gradient of the hard step (kappa = 0)       */
+#define SHH_BREAKDOWN           (-6) /* CG breakdown: p^T K p <= 0 or NaN                */
+#define SHH_NOT_FOUND           (-7) /* engine: unknown request id                       */
+
+#define SHH_PREC_FP64  0  /* FP64 stencil, vectors, dots and reductions                 */
+#define SHH_PREC_MIXED 1  /* FP32 stencil and CG vectors; FP64 dots, residual
+                             recompute, solution accumulator and C^H reduction           */
+
+/* One design (Eq. (6)-(7) parameters and material). */
+typedef struct {
+  int32_t n;            /* voxels per axis, 2 <= n <= 1024                              */
+  int32_t num_charges;  /* N >= 1                                                        */
+  const double *pos;    /* host [N][3] charge positions (any real; the field is
+                           1-periodic)                                                   */
+  const double *q;      /* host [N] charge values (the paper uses +-1, equal counts)     */
+  int32_t K;            /* truncation order, 0 <= h, k, l <= K; the paper uses K = 3    */
+  const double *alpha;  /* host [(K+1)^3] spectral weights alpha_hkl, index
+                           (h (K+1) + k) (K+1) + l; NULL means all ones                 */
+  double iso;           /* iso-level c of the surface F = c (the paper uses 0)           */
+  double thickness;     /* shell half-thickness t in cell units; < 0: choose t so that
+                           the volume fraction equals target_vf                         */
+  double target_vf;     /* used when thickness < 0: hard step -> t is the midpoint of
+                           the k-th and (k+1)-th smallest d, k = round(vf n^3);
+                           logistic -> bisection until |V - vf| <= 1e-12                */
+  double kappa;         /* 0: hard step beta = [d < t];  > 0: logistic sharpness         */
+  int32_t dist_mode;    /* 0: d = |F - c| / ||grad F|| (Eq. (7));  1: d = |F - c|       */
+  double E;             /* solid Young's modulus, > 0                                    */
+  double nu;            /* Poisson ratio, -1 < nu < 0.5                                  */
+  double E_void;        /* void stiffness floor, 0 <= E_void <= E (0 makes K singular
+                           beyond the rigid modes if the solid is not connected)         */
+} shh_design;
+
+/* Solver options. */
+typedef struct {
+  int32_t precision;        /* SHH_PREC_FP64 or SHH_PREC_MIXED                            */
+  double rtol;              /* stop a load case when ||f - K u||_2 <= rtol ||f||_2        */
+  int32_t max_iter;         /* CG iteration cap per load case                            */
+  int32_t recompute_every;  /* R: replace the recursive residual by f - K u, computed in
+                               FP64, every R iterations (0: default 50 mixed / 0 FP64;
+                               the true residual is always recomputed at the end)        */
+  int32_t save_for_backward;/* keep F, grad F and the solution for shh_grad               */
+  int32_t check_every;      /* host polls convergence every this many iterations (0: 16) */
+} shh_opts;
+
+/* Result of one homogenization. */
+typedef struct {
+  double CH[36];        /* homogenized tensor, row-major Voigt                            */
+  double vol_frac;      /* V = mean beta                                                  */
+  double t_used;        /* half-thickness used                                            */
+  int32_t iters[6];     /* CG iterations per load case                                    */
+  double rel_res[6];    /* final true relative residual per load case (FP64)             */
+  double ms[5];         /* wall time: field+threshold, rhs, solve, C^H, total            */
+  int32_t status;       /* SHH_OK, SHH_NOT_CONVERGED or a negative code                  */
+} shh_result;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t shh_version(void);
+
+/* Human-readable text of a status code (static storage). */
+const char *shh_strerror(int32_t code);
+
+/* Device workspace bytes that shh_homogenize needs for this design and these
+   options.  Validates the arguments (returns SHH_INVALID_ARG if invalid). */
+int32_t shh_workspace_bytes(const shh_design *design, const shh_opts *opts, size_t *bytes);
+
+/* The whole path for one design: field -> threshold -> six-case PCG -> C^H.
+   d_ws: caller-owned device workspace of at least shh_workspace_bytes bytes,
+   256-byte aligned; it must stay allocated until shh_grad if save_for_backward.
+   Returns SHH_OK, SHH_NOT_CONVERGED, or an error. */
+int32_t shh_homogenize(const shh_design *design, const shh_opts *opts,
+                       void *d_ws, size_t ws_bytes, void *hip_stream, shh_result *out);
+
+/* The same path for `count` designs at once: every phase is one batched launch
+   over all designs (different n and charge counts allowed).  d_ws[i] and
+   ws_bytes[i] are per-design workspaces as for shh_homogenize; out[i] receives
+   design i's result.  Returns the first negative status, else SHH_NOT_CONVERGED
+   if any design did not converge, else SHH_OK. */
+int32_t shh_homogenize_batch(const shh_design *designs, int32_t count, const shh_opts *opts,
+                             void *const *d_ws, const size_t *ws_bytes, void *hip_stream,
+                             shh_result *out);
+
+/* Steps 3-4 only, for a given voxel stiffness field: d_E is a device array of
+   n^3 doubles (the E_e of Eq. (7), > 0 somewhere).  Workspace size from
+   shh_workspace_bytes_stiffness.  out->vol_frac is mean(E)/max(E). */
+int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *bytes);
+int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const shh_opts *opts,
+                                 void *d_ws, size_t ws_bytes, void *hip_stream, shh_result *out);
+
+/* Steps 1-2 only (Eq. (6)-(7)).  Writes the device arrays d_F [n^3],
+   d_G [3][n^3] (dF/dx, dF/dy, dF/dz), d_d [n^3] (distance) and d_beta [n^3]
+   (occupancy), all doubles; any of them may be NULL.  out->vol_frac and
+   out->t_used are set.  Uses the shh_homogenize workspace. */
+int32_t shh_field(const shh_design *design, void *d_ws, size_t ws_bytes, double *d_F,
+                  double *d_G, double *d_d, double *d_beta, void *hip_stream, shh_result *out);
+
+/* The matrix-free periodic stiffness operator: d_q = K d_p for `nrhs` nodal
+   vector fields [nrhs][3][n^3], K = sum_e E_e P_e^T K_0 P_e (Sec. 4.1, K_0 the
+   unit-voxel 8-node-hex matrix at E = 1 and Poisson ratio nu).  precision
+   SHH_PREC_FP64: d_p, d_q are doubles; SHH_PREC_MIXED: floats (E rounded to
+   float).  d_E: device n^3 doubles.  d_ws: device scratch of at least
+   4 n^3 + 4096 bytes. */
+int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, double nu,
+                            int32_t nrhs, const void *d_p, void *d_q, void *d_ws, size_t ws_bytes,
+                            void *hip_stream);
+
+/* Right-hand sides f^(k) = -sum_e E_e P_e^T K_0 chi^k of the six load cases
+   (Eq. (8)) in FP64: d_f [6][3][n^3].  d_ws as for shh_apply_stiffness. */
+int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, void *d_ws,
+                         size_t ws_bytes, void *hip_stream);
+
+/* Energy form of Eq. (8) for given displacements d_u [6][3][n^3] (doubles):
+   CH[36] = (1/n^3) sum_e E_e (chi^i + u^i_e)^T K_0 (chi^j + u^j_e). */
+int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, double CH[36],
+                   void *d_ws, size_t ws_bytes, void *hip_stream);
+
+/* Adjoint of Eq. (9) for the forward run that used d_ws (which must have had
+   save_for_backward = 1 and kappa > 0, t held fixed): given dL/dC^H (36 doubles,
+   row-major) and dL/dV, writes dL/dpos [N][3] and dL/dq [N] (host arrays).
+   Returns SHH_UNSUPPORTED for the hard step. */
+int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
+                 const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq,
+                 void *hip_stream);
+
+/* Batched adjoint over the designs of one shh_homogenize_batch call.
+   dL_dCH: [count][36]; dL_dV: [count]; dL_dpos, dL_dq: per-design host arrays
+   laid out back to back ([sum N_i][3] and [sum N_i]). */
+int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts *opts,
+                       void *const *d_ws, const size_t *ws_bytes, const double *dL_dCH,
+                       const double *dL_dV, double *dL_dpos, double *dL_dq, void *hip_stream);
+
+/* ---- instrumentation ------------------------------------------------------
+   When enabled, every launch of the CG stencil kernel (q = K p fused with the
+   direction update, the dominant kernel) is bracketed by two HIP events on the
+   stream it runs on; elapsed times are accumulated process-wide when the
+   solver next synchronizes.  shh_profile_read returns the number of timed
+   launches and their total milliseconds; shh_profile_enable(1) also resets. */
+int32_t shh_profile_enable(int32_t on);
+int32_t shh_profile_read(int64_t *launches, double *ms_total);
+
+/* ---- serving engine: continuous batching ------------------------------
+   Requests are admitted into slots while a free slot and enough arena memory
+   exist (first fit), run together -- every CG phase is one launch over all
+   resident designs -- and leave when their six load cases have converged.
+   Admission happens at iteration boundaries inside shh_engine_step.
+   d_arena: caller-owned device memory (e.g. a PyTorch uint8 tensor) of
+   arena_bytes bytes, the engine's whole HBM budget; it must outlive the engine.
+   Designs and options are copied at submit.  Not thread-safe: one host thread
+   per engine. */
+typedef struct shh_engine shh_engine;
+
+int32_t shh_engine_create(void *d_arena, size_t arena_bytes, int32_t max_slots, void *hip_stream,
+                          shh_engine **out);
+/* Footprint (arena bytes) a design would take; SHH_OVER_BUDGET from submit if
+   it exceeds the whole arena. */
+int32_t shh_engine_footprint(const shh_design *design, const shh_opts *opts, size_t *bytes);
+int32_t shh_engine_submit(shh_engine *eng, const shh_design *design, const shh_opts *opts,
+                          uint64_t request_id);
+/* Admit what fits, then run `iters` CG iterations of every resident design,
+   retire the converged ones.  *n_resident / *n_queued receive the counts after
+   the step (either may be NULL). */
+int32_t shh_engine_step(shh_engine *eng, int32_t iters, int32_t *n_resident, int32_t *n_queued);
+/* Move up to `max` finished results out: out[i] and ids[i]. */
+int32_t shh_engine_poll(shh_engine *eng, shh_result *out, uint64_t *ids, int32_t max,
+                        int32_t *n_out);
+/* Remove a queued or resident request (its result is dropped). */
+int32_t shh_engine_cancel(shh_engine *eng, uint64_t request_id);
+void shh_engine_destroy(shh_engine *eng);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHELLHOM_H */

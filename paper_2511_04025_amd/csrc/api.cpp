@@ -1,0 +1,640 @@
+// extern "C" entry points of libshellhom (declared in include/shellhom.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+using namespace shh;
+
+#define SHH_HIP(call)                                \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return SHH_HIP_ERROR;      \
+  } while (0)
+#define SHH_TRY(call)                                \
+  do {                                               \
+    int rc_ = (call);                                \
+    if (rc_ < 0) return rc_;                         \
+  } while (0)
+
+namespace {
+
+constexpr int MAX_BATCH = 64;
+
+// Segment tables of one solve live in a fixed block of the first workspace.
+size_t seg_region() { return Solver::seg_bytes(MAX_BATCH); }
+
+size_t ws_bytes_for(const shh_design *d, const shh_opts *o) {
+  const Layout L = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0);
+  return L.total + seg_region() + 256;
+}
+
+char *aligned(void *p) {
+  const uintptr_t v = (uintptr_t)p;
+  return (char *)((v + 255) & ~uintptr_t(255));
+}
+
+struct Events {
+  Slot *s;
+  explicit Events(Slot *slot) : s(slot) {
+    for (auto &e : s->ev) hipEventCreate(&e);
+  }
+  ~Events() {
+    for (auto &e : s->ev) {
+      if (e) hipEventDestroy(e);
+      e = nullptr;
+    }
+  }
+};
+
+int prepare_slot(Slot &s, const shh_design *d, const shh_opts *o, void *d_ws, size_t ws_bytes,
+                 char **seg_mem) {
+  copy_design(d, s.design);
+  s.opts = *o;
+  s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0);
+  if (!d_ws) return SHH_INVALID_ARG;
+  char *base = aligned(d_ws);
+  const size_t need = s.lay.total + seg_region() + size_t(base - (char *)d_ws);
+  if (ws_bytes < need) return SHH_WORKSPACE_TOO_SMALL;
+  s.base = base;
+  if (seg_mem) *seg_mem = base + s.lay.total;
+  s.R = o->recompute_every;
+  return SHH_OK;
+}
+
+// Run the PCG of already-set-up slots to completion.
+int solve_all(Solver &sv, std::vector<Slot *> slots, int check_every, int max_iter) {
+  SHH_TRY(sv.start(slots));
+  long long guard = 0;
+  const long long guard_max = (long long)max_iter * 4 + 64 * (long long)check_every + 1024;
+  while (!slots.empty()) {
+    SHH_TRY(sv.iterate(slots, check_every));
+    std::vector<Slot *> done;
+    SHH_TRY(sv.poll(slots, done));
+    std::vector<Slot *> rest;
+    for (Slot *s : slots)
+      if (!s->finished) rest.push_back(s);
+    slots.swap(rest);
+    guard += check_every;
+    if (guard > guard_max) {
+      for (Slot *s : slots) s->status = SHH_NOT_CONVERGED;
+      break;
+    }
+  }
+  return SHH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t shh_version(void) { return 10000; }
+
+const char *shh_strerror(int32_t code) {
+  switch (code) {
+    case SHH_OK: return "ok";
+    case SHH_NOT_CONVERGED: return "not converged: residual above rtol after max_iter";
+    case SHH_INVALID_ARG: return "invalid argument";
+    case SHH_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case SHH_HIP_ERROR: return "HIP runtime error";
+    case SHH_OVER_BUDGET: return "request footprint exceeds the engine arena";
+    case SHH_UNSUPPORTED: return "unsupported (gradient of the hard step)";
+    case SHH_BREAKDOWN: return "CG breakdown (p^T K p <= 0 or NaN)";
+    case SHH_NOT_FOUND: return "unknown request id";
+    default: return "unknown status";
+  }
+}
+
+int32_t shh_workspace_bytes(const shh_design *design, const shh_opts *opts, size_t *bytes) {
+  SHH_TRY(validate_design(design));
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  if (!bytes) return SHH_INVALID_ARG;
+  *bytes = ws_bytes_for(design, &o);
+  return SHH_OK;
+}
+
+int32_t shh_homogenize_batch(const shh_design *designs, int32_t count, const shh_opts *opts,
+                             void *const *d_ws, const size_t *ws_bytes, void *hip_stream,
+                             shh_result *out) {
+  if (count < 1 || count > MAX_BATCH || !designs || !d_ws || !ws_bytes || !out) return SHH_INVALID_ARG;
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  for (int i = 0; i < count; ++i) SHH_TRY(validate_design(&designs[i]));
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<std::unique_ptr<Slot>> slots;
+  std::vector<std::unique_ptr<Events>> evs;
+  char *seg_mem = nullptr;
+  for (int i = 0; i < count; ++i) {
+    slots.emplace_back(new Slot());
+    SHH_TRY(prepare_slot(*slots.back(), &designs[i], &o, d_ws[i], ws_bytes[i], i == 0 ? &seg_mem : nullptr));
+    evs.emplace_back(new Events(slots.back().get()));
+  }
+  for (auto &s : slots) {
+    SHH_HIP(hipEventRecord(s->ev[0], st));
+    SHH_TRY(slot_init(*s, s->base, st));
+    SHH_TRY(slot_setup_field(*s, nullptr, st));
+  }
+  Solver sv(st);
+  sv.set_segment_memory(seg_mem, seg_region());
+  std::vector<Slot *> ptrs;
+  for (auto &s : slots) ptrs.push_back(s.get());
+  SHH_TRY(solve_all(sv, ptrs, o.check_every, o.max_iter));
+  int worst = SHH_OK;
+  for (int i = 0; i < count; ++i) {
+    fill_result(*slots[i], &out[i]);
+    const int s = slots[i]->status;
+    if (s < 0 && (worst >= 0 || s < worst)) worst = s;
+    else if (s > 0 && worst == SHH_OK) worst = s;
+  }
+  return worst;
+}
+
+int32_t shh_homogenize(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
+                       void *hip_stream, shh_result *out) {
+  return shh_homogenize_batch(design, 1, opts, &d_ws, &ws_bytes, hip_stream, out);
+}
+
+int32_t shh_field(const shh_design *design, void *d_ws, size_t ws_bytes, double *d_F, double *d_G,
+                  double *d_d, double *d_beta, void *hip_stream, shh_result *out) {
+  SHH_TRY(validate_design(design));
+  shh_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = SHH_PREC_FP64;
+  o.rtol = 1e-10;
+  o.max_iter = 1;
+  SHH_TRY(normalize_opts(&o, &o));
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  SHH_TRY(prepare_slot(s, design, &o, d_ws, ws_bytes, nullptr));
+  SHH_TRY(slot_init(s, s.base, st));
+  SHH_TRY(slot_setup_field(s, d_beta, st));
+  const size_t nb = sizeof(double) * (size_t)s.host.nn;
+  if (d_F) SHH_HIP(hipMemcpyAsync(d_F, s.host.F, nb, hipMemcpyDeviceToDevice, st));
+  if (d_G) SHH_HIP(hipMemcpyAsync(d_G, s.host.G, 3 * nb, hipMemcpyDeviceToDevice, st));
+  if (d_d) SHH_HIP(hipMemcpyAsync(d_d, s.host.d, nb, hipMemcpyDeviceToDevice, st));
+  SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->vol_frac = s.state.V;
+    out->t_used = s.state.t;
+  }
+  return SHH_OK;
+}
+
+// ---- solver-only and component entry points ---------------------------------
+
+static shh_design stiffness_design(int32_t n, double nu) {
+  static const double zero3[3] = {0.0, 0.0, 0.0};
+  static const double one = 1.0;
+  shh_design d;
+  std::memset(&d, 0, sizeof(d));
+  d.n = n;
+  d.num_charges = 1;
+  d.pos = zero3;
+  d.q = &one;
+  d.K = 1;
+  d.thickness = 0.0;
+  d.E = 1.0;
+  d.nu = nu;
+  d.E_void = 0.0;
+  return d;
+}
+
+int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *bytes) {
+  if (n < 2 || n > 1024 || !bytes) return SHH_INVALID_ARG;
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  o.save_for_backward = 0;
+  const shh_design d = stiffness_design(n, 0.3);
+  *bytes = ws_bytes_for(&d, &o);
+  return SHH_OK;
+}
+
+// Slot over a workspace with moduli copied from d_E (scale taken from max E).
+static int moduli_slot(Slot &s, int32_t n, const double *d_E, double nu, const shh_opts *o, void *d_ws,
+                       size_t ws_bytes, hipStream_t st, char **seg_mem) {
+  if (n < 2 || n > 1024 || !d_E || !(nu > -1.0 && nu < 0.5)) return SHH_INVALID_ARG;
+  shh_opts oo = *o;
+  oo.save_for_backward = 0;
+  const shh_design d = stiffness_design(n, nu);
+  SHH_TRY(prepare_slot(s, &d, &oo, d_ws, ws_bytes, seg_mem));
+  SHH_TRY(slot_init(s, s.base, st));
+  SHH_TRY(slot_setup_moduli(s, d_E, st));
+  SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  const double emax = s.state.Emax;
+  if (!(emax > 0.0) || !std::isfinite(emax)) return SHH_INVALID_ARG;
+  s.host.E = emax;
+  s.host.ffloor = 1e-12 * emax * std::sqrt(3.0 * double(s.host.nn));
+  SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const shh_opts *opts,
+                                 void *d_ws, size_t ws_bytes, void *hip_stream, shh_result *out) {
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  if (!out) return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  char *seg_mem = nullptr;
+  Events ev(&s);
+  SHH_HIP(hipEventRecord(s.ev[0], st));
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
+  Solver sv(st);
+  sv.set_segment_memory(seg_mem, seg_region());
+  SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
+  fill_result(s, out);
+  return s.status;
+}
+
+int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, double nu, int32_t nrhs,
+                            const void *d_p, void *d_q, void *d_ws, size_t ws_bytes, void *hip_stream) {
+  if (nrhs < 1 || nrhs > NRHS || !d_p || !d_q) return SHH_INVALID_ARG;
+  shh_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = precision;
+  o.rtol = 1e-10;
+  o.max_iter = 1;
+  SHH_TRY(normalize_opts(&o, &o));
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  char *seg_mem = nullptr;
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
+  s.host.p0 = const_cast<void *>(d_p);
+  s.host.q = d_q;
+  SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
+  Segment g;
+  std::memset(&g, 0, sizeof(g));
+  g.slot = s.d_slot;
+  g.first = 0;
+  g.nrhs = nrhs;
+  for (int r = 0; r < nrhs; ++r) g.rhs[r] = r;
+  g.nblocks = s.host.ntiles * nrhs;
+  SHH_HIP(hipMemcpyAsync(seg_mem, &g, sizeof(g), hipMemcpyHostToDevice, st));
+  LaunchArgs la{(const Segment *)seg_mem, 1, g.nblocks};
+  SHH_HIP(launch_stencil_apply(la, precision, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, void *d_ws, size_t ws_bytes,
+                         void *hip_stream) {
+  if (!d_f) return SHH_INVALID_ARG;
+  shh_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = SHH_PREC_FP64;
+  o.rtol = 1e-10;
+  o.max_iter = 1;
+  SHH_TRY(normalize_opts(&o, &o));
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  char *seg_mem = nullptr;
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
+  s.host.r = d_f;
+  SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
+  Segment g;
+  std::memset(&g, 0, sizeof(g));
+  g.slot = s.d_slot;
+  g.nrhs = NRHS;
+  for (int r = 0; r < NRHS; ++r) g.rhs[r] = r;
+  g.nblocks = s.host.ntiles * NRHS;
+  g.flag = RES_INIT;
+  SHH_HIP(hipMemcpyAsync(seg_mem, &g, sizeof(g), hipMemcpyHostToDevice, st));
+  LaunchArgs la{(const Segment *)seg_mem, 1, g.nblocks};
+  SHH_HIP(launch_stencil_resid(la, SHH_PREC_FP64, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, double CH[36], void *d_ws,
+                   size_t ws_bytes, void *hip_stream) {
+  if (!d_u || !CH) return SHH_INVALID_ARG;
+  shh_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = SHH_PREC_FP64;
+  o.rtol = 1e-10;
+  o.max_iter = 1;
+  SHH_TRY(normalize_opts(&o, &o));
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, nullptr));
+  s.host.x64 = const_cast<double *>(d_u);
+  SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
+  SHH_HIP(launch_energy(s.d_slot, s.host.nn, st));
+  SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < 36; ++i) CH[i] = s.state.C[i];
+  return SHH_OK;
+}
+
+// ---- adjoint -------------------------------------------------------------------
+
+int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
+                 const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq, void *hip_stream) {
+  SHH_TRY(validate_design(design));
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  if (!dL_dCH || !dL_dpos || !dL_dq || !std::isfinite(dL_dV)) return SHH_INVALID_ARG;
+  if (!(design->kappa > 0.0)) return SHH_UNSUPPORTED;
+  if (!o.save_for_backward) return SHH_INVALID_ARG;
+  for (int i = 0; i < 36; ++i)
+    if (!std::isfinite(dL_dCH[i])) return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  SHH_TRY(prepare_slot(s, design, &o, d_ws, ws_bytes, nullptr));
+  // the device descriptor written by the forward call is still in place; read it back
+  SHH_HIP(hipMemcpyAsync(&s.host, (SlotDev *)(s.base + s.lay.slotdev), sizeof(SlotDev),
+                         hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  s.d_slot = (SlotDev *)(s.base + s.lay.slotdev);
+  if (s.host.n != design->n || s.host.N != design->num_charges || s.host.prec != o.precision)
+    return SHH_INVALID_ARG;
+  // dL/dE_e weights: symmetric fold of dL/dC over the 21 distinct entries
+  double g21[21];
+  int t = 0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = i; j < 6; ++j) g21[t++] = (i == j) ? dL_dCH[i * 6 + i] : dL_dCH[i * 6 + j] + dL_dCH[j * 6 + i];
+  const int N = s.host.N;
+  double *d_g21 = (double *)(s.base + s.lay.segs);
+  double *d_out = s.host.partials;  // N x 4 doubles; free after the forward
+  if (sizeof(double) * 4 * (size_t)N > sizeof(double) * NRHS * (size_t)s.lay.maxparts * 4)
+    return SHH_WORKSPACE_TOO_SMALL;
+  double *d_gE = (double *)s.host.r;     // n^3 doubles
+  double *d_scr = (double *)s.host.p0;   // p0, p1, q: 4 n^3 + small
+  SHH_HIP(hipMemcpyAsync(d_g21, g21, sizeof(g21), hipMemcpyHostToDevice, st));
+  SHH_HIP(launch_energy_sens(s.d_slot, s.host.nn, d_g21, d_gE, st));
+  SHH_HIP(launch_adjoint(s.d_slot, s.host.n, s.host.nb, N, d_gE, dL_dV, d_scr, d_out, st));
+  std::vector<double> host(4 * (size_t)N);
+  SHH_HIP(hipMemcpyAsync(host.data(), d_out, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < N; ++j) {
+    dL_dpos[3 * j] = host[4 * j];
+    dL_dpos[3 * j + 1] = host[4 * j + 1];
+    dL_dpos[3 * j + 2] = host[4 * j + 2];
+    dL_dq[j] = host[4 * j + 3];
+  }
+  return SHH_OK;
+}
+
+int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts *opts, void *const *d_ws,
+                       const size_t *ws_bytes, const double *dL_dCH, const double *dL_dV, double *dL_dpos,
+                       double *dL_dq, void *hip_stream) {
+  if (count < 1 || !designs || !d_ws || !ws_bytes || !dL_dCH || !dL_dV || !dL_dpos || !dL_dq)
+    return SHH_INVALID_ARG;
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    SHH_TRY(shh_grad(&designs[i], opts, d_ws[i], ws_bytes[i], dL_dCH + 36 * i, dL_dV[i], dL_dpos + 3 * off,
+                     dL_dq + off, hip_stream));
+    off += designs[i].num_charges;
+  }
+  return SHH_OK;
+}
+
+int32_t shh_profile_enable(int32_t on) {
+  profile_enable(on != 0);
+  return SHH_OK;
+}
+
+int32_t shh_profile_read(int64_t *launches, double *ms_total) {
+  long long l = 0;
+  double m = 0.0;
+  profile_read(&l, &m);
+  if (launches) *launches = l;
+  if (ms_total) *ms_total = m;
+  return SHH_OK;
+}
+
+}  // extern "C"
+
+// ---- serving engine ---------------------------------------------------------------
+
+struct shh_engine {
+  hipStream_t st = nullptr;
+  char *arena = nullptr;
+  size_t bytes = 0;
+  size_t header = 0;
+  int max_slots = 0;
+  int prec = -1;
+  // free list of [begin, end) byte ranges inside the arena
+  std::map<size_t, size_t> free_ranges;
+  struct Pending {
+    uint64_t id;
+    DesignCopy design;
+    shh_opts opts;
+  };
+  std::deque<Pending> queue;
+  std::vector<std::unique_ptr<Slot>> resident;
+  std::vector<size_t> resident_off;
+  std::deque<std::pair<uint64_t, shh_result>> completed;
+  std::unique_ptr<Solver> solver;
+
+  bool alloc(size_t need, size_t &off) {
+    need = (need + 255) & ~size_t(255);
+    for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+      const size_t b = it->first, e = it->second;
+      if (e - b >= need) {
+        off = b;
+        free_ranges.erase(it);
+        if (e - b > need) free_ranges[b + need] = e;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t need) {
+    need = (need + 255) & ~size_t(255);
+    size_t b = off, e = off + need;
+    auto nx = free_ranges.lower_bound(b);
+    if (nx != free_ranges.end() && nx->first == e) {
+      e = nx->second;
+      nx = free_ranges.erase(nx);
+    }
+    if (nx != free_ranges.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->second == b) {
+        b = pv->first;
+        free_ranges.erase(pv);
+      }
+    }
+    free_ranges[b] = e;
+  }
+};
+
+extern "C" {
+
+int32_t shh_engine_footprint(const shh_design *design, const shh_opts *opts, size_t *bytes) {
+  SHH_TRY(validate_design(design));
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  if (!bytes) return SHH_INVALID_ARG;
+  const Layout L = make_layout(design->n, design->num_charges, design->K, o.precision, o.save_for_backward != 0);
+  *bytes = (L.total + 255) & ~size_t(255);
+  return SHH_OK;
+}
+
+int32_t shh_engine_create(void *d_arena, size_t arena_bytes, int32_t max_slots, void *hip_stream,
+                          shh_engine **out) {
+  if (!d_arena || !out || max_slots < 1 || max_slots > 4096) return SHH_INVALID_ARG;
+  shh_engine *e = new (std::nothrow) shh_engine();
+  if (!e) return SHH_INVALID_ARG;
+  e->st = (hipStream_t)hip_stream;
+  e->arena = aligned(d_arena);
+  const size_t lost = size_t(e->arena - (char *)d_arena);
+  if (arena_bytes <= lost) {
+    delete e;
+    return SHH_WORKSPACE_TOO_SMALL;
+  }
+  e->bytes = arena_bytes - lost;
+  e->max_slots = max_slots;
+  e->header = (Solver::seg_bytes(max_slots) + 255) & ~size_t(255);
+  if (e->header >= e->bytes) {
+    delete e;
+    return SHH_WORKSPACE_TOO_SMALL;
+  }
+  e->free_ranges[e->header] = e->bytes;
+  e->solver.reset(new Solver(e->st));
+  e->solver->set_segment_memory(e->arena, e->header);
+  *out = e;
+  return SHH_OK;
+}
+
+int32_t shh_engine_submit(shh_engine *eng, const shh_design *design, const shh_opts *opts, uint64_t request_id) {
+  if (!eng) return SHH_INVALID_ARG;
+  SHH_TRY(validate_design(design));
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  if (eng->prec >= 0 && o.precision != eng->prec) return SHH_INVALID_ARG;
+  size_t need = 0;
+  SHH_TRY(shh_engine_footprint(design, &o, &need));
+  if (need > eng->bytes - eng->header) return SHH_OVER_BUDGET;
+  eng->prec = o.precision;
+  shh_engine::Pending p;
+  p.id = request_id;
+  copy_design(design, p.design);
+  p.opts = o;
+  eng->queue.push_back(std::move(p));
+  return SHH_OK;
+}
+
+static int engine_admit(shh_engine *eng, std::vector<Slot *> &fresh) {
+  while (!eng->queue.empty() && (int)eng->resident.size() < eng->max_slots) {
+    shh_engine::Pending &p = eng->queue.front();
+    const Layout L = make_layout(p.design.d.n, p.design.d.num_charges, p.design.d.K, p.opts.precision,
+                                 p.opts.save_for_backward != 0);
+    size_t off = 0;
+    if (!eng->alloc(L.total, off)) break;  // first in line waits for memory
+    std::unique_ptr<Slot> s(new Slot());
+    s->design = std::move(p.design);
+    s->design.d.pos = s->design.pos.data();
+    s->design.d.q = s->design.q.data();
+    s->design.d.alpha = s->design.alpha.empty() ? nullptr : s->design.alpha.data();
+    s->opts = p.opts;
+    s->lay = L;
+    s->R = p.opts.recompute_every;
+    s->id = p.id;
+    for (auto &ev : s->ev) hipEventCreate(&ev);
+    eng->queue.pop_front();
+    SHH_HIP(hipEventRecord(s->ev[0], eng->st));
+    int rc = slot_init(*s, eng->arena + off, eng->st);
+    if (rc == SHH_OK) rc = slot_setup_field(*s, nullptr, eng->st);
+    if (rc != SHH_OK) {
+      eng->release(off, L.total);
+      shh_result r;
+      std::memset(&r, 0, sizeof(r));
+      r.status = rc;
+      eng->completed.emplace_back(s->id, r);
+      for (auto &ev : s->ev) hipEventDestroy(ev);
+      continue;
+    }
+    fresh.push_back(s.get());
+    eng->resident.push_back(std::move(s));
+    eng->resident_off.push_back(off);
+  }
+  return SHH_OK;
+}
+
+static void engine_retire(shh_engine *eng, size_t idx) {
+  Slot *s = eng->resident[idx].get();
+  for (auto &ev : s->ev) {
+    if (ev) hipEventDestroy(ev);
+    ev = nullptr;
+  }
+  eng->release(eng->resident_off[idx], s->lay.total);
+  eng->resident.erase(eng->resident.begin() + idx);
+  eng->resident_off.erase(eng->resident_off.begin() + idx);
+}
+
+int32_t shh_engine_step(shh_engine *eng, int32_t iters, int32_t *n_resident, int32_t *n_queued) {
+  if (!eng || iters < 0) return SHH_INVALID_ARG;
+  std::vector<Slot *> fresh;
+  SHH_TRY(engine_admit(eng, fresh));
+  SHH_TRY(eng->solver->start(fresh));
+  std::vector<Slot *> live;
+  for (auto &s : eng->resident) live.push_back(s.get());
+  if (!live.empty() && iters > 0) {
+    SHH_TRY(eng->solver->iterate(live, iters));
+    std::vector<Slot *> done;
+    SHH_TRY(eng->solver->poll(live, done));
+    for (Slot *d : done) {
+      shh_result r;
+      fill_result(*d, &r);
+      eng->completed.emplace_back(d->id, r);
+    }
+    for (size_t i = eng->resident.size(); i-- > 0;)
+      if (eng->resident[i]->finished) engine_retire(eng, i);
+  }
+  if (n_resident) *n_resident = (int32_t)eng->resident.size();
+  if (n_queued) *n_queued = (int32_t)eng->queue.size();
+  return SHH_OK;
+}
+
+int32_t shh_engine_poll(shh_engine *eng, shh_result *out, uint64_t *ids, int32_t max, int32_t *n_out) {
+  if (!eng || !n_out || max < 0 || (max > 0 && (!out || !ids))) return SHH_INVALID_ARG;
+  int k = 0;
+  while (k < max && !eng->completed.empty()) {
+    ids[k] = eng->completed.front().first;
+    out[k] = eng->completed.front().second;
+    eng->completed.pop_front();
+    ++k;
+  }
+  *n_out = k;
+  return SHH_OK;
+}
+
+int32_t shh_engine_cancel(shh_engine *eng, uint64_t request_id) {
+  if (!eng) return SHH_INVALID_ARG;
+  for (auto it = eng->queue.begin(); it != eng->queue.end(); ++it) {
+    if (it->id == request_id) {
+      eng->queue.erase(it);
+      return SHH_OK;
+    }
+  }
+  for (size_t i = 0; i < eng->resident.size(); ++i) {
+    if (eng->resident[i]->id == request_id) {
+      SHH_HIP(hipStreamSynchronize(eng->st));  // its memory may still be in use
+      engine_retire(eng, i);
+      return SHH_OK;
+    }
+  }
+  return SHH_NOT_FOUND;
+}
+
+void shh_engine_destroy(shh_engine *eng) {
+  if (!eng) return;
+  hipStreamSynchronize(eng->st);
+  while (!eng->resident.empty()) engine_retire(eng, eng->resident.size() - 1);
+  delete eng;
+}
+
+}  // extern "C"

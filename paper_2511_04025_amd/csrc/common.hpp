@@ -1,0 +1,215 @@
+// Shared definitions of the HIP kernels and the host runtime of libshellhom.
+//
+// One "slot" is one design resident on the GPU: its voxel grid, its six-load-
+// case CG vectors and a small device-resident state block (CG scalars,
+// reduction counters, results).  Every kernel works on a list of slots at
+// once; a launch covers "segments" (slot, active load cases, tiles) and each
+// workgroup decodes its (slot, load case, tile) from its block index.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shh {
+
+constexpr int NRHS = 6;       // Voigt unit-strain load cases (Eq. (8))
+constexpr int MAXK = 6;       // largest truncation order supported
+constexpr int MAXB = 2 * MAXK + 1;  // 1D basis functions per axis: 1, cos, sin up to K
+
+// ---- stencil tiling: output tile TX x TY nodes, z-marching over TZ planes ----
+constexpr int TX = 32;
+constexpr int TY = 8;
+constexpr int HX = TX + 2;          // node halo tile width
+constexpr int HY = TY + 2;
+constexpr int EXC = TX + 1;         // element columns needed by the tile
+constexpr int EYC = TY + 1;
+constexpr int NHALO = HX * HY;      // 340
+constexpr int NELEMC = EXC * EYC;   // 297
+constexpr int STENCIL_THREADS = 320;  // 5 waves of 64
+
+// ---- vector-update chunking ----
+constexpr int CHUNK = 1024;         // nodes per workgroup in the update kernels (4 per thread)
+constexpr int VEC_THREADS = 256;
+
+// ---- per-slot device state ----
+enum SolveStatus : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_BREAKDOWN = -6 };
+
+struct CgState {
+  double rho[NRHS];       // r^T D^-1 r of the current residual
+  double rho_prev[NRHS];  // the previous one (for a replaced residual's beta)
+  double alpha[NRHS];
+  double beta[NRHS];
+  double rr[NRHS];        // ||r||^2 (recursive, or true after a recompute)
+  double ff[NRHS];        // ||f||^2
+  double rel[NRHS];       // ||r|| / ||f|| last seen
+  double rel_true[NRHS];  // ||f - K u|| / ||f|| at the last recompute
+  double mean[NRHS][3];   // mean of the recomputed residual per component
+  int active[NRHS];       // 1 while load case k iterates
+  int status[NRHS];
+  int iters[NRHS];
+  int pcur[NRHS];         // which of the two p buffers holds the current p
+  unsigned cnt[8];        // last-workgroup counters (0..5 per load case, 6, 7 misc)
+  double V;               // volume fraction
+  double t;               // half-thickness used
+  double gmax;            // max ||grad F|| (stored as bits for atomicMax)
+  unsigned long long gmax_bits;
+  double Emax;
+  double C[36];           // homogenized tensor
+  // thickness selection state
+  unsigned long long sel_lo[2], sel_hi[2];  // bisection over distance bit patterns
+  double bis_lo, bis_hi, bis_V;             // logistic bisection on t
+  int bis_done;
+  int pad_;
+};
+
+struct SlotDev {
+  int n;
+  int prec;             // 0 FP64, 1 mixed
+  long long nn;         // n^3
+  int tiles_x, tiles_y, tiles_z, ntiles, tz;
+  int nchunks;
+  int K, nb, N;
+  int dist_mode;
+  int maxparts;
+  int mode_t;           // 0: thickness given, 1: hard-step selection, 2: logistic bisection
+  double lam, mu;       // Lame parameters at E = 1
+  double E, E_void, iso, kappa, t_given, target_vf;
+  double rtol;
+  double ffloor;        // ||f|| at or below this counts as a zero load
+  int max_iter;
+  int pad_;
+  // element operator in the per-axis Walsh-Hadamard basis, already scaled by
+  // 1/64: 24 diagonal entries [component][mode] then the couplings
+  // 4 lambda Mhat[s|d] / 64 and 4 mu Mhat[s|d] / 64
+  double kop64[28];
+  float kop32[28];
+  // buffers
+  double *charges;      // [N][4]: x, y, z, q
+  double *alpha;        // [(K+1)^3]
+  double *coef;         // [nb^3] trig coefficient tensor of the field
+  double *F, *G, *d;    // field, gradient [3][nn], distance
+  double *E64;          // element moduli
+  float *E32;           // element moduli rounded to float (mixed)
+  void *Dinv;           // inverse Jacobi diagonal (float mixed / double FP64)
+  void *r, *p0, *p1, *q, *x;  // CG vectors [6][3][nn] (float mixed / double FP64)
+  double *x64;          // FP64 solution accumulator (mixed); == x for FP64
+  double *partials;     // [NRHS][maxparts][4]
+  CgState *st;
+};
+
+// A launch segment: `nblocks` consecutive logical workgroups for one slot.
+// Logical block L in [first, first + nblocks) maps to
+//   local = L - first, case index = local % nrhs, tile = local / nrhs.
+struct Segment {
+  SlotDev *slot;
+  int first;
+  int nblocks;
+  int nrhs;             // load cases in this segment (6, or 1 for per-slot kernels)
+  int rhs[NRHS];        // which load cases
+  int flag;             // kernel-specific (e.g. recompute mode)
+  int pad_;
+};
+
+struct LaunchArgs {
+  const Segment *segs;
+  int nseg;
+  int total;            // logical workgroups (before padding to a multiple of 8)
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  Give each XCD a contiguous run of logical workgroups so that
+// neighbouring tiles (shared halos) and the six load cases of one tile (shared
+// moduli) meet in the same L2.
+__device__ __forceinline__ int logical_block(int b, int grid) {
+  const int per = grid >> 3;  // grid is a multiple of 8
+  return (b & 7) * per + (b >> 3);
+}
+
+struct Work {
+  SlotDev *slot;
+  int rhs;
+  int tile;
+  int flag;
+  int seg;
+};
+
+__device__ __forceinline__ bool decode_work(const LaunchArgs &a, Work &w) {
+  const int L = logical_block(blockIdx.x, gridDim.x);
+  if (L >= a.total) return false;
+  int lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {  // last segment with first <= L
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.segs[mid].first <= L) lo = mid; else hi = mid - 1;
+  }
+  const Segment &s = a.segs[lo];
+  const int local = L - s.first;
+  if (local >= s.nblocks) return false;
+  w.slot = s.slot;
+  w.rhs = s.rhs[local % s.nrhs];
+  w.tile = local / s.nrhs;
+  w.flag = s.flag;
+  w.seg = lo;
+  return true;
+}
+
+// ---- deterministic block reductions in FP64 ----
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *red, int nthreads) {
+  // red: shared scratch of NV * 16 doubles
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (nthreads + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * 16 + wave] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[i * 16 + w];
+      v[i] = s;
+    }
+  }
+}
+
+// Publish a workgroup partial and find out whether this workgroup is the last
+// of `total` to arrive; the last one then sees every partial.  Thread 0 must
+// have stored this workgroup's partials before the call.
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, int *flag_smem) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    *flag_smem = (prev == total - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *flag_smem != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Sum `count` partials of NV values each (stride 4 doubles) in a fixed order:
+// thread t adds partials t, t + nthreads, ...; then a fixed-tree block sum.
+template <int NV, int STRIDE = 4>
+__device__ __forceinline__ void sum_partials(const double *parts, int count, double (&out)[NV],
+                                             double *red, int nthreads) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = 0.0;
+  for (int k = threadIdx.x; k < count; k += nthreads) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] += parts[STRIDE * k + i];
+  }
+  block_sum<NV>(out, red, nthreads);
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+}  // namespace shh

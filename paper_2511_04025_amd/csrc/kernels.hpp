@@ -1,0 +1,40 @@
+// Host-side launchers of the HIP kernels (implemented in the .hip files).
+#pragma once
+
+#include "common.hpp"
+
+namespace shh {
+
+enum { RES_INIT = 0, RES_RECOMPUTE = 1, RES_FINAL = 2 };
+enum { PH_ALPHA = 0, PH_BETA = 1, PH_MEAN = 2, PH_RESID = 3 };
+
+// field.hip (single slot per launch; d_slot is the device copy of the slot)
+hipError_t launch_field(SlotDev *d_slot, int n, int nb, hipStream_t st);
+int reduce_blocks(long long nn);
+hipError_t launch_select_hard(SlotDev *d_slot, long long nn, long long k, hipStream_t st);
+hipError_t launch_minmax_d(SlotDev *d_slot, long long nn, hipStream_t st);
+hipError_t launch_bisect_steps(SlotDev *d_slot, long long nn, int steps, hipStream_t st);
+hipError_t launch_occupancy(SlotDev *d_slot, long long nn, double *beta_out, hipStream_t st);
+hipError_t launch_moduli_copy(SlotDev *d_slot, long long nn, const double *E, hipStream_t st);
+hipError_t launch_dinv(SlotDev *d_slot, long long nn, int prec, hipStream_t st);
+
+// stencil.hip (segments of (slot, load case, tile))
+hipError_t launch_stencil_pcg(const LaunchArgs &la, int prec, hipStream_t st);
+hipError_t launch_stencil_resid(const LaunchArgs &la, int prec, hipStream_t st);
+hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st);
+
+// cg.hip (segments of (slot, load case, chunk); fold/zero use one case per slot)
+hipError_t launch_update(const LaunchArgs &la, int prec, hipStream_t st);
+hipError_t launch_finish_resid(const LaunchArgs &la, int prec, hipStream_t st);
+hipError_t launch_scalar(const LaunchArgs &la, int phase, hipStream_t st);
+hipError_t launch_fold(const LaunchArgs &la, hipStream_t st);
+hipError_t launch_zero_vectors(const LaunchArgs &la, int prec, hipStream_t st);
+
+// energy.hip
+hipError_t launch_energy(SlotDev *d_slot, long long nn, hipStream_t st);
+hipError_t launch_energy_sens(SlotDev *d_slot, long long nn, const double *d_G36, double *d_out,
+                              hipStream_t st);
+hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, const double *d_gE, double gV,
+                          double *d_scratch, double *d_out, hipStream_t st);
+
+}  // namespace shh

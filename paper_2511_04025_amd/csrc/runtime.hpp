@@ -1,0 +1,108 @@
+// Host runtime of libshellhom: slot layout and setup, the batched six-load-case
+// PCG driver, and the serving engine.  Everything here is host C++; the
+// arithmetic of the path runs in the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/shellhom.h"
+#include "common.hpp"
+
+namespace shh {
+
+// Byte offsets of one design's buffers inside its device region.
+struct Layout {
+  size_t slotdev, state, charges, alpha, coef, partials, segs;
+  size_t E64, E32, Dinv, x64, vec, field;
+  size_t vec_bytes;   // one [6][3][n^3] vector
+  size_t total;
+  int maxparts;
+};
+
+struct DesignCopy {
+  shh_design d;                 // pointers below point into the vectors
+  std::vector<double> pos, q, alpha;
+};
+
+struct Slot {
+  DesignCopy design;
+  shh_opts opts;
+  Layout lay;
+  char *base = nullptr;         // device region
+  SlotDev host;                 // host image of the device descriptor
+  SlotDev *d_slot = nullptr;
+  CgState *d_state = nullptr;
+  CgState state;                // last copy read back
+  int launched = 0;             // CG iterations launched while resident
+  int finals = 0;               // final-residual checks done
+  int R = 0;                    // recompute period (0: never)
+  bool finished = false;
+  int status = SHH_OK;
+  uint64_t id = 0;
+  double t_arrive_ms = 0.0;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double ms[5] = {0, 0, 0, 0, 0};
+};
+
+int validate_design(const shh_design *d);
+int normalize_opts(const shh_opts *in, shh_opts *out);
+Layout make_layout(int n, int N, int K, int prec, bool save);
+void copy_design(const shh_design *src, DesignCopy &dst);
+
+// Fill the slot descriptor for a region and upload it (+ charges, alpha, zeroed state).
+int slot_init(Slot &s, char *base, hipStream_t st);
+// Field, distance, thickness, occupancy, Jacobi diagonal (steps 1-2).
+int slot_setup_field(Slot &s, double *beta_out, hipStream_t st);
+// Moduli given directly instead of steps 1-2.
+int slot_setup_moduli(Slot &s, const double *d_E, hipStream_t st);
+
+// Batched solver over a set of slots sharing one stream.
+class Solver {
+ public:
+  explicit Solver(hipStream_t st) : st_(st) {}
+  // Device memory for the segment tables (must hold seg_bytes(max_slots)).
+  void set_segment_memory(char *d_mem, size_t bytes);
+  static size_t seg_bytes(int max_slots);
+  // zero vectors + initial residual for newly set-up slots
+  int start(const std::vector<Slot *> &slots);
+  // run `iters` CG iterations over the resident slots (recomputes as due)
+  int iterate(const std::vector<Slot *> &slots, int iters);
+  // read back states; for slots whose load cases are all inactive run the final
+  // residual check and, if it holds, the C^H reduction. Returns slots finished now.
+  int poll(const std::vector<Slot *> &slots, std::vector<Slot *> &done);
+  int sync();
+
+ private:
+  enum Kind { K_STENCIL = 0, K_UPDATE, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_NKIND };
+  int residual(const std::vector<Slot *> &slots, int mode);
+  int build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_rhs, LaunchArgs &la);
+  int read_states(const std::vector<Slot *> &slots);
+  int final_check(const std::vector<Slot *> &slots);
+  hipStream_t st_;
+  char *seg_mem_ = nullptr;
+  size_t seg_cap_ = 0;
+  std::vector<Segment> host_segs_[K_NKIND];
+  // events bracketing stencil launches, resolved at the next synchronization
+  std::vector<hipEvent_t> ev_pool_;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending_;
+  hipEvent_t get_event();
+  void resolve_events();
+
+ public:
+  ~Solver();
+};
+
+// process-wide stencil-launch timing (shh_profile_*)
+void profile_enable(bool on);
+bool profile_on();
+void profile_read(long long *launches, double *ms);
+void profile_add(double ms);
+
+double now_ms();
+void fill_result(const Slot &s, shh_result *out);
+
+}  // namespace shh

@@ -1,0 +1,109 @@
+"""The adjoint (Eq. (9)) on the GPU: against the FP64 oracle's gradients
+(stored for the 24^3 logistic designs, live for a small grid) and against
+central finite differences of the GPU forward path through
+torch.autograd.Function."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import torch
+from oracle import adjoint as adj, field as fld, homogenize as hom
+from paper_2511_04025_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def golden(name):
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        return json.load(f)
+
+
+def rel_err(a, b):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("seed", [5000, 5001])
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-11, 1e-7), ("mixed", 1e-7, 1e-4)])
+def test_gradient_matches_oracle_golden(seed, precision, rtol, tol):
+    from paper_2511_04025_amd import api
+    g = golden(f"c5_n24_seed{seed}.json")
+    d = wl.config5(seed, n=24).with_(thickness=g["t"])
+    r = api.homogenize(d, precision=precision, rtol=rtol, save_for_backward=True, return_workspace=True)
+    assert r["status"] == 0
+    for tag, dV in (("loss", 0.0), ("rand", g["dL_dV_rand"])):
+        dpos, dq = api.grad(d, r["opts"], r["workspace"], np.array(g[f"dL_dC_{tag}"]), dV)
+        ref_p, ref_q = np.array(g[f"dpos_{tag}"]), np.array(g[f"dq_{tag}"])
+        scale = max(np.abs(ref_p).max(), np.abs(ref_q).max())
+        assert np.max(np.abs(dpos - ref_p)) <= tol * scale, (tag, rel_err(dpos, ref_p))
+        assert np.max(np.abs(dq - ref_q)) <= tol * scale, (tag, rel_err(dq, ref_q))
+
+
+def test_gradient_matches_oracle_live_small():
+    from paper_2511_04025_amd import api
+    n = 12
+    d = wl.random_design(61, n, N=8, vf=0.25, E_void=1e-3, kappa=4.0 * n)
+    F, G = fld.field_and_gradient(d.pos, d.q, n)
+    t = fld.thickness_for_volume(fld.distance(F, G), 0.25, d.kappa)
+    C, info = hom.homogenize_design(d.pos, d.q, n, thickness=t, kappa=d.kappa, E_void=d.E_void, solver="direct")
+    rng = np.random.default_rng(8)
+    dLdC = rng.standard_normal((6, 6))
+    dpos_o, dq_o = adj.design_gradient(info, d.pos, d.q, n, dLdC, -0.3, kappa=d.kappa, E_void=d.E_void)
+    r = api.homogenize(d.with_(thickness=t), precision="fp64", rtol=1e-12, save_for_backward=True,
+                       return_workspace=True)
+    dpos, dq = api.grad(d.with_(thickness=t), r["opts"], r["workspace"], dLdC, -0.3)
+    scale = max(np.abs(dpos_o).max(), np.abs(dq_o).max())
+    assert np.max(np.abs(dpos - dpos_o)) <= 1e-8 * scale
+    assert np.max(np.abs(dq - dq_o)) <= 1e-8 * scale
+
+
+def test_hard_step_gradient_unsupported():
+    from paper_2511_04025_amd import api, binding as B
+    d = wl.random_design(62, 8, N=6, vf=0.2)
+    r = api.homogenize(d, precision="fp64", save_for_backward=True, return_workspace=True)
+    with pytest.raises(B.ShellhomError) as e:
+        api.grad(d, r["opts"], r["workspace"], np.eye(6), 0.0)
+    assert e.value.code == B.SHH_UNSUPPORTED
+
+
+def test_autograd_function_against_finite_differences():
+    from paper_2511_04025_amd import autograd as AG
+    n = 16
+    base = [wl.random_design(70 + b, n, N=8, vf=0.2, E_void=1e-3, kappa=4.0 * n) for b in range(2)]
+    t = AG.initial_thickness(base)
+    spec = AG.Spec(n=n, thickness=t, kappa=4.0 * n, E_void=1e-3, precision="fp64", rtol=1e-12)
+    pos = torch.tensor(np.stack([d.pos for d in base]), dtype=torch.float64, requires_grad=True)
+    q = torch.tensor(np.stack([d.q for d in base]), dtype=torch.float64, requires_grad=True)
+    C, V = AG.Homogenize.apply(pos, q, spec)
+    K_target = 0.3 * AG.voigt_bulk(C).detach()
+    L = AG.bulk_poisson_loss(C, K_target, 0.0) + 0.5 * V.sum()
+    L.backward()
+    gp, gq = pos.grad.numpy(), q.grad.numpy()
+
+    def loss_at(P, Q):
+        with torch.no_grad():
+            Cc, Vv = AG.Homogenize.apply(torch.tensor(P), torch.tensor(Q), spec)
+            return float(AG.bulk_poisson_loss(Cc, K_target, 0.0) + 0.5 * Vv.sum())
+
+    # central differences with one Richardson step (error O(h^4)): the logistic
+    # occupancy is sharp (kappa = 4n), so plain O(h^2) differences are too coarse
+    def deriv(f, x0, idx, h=2e-4):
+        def at(step):
+            xp, xm = x0.copy(), x0.copy()
+            xp[idx] += step
+            xm[idx] -= step
+            return (f(xp) - f(xm)) / (2 * step)
+        return (4.0 * at(h / 2) - at(h)) / 3.0
+
+    P0, Q0 = pos.detach().numpy().copy(), q.detach().numpy().copy()
+    scale = max(np.abs(gp).max(), np.abs(gq).max())
+    for idx in [(0, 0, 0), (0, 3, 2), (1, 5, 1)]:
+        fd = deriv(lambda P: loss_at(P, Q0), P0, idx)
+        assert abs(fd - gp[idx]) <= 1e-4 * scale, (idx, fd, gp[idx])
+    for idx in [(0, 2), (1, 6)]:
+        fd = deriv(lambda Q: loss_at(P0, Q), Q0, idx)
+        assert abs(fd - gq[idx]) <= 1e-4 * scale, (idx, fd, gq[idx])
+    # d is invariant to scaling the charges (iso = 0): the loss is flat along q
+    for b in range(2):
+        assert abs(np.dot(Q0[b], gq[b])) <= 1e-8 * scale * np.abs(Q0[b]).sum()

@@ -1,0 +1,138 @@
+"""Continuous-batching engine: results are the same alone and in a mix of
+designs of different resolutions and charge counts, admission respects the
+arena budget and the slot count, cancellation and failure stay isolated."""
+import numpy as np
+import pytest
+
+from gpu_helpers import torch
+from paper_2511_04025_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def engine(arena, slots=8, **kw):
+    from paper_2511_04025_amd import serving
+    return serving.Engine(arena, max_slots=slots, **kw)
+
+
+def run_all(eng, designs, ids=None, iters=16, limit=4000):
+    ids = list(range(len(designs))) if ids is None else ids
+    for i, d in zip(ids, designs):
+        eng.submit(d, i)
+    res, peak = {}, 0
+    for _ in range(limit):
+        nr, nq = eng.step(iters)
+        peak = max(peak, nr)
+        for rid, r in eng.poll():
+            res[rid] = r
+        if nr == 0 and nq == 0:
+            break
+    return res, peak
+
+
+def mix():
+    return [wl.random_design(300, 24, N=16, vf=0.12, E_void=1e-6, pm=False),
+            wl.random_design(301, 20, N=40, vf=0.18, E_void=1e-6, pm=False),
+            wl.random_design(302, 33, N=24, vf=0.08, E_void=1e-6, pm=False),
+            wl.random_design(303, 16, N=64, vf=0.05, E_void=1e-6, pm=False)]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_alone_equals_in_mix(precision):
+    ds = mix()
+    alone = {}
+    for i, d in enumerate(ds):
+        e = engine(1 << 30, precision=precision)
+        r, _ = run_all(e, [d], ids=[i])
+        alone[i] = r[i]
+        e.close()
+    e = engine(1 << 30, precision=precision)
+    # staggered arrivals: two now, two after some iterations
+    e.submit(ds[0], 0)
+    e.submit(ds[1], 1)
+    e.step(40)
+    rest, peak = run_all(e, ds[2:], ids=[2, 3])
+    got = {rid: r for rid, r in e.poll()}
+    got.update(rest)
+    e.close()
+    assert peak >= 2
+    for i in range(len(ds)):
+        a, b = alone[i], got[i]
+        assert a["status"] == 0 and b["status"] == 0
+        # deterministic reductions: bit-for-bit the same result in or out of the mix
+        assert np.array_equal(a["C"], b["C"]), i
+        assert np.array_equal(a["iters"], b["iters"]), i
+        assert a["V"] == b["V"]
+
+
+def test_engine_matches_single_entry_point():
+    from paper_2511_04025_amd import api
+    d = mix()[2]
+    r1 = api.homogenize(d, precision="mixed")
+    e = engine(1 << 30)
+    r2, _ = run_all(e, [d])
+    e.close()
+    assert np.array_equal(r1["C"], r2[0]["C"])
+
+
+def test_admission_by_footprint_and_slots():
+    ds = [wl.random_design(310 + i, 24, N=16, vf=0.12, E_void=1e-3) for i in range(5)]
+    probe = engine(1 << 20, slots=1)
+    fp = probe.footprint(ds[0])
+    probe.close()
+    # room for two designs' memory: never more than two resident
+    e = engine(2 * fp + (4 << 20), slots=8)
+    res, peak = run_all(e, ds)
+    e.close()
+    assert peak == 2 and len(res) == 5 and all(r["status"] == 0 for r in res.values())
+    # slot limit of one
+    e = engine(8 * fp, slots=1)
+    res, peak = run_all(e, ds[:3])
+    e.close()
+    assert peak == 1 and len(res) == 3
+
+
+def test_over_budget_rejected_and_isolation():
+    from paper_2511_04025_amd import binding as B
+    small = wl.random_design(320, 16, N=8, vf=0.2, E_void=1e-3)
+    big = wl.random_design(321, 64, N=8, vf=0.2, E_void=1e-3)
+    probe = engine(1 << 20, slots=1)
+    fp_small = probe.footprint(small)
+    probe.close()
+    e = engine(fp_small + (8 << 20), slots=4)
+    with pytest.raises(B.ShellhomError) as ex:
+        e.submit(big, 9)
+    assert ex.value.code == B.SHH_OVER_BUDGET
+    bad = small.with_(pos=np.full_like(small.pos, np.nan))
+    with pytest.raises(B.ShellhomError) as ex:
+        e.submit(bad, 8)
+    assert ex.value.code == B.SHH_INVALID_ARG
+    res, _ = run_all(e, [small])
+    assert res[0]["status"] == 0
+    e.close()
+
+
+def test_cancel_and_failure_isolation():
+    from paper_2511_04025_amd import binding as B, serving
+    ds = [wl.random_design(330 + i, 20, N=16, vf=0.15, E_void=1e-3) for i in range(3)]
+    e = engine(1 << 30, slots=2)
+    for i, d in enumerate(ds):
+        e.submit(d, i)
+    e.step(4)                 # 0, 1 resident; 2 queued
+    assert e.cancel(2) == B.SHH_OK   # queued
+    assert e.cancel(0) == B.SHH_OK   # resident
+    assert e.cancel(42) == B.SHH_NOT_FOUND
+    res, _ = run_all(e, [])
+    e.close()
+    assert set(res) == {1} and res[1]["status"] == 0
+    # a request capped at 3 iterations reports NOT_CONVERGED without disturbing its neighbour
+    e2 = serving.Engine(1 << 30, max_slots=4)
+    r_alone, _ = run_all(e2, [ds[1]])
+    e2.close()
+    e1 = serving.Engine(1 << 30, max_slots=4)
+    e1.submit(ds[0], 0, opts=B.make_opts("mixed", max_iter=3))
+    e1.submit(ds[1], 1)
+    res, _ = run_all(e1, [])
+    e1.close()
+    assert res[0]["status"] == B.SHH_NOT_CONVERGED and res[0]["iters"].max() <= 3
+    assert res[1]["status"] == 0 and np.array_equal(res[1]["C"], r_alone[0]["C"])
