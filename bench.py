@@ -41,7 +41,98 @@ def parse():
                     help="CG iteration cap (lower it only for hardware-counter runs)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device-to-device copy (counter calibration) and exit")
+    ap.add_argument("--mode", default="homogenize", choices=["homogenize", "serving-trace", "inverse-step"],
+                    help="homogenize: the headline line; serving-trace: Poisson trace of mixed resolutions; "
+                         "inverse-step: batched forward + adjoint of the bulk/Poisson loss")
+    ap.add_argument("--trace-count", type=int, default=64, help="requests in the serving trace")
+    ap.add_argument("--rate", type=float, default=0.0, help="arrival rate (requests/s); 0: 0.7 x saturated")
+    ap.add_argument("--arena-gb", type=float, default=64.0, help="engine arena for the serving trace")
+    ap.add_argument("--inverse-batch", type=int, default=32)
+    ap.add_argument("--inverse-n", type=int, default=96)
     return ap.parse_args()
+
+
+def serving_trace(args):
+    """Poisson arrivals of requests with n in {64, 96, 128}, 16-64 charges and
+    V in [0.03, 0.2] against the continuous-batching engine."""
+    import numpy as np
+    import torch
+    from paper_2511_04025_amd import serving, workloads as wl
+    designs = wl.config4_trace(count=args.trace_count)
+    engine = serving.Engine(int(args.arena_gb * (1 << 30)), max_slots=256, precision="mixed", rtol=args.rtol)
+    rate = args.rate
+    if rate <= 0:
+        # saturated throughput of a closed batch of the first 16 requests
+        t0 = time.perf_counter()
+        for i, d in enumerate(designs[:16]):
+            engine.submit(d, 10 ** 6 + i)
+        got = 0
+        while got < 16:
+            engine.step(args.iters_per_step)
+            got += len(engine.poll())
+        sat = 16 / (time.perf_counter() - t0)
+        rate = 0.7 * sat
+        print(f"serving: saturated {sat:.3f} designs/s, arrival rate {rate:.3f}/s", file=sys.stderr, flush=True)
+    arrivals = wl.poisson_arrivals(len(designs), rate)
+    torch.cuda.synchronize()
+    res, lat, wall = serving.run_trace(engine, designs, arrivals, iters_per_step=args.iters_per_step,
+                                       timeout_s=3000.0)
+    engine.close()
+    L = np.array([lat[i] for i in range(len(designs))])
+    bad = sum(1 for r in res.values() if r["status"] != 0)
+    by_n = {}
+    for i, d in enumerate(designs):
+        by_n.setdefault(d.n, []).append(L[i])
+    print(json.dumps({
+        "metric": "serving trace: homogenized designs/s and latency (Poisson arrivals)",
+        "value": round(len(designs) / wall, 4), "unit": "designs/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": f"config4: {len(designs)} requests, n in {{64,96,128}}, N U{{16..64}}, "
+                               f"V U[0.03,0.2], void E 1e-6, mixed, rtol {args.rtol}", "rate": round(rate, 4)},
+        "latency_p50_s": round(float(np.percentile(L, 50)), 4),
+        "latency_p99_s": round(float(np.percentile(L, 99)), 4),
+        "latency_p50_by_n": {str(k): round(float(np.percentile(v, 50)), 4) for k, v in sorted(by_n.items())},
+        "status_failures": bad, "wall_s": round(wall, 2)}))
+
+
+def inverse_step(args):
+    """One differentiable design step: forward of a batch at n^3 with the
+    logistic shell (t fixed from V = 0.10 at the initial design), the
+    bulk-modulus / Poisson-ratio loss, and the adjoint to charge positions and
+    values through torch.autograd."""
+    import numpy as np
+    import torch
+    from paper_2511_04025_amd import autograd as AG, workloads as wl
+    designs = wl.config5_batch(n=args.inverse_n, count=args.inverse_batch)
+    t = AG.initial_thickness(designs)
+    spec = AG.Spec(n=args.inverse_n, thickness=t, kappa=designs[0].kappa, E_void=designs[0].E_void,
+                   precision="mixed", rtol=args.rtol)
+    pos = torch.tensor(np.stack([d.pos for d in designs]), dtype=torch.float64, requires_grad=True)
+    q = torch.tensor(np.stack([d.q for d in designs]), dtype=torch.float64, requires_grad=True)
+    times = []
+    for step in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, V = AG.Homogenize.apply(pos, q, spec)
+        K_target = 0.5 * AG.voigt_bulk(C).detach().mean()
+        L = AG.bulk_poisson_loss(C, K_target, 0.0)
+        pos.grad = None
+        q.grad = None
+        L.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"inverse: step {step} {dt:.2f} s loss {float(L):.4e}", file=sys.stderr, flush=True)
+        if step >= args.warmup:
+            times.append(dt)
+    ms = 1e3 * float(np.mean(times))
+    print(json.dumps({
+        "metric": "differentiable design step: designs/s (forward + adjoint)",
+        "value": round(args.inverse_batch / (ms / 1e3), 4), "unit": "designs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 1), "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": f"config5: batch {args.inverse_batch} at {args.inverse_n}^3, 32 charges +-1, "
+                               f"logistic shell kappa=4n, t from V=0.10, mixed, rtol {args.rtol}"},
+        "grad_norm_pos": float(pos.grad.norm()), "grad_norm_q": float(q.grad.norm())}))
 
 
 def copy_calibration():
@@ -118,6 +209,12 @@ def main():
         sys.exit(2)
     if args.copy_only:
         copy_calibration()
+        return
+    if args.mode == "serving-trace":
+        serving_trace(args)
+        return
+    if args.mode == "inverse-step":
+        inverse_step(args)
         return
     import numpy as np
     import torch

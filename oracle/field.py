@@ -105,6 +105,32 @@ def field_at_points(pts, pos, q, K=3, alpha=None):
     return F
 
 
+def field_and_gradient_at_points(pts, pos, q, K=3, alpha=None):
+    """F and grad F of Eq. (6) at arbitrary points pts (m, 3), by direct
+    summation over every (charge, mode) term.  Returns (F (m,), G (m, 3))."""
+    pts = np.asarray(pts, dtype=np.float64)
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    a = _alpha(alpha, K)
+    F = np.zeros(len(pts))
+    G = np.zeros((len(pts), 3))
+    tp = 2.0 * np.pi
+    for j in range(len(q)):
+        for (h, k, l) in modes(K):
+            coef = a[h, k, l] * mode_weight(h, k, l) / (h * h + k * k + l * l) * q[j]
+            if coef == 0.0:
+                continue
+            ax = tp * h * (pts[:, 0] - pos[j, 0])
+            ay = tp * k * (pts[:, 1] - pos[j, 1])
+            az = tp * l * (pts[:, 2] - pos[j, 2])
+            cx, cy, cz = np.cos(ax), np.cos(ay), np.cos(az)
+            F += coef * cx * cy * cz
+            G[:, 0] += coef * (-tp * h * np.sin(ax)) * cy * cz
+            G[:, 1] += coef * cx * (-tp * k * np.sin(ay)) * cz
+            G[:, 2] += coef * cx * cy * (-tp * l * np.sin(az))
+    return F, G
+
+
 def distance(F, G, iso=0.0, dist_mode=0):
     """d_e of Eq. (7): |F - c| / ||grad F|| (dist_mode 0) or |F - c| (dist_mode 1).
 

@@ -44,11 +44,11 @@ char *aligned(void *p) {
 struct Events {
   Slot *s;
   explicit Events(Slot *slot) : s(slot) {
-    for (auto &e : s->ev) hipEventCreate(&e);
+    for (auto &e : s->ev) (void)hipEventCreate(&e);
   }
   ~Events() {
     for (auto &e : s->ev) {
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);
       e = nullptr;
     }
   }
@@ -543,7 +543,7 @@ static int engine_admit(shh_engine *eng, std::vector<Slot *> &fresh) {
     s->lay = L;
     s->R = p.opts.recompute_every;
     s->id = p.id;
-    for (auto &ev : s->ev) hipEventCreate(&ev);
+    for (auto &ev : s->ev) (void)hipEventCreate(&ev);
     eng->queue.pop_front();
     SHH_HIP(hipEventRecord(s->ev[0], eng->st));
     int rc = slot_init(*s, eng->arena + off, eng->st);
@@ -554,7 +554,7 @@ static int engine_admit(shh_engine *eng, std::vector<Slot *> &fresh) {
       std::memset(&r, 0, sizeof(r));
       r.status = rc;
       eng->completed.emplace_back(s->id, r);
-      for (auto &ev : s->ev) hipEventDestroy(ev);
+      for (auto &ev : s->ev) (void)hipEventDestroy(ev);
       continue;
     }
     fresh.push_back(s.get());
@@ -567,7 +567,7 @@ static int engine_admit(shh_engine *eng, std::vector<Slot *> &fresh) {
 static void engine_retire(shh_engine *eng, size_t idx) {
   Slot *s = eng->resident[idx].get();
   for (auto &ev : s->ev) {
-    if (ev) hipEventDestroy(ev);
+    if (ev) (void)hipEventDestroy(ev);
     ev = nullptr;
   }
   eng->release(eng->resident_off[idx], s->lay.total);
@@ -632,7 +632,7 @@ int32_t shh_engine_cancel(shh_engine *eng, uint64_t request_id) {
 
 void shh_engine_destroy(shh_engine *eng) {
   if (!eng) return;
-  hipStreamSynchronize(eng->st);
+  (void)hipStreamSynchronize(eng->st);
   while (!eng->resident.empty()) engine_retire(eng, eng->resident.size() - 1);
   delete eng;
 }

@@ -17,15 +17,24 @@ constexpr int MAXK = 6;       // largest truncation order supported
 constexpr int MAXB = 2 * MAXK + 1;  // 1D basis functions per axis: 1, cos, sin up to K
 
 // ---- stencil tiling: output tile TX x TY nodes, z-marching over TZ planes ----
-constexpr int TX = 32;
-constexpr int TY = 8;
+#ifndef SHH_TILE_X
+#define SHH_TILE_X 32
+#endif
+#ifndef SHH_TILE_Y
+#define SHH_TILE_Y 4
+#endif
+constexpr int TX = SHH_TILE_X;
+constexpr int TY = SHH_TILE_Y;
 constexpr int HX = TX + 2;          // node halo tile width
 constexpr int HY = TY + 2;
 constexpr int EXC = TX + 1;         // element columns needed by the tile
 constexpr int EYC = TY + 1;
-constexpr int NHALO = HX * HY;      // 340
-constexpr int NELEMC = EXC * EYC;   // 297
-constexpr int STENCIL_THREADS = 320;  // 5 waves of 64
+constexpr int NHALO = HX * HY;      // 204 for 32 x 4
+constexpr int NELEMC = EXC * EYC;   // 165 for 32 x 4
+// one thread per element column, rounded up to whole waves (192 for 32 x 4)
+constexpr int STENCIL_THREADS = ((NELEMC + 63) / 64) * 64;
+static_assert(2 * STENCIL_THREADS >= NHALO, "each thread stages at most two halo nodes");
+static_assert(TX * TY <= STENCIL_THREADS, "one output node per thread");
 
 // ---- vector-update chunking ----
 constexpr int CHUNK = 1024;         // nodes per workgroup in the update kernels (4 per thread)

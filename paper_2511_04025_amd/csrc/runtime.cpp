@@ -376,7 +376,7 @@ int Solver::start(const std::vector<Slot *> &slots) {
 
 Solver::~Solver() {
   resolve_events();
-  for (hipEvent_t e : ev_pool_) hipEventDestroy(e);
+  for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
 }
 
 hipEvent_t Solver::get_event() {

@@ -9,7 +9,7 @@
 #include <cstdint>
 #include <vector>
 
-#include "../../include/shellhom.h"
+#include "shellhom.h"
 #include "common.hpp"
 
 namespace shh {

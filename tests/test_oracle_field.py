@@ -172,3 +172,18 @@ def test_thickness_for_volume_logistic():
     assert fld.occupancy(np.array([t]), t, kappa)[0] == 0.5
     # logistic tends to the hard step as kappa grows
     assert np.all(fld.occupancy(np.array([t - 0.1, t + 0.1]), t, 1e4) == np.array([1.0, 0.0]))
+
+
+def test_point_evaluation_matches_grid():
+    d = wl.random_design(12, 7, N=6, pm=False)
+    n = 7
+    F, G = fld.field_and_gradient(d.pos, d.q, n)
+    c = fld.voxel_centers(n)
+    rng = np.random.default_rng(4)
+    idx = rng.integers(0, n, (30, 3))  # (i, j, k)
+    pts = np.stack([c[idx[:, 0]], c[idx[:, 1]], c[idx[:, 2]]], axis=1)
+    Fp, Gp = fld.field_and_gradient_at_points(pts, d.pos, d.q)
+    assert np.max(np.abs(Fp - F[idx[:, 2], idx[:, 1], idx[:, 0]])) < 1e-13
+    for ax in range(3):
+        assert np.max(np.abs(Gp[:, ax] - G[ax][idx[:, 2], idx[:, 1], idx[:, 0]])) < 1e-12
+    assert np.max(np.abs(Fp - fld.field_at_points(pts, d.pos, d.q))) < 1e-13
