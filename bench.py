@@ -148,15 +148,16 @@ def copy_calibration():
 
 
 def stencil_bytes(results, n, prec_bytes):
-    """Algorithmic HBM bytes moved by the CG stencil kernel over the given
-    results: per active load case and node it reads r and p_old and writes p
-    and q (4 x 3 values); per node and launch it reads E_e and D^-1 once."""
+    """Algorithmic HBM bytes moved by the CG pass kernel (one whole PCG
+    iteration) over the given results: per active load case and node it reads
+    r, q, p of the previous iteration and x and writes the new r, q, p and x
+    (8 x 3 values); per node and launch it reads E_e and D^-1 once."""
     nn = n ** 3
     total = 0
     launches = 0
     for r in results:
         it = r["iters"]
-        total += int(it.sum()) * nn * 12 * prec_bytes + int(it.max()) * nn * 2 * prec_bytes
+        total += int(it.sum()) * nn * 24 * prec_bytes + int(it.max()) * nn * 2 * prec_bytes
         launches += int(it.max())
     return total, launches
 
@@ -268,7 +269,7 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     bad = [r["status"] for r in all_res if r["status"] != 0]
 
-    # roofline of the CG stencil kernel: algorithmic bytes / event-timed duration
+    # roofline of the CG pass kernel: algorithmic bytes / event-timed duration
     nbytes, _ = stencil_bytes(all_res, args.n, 4)
     n_launch = launches.value
     t_stencil = ms_total.value / 1e3

@@ -60,7 +60,7 @@ extern "C" {
 
 /* One design (Eq. (6)-(7) parameters and material). */
 typedef struct {
-  int32_t n;            /* voxels per axis, 2 <= n <= 1024                              */
+  int32_t n;            /* voxels per axis, 2 <= n <= 512                               */
   int32_t num_charges;  /* N >= 1                                                        */
   const double *pos;    /* host [N][3] charge positions (any real; the field is
                            1-periodic)                                                   */
@@ -150,18 +150,22 @@ int32_t shh_field(const shh_design *design, void *d_ws, size_t ws_bytes, double 
    unit-voxel 8-node-hex matrix at E = 1 and Poisson ratio nu).  precision
    SHH_PREC_FP64: d_p, d_q are doubles; SHH_PREC_MIXED: floats (E rounded to
    float).  d_E: device n^3 doubles.  d_ws: device scratch of at least
-   4 n^3 + 4096 bytes. */
+   shh_workspace_bytes_stiffness(n, opts) bytes for opts with this precision
+   (SHH_INVALID_ARG / SHH_WORKSPACE_TOO_SMALL otherwise).  Synchronizes the
+   stream before returning. */
 int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, double nu,
                             int32_t nrhs, const void *d_p, void *d_q, void *d_ws, size_t ws_bytes,
                             void *hip_stream);
 
 /* Right-hand sides f^(k) = -sum_e E_e P_e^T K_0 chi^k of the six load cases
-   (Eq. (8)) in FP64: d_f [6][3][n^3].  d_ws as for shh_apply_stiffness. */
+   (Eq. (8)) in FP64: d_f [6][3][n^3].  d_ws as for shh_apply_stiffness with
+   precision SHH_PREC_FP64. */
 int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, void *d_ws,
                          size_t ws_bytes, void *hip_stream);
 
 /* Energy form of Eq. (8) for given displacements d_u [6][3][n^3] (doubles):
-   CH[36] = (1/n^3) sum_e E_e (chi^i + u^i_e)^T K_0 (chi^j + u^j_e). */
+   CH[36] = (1/n^3) sum_e E_e (chi^i + u^i_e)^T K_0 (chi^j + u^j_e).
+   d_ws as for shh_load_vectors. */
 int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, double CH[36],
                    void *d_ws, size_t ws_bytes, void *hip_stream);
 

@@ -222,7 +222,7 @@ int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *b
 // Slot over a workspace with moduli copied from d_E (scale taken from max E).
 static int moduli_slot(Slot &s, int32_t n, const double *d_E, double nu, const shh_opts *o, void *d_ws,
                        size_t ws_bytes, hipStream_t st, char **seg_mem) {
-  if (n < 2 || n > 1024 || !d_E || !(nu > -1.0 && nu < 0.5)) return SHH_INVALID_ARG;
+  if (n < 2 || n > 512 || !d_E || !(nu > -1.0 && nu < 0.5)) return SHH_INVALID_ARG;
   shh_opts oo = *o;
   oo.save_for_backward = 0;
   const shh_design d = stiffness_design(n, nu);
@@ -271,8 +271,8 @@ int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, dou
   Slot s;
   char *seg_mem = nullptr;
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
-  s.host.p0 = const_cast<void *>(d_p);
-  s.host.q = d_q;
+  s.host.p[0] = const_cast<void *>(d_p);
+  s.host.q[0] = d_q;
   SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
   Segment g;
   std::memset(&g, 0, sizeof(g));
@@ -301,7 +301,7 @@ int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, v
   Slot s;
   char *seg_mem = nullptr;
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
-  s.host.r = d_f;
+  s.host.r[0] = d_f;
   SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
   Segment g;
   std::memset(&g, 0, sizeof(g));
@@ -368,10 +368,10 @@ int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, siz
   const int N = s.host.N;
   double *d_g21 = (double *)(s.base + s.lay.segs);
   double *d_out = s.host.partials;  // N x 4 doubles; free after the forward
-  if (sizeof(double) * 4 * (size_t)N > sizeof(double) * NRHS * (size_t)s.lay.maxparts * 4)
+  if (sizeof(double) * 4 * (size_t)N > sizeof(double) * NRHS * (size_t)s.lay.maxparts * PSTRIDE)
     return SHH_WORKSPACE_TOO_SMALL;
-  double *d_gE = (double *)s.host.r;     // n^3 doubles
-  double *d_scr = (double *)s.host.p0;   // p0, p1, q: 4 n^3 + small
+  double *d_gE = (double *)s.host.r[0];  // n^3 doubles
+  double *d_scr = (double *)s.host.p[0]; // p[0], p[1], q[0], ...: 4 n^3 + small
   SHH_HIP(hipMemcpyAsync(d_g21, g21, sizeof(g21), hipMemcpyHostToDevice, st));
   SHH_HIP(launch_energy_sens(s.d_slot, s.host.nn, d_g21, d_gE, st));
   SHH_HIP(launch_adjoint(s.d_slot, s.host.n, s.host.nb, N, d_gE, dL_dV, d_scr, d_out, st));

@@ -1,124 +1,66 @@
-// CG vector kernels of the six-load-case Jacobi-PCG: streaming, one load
-// case and one CHUNK of nodes (3 components) per workgroup, FP64 dot products
-// written as per-workgroup partials; a scalar kernel per phase reduces them in
-// a fixed order and updates the load case's scalars on the device.
+// CG vector and scalar kernels of the six-load-case Jacobi-PCG (the CG pass
+// itself is the PCG mode of the stencil kernel).  Streaming kernels take one
+// load case and one CHUNK of nodes (3 components) per workgroup and write FP64
+// per-workgroup partials; a scalar kernel per phase reduces them in a fixed
+// order and updates the load case's scalars on the device.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace shh {
 
-// x += alpha p; r -= alpha q; rho' = r . D^-1 r, ||r||^2; then beta, convergence.
-// Each thread owns NPT nodes (stride VEC_THREADS); all loads are issued before
-// any store so that a wave keeps NPT * 13 loads in flight.
-template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void update_kernel(LaunchArgs la) {
-  __shared__ double red[2 * 16];
-  Work w;
-  if (!decode_work(la, w)) return;
-  SlotDev *s = w.slot;
-  CgState *st = s->st;
-  const int rhs = w.rhs;
-  if (!st->active[rhs]) return;
-  const long long nn = s->nn;
-  const long long i0 = (long long)w.tile * CHUNK;
-  const T a = (T)st->alpha[rhs];
-  const long long vb = (long long)rhs * 3 * nn;
-  T *__restrict__ x = (T *)s->x + vb;
-  T *__restrict__ r = (T *)s->r + vb;
-  const T *__restrict__ q = (const T *)s->q + vb;
-  const T *__restrict__ p = (const T *)(st->pcur[rhs] ? s->p1 : s->p0) + vb;
-  const T *__restrict__ dinv = (const T *)s->Dinv;
-  constexpr int NPT = CHUNK / VEC_THREADS;
-  T dv[NPT], pv[NPT][3], xv[NPT][3], rv[NPT][3], qv[NPT][3];
-  bool ok[NPT];
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const long long i = i0 + threadIdx.x + (long long)k * VEC_THREADS;
-    ok[k] = i < nn;
-    const long long ii = ok[k] ? i : 0;
-    dv[k] = dinv[ii];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      pv[k][c] = p[c * nn + ii];
-      xv[k][c] = x[c * nn + ii];
-      rv[k][c] = r[c * nn + ii];
-      qv[k][c] = q[c * nn + ii];
-    }
-  }
-  double acc[2] = {0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    if (!ok[k]) continue;
-    const long long i = i0 + threadIdx.x + (long long)k * VEC_THREADS;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      x[c * nn + i] = xv[k][c] + a * pv[k][c];
-      const T rn = rv[k][c] - a * qv[k][c];
-      r[c * nn + i] = rn;
-      const T zv = dv[k] * rn;
-      acc[0] += (double)rn * (double)zv;
-      acc[1] += (double)rn * (double)rn;
-    }
-  }
-  block_sum<2>(acc, red, VEC_THREADS);
-  double *parts = s->partials + (long long)rhs * s->maxparts * 4;
-  if (threadIdx.x == 0) {
-    parts[4 * w.tile + 0] = acc[0];
-    parts[4 * w.tile + 1] = acc[1];
-  }
-}
-
 // After the FP64 residual stencil: r -= mean (per component), rho = r . D^-1 r,
-// ||r||^2, and the scalar update for the initial / periodic / final residual.
+// ||r||^2, for the initial / periodic / final residual.
 template <typename T>
 __global__ __launch_bounds__(VEC_THREADS) void finish_resid_kernel(LaunchArgs la) {
   __shared__ double red[2 * 16];
   Work w;
   if (!decode_work(la, w)) return;
-  SlotDev *s = w.slot;
-  CgState *st = s->st;
+  const SHH_CONST SlotDev *s = to_const(w.slot);
+  const SHH_CONST CgState *st = to_const(s->st);
   const int rhs = w.rhs;
   const int mode = w.flag;
   if (mode == RES_RECOMPUTE && !st->active[rhs]) return;
   if (mode == RES_FINAL && !(st->ff[rhs] > s->ffloor * s->ffloor)) return;
   const long long nn = s->nn;
-  const long long i0 = (long long)w.tile * CHUNK;
+  constexpr uint32_t SZ = sizeof(T);
+  const uint32_t i0 = (uint32_t)w.tile * CHUNK;
+  const uint32_t base = i0 * SZ;
+  const uint32_t cS[3] = {0u, (uint32_t)nn * SZ, 2u * (uint32_t)nn * SZ};
   const long long vb = (long long)rhs * 3 * nn;
-  T *__restrict__ r = (T *)s->r + vb;
-  const T *__restrict__ dinv = (const T *)s->Dinv;
-  const double m0 = st->mean[rhs][0], m1 = st->mean[rhs][1], m2 = st->mean[rhs][2];
+  const rsrc_t rR = make_rsrc((const T *)s->r[st->pcur[rhs]] + vb, 3ull * nn * SZ);
+  const rsrc_t rD = make_rsrc(s->Dinv, (uint64_t)nn * SZ);
+  const double mean[3] = {st->mean[rhs][0], st->mean[rhs][1], st->mean[rhs][2]};
   constexpr int NPT = CHUNK / VEC_THREADS;
   T dv[NPT], rv[NPT][3];
   bool ok[NPT];
+  uint32_t vo[NPT];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    const long long i = i0 + threadIdx.x + (long long)k * VEC_THREADS;
-    ok[k] = i < nn;
-    const long long ii = ok[k] ? i : 0;
-    dv[k] = dinv[ii];
+    const uint32_t l = threadIdx.x + k * VEC_THREADS;
+    ok[k] = (long long)(i0 + l) < nn;
+    vo[k] = ok[k] ? l * SZ : 0u;  // the chunk's first node stands in past the end
+    dv[k] = bload<T>(rD, vo[k], base);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) rv[k][c] = r[c * nn + ii];
+    for (int c = 0; c < 3; ++c) rv[k][c] = bload<T>(rR, vo[k], base + cS[c]);
   }
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if (!ok[k]) continue;
-    const long long i = i0 + threadIdx.x + (long long)k * VEC_THREADS;
     const double d = (double)dv[k];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double mc = c == 0 ? m0 : (c == 1 ? m1 : m2);
-      const T rn = (T)((double)rv[k][c] - mc);
-      r[c * nn + i] = rn;
+      const T rn = (T)((double)rv[k][c] - mean[c]);
+      bstore<T>(rn, rR, vo[k], base + cS[c]);
       acc[0] += (double)rn * d * (double)rn;
       acc[1] += (double)rn * (double)rn;
     }
   }
   block_sum<2>(acc, red, VEC_THREADS);
-  double *parts = s->partials + (long long)rhs * s->maxparts * 4;
+  double *parts = w.slot->partials + ((long long)rhs * s->maxparts + w.tile) * PSTRIDE;
   if (threadIdx.x == 0) {
-    parts[4 * w.tile + 0] = acc[0];
-    parts[4 * w.tile + 1] = acc[1];
+    parts[0] = acc[0];
+    parts[1] = acc[1];
   }
 }
 
@@ -128,57 +70,53 @@ __global__ __launch_bounds__(VEC_THREADS) void finish_resid_kernel(LaunchArgs la
 // producers, so no fences or atomics are needed and the result is
 // deterministic.  Skip rules repeat the producers' so both see the same set.
 __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int phase) {
-  __shared__ double red[3 * 16];
+  __shared__ double red[5 * 16];
   Work w;
   if (!decode_work(la, w)) return;
   SlotDev *s = w.slot;
   CgState *st = s->st;
   const int rhs = w.rhs;
   const int mode = w.flag;
-  const double *parts = s->partials + (long long)rhs * s->maxparts * 4;
-  if (phase == PH_ALPHA) {  // after the PCG stencil: alpha = rho / (p . K p)
+  const double *parts = s->partials + (long long)rhs * s->maxparts * PSTRIDE;
+  if (phase == PH_ITER) {
+    // after CG pass j: the pass's sums r.z, r.r, p.q, q.z, q.D^-1 q
     if (!st->active[rhs]) return;
-    double tot[1];
-    sum_partials<1>(parts, s->ntiles, tot, red, VEC_THREADS);
-    if (threadIdx.x == 0) {
-      const double sigma = tot[0];
-      if (!(sigma > 0.0) || !isfinite(sigma)) {
-        st->status[rhs] = ST_BREAKDOWN;
-        st->active[rhs] = 0;
-      } else {
-        st->alpha[rhs] = st->rho[rhs] / sigma;
-      }
-      st->pcur[rhs] ^= 1;
+    double tot[5];
+    sum_partials<5, PSTRIDE>(parts, s->ntiles, tot, red, VEC_THREADS);
+    if (threadIdx.x != 0) return;
+    const double rho = tot[0], rr = tot[1], sigma = tot[2], tau = tot[3], mu = tot[4];
+    st->iters[rhs] += 1;
+    st->pcur[rhs] ^= 1;  // the pass wrote r_j, p_j, q_j into the other set
+    st->rho[rhs] = rho;
+    st->rr[rhs] = rr;
+    const double rel = sqrt(rr / st->ff[rhs]);
+    st->rel[rhs] = rel;
+    const bool ok = isfinite(rho) && rho >= 0.0 && isfinite(sigma) && sigma > 0.0;
+    // alpha_j = rho_j / p_j.K p_j, still to be applied to x and r
+    const double a = ok ? rho / sigma : 0.0;
+    st->alpha[rhs] = a;
+    if (ok) {
+      // rho_{j+1} = (r_j - a q_j) . D^-1 (r_j - a q_j), expanded with this
+      // pass's sums (rounding can only push a vanishing value below zero)
+      const double rho_next = fmax(rho - 2.0 * a * tau + a * a * mu, 0.0);
+      st->beta[rhs] = rho > 0.0 ? rho_next / rho : 0.0;
     }
-  } else if (phase == PH_BETA) {  // after the update: beta, convergence
-    if (!st->active[rhs]) return;
-    double tot[2];
-    sum_partials<2>(parts, s->nchunks, tot, red, VEC_THREADS);
-    if (threadIdx.x == 0) {
-      const double rho = tot[0], rr = tot[1];
-      st->iters[rhs] += 1;
-      st->rho_prev[rhs] = st->rho[rhs];
-      st->beta[rhs] = rho / st->rho[rhs];
-      st->rho[rhs] = rho;
-      st->rr[rhs] = rr;
-      const double rel = sqrt(rr / st->ff[rhs]);
-      st->rel[rhs] = rel;
-      if (!isfinite(rho) || rho < 0.0) {
-        st->status[rhs] = ST_BREAKDOWN;
-        st->active[rhs] = 0;
-      } else if (rel <= s->rtol) {
-        st->status[rhs] = ST_CONVERGED;
-        st->active[rhs] = 0;
-      } else if (st->iters[rhs] >= s->max_iter) {
-        st->status[rhs] = ST_MAXIT;
-        st->active[rhs] = 0;
-      }
+    if (rel <= s->rtol) {
+      st->status[rhs] = ST_CONVERGED;
+      st->active[rhs] = 0;
+    } else if (!ok || !isfinite(rel)) {
+      st->status[rhs] = ST_BREAKDOWN;
+      st->active[rhs] = 0;
+      st->alpha[rhs] = 0.0;
+    } else if (st->iters[rhs] >= s->max_iter) {
+      st->status[rhs] = ST_MAXIT;
+      st->active[rhs] = 0;
     }
   } else if (phase == PH_MEAN) {  // after the residual stencil: component means
     if (mode == RES_RECOMPUTE && !st->active[rhs]) return;
     if (mode == RES_FINAL && !(st->ff[rhs] > s->ffloor * s->ffloor)) return;
     double tot[3];
-    sum_partials<3>(parts, s->ntiles, tot, red, VEC_THREADS);
+    sum_partials<3, PSTRIDE>(parts, s->ntiles, tot, red, VEC_THREADS);
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) st->mean[rhs][c] = tot[c] / double(s->nn);
@@ -187,7 +125,7 @@ __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int 
     if (mode == RES_RECOMPUTE && !st->active[rhs]) return;
     if (mode == RES_FINAL && !(st->ff[rhs] > s->ffloor * s->ffloor)) return;
     double tot[2];
-    sum_partials<2>(parts, s->nchunks, tot, red, VEC_THREADS);
+    sum_partials<2, PSTRIDE>(parts, s->nchunks, tot, red, VEC_THREADS);
     if (threadIdx.x != 0) return;
     const double rho = tot[0], rr = tot[1];
     if (mode == RES_INIT) {
@@ -211,9 +149,12 @@ __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int 
         st->rel_true[rhs] = 1.0;
       }
     } else {
-      // residual replacement: keep p, restart the rho recurrence from the true residual
+      // residual replacement: the fold has applied the pending update to x;
+      // keep p and restart the recurrences from the true residual
+      st->rho_prev[rhs] = st->rho[rhs];
+      st->beta[rhs] = st->rho[rhs] > 0.0 ? rho / st->rho[rhs] : 0.0;
+      st->alpha[rhs] = 0.0;
       st->rho[rhs] = rho;
-      st->beta[rhs] = rho / st->rho_prev[rhs];
       st->rr[rhs] = rr;
       const double rel = sqrt(rr / st->ff[rhs]);
       st->rel[rhs] = rel;
@@ -237,55 +178,67 @@ __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int 
   }
 }
 
-// Mixed precision: x64 += x32, x32 = 0 for all six load cases of a chunk.
+// Before a residual replacement (flag RES_RECOMPUTE) or the final check
+// (RES_FINAL): apply each selected load case's pending update x += alpha p
+// (selection as in the residual kernels that follow, whose scalar phase then
+// clears alpha), and in mixed precision move the FP32 x into the FP64
+// accumulator: x64 += x32 (+ alpha p), x32 = 0.
+template <typename T>
 __global__ __launch_bounds__(VEC_THREADS) void fold_kernel(LaunchArgs la) {
   Work w;
   if (!decode_work(la, w)) return;
-  SlotDev *s = w.slot;
+  const SHH_CONST SlotDev *s = to_const(w.slot);
+  const SHH_CONST CgState *st = to_const(s->st);
+  const int mode = w.flag;
   const long long nn = s->nn;
   const long long i0 = (long long)w.tile * CHUNK;
   const long long i1 = min(i0 + CHUNK, nn);
-  float *x32 = (float *)s->x;
-  double *x64 = s->x64;
-  for (int f = 0; f < 3 * NRHS; ++f) {
-    for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
-      const long long j = f * nn + i;
-      x64[j] += (double)x32[j];
-      x32[j] = 0.0f;
+  for (int k = 0; k < NRHS; ++k) {
+    const bool sel = mode == RES_RECOMPUTE ? st->active[k] != 0 : st->ff[k] > s->ffloor * s->ffloor;
+    const double a = sel ? st->alpha[k] : 0.0;
+    const T *p = (const T *)s->p[st->pcur[k]] + (long long)k * 3 * nn;
+    T *x = (T *)s->x + (long long)k * 3 * nn;
+    double *x64 = s->x64 + (long long)k * 3 * nn;
+    for (int c = 0; c < 3; ++c) {
+      for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+        const long long j = c * nn + i;
+        if constexpr (sizeof(T) == 4) {
+          x64[j] += (double)x[j] + a * (double)p[j];
+          x[j] = T(0);
+        } else {
+          x[j] += a * p[j];  // FP64: x is the accumulator
+        }
+      }
     }
   }
 }
 
-// Zero x, both p buffers, q (and x64) of every load case before a solve.
+// Zero x, both p and both q buffers (and x64) of every load case before a solve.
 template <typename T>
 __global__ __launch_bounds__(VEC_THREADS) void zero_kernel(LaunchArgs la) {
   Work w;
   if (!decode_work(la, w)) return;
-  SlotDev *s = w.slot;
+  const SHH_CONST SlotDev *s = to_const(w.slot);
   const long long nn = s->nn;
   const long long i0 = (long long)w.tile * CHUNK;
   const long long i1 = min(i0 + CHUNK, nn);
-  T *x = (T *)s->x, *p0 = (T *)s->p0, *p1 = (T *)s->p1, *q = (T *)s->q;
+  T *x = (T *)s->x, *p0 = (T *)s->p[0], *p1 = (T *)s->p[1], *q0 = (T *)s->q[0], *q1 = (T *)s->q[1];
+  double *x64 = s->x64;
+  const bool mixed = s->prec == 1;
   for (int f = 0; f < 3 * NRHS; ++f) {
     for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
       const long long j = f * nn + i;
       x[j] = T(0);
       p0[j] = T(0);
       p1[j] = T(0);
-      q[j] = T(0);
-      if (s->prec == 1) s->x64[j] = 0.0;
+      q0[j] = T(0);
+      q1[j] = T(0);
+      if (mixed) x64[j] = 0.0;
     }
   }
 }
 
 static int padded_grid(int total) { return ((total + 7) / 8) * 8; }
-
-hipError_t launch_update(const LaunchArgs &la, int prec, hipStream_t st) {
-  if (la.total == 0) return hipSuccess;
-  if (prec == 0) update_kernel<double><<<padded_grid(la.total), VEC_THREADS, 0, st>>>(la);
-  else update_kernel<float><<<padded_grid(la.total), VEC_THREADS, 0, st>>>(la);
-  return hipGetLastError();
-}
 
 hipError_t launch_finish_resid(const LaunchArgs &la, int prec, hipStream_t st) {
   if (la.total == 0) return hipSuccess;
@@ -300,9 +253,10 @@ hipError_t launch_scalar(const LaunchArgs &la, int phase, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fold(const LaunchArgs &la, hipStream_t st) {
+hipError_t launch_fold(const LaunchArgs &la, int prec, hipStream_t st) {
   if (la.total == 0) return hipSuccess;
-  fold_kernel<<<padded_grid(la.total), VEC_THREADS, 0, st>>>(la);
+  if (prec == 0) fold_kernel<double><<<padded_grid(la.total), VEC_THREADS, 0, st>>>(la);
+  else fold_kernel<float><<<padded_grid(la.total), VEC_THREADS, 0, st>>>(la);
   return hipGetLastError();
 }
 

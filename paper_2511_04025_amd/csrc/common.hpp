@@ -39,6 +39,7 @@ static_assert(TX * TY <= STENCIL_THREADS, "one output node per thread");
 // ---- vector-update chunking ----
 constexpr int CHUNK = 1024;         // nodes per workgroup in the update kernels (4 per thread)
 constexpr int VEC_THREADS = 256;
+constexpr int PSTRIDE = 8;          // doubles per workgroup partial of the CG kernels
 
 // ---- per-slot device state ----
 enum SolveStatus : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_BREAKDOWN = -6 };
@@ -46,8 +47,8 @@ enum SolveStatus : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_BREA
 struct CgState {
   double rho[NRHS];       // r^T D^-1 r of the current residual
   double rho_prev[NRHS];  // the previous one (for a replaced residual's beta)
-  double alpha[NRHS];
-  double beta[NRHS];
+  double alpha[NRHS];     // step length of the update still to be applied to x, r
+  double beta[NRHS];      // coefficient of the next direction update
   double rr[NRHS];        // ||r||^2 (recursive, or true after a recompute)
   double ff[NRHS];        // ||f||^2
   double rel[NRHS];       // ||r|| / ||f|| last seen
@@ -56,7 +57,7 @@ struct CgState {
   int active[NRHS];       // 1 while load case k iterates
   int status[NRHS];
   int iters[NRHS];
-  int pcur[NRHS];         // which of the two p buffers holds the current p
+  int pcur[NRHS];         // which of the two r, p, q buffer sets is current
   unsigned cnt[8];        // last-workgroup counters (0..5 per load case, 6, 7 misc)
   double V;               // volume fraction
   double t;               // half-thickness used
@@ -100,9 +101,11 @@ struct SlotDev {
   double *E64;          // element moduli
   float *E32;           // element moduli rounded to float (mixed)
   void *Dinv;           // inverse Jacobi diagonal (float mixed / double FP64)
-  void *r, *p0, *p1, *q, *x;  // CG vectors [6][3][nn] (float mixed / double FP64)
+  // CG vectors [6][3][nn] (float mixed / double FP64).  r, p and q are double
+  // buffered: a CG pass reads set pcur[k] of load case k and writes the other
+  void *r[2], *p[2], *q[2], *x;
   double *x64;          // FP64 solution accumulator (mixed); == x for FP64
-  double *partials;     // [NRHS][maxparts][4]
+  double *partials;     // [NRHS][maxparts][PSTRIDE]
   CgState *st;
 };
 
@@ -142,15 +145,26 @@ struct Work {
   int seg;
 };
 
+// Segments, slot descriptors and (within one kernel) the CG scalars are never
+// written while a kernel reads them: reading them through the constant address
+// space lets the compiler use scalar loads and keep them in scalar registers.
+#define SHH_CONST __attribute__((address_space(4)))
+
+template <typename T>
+__device__ __forceinline__ const SHH_CONST T *to_const(const T *p) {
+  return (const SHH_CONST T *)p;
+}
+
 __device__ __forceinline__ bool decode_work(const LaunchArgs &a, Work &w) {
   const int L = logical_block(blockIdx.x, gridDim.x);
   if (L >= a.total) return false;
+  const SHH_CONST Segment *segs = to_const(a.segs);
   int lo = 0, hi = a.nseg - 1;
   while (lo < hi) {  // last segment with first <= L
     const int mid = (lo + hi + 1) >> 1;
-    if (a.segs[mid].first <= L) lo = mid; else hi = mid - 1;
+    if (segs[mid].first <= L) lo = mid; else hi = mid - 1;
   }
-  const Segment &s = a.segs[lo];
+  const SHH_CONST Segment &s = segs[lo];
   const int local = L - s.first;
   if (local >= s.nblocks) return false;
   w.slot = s.slot;
@@ -219,6 +233,72 @@ __device__ __forceinline__ void sum_partials(const double *parts, int count, dou
 __device__ __forceinline__ int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
+}
+
+// Periodic wrap of an index known to lie in [-n, 2n).
+__device__ __forceinline__ int wrap1(int v, int n) {
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// ---- global-memory access ----
+// Slot buffers are reached through pointers stored in device memory, which the
+// compiler would otherwise treat as generic (FLAT) addresses.  FLAT loads count
+// against the LDS wait counter as well, so every LDS wait would also wait for
+// the prefetched HBM loads.  The hot kernels therefore address global memory
+// through address-space-1 pointers held in scalar registers, with 32-bit byte
+// offsets (the "saddr + voffset" form of global_load / global_store).
+#define SHH_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ SHH_GLOBAL T *to_global(T *p) {
+  // the pointer is the same for every lane: keep it in scalar registers
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (SHH_GLOBAL T *)(((uint64_t)hi << 32) | lo);
+}
+
+// ---- buffer access (the streaming arrays of the stencil and CG kernels) ----
+// A buffer resource holds the base address and byte size of one array in
+// scalar registers; each access adds a per-lane 32-bit byte offset (fixed per
+// thread: its place in the tile or chunk) and a wave-uniform scalar offset
+// (plane and component), so the hot loops do no per-lane address arithmetic.
+// Every array covered by one resource is below 4 GiB (n <= 512).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;  // gfx9: 32-bit data format, raw access
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)(uint32_t)bytes,
+                                           RSRC_WORD3);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit elements");
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t voff, uint32_t soff) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit elements");
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(
+        __builtin_bit_cast(uint32_t __attribute__((ext_vector_type(2))), v), r, voff, soff, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T gld(const SHH_GLOBAL T *base, uint32_t byte_off) {
+  return *(const SHH_GLOBAL T *)((const SHH_GLOBAL char *)base + byte_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void gst(SHH_GLOBAL T *base, uint32_t byte_off, T v) {
+  *(SHH_GLOBAL T *)((SHH_GLOBAL char *)base + byte_off) = v;
 }
 
 }  // namespace shh

@@ -19,13 +19,18 @@
 
 namespace shh {
 
-template <typename T>
-__device__ __forceinline__ void hex_apply(const T *__restrict__ kop, const T (&h)[3][8],
-                                          T (&y)[3][8], T e) {
+//
+// The all-sum mode m = 0 of each component is a rigid translation: its
+// diagonal entry is zero (every term carries S along some axis) and no
+// coupling touches it, so h[c][0] is never read and y[c][0] is exactly zero.
+template <typename T, typename KP>
+__device__ __forceinline__ void hex_apply(KP kop, const T (&h)[3][8], T (&y)[3][8], T e) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) {
+    y[c][0] = T(0);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) y[c][m] = kop[c * 8 + m] * h[c][m];
+    for (int m = 1; m < 8; ++m) y[c][m] = kop[c * 8 + m] * h[c][m];
+  }
   // couplings of components (i, j) with third axis k:
   //   y_i(i=d, j=s) += 4 lam M_k h_j(i=s, j=d)   y_i(i=s, j=d) += 4 mu M_k h_j(i=d, j=s)
   //   y_j(i=s, j=d) += 4 lam M_k h_i(i=d, j=s)   y_j(i=d, j=s) += 4 mu M_k h_i(i=s, j=d)
@@ -46,7 +51,7 @@ __device__ __forceinline__ void hex_apply(const T *__restrict__ kop, const T (&h
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) y[c][m] *= e;
+    for (int m = 1; m < 8; ++m) y[c][m] *= e;
 }
 
 // Hadamard coefficients of the unit-strain test displacement chi^k

@@ -6,7 +6,7 @@
 namespace shh {
 
 enum { RES_INIT = 0, RES_RECOMPUTE = 1, RES_FINAL = 2 };
-enum { PH_ALPHA = 0, PH_BETA = 1, PH_MEAN = 2, PH_RESID = 3 };
+enum { PH_ITER = 0, PH_MEAN = 2, PH_RESID = 3 };
 
 // field.hip (single slot per launch; d_slot is the device copy of the slot)
 hipError_t launch_field(SlotDev *d_slot, int n, int nb, hipStream_t st);
@@ -18,16 +18,16 @@ hipError_t launch_occupancy(SlotDev *d_slot, long long nn, double *beta_out, hip
 hipError_t launch_moduli_copy(SlotDev *d_slot, long long nn, const double *E, hipStream_t st);
 hipError_t launch_dinv(SlotDev *d_slot, long long nn, int prec, hipStream_t st);
 
-// stencil.hip (segments of (slot, load case, tile))
+// stencil.hip (segments of (slot, load case, tile)); the PCG launch is one
+// whole CG iteration of every listed load case
 hipError_t launch_stencil_pcg(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_stencil_resid(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st);
 
 // cg.hip (segments of (slot, load case, chunk); fold/zero use one case per slot)
-hipError_t launch_update(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_finish_resid(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_scalar(const LaunchArgs &la, int phase, hipStream_t st);
-hipError_t launch_fold(const LaunchArgs &la, hipStream_t st);
+hipError_t launch_fold(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_zero_vectors(const LaunchArgs &la, int prec, hipStream_t st);
 
 // energy.hip

@@ -56,7 +56,7 @@ static bool finite(double v) { return std::isfinite(v); }
 
 int validate_design(const shh_design *d) {
   if (!d) return SHH_INVALID_ARG;
-  if (d->n < 2 || d->n > 1024) return SHH_INVALID_ARG;
+  if (d->n < 2 || d->n > 512) return SHH_INVALID_ARG;  // 32-bit byte offsets per vector
   if (d->num_charges < 1 || !d->pos || !d->q) return SHH_INVALID_ARG;
   if (d->K < 1 || d->K > MAXK) return SHH_INVALID_ARG;
   for (int j = 0; j < d->num_charges; ++j) {
@@ -118,14 +118,14 @@ Layout make_layout(int n, int N, int K, int prec, bool save) {
   L.charges = take(sizeof(double) * 4 * (size_t)N);
   L.alpha = take(sizeof(double) * (size_t)(K + 1) * (K + 1) * (K + 1));
   L.coef = take(sizeof(double) * (size_t)nb * nb * nb);
-  L.partials = take(sizeof(double) * (size_t)NRHS * L.maxparts * 4);
+  L.partials = take(sizeof(double) * (size_t)NRHS * L.maxparts * PSTRIDE);
   L.segs = take(4096);
   L.E64 = take(sizeof(double) * nn);
   L.E32 = prec == SHH_PREC_MIXED ? take(sizeof(float) * nn) : 0;
   L.Dinv = take(ts * nn);
   L.x64 = prec == SHH_PREC_MIXED ? take(sizeof(double) * NRHS * 3 * nn) : 0;
   L.vec_bytes = align256(ts * NRHS * 3 * nn);
-  L.vec = take(5 * L.vec_bytes);  // r, p0, p1, q, x
+  L.vec = take(7 * L.vec_bytes);  // r[2], p[2], q[2], x
   L.field = save ? take(sizeof(double) * 5 * nn) : L.vec;  // F, G[3], d (aliased unless saved)
   L.total = off;
   return L;
@@ -211,11 +211,12 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.E64 = (double *)(base + L.E64);
   h.E32 = prec == SHH_PREC_MIXED ? (float *)(base + L.E32) : nullptr;
   h.Dinv = base + L.Dinv;
-  h.r = base + L.vec;
-  h.p0 = base + L.vec + L.vec_bytes;
-  h.p1 = base + L.vec + 2 * L.vec_bytes;
-  h.q = base + L.vec + 3 * L.vec_bytes;
-  h.x = base + L.vec + 4 * L.vec_bytes;
+  for (int b = 0; b < 2; ++b) {
+    h.r[b] = base + L.vec + (0 + b) * L.vec_bytes;
+    h.p[b] = base + L.vec + (2 + b) * L.vec_bytes;
+    h.q[b] = base + L.vec + (4 + b) * L.vec_bytes;
+  }
+  h.x = base + L.vec + 6 * L.vec_bytes;
   h.x64 = prec == SHH_PREC_MIXED ? (double *)(base + L.x64) : (double *)h.x;
   h.partials = (double *)(base + L.partials);
   h.st = (CgState *)(base + L.state);
@@ -342,9 +343,10 @@ int Solver::residual(const std::vector<Slot *> &slots, int mode) {
   const bool all = mode != RES_RECOMPUTE;
   LaunchArgs la;
   int rc;
-  if (prec == SHH_PREC_MIXED && mode != RES_INIT) {
-    if ((rc = build(K_FOLD, slots, 0, true, la))) return rc;
-    SHH_HIP(launch_fold(la, st_));
+  if (mode != RES_INIT) {
+    // apply the pending x update (and, mixed, move x into the FP64 accumulator)
+    if ((rc = build(K_FOLD, slots, mode, true, la))) return rc;
+    SHH_HIP(launch_fold(la, prec, st_));
   }
   if ((rc = build(K_RESID, slots, mode, all, la))) return rc;
   SHH_HIP(launch_stencil_resid(la, prec, st_));
@@ -404,10 +406,9 @@ void Solver::resolve_events() {
 int Solver::iterate(const std::vector<Slot *> &slots, int iters) {
   if (slots.empty()) return SHH_OK;
   const int prec = slots[0]->host.prec;
-  LaunchArgs la_s, la_u;
+  LaunchArgs la_s;
   int rc;
   if ((rc = build(K_STENCIL, slots, 0, false, la_s))) return rc;
-  if ((rc = build(K_UPDATE, slots, 0, false, la_u))) return rc;
   const bool prof = profile_on();
   LaunchArgs la_c;
   if ((rc = build(K_SCAL_IT, slots, 0, false, la_c))) return rc;
@@ -423,9 +424,7 @@ int Solver::iterate(const std::vector<Slot *> &slots, int iters) {
       SHH_HIP(hipEventRecord(e1, st_));
       ev_pending_.emplace_back(e0, e1);
     }
-    SHH_HIP(launch_scalar(la_c, PH_ALPHA, st_));
-    SHH_HIP(launch_update(la_u, prec, st_));
-    SHH_HIP(launch_scalar(la_c, PH_BETA, st_));
+    SHH_HIP(launch_scalar(la_c, PH_ITER, st_));
     std::vector<Slot *> due;
     for (Slot *s : slots) {
       s->launched += 1;

@@ -77,7 +77,7 @@ class Solver {
   int sync();
 
  private:
-  enum Kind { K_STENCIL = 0, K_UPDATE, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_NKIND };
+  enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_NKIND };
   int residual(const std::vector<Slot *> &slots, int mode);
   int build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_rhs, LaunchArgs &la);
   int read_states(const std::vector<Slot *> &slots);

@@ -10,20 +10,36 @@
 //   3. applies E_e K_0 in that basis (hexop.hpp) and transforms back along z
 //      (the half for the lower node plane completes it; the upper half is
 //      carried to the next layer in registers),
-//   4. transforms back along x-y through LDS and writes one output node per
-//      thread.
-// Every global access is a coalesced x-row; the periodic wrap is an index
-// map on the halo only.
+//   4. transforms the lower node plane's share back to the four x-y corners,
+//      exchanges them through LDS and sums four per output node.
+// Thread t < TX*TY both stages and outputs interior node (t % TX, t / TX) of
+// the tile; the ring of halo nodes around the tile is staged by the remaining
+// threads (and, past those, by a second slot of the first threads).  Every
+// global access is a coalesced x-row of one buffer resource; the periodic
+// wrap is an index map on the halo only.
 //
 // Modes
-//   PCG   : the node values are p_new = D^-1 r + beta p_old (the CG direction
-//           update, fused); owned nodes store p_new into the other p buffer;
-//           output q = K p_new and the FP64 partial p_new . q (alpha is formed
-//           by the scalar kernel that follows).
+//   PCG   : one whole Jacobi-PCG iteration of the load case per pass.  Pass j
+//           reads r_{j-1}, q_{j-1}, p_{j-1} (set pcur) and, at every staged
+//           node, forms
+//             r_j = r_{j-1} - alpha q_{j-1},  z_j = D^-1 r_j,
+//             p_j = z_j + beta p_{j-1}
+//           with the alpha, beta left by the scalar kernel after pass j-1.
+//           At owned nodes it writes r_j, p_j (other set) and
+//           x_j = x_{j-1} + alpha p_{j-1}, and sums r_j . z_j and r_j . r_j;
+//           at the outputs it writes q_j = K p_j (other set) and sums
+//           p_j . q_j, q_j . z_j and q_j . D^-1 q_j (all sums FP64).
+//           The scalar kernel turns these into alpha_j and, by expanding
+//           (r_j - alpha_j q_j) . D^-1 (r_j - alpha_j q_j), the next rho and
+//           beta: standard PCG whose x, r update is carried into the next
+//           pass instead of a pass of its own.  Both p buffers and both q
+//           buffers are zeroed when a solve starts and stay finite, so
+//           alpha = beta = 0 needs no special case.
 //   RESID : FP64 arithmetic on the FP64 solution x: r = -K (x + chi^k), i.e.
 //           f - K x with f = -sum_e E_e P_e^T K_0 chi^k added at the element;
-//           stored in the vector precision, with FP64 sums of r for the
-//           mean projection.  Flag 0 (initial) treats x as zero.
+//           stored in the vector precision into the current r, with FP64
+//           sums of r for the mean projection.  Flag 0 (initial) treats x as
+//           zero.
 //   APPLY : plain q = K p (component entry point and tests).
 #include <type_traits>
 
@@ -39,17 +55,29 @@ enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2 };
 #define SHH_STENCIL_WAVES_PER_EU 1
 #endif
 
+constexpr int NINT = TX * TY;        // interior (owned) nodes of a tile
+constexpr int NRING = NHALO - NINT;  // halo ring: 2 (TX + 2) + 2 TY nodes
+
+// Halo-tile index of ring node j: the bottom row, the top row, then the left
+// and right columns between them.
+__device__ __forceinline__ int ring_h(int j) {
+  if (j < HX) return j;
+  if (j < 2 * HX) return (HY - 1) * HX + (j - HX);
+  if (j < 2 * HX + (HY - 2)) return (1 + j - 2 * HX) * HX;
+  return (2 + j - 2 * HX - (HY - 2)) * HX - 1;
+}
+
 template <typename TC, typename TS, int MODE>
 __global__ __launch_bounds__(STENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(SHH_STENCIL_WAVES_PER_EU)))
 void stencil_kernel(LaunchArgs la) {
   __shared__ TC nbuf[2][3][NHALO];
   __shared__ TC ebuf[2][12][NELEMC];
-  __shared__ double red[3 * 16];
+  __shared__ double red[5 * 16];
 
   Work w;
   if (!decode_work(la, w)) return;
-  SlotDev *s = w.slot;
-  CgState *st = s->st;
+  const SHH_CONST SlotDev *s = to_const(w.slot);
+  const SHH_CONST CgState *st = to_const(s->st);
   const int rhs = w.rhs;
   if (MODE == MODE_PCG && !st->active[rhs]) return;
   if (MODE == MODE_RESID) {
@@ -57,9 +85,12 @@ void stencil_kernel(LaunchArgs la) {
     if (w.flag == RES_FINAL && !(st->ff[rhs] > s->ffloor * s->ffloor)) return;
   }
 
+  // n <= 512: every byte offset into one load case's [3][n^3] vector fits in
+  // 32 bits.  Per-lane offsets are fixed per thread; plane and component
+  // offsets are wave-uniform scalars.
   const int n = s->n;
+  const uint32_t plane = (uint32_t)n * (uint32_t)n;
   const long long nn = s->nn;
-  const long long plane = (long long)n * n;
   const int tile = w.tile;
   const int tix = tile % s->tiles_x;
   const int tiy = (tile / s->tiles_x) % s->tiles_y;
@@ -68,114 +99,157 @@ void stencil_kernel(LaunchArgs la) {
   const int z1 = min(z0 + s->tz, n);
   const int tid = threadIdx.x;
 
+  using TL = typename std::conditional<MODE == MODE_RESID, double, TS>::type;
+  constexpr uint32_t SL = sizeof(TL), SS = sizeof(TS), SC = sizeof(TC);
+
   // element-column role
   const bool is_elem = tid < NELEMC;
   const int ecx = tid % EXC, ecy = tid / EXC;
-  const long long eoff = (long long)wrapi(y0 - 1 + ecy, n) * n + wrapi(x0 - 1 + ecx, n);
-  // output role
+  const uint32_t eoff = ((uint32_t)wrapi(y0 - 1 + ecy, n) * n + (uint32_t)wrapi(x0 - 1 + ecx, n)) * SC;
+  // output role (also the owner of the node in the PCG update)
   const int ox = tid % TX, oy = tid / TX;
-  const bool is_out = tid < TX * TY && x0 + ox < n && y0 + oy < n;
-  const long long ooff = (long long)(y0 + oy) * n + (x0 + ox);
-  // element columns (ecx, ecy) = (ox + 1, oy + 1) is the one whose 2x2 node
-  // block has this output node at its lower corner: the output thread reads
-  // its own p from that block's position in the node buffer
-  const int own_h = (oy + 1) * HX + ox + 1;
-  // halo-load role: up to two halo nodes per thread
-  bool hval[2], hown[2];
-  long long hoff[2];
+  const bool is_out = tid < NINT && x0 + ox < n && y0 + oy < n;
+  const uint32_t ooff = ((uint32_t)(y0 + oy) * n + (uint32_t)(x0 + ox)) * SS;
+  // staging role: slot 0 of thread t < NINT is its own interior node; ring
+  // nodes fill the remaining slot-0 threads and then slot 1 of the first ones
+  bool hval[2];
+  int hslot[2];
+  uint32_t hoS[2], hoL[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int h = tid + k * STENCIL_THREADS;
-    hval[k] = h < NHALO;
+    int h;
+    if (k == 0 && tid < NINT) {
+      h = (oy + 1) * HX + ox + 1;
+      hval[k] = true;
+    } else {
+      const int j = k == 0 ? tid - NINT : tid + STENCIL_THREADS - NINT;
+      hval[k] = j < NRING;
+      h = hval[k] ? ring_h(j) : 0;
+    }
+    hslot[k] = h;
     const int hx = h % HX, hy = h / HX;
-    hoff[k] = (long long)wrapi(y0 - 1 + hy, n) * n + wrapi(x0 - 1 + hx, n);
-    hown[k] = hval[k] && hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && x0 + hx - 1 < n &&
-              y0 + hy - 1 < n;
+    const uint32_t o = (uint32_t)wrapi(y0 - 1 + hy, n) * n + (uint32_t)wrapi(x0 - 1 + hx, n);
+    hoS[k] = o * SS;
+    hoL[k] = o * SL;
   }
 
-  const TC *__restrict__ kop;
-  if constexpr (sizeof(TC) == 8) kop = (const TC *)s->kop64; else kop = (const TC *)s->kop32;
-  const TC *__restrict__ E;
-  if constexpr (sizeof(TC) == 8) E = (const TC *)s->E64; else E = (const TC *)s->E32;
+  const SHH_CONST TC *kop;
+  if constexpr (sizeof(TC) == 8) kop = (const SHH_CONST TC *)s->kop64;
+  else kop = (const SHH_CONST TC *)s->kop32;
+  rsrc_t rE;
+  if constexpr (sizeof(TC) == 8) rE = make_rsrc(s->E64, (uint64_t)nn * SC);
+  else rE = make_rsrc(s->E32, (uint64_t)nn * SC);
 
+  // component c of a load case's vector starts c * n^3 elements in
+  const uint32_t cS[3] = {0u, (uint32_t)nn * SS, 2u * (uint32_t)nn * SS};
+  const uint32_t cL[3] = {0u, (uint32_t)nn * SL, 2u * (uint32_t)nn * SL};
   const long long vbase = (long long)rhs * 3 * nn;
-  const TS *__restrict__ rin = nullptr;
-  const TS *__restrict__ pold = nullptr;
-  const TS *__restrict__ dinv = nullptr;
-  const TS *__restrict__ pin = nullptr;
-  const double *__restrict__ xin = nullptr;
-  TS *__restrict__ pnew = nullptr;
-  TS *__restrict__ qout = nullptr;
-  TC beta = TC(0);
+  const uint64_t vbytesS = 3ull * nn * SS, vbytesL = 3ull * nn * SL;
+  // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX, rD
+  // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q.
+  rsrc_t rA, rB, rC, rR, rQ, rP, rX, rD;
+  TC alpha = TC(0), beta = TC(0);
   if constexpr (MODE == MODE_PCG) {
     const int pc = st->pcur[rhs];
-    rin = (const TS *)s->r + vbase;
-    pold = (const TS *)(pc ? s->p1 : s->p0) + vbase;
-    pnew = (TS *)(pc ? s->p0 : s->p1) + vbase;
-    dinv = (const TS *)s->Dinv;
-    qout = (TS *)s->q + vbase;
+    rA = make_rsrc((const TS *)s->r[pc] + vbase, vbytesS);
+    rB = make_rsrc((const TS *)s->q[pc] + vbase, vbytesS);
+    rC = make_rsrc((const TS *)s->p[pc] + vbase, vbytesS);
+    rR = make_rsrc((const TS *)s->r[pc ^ 1] + vbase, vbytesS);
+    rQ = make_rsrc((const TS *)s->q[pc ^ 1] + vbase, vbytesS);
+    rP = make_rsrc((const TS *)s->p[pc ^ 1] + vbase, vbytesS);
+    rX = make_rsrc((const TS *)s->x + vbase, vbytesS);
+    rD = make_rsrc(s->Dinv, (uint64_t)nn * SS);
+    alpha = (TC)st->alpha[rhs];
     beta = (TC)st->beta[rhs];
   } else if constexpr (MODE == MODE_RESID) {
-    xin = s->x64 + vbase;
-    qout = (TS *)s->r + vbase;
+    rA = make_rsrc(s->x64 + vbase, vbytesL);
+    rQ = make_rsrc((const TS *)s->r[st->pcur[rhs]] + vbase, vbytesS);
   } else {
-    pin = (const TS *)s->p0 + vbase;
-    qout = (TS *)s->q + vbase;
+    rA = make_rsrc((const TS *)s->p[0] + vbase, vbytesL);
+    rQ = make_rsrc((const TS *)s->q[0] + vbase, vbytesS);
   }
   const bool zero_x = (MODE == MODE_RESID) && (w.flag == RES_INIT);
-  const bool use_pold = beta != TC(0);
 
-  // ---- plane staging, split into issue (global loads into registers) and
-  //      finish (combine, store owned p, store to LDS) so that the loads of a
-  //      plane are in flight during the previous plane's element work
-  using TL = typename std::conditional<MODE == MODE_RESID, double, TS>::type;
-  TL raw_a[2][3], raw_b[2][3];
-  TS raw_d[2];
+  // FP64 partial sums: PCG r.z, r.r, p.q, q.z, q.D^-1 q; RESID sums of r
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  // owned-node values kept from staging to output (two steps later), by
+  // parity of the step that staged them: z, D^-1 and p of the node
+  TC own_z[2][3], own_p[2][3], own_d[2];
+
+  // ---- plane staging, split into issue (loads into registers) and finish
+  //      (combine, store owned values, store to LDS) so that the loads of a
+  //      plane are in flight during the previous plane's element work.
+  //      Node planes z0-1 .. z1 are touched, so a single wrap suffices.
+  TL raw_a[2][3];
+  TS raw_b[2][3], raw_c[2][3], raw_d[2], raw_x[3];
   auto issue = [&](int z) {
-    const long long pb = (long long)wrapi(z, n) * plane;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (!hval[k]) continue;
-      const long long i = pb + hoff[k];
-      if constexpr (MODE == MODE_PCG) {
-        raw_d[k] = dinv[i];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          raw_a[k][c] = rin[c * nn + i];
-          raw_b[k][c] = use_pold ? pold[c * nn + i] : TS(0);
-        }
-      } else if constexpr (MODE == MODE_RESID) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) raw_a[k][c] = zero_x ? 0.0 : xin[c * nn + i];
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) raw_a[k][c] = pin[c * nn + i];
-      }
-    }
-  };
-  auto finish = [&](int z, int b) {
-    const long long pb = (long long)wrapi(z, n) * plane;
+    const uint32_t pz = (uint32_t)wrap1(z, n) * plane;
     const bool ownz = z >= z0 && z < z1;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (!hval[k]) continue;
-      const int hslot = tid + k * STENCIL_THREADS;
+      if constexpr (MODE == MODE_PCG) {
+        raw_d[k] = bload<TS>(rD, hoS[k], pz * SS);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        TC v;
-        if constexpr (MODE == MODE_PCG) {
-          const TC zc = (TC)raw_d[k] * (TC)raw_a[k][c];
-          v = beta * (TC)raw_b[k][c] + zc;
-          if (hown[k] && ownz) pnew[c * nn + pb + hoff[k]] = (TS)v;
-        } else {
-          v = (TC)raw_a[k][c];
+        for (int c = 0; c < 3; ++c) {
+          raw_a[k][c] = bload<TS>(rA, hoS[k], pz * SS + cS[c]);
+          raw_b[k][c] = bload<TS>(rB, hoS[k], pz * SS + cS[c]);
+          raw_c[k][c] = bload<TS>(rC, hoS[k], pz * SS + cS[c]);
         }
-        nbuf[b][c][hslot] = v;
+        if (k == 0 && is_out && ownz) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) raw_x[c] = bload<TS>(rX, hoS[0], pz * SS + cS[c]);
+        }
+      } else if constexpr (MODE == MODE_RESID) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) raw_a[k][c] = zero_x ? 0.0 : bload<TL>(rA, hoL[k], pz * SL + cL[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) raw_a[k][c] = bload<TL>(rA, hoL[k], pz * SL + cL[c]);
+      }
+    }
+  };
+  auto finish = [&](int z, auto bc) {
+    constexpr int b = decltype(bc)::value;
+    const uint32_t pz = (uint32_t)wrap1(z, n) * plane;
+    const bool ownz = z >= z0 && z < z1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (!hval[k]) continue;
+      if constexpr (MODE == MODE_PCG) {
+        const TC dk = (TC)raw_d[k];
+        TC rn[3], zn[3], pn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          rn[c] = (TC)raw_a[k][c] - alpha * (TC)raw_b[k][c];
+          zn[c] = dk * rn[c];
+          pn[c] = beta * (TC)raw_c[k][c] + zn[c];
+          nbuf[b][c][hslot[k]] = pn[c];
+        }
+        if (k == 0 && is_out && ownz) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const uint32_t so = pz * SS + cS[c];
+            bstore<TS>((TS)rn[c], rR, hoS[0], so);
+            bstore<TS>((TS)pn[c], rP, hoS[0], so);
+            bstore<TS>((TS)((TC)raw_x[c] + alpha * (TC)raw_c[0][c]), rX, hoS[0], so);
+            const double r64 = (double)rn[c];
+            acc[0] += r64 * (double)zn[c];
+            acc[1] += r64 * r64;
+            own_z[b][c] = zn[c];
+            own_p[b][c] = pn[c];
+          }
+          own_d[b] = dk;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nbuf[b][c][hslot[k]] = (TC)raw_a[k][c];
       }
     }
   };
   // x-y Hadamard coefficients of the 2x2 node block of this element column
-  auto xy_hadamard = [&](int b, TC (&A)[3][4]) {
+  auto xy_hadamard = [&](auto bc, TC (&A)[3][4]) {
+    constexpr int b = decltype(bc)::value;
     const int i00 = ecy * HX + ecx;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -188,123 +262,153 @@ void stencil_kernel(LaunchArgs la) {
       A[c][3] = dx1 - dx0;
     }
   };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
 
-  TC A[3][4], Bacc[3][4];
-  TC pc_next[3] = {TC(0), TC(0), TC(0)};
-  TC pc_cur[3] = {TC(0), TC(0), TC(0)};
-  double acc[3] = {0.0, 0.0, 0.0};
+  // Values carried from one element layer to the next are double-buffered by
+  // layer parity (index b of the step that reads them) so that the two-step
+  // unrolled loop needs no register copies: the x-y Hadamard coefficients of
+  // the lower node plane (A), the upper-plane half of the layer below (Bc)
+  // and the element modulus (ev).
+  TC A[2][3][4], Bc[2][3][4];
+  TC ev[2];
 
   // prologue: planes z0-1 and z0 staged, plane z0+1 in flight
   issue(z0 - 1);
-  finish(z0 - 1, 0);
+  finish(z0 - 1, B0{});
   issue(z0);
-  TC e_next = is_elem ? E[(long long)wrapi(z0 - 1, n) * plane + eoff] : TC(0);
+  ev[0] = is_elem ? bload<TC>(rE, eoff, (uint32_t)wrap1(z0 - 1, n) * plane * SC) : TC(0);
   __syncthreads();
   if (is_elem) {
-    xy_hadamard(0, A);
+    xy_hadamard(B0{}, A[0]);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) Bacc[c][m] = TC(0);
+      for (int m = 0; m < 4; ++m) Bc[0][c][m] = TC(0);
   }
-  finish(z0, 1);
+  finish(z0, B1{});
   const int S = z1 - z0 + 1;  // element layers z0-1 .. z1-1
   if (S > 1) issue(z0 + 1);
   __syncthreads();
 
-  for (int sl = 0; sl < S; ++sl) {
-    const int kk = z0 - 1 + sl;  // element layer between node planes kk and kk+1
-    const int b = sl & 1;
-    const TC e = e_next;
-    if (is_elem && sl + 1 < S) e_next = E[(long long)wrapi(kk + 1, n) * plane + eoff];
+  // one element layer: kk = z0 - 1 + sl lies between node planes kk and kk+1;
+  // the layer's node planes sit in nbuf[b] and nbuf[b ^ 1] with b = sl & 1
+  auto step = [&](const int sl, auto bc) {
+    constexpr int b = decltype(bc)::value;
+    constexpr int bn = b ^ 1;
+    using BN = std::integral_constant<int, bn>;
+    const int kk = z0 - 1 + sl;
+    const TC e = ev[b];
+    if (is_elem && sl + 1 < S) ev[bn] = bload<TC>(rE, eoff, (uint32_t)wrap1(kk + 1, n) * plane * SC);
+    // the owned values of output plane kk (staged two steps ago, same parity)
+    // before this step's staging replaces them
+    TC oz[3], op[3], od = TC(0);
     if constexpr (MODE == MODE_PCG) {
-      // this thread's p at the next output plane (node plane kk+1, in nbuf[b ^ 1])
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        pc_cur[c] = pc_next[c];
-        if (is_out) pc_next[c] = nbuf[b ^ 1][c][own_h];
+        oz[c] = own_z[b][c];
+        op[c] = own_p[b][c];
       }
+      od = own_d[b];
     }
     if (is_elem) {
-      TC An[3][4];
-      xy_hadamard(b ^ 1, An);
+      const TC (&Ac)[3][4] = A[b];
+      TC (&An)[3][4] = A[bn];
+      xy_hadamard(BN{}, An);
       TC h[3][8], y[3][8];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c) {
+        h[c][0] = TC(0);  // rigid mode: not read by hex_apply
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          h[c][m] = A[c][m] + An[c][m];
-          h[c][m + 4] = An[c][m] - A[c][m];
-        }
+        for (int m = 1; m < 4; ++m) h[c][m] = Ac[c][m] + An[c][m];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) h[c][m + 4] = An[c][m] - Ac[c][m];
+      }
       if constexpr (MODE == MODE_RESID) add_chi<TC>(rhs, h);
       hex_apply<TC>(kop, h, y, e);
       if (sl > 0) {
+        // lower node plane kk: this layer's lower half completes the upper
+        // half carried from the layer below; store its four x-y corners
+        const TC (&Bacc)[3][4] = Bc[b];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int m = 0; m < 4; ++m) ebuf[b][c * 4 + m][tid] = Bacc[c][m] + (y[c][m] - y[c][m + 4]);
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          Bacc[c][m] = y[c][m] + y[c][m + 4];
-          A[c][m] = An[c][m];
+        for (int c = 0; c < 3; ++c) {
+          const TC L0 = Bacc[c][0] - y[c][4];  // y[c][0] == 0
+          const TC L1 = Bacc[c][1] + (y[c][1] - y[c][5]);
+          const TC L2 = Bacc[c][2] + (y[c][2] - y[c][6]);
+          const TC L3 = Bacc[c][3] + (y[c][3] - y[c][7]);
+          const TC u0 = L0 - L1, u1 = L0 + L1, v0 = L2 - L3, v1 = L2 + L3;
+          ebuf[b][c * 4 + 0][tid] = u0 - v0;
+          ebuf[b][c * 4 + 1][tid] = u1 - v1;
+          ebuf[b][c * 4 + 2][tid] = u0 + v0;
+          ebuf[b][c * 4 + 3][tid] = u1 + v1;
         }
+      }
+      TC (&Bnew)[3][4] = Bc[bn];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Bnew[c][0] = y[c][4];
+#pragma unroll
+        for (int m = 1; m < 4; ++m) Bnew[c][m] = y[c][m] + y[c][m + 4];
+      }
     }
     // stage node plane kk+2 (its loads were issued a step ago), issue kk+3
-    if (sl + 1 < S) finish(z0 + sl + 1, b);
+    if (sl + 1 < S) finish(z0 + sl + 1, bc);
     if (sl + 2 < S) issue(z0 + sl + 2);
     __syncthreads();
     if (sl > 0 && is_out) {
-      // node (x0+ox, y0+oy, kk) gathers the element columns at offsets
-      // (ax, ay) in {0,1}^2: column index (ox + 1 - ax, oy + 1 - ay)
-      const int e00 = (oy + 1) * EXC + ox + 1, e10 = e00 - 1, e01 = e00 - EXC, e11 = e01 - 1;
+      // node (x0+ox, y0+oy, kk) is corner (ax, ay) of element column
+      // (ox + 1 - ax, oy + 1 - ay)
+      const int e00 = (oy + 1) * EXC + ox + 1;
       TC qv[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const TC *B0 = ebuf[b][c * 4 + 0], *B1 = ebuf[b][c * 4 + 1], *B2 = ebuf[b][c * 4 + 2],
-                 *B3 = ebuf[b][c * 4 + 3];
-        const TC a00 = (B0[e00] - B1[e00]) - (B2[e00] - B3[e00]);
-        const TC a10 = (B0[e10] + B1[e10]) - (B2[e10] + B3[e10]);
-        const TC a01 = (B0[e01] - B1[e01]) + (B2[e01] - B3[e01]);
-        const TC a11 = (B0[e11] + B1[e11]) + (B2[e11] + B3[e11]);
-        qv[c] = (a00 + a10) + (a01 + a11);
-      }
-      const long long i = (long long)kk * plane + ooff;
+      for (int c = 0; c < 3; ++c)
+        qv[c] = (ebuf[b][c * 4 + 0][e00] + ebuf[b][c * 4 + 1][e00 - 1]) +
+                (ebuf[b][c * 4 + 2][e00 - EXC] + ebuf[b][c * 4 + 3][e00 - EXC - 1]);
+      const uint32_t pk = (uint32_t)kk * plane * SS;
       if constexpr (MODE == MODE_PCG) {
+        const double d64 = (double)od;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          qout[c * nn + i] = (TS)qv[c];
-          acc[0] += (double)pc_cur[c] * (double)qv[c];
+          bstore<TS>((TS)qv[c], rQ, ooff, pk + cS[c]);
+          const double q64 = (double)qv[c];
+          acc[2] += (double)op[c] * q64;
+          acc[3] += (double)oz[c] * q64;
+          acc[4] += d64 * q64 * q64;
         }
       } else if constexpr (MODE == MODE_RESID) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const TS rv = (TS)(-qv[c]);
-          qout[c * nn + i] = rv;
+          bstore<TS>(rv, rQ, ooff, pk + cS[c]);
           acc[c] += (double)rv;
         }
       } else {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) qout[c * nn + i] = (TS)qv[c];
+        for (int c = 0; c < 3; ++c) bstore<TS>((TS)qv[c], rQ, ooff, pk + cS[c]);
       }
     }
+  };
+  int sl = 0;
+  for (; sl + 1 < S; sl += 2) {
+    step(sl, B0{});
+    step(sl + 1, B1{});
   }
+  if (sl < S) step(sl, B0{});
 
   // workgroup partials only; the scalar kernel that follows reduces them
+  double *parts = w.slot->partials + ((long long)rhs * s->maxparts + tile) * PSTRIDE;
   if constexpr (MODE == MODE_PCG) {
-    double a1[1] = {acc[0]};
-    block_sum<1>(a1, red, STENCIL_THREADS);
-    double *parts = s->partials + (long long)rhs * s->maxparts * 4;
-    if (tid == 0) parts[4 * tile] = a1[0];
-  } else if constexpr (MODE == MODE_RESID) {
-    block_sum<3>(acc, red, STENCIL_THREADS);
-    double *parts = s->partials + (long long)rhs * s->maxparts * 4;
+    block_sum<5>(acc, red, STENCIL_THREADS);
     if (tid == 0) {
-      parts[4 * tile + 0] = acc[0];
-      parts[4 * tile + 1] = acc[1];
-      parts[4 * tile + 2] = acc[2];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) parts[i] = acc[i];
+    }
+  } else if constexpr (MODE == MODE_RESID) {
+    double a3[3] = {acc[0], acc[1], acc[2]};
+    block_sum<3>(a3, red, STENCIL_THREADS);
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) parts[i] = a3[i];
     }
   }
 }
