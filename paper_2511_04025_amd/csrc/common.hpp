@@ -21,7 +21,7 @@ constexpr int MAXB = 2 * MAXK + 1;  // 1D basis functions per axis: 1, cos, sin 
 #define SHH_TILE_X 32
 #endif
 #ifndef SHH_TILE_Y
-#define SHH_TILE_Y 4
+#define SHH_TILE_Y 8
 #endif
 constexpr int TX = SHH_TILE_X;
 constexpr int TY = SHH_TILE_Y;
@@ -29,9 +29,9 @@ constexpr int HX = TX + 2;          // node halo tile width
 constexpr int HY = TY + 2;
 constexpr int EXC = TX + 1;         // element columns needed by the tile
 constexpr int EYC = TY + 1;
-constexpr int NHALO = HX * HY;      // 204 for 32 x 4
-constexpr int NELEMC = EXC * EYC;   // 165 for 32 x 4
-// one thread per element column, rounded up to whole waves (192 for 32 x 4)
+constexpr int NHALO = HX * HY;      // 340 for 32 x 8
+constexpr int NELEMC = EXC * EYC;   // 297 for 32 x 8
+// one thread per element column, rounded up to whole waves (320 for 32 x 8)
 constexpr int STENCIL_THREADS = ((NELEMC + 63) / 64) * 64;
 static_assert(2 * STENCIL_THREADS >= NHALO, "each thread stages at most two halo nodes");
 static_assert(TX * TY <= STENCIL_THREADS, "one output node per thread");
@@ -281,14 +281,21 @@ __device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
+// Cache policy of the streaming stores (CPol bits: 2 = non-temporal on gfx950):
+// the CG vectors written by one pass are read back only by the next, long
+// after they would have left the L2, so they are streamed past it.
+#ifndef SHH_STORE_AUX
+#define SHH_STORE_AUX 2
+#endif
+
 template <typename T>
 __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t voff, uint32_t soff) {
   static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit elements");
   if constexpr (sizeof(T) == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, SHH_STORE_AUX);
   else
     __builtin_amdgcn_raw_buffer_store_b64(
-        __builtin_bit_cast(uint32_t __attribute__((ext_vector_type(2))), v), r, voff, soff, 0);
+        __builtin_bit_cast(uint32_t __attribute__((ext_vector_type(2))), v), r, voff, soff, SHH_STORE_AUX);
 }
 
 template <typename T>

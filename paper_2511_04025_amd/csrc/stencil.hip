@@ -54,6 +54,9 @@ enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2 };
 #ifndef SHH_STENCIL_WAVES_PER_EU
 #define SHH_STENCIL_WAVES_PER_EU 1
 #endif
+#ifndef SHH_CARRY_DB
+#define SHH_CARRY_DB 0
+#endif
 
 constexpr int NINT = TX * TY;        // interior (owned) nodes of a tile
 constexpr int NRING = NHALO - NINT;  // halo ring: 2 (TX + 2) + 2 TY nodes
@@ -72,6 +75,7 @@ __global__ __launch_bounds__(STENCIL_THREADS) __attribute__((amdgpu_waves_per_eu
 void stencil_kernel(LaunchArgs la) {
   __shared__ TC nbuf[2][3][NHALO];
   __shared__ TC ebuf[2][12][NELEMC];
+  __shared__ TC mbuf[2][NHALO];  // element moduli, by the halo slot of the element's lower corner
   __shared__ double red[5 * 16];
 
   Work w;
@@ -105,16 +109,20 @@ void stencil_kernel(LaunchArgs la) {
   // element-column role
   const bool is_elem = tid < NELEMC;
   const int ecx = tid % EXC, ecy = tid / EXC;
-  const uint32_t eoff = ((uint32_t)wrapi(y0 - 1 + ecy, n) * n + (uint32_t)wrapi(x0 - 1 + ecx, n)) * SC;
   // output role (also the owner of the node in the PCG update)
   const int ox = tid % TX, oy = tid / TX;
   const bool is_out = tid < NINT && x0 + ox < n && y0 + oy < n;
   const uint32_t ooff = ((uint32_t)(y0 + oy) * n + (uint32_t)(x0 + ox)) * SS;
   // staging role: slot 0 of thread t < NINT is its own interior node; ring
   // nodes fill the remaining slot-0 threads and then slot 1 of the first ones
-  bool hval[2];
+  // The element moduli of a layer are staged with a node plane: element
+  // column (ecx, ecy) is the voxel whose lower corner is halo node (ecx, ecy),
+  // so the thread staging that node loads the voxel's E_e at the same offset
+  // (hel).  Keeping every global load in the staging batch means the element
+  // work never waits on the memory counter, which retires in issue order.
+  bool hval[2], hel[2];
   int hslot[2];
-  uint32_t hoS[2], hoL[2];
+  uint32_t hoS[2], hoL[2], hoC[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     int h;
@@ -131,6 +139,8 @@ void stencil_kernel(LaunchArgs la) {
     const uint32_t o = (uint32_t)wrapi(y0 - 1 + hy, n) * n + (uint32_t)wrapi(x0 - 1 + hx, n);
     hoS[k] = o * SS;
     hoL[k] = o * SL;
+    hoC[k] = o * SC;
+    hel[k] = hval[k] && hx < EXC && hy < EYC;
   }
 
   const SHH_CONST TC *kop;
@@ -176,18 +186,23 @@ void stencil_kernel(LaunchArgs la) {
   // parity of the step that staged them: z, D^-1 and p of the node
   TC own_z[2][3], own_p[2][3], own_d[2];
 
-  // ---- plane staging, split into issue (loads into registers) and finish
-  //      (combine, store owned values, store to LDS) so that the loads of a
-  //      plane are in flight during the previous plane's element work.
+  // ---- plane staging, split into issue (loads into registers), finish
+  //      (combine, store to LDS) and commit (store owned values) so that the
+  //      loads of a plane are in flight during the previous plane's element
+  //      work.
   //      Node planes z0-1 .. z1 are touched, so a single wrap suffices.
   TL raw_a[2][3];
   TS raw_b[2][3], raw_c[2][3], raw_d[2], raw_x[3];
+  TC raw_e[2];
+  // node plane z, and the element layer z - 1 below it
   auto issue = [&](int z) {
     const uint32_t pz = (uint32_t)wrap1(z, n) * plane;
+    const uint32_t pe = (uint32_t)wrap1(z - 1, n) * plane;
     const bool ownz = z >= z0 && z < z1;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (!hval[k]) continue;
+      if (hel[k]) raw_e[k] = bload<TC>(rE, hoC[k], pe * SC);
       if constexpr (MODE == MODE_PCG) {
         raw_d[k] = bload<TS>(rD, hoS[k], pz * SS);
 #pragma unroll
@@ -209,6 +224,25 @@ void stencil_kernel(LaunchArgs la) {
       }
     }
   };
+  // the owned node's new r, p, x, written by commit() after the next plane's
+  // loads are issued (so that waiting for those loads never waits for these
+  // stores: the memory counter retires in issue order)
+  TS out_r[3], out_p[3], out_x[3];
+  auto commit = [&](int z) {
+    if constexpr (MODE == MODE_PCG) {
+      const uint32_t pz = (uint32_t)wrap1(z, n) * plane;
+      const bool ownz = z >= z0 && z < z1;
+      if (is_out && ownz) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const uint32_t so = pz * SS + cS[c];
+          bstore<TS>(out_r[c], rR, hoS[0], so);
+          bstore<TS>(out_p[c], rP, hoS[0], so);
+          bstore<TS>(out_x[c], rX, hoS[0], so);
+        }
+      }
+    }
+  };
   auto finish = [&](int z, auto bc) {
     constexpr int b = decltype(bc)::value;
     const uint32_t pz = (uint32_t)wrap1(z, n) * plane;
@@ -216,6 +250,7 @@ void stencil_kernel(LaunchArgs la) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (!hval[k]) continue;
+      if (hel[k]) mbuf[b][hslot[k]] = raw_e[k];
       if constexpr (MODE == MODE_PCG) {
         const TC dk = (TC)raw_d[k];
         TC rn[3], zn[3], pn[3];
@@ -229,10 +264,9 @@ void stencil_kernel(LaunchArgs la) {
         if (k == 0 && is_out && ownz) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const uint32_t so = pz * SS + cS[c];
-            bstore<TS>((TS)rn[c], rR, hoS[0], so);
-            bstore<TS>((TS)pn[c], rP, hoS[0], so);
-            bstore<TS>((TS)((TC)raw_x[c] + alpha * (TC)raw_c[0][c]), rX, hoS[0], so);
+            out_r[c] = (TS)rn[c];
+            out_p[c] = (TS)pn[c];
+            out_x[c] = (TS)((TC)raw_x[c] + alpha * (TC)raw_c[0][c]);
             const double r64 = (double)rn[c];
             acc[0] += r64 * (double)zn[c];
             acc[1] += r64 * r64;
@@ -265,19 +299,20 @@ void stencil_kernel(LaunchArgs la) {
   using B0 = std::integral_constant<int, 0>;
   using B1 = std::integral_constant<int, 1>;
 
-  // Values carried from one element layer to the next are double-buffered by
-  // layer parity (index b of the step that reads them) so that the two-step
-  // unrolled loop needs no register copies: the x-y Hadamard coefficients of
-  // the lower node plane (A), the upper-plane half of the layer below (Bc)
-  // and the element modulus (ev).
-  TC A[2][3][4], Bc[2][3][4];
-  TC ev[2];
+  // Values carried from one element layer to the next: the x-y Hadamard
+  // coefficients of the lower node plane (A) and the upper-plane half of the
+  // layer below (Bc).  With SHH_CARRY_DB (FP32 only) they
+  // are double-buffered by layer parity (index b of the step that reads them),
+  // which spares the register copies of the two-step unrolled loop at the
+  // cost of 24 more registers.
+  constexpr int NB = (SHH_CARRY_DB && sizeof(TC) == 4) ? 2 : 1;
+  TC A[NB][3][4], Bc[NB][3][4];
 
   // prologue: planes z0-1 and z0 staged, plane z0+1 in flight
   issue(z0 - 1);
   finish(z0 - 1, B0{});
   issue(z0);
-  ev[0] = is_elem ? bload<TC>(rE, eoff, (uint32_t)wrap1(z0 - 1, n) * plane * SC) : TC(0);
+  commit(z0 - 1);
   __syncthreads();
   if (is_elem) {
     xy_hadamard(B0{}, A[0]);
@@ -289,6 +324,7 @@ void stencil_kernel(LaunchArgs la) {
   finish(z0, B1{});
   const int S = z1 - z0 + 1;  // element layers z0-1 .. z1-1
   if (S > 1) issue(z0 + 1);
+  commit(z0);
   __syncthreads();
 
   // one element layer: kk = z0 - 1 + sl lies between node planes kk and kk+1;
@@ -298,8 +334,6 @@ void stencil_kernel(LaunchArgs la) {
     constexpr int bn = b ^ 1;
     using BN = std::integral_constant<int, bn>;
     const int kk = z0 - 1 + sl;
-    const TC e = ev[b];
-    if (is_elem && sl + 1 < S) ev[bn] = bload<TC>(rE, eoff, (uint32_t)wrap1(kk + 1, n) * plane * SC);
     // the owned values of output plane kk (staged two steps ago, same parity)
     // before this step's staging replaces them
     TC oz[3], op[3], od = TC(0);
@@ -312,9 +346,12 @@ void stencil_kernel(LaunchArgs la) {
       od = own_d[b];
     }
     if (is_elem) {
-      const TC (&Ac)[3][4] = A[b];
-      TC (&An)[3][4] = A[bn];
+      constexpr int ib = NB == 2 ? b : 0, ibn = NB == 2 ? bn : 0;
+      const TC (&Ac)[3][4] = A[ib];
+      TC An[3][4];
       xy_hadamard(BN{}, An);
+      // layer kk's modulus was staged with node plane kk+1
+      const TC e = mbuf[bn][ecy * HX + ecx];
       TC h[3][8], y[3][8];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -329,7 +366,7 @@ void stencil_kernel(LaunchArgs la) {
       if (sl > 0) {
         // lower node plane kk: this layer's lower half completes the upper
         // half carried from the layer below; store its four x-y corners
-        const TC (&Bacc)[3][4] = Bc[b];
+        const TC (&Bacc)[3][4] = Bc[ib];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const TC L0 = Bacc[c][0] - y[c][4];  // y[c][0] == 0
@@ -343,17 +380,20 @@ void stencil_kernel(LaunchArgs la) {
           ebuf[b][c * 4 + 3][tid] = u1 + v1;
         }
       }
-      TC (&Bnew)[3][4] = Bc[bn];
+      TC (&Bnew)[3][4] = Bc[ibn];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         Bnew[c][0] = y[c][4];
 #pragma unroll
         for (int m = 1; m < 4; ++m) Bnew[c][m] = y[c][m] + y[c][m + 4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) A[ibn][c][m] = An[c][m];
       }
     }
     // stage node plane kk+2 (its loads were issued a step ago), issue kk+3
     if (sl + 1 < S) finish(z0 + sl + 1, bc);
     if (sl + 2 < S) issue(z0 + sl + 2);
+    if (sl + 1 < S) commit(z0 + sl + 1);
     __syncthreads();
     if (sl > 0 && is_out) {
       // node (x0+ox, y0+oy, kk) is corner (ax, ay) of element column
