@@ -24,6 +24,33 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the CG pass kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE; one 128^3 design, all six load cases active), each scaled by
+# what the counter reads for a 1 GiB device copy (FETCH x2.0, WRITE x1.0), per
+# (node, active load case); see profiles/stencil_pcg_128_hbm_traffic.md.  It
+# holds only for the kernel sources it was measured on (digest below): after
+# any change to them the bench reports null until the counters are taken again.
+PCG_TRAFFIC = {
+    "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
+    "sha256": "a533fbb52eb8a7d7f6ae2c95af794fcc965db1b00cbf8968c11f1185b9d39a7d",
+    "fetch_bytes_per_node_case": 90.90,
+    "write_bytes_per_node_case": 48.01,
+}
+
+
+def pcg_traffic_per_node_case():
+    """Measured HBM bytes per (node, active load case) of the CG pass, or None
+    when the kernel sources differ from the ones the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_04025_amd", "csrc")
+    for f in PCG_TRAFFIC["sources"]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != PCG_TRAFFIC["sha256"]:
+        return None
+    return PCG_TRAFFIC["fetch_bytes_per_node_case"] + PCG_TRAFFIC["write_bytes_per_node_case"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -274,9 +301,14 @@ def main():
     n_launch = launches.value
     t_stencil = ms_total.value / 1e3
     achieved = nbytes / t_stencil / 1e9 if t_stencil > 0 else 0.0
+    # measured HBM bytes per launch: per-(node, load case) counter figure times
+    # the (node, load case) pairs an average launch of this run processed
+    node_cases = sum(int(r["iters"].sum()) for r in all_res) * args.n ** 3
+    per_nc = pcg_traffic_per_node_case()
+    traffic = int(per_nc * node_cases / max(n_launch, 1)) if per_nc is not None else None
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
         "kernel": "stencil_kernel<float,float,PCG>", "launches": n_launch,
         "avg_launch_ms": round(ms_total.value / max(n_launch, 1), 4),
         "algorithmic_bytes_per_launch": int(nbytes / max(n_launch, 1)),
