@@ -185,10 +185,10 @@ int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts 
                        const double *dL_dV, double *dL_dpos, double *dL_dq, void *hip_stream);
 
 /* ---- instrumentation ------------------------------------------------------
-   When enabled, every launch of the CG stencil kernel (q = K p fused with the
-   direction update, the dominant kernel) is bracketed by two HIP events on the
-   stream it runs on; elapsed times are accumulated process-wide when the
-   solver next synchronizes.  shh_profile_read returns the number of timed
+   When enabled, every launch of the CG pass kernel (one whole PCG iteration:
+   q = K p fused with the vector updates, the dominant kernel) is bracketed by
+   two HIP events on the stream it runs on; elapsed times are accumulated
+   process-wide when the solver next synchronizes.  shh_profile_read returns the number of timed
    launches and their total milliseconds; shh_profile_enable(1) also resets. */
 int32_t shh_profile_enable(int32_t on);
 int32_t shh_profile_read(int64_t *launches, double *ms_total);
