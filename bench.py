@@ -32,10 +32,14 @@ HBM_PEAK_GBS = 8000.0
 # any change to them the bench reports null until the counters are taken again.
 PCG_TRAFFIC = {
     "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
-    "sha256": "a533fbb52eb8a7d7f6ae2c95af794fcc965db1b00cbf8968c11f1185b9d39a7d",
-    "fetch_bytes_per_node_case": 90.90,
+    "sha256": "1d15ae20bf2b468895d27a852011272dcd24f7167ca376926a0c4abae67d57d4",
+    "fetch_bytes_per_node_case": 91.37,
     "write_bytes_per_node_case": 48.01,
 }
+# What a plain 1 GiB device-to-device copy sustains on this GPU (read + write,
+# kernel trace of `bench.py --copy-only`): the achievable ceiling of a stream
+# that reads and writes, reported beside the 8 TB/s peak.
+COPY_CEILING_GBS = 5020.0
 
 
 def pcg_traffic_per_node_case():
@@ -59,8 +63,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--designs", type=int, default=8)
-    ap.add_argument("--rtol", type=float, default=1e-6)
-    ap.add_argument("--fp64-designs", type=int, default=2, help="designs also run on the FP64 GPU path")
+    # CG tolerance of the served path: ||f - K u|| / ||f|| <= 3e-6 keeps every C^H entry of
+    # the headline designs within 1e-4 of the FP64 path with a ~5x margin (measured: 1.9e-5;
+    # 1e-5 gives 6.2e-5, 1e-4 gives 1.7e-4).  The run checks it on the FP64 subset below.
+    ap.add_argument("--rtol", type=float, default=3e-6)
+    ap.add_argument("--fp64-designs", type=int, default=8, help="designs also run on the FP64 GPU path")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--iters-per-step", type=int, default=16)
@@ -309,6 +316,8 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+        "measured_gbs": round(traffic / (ms_total.value / max(n_launch, 1)) / 1e6, 1) if traffic else None,
+        "copy_ceiling_gbs": COPY_CEILING_GBS,
         "kernel": "stencil_kernel<float,float,PCG>", "launches": n_launch,
         "avg_launch_ms": round(ms_total.value / max(n_launch, 1), 4),
         "algorithmic_bytes_per_launch": int(nbytes / max(n_launch, 1)),
@@ -323,13 +332,16 @@ def main():
         r64 = api.homogenize_batch(sub, precision="fp64", rtol=1e-10)
         torch.cuda.synchronize()
         w64 = time.perf_counter() - t1
-        errs = []
+        errs, small = [], []
         for k, r in enumerate(r64):
             C, Cm = r["C"], all_res[k]["C"]
             s = np.abs(C).max()
             big = np.abs(C) >= 1e-3 * s
             errs.append(float(np.max(np.abs(Cm - C)[big] / np.abs(C)[big])))
+            # entries below 1e-3 max|C|: absolute error relative to max|C| (bar 1e-7)
+            small.append(float(np.max(np.abs(Cm - C)[~big], initial=0.0) / s))
         fp64 = {"fp64_designs_per_s": round(len(sub) / w64, 4), "ch_max_rel_err_vs_fp64": max(errs),
+                "ch_small_entry_err_vs_fp64": max(small),
                 "fp64_iters_mean": float(np.mean([r["iters"].max() for r in r64]))}
 
     iters = [int(r["iters"].max()) for r in all_res]

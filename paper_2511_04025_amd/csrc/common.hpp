@@ -13,6 +13,7 @@
 namespace shh {
 
 constexpr int NRHS = 6;       // Voigt unit-strain load cases (Eq. (8))
+constexpr int KOP_N = 10;     // constants of the factored element operator
 constexpr int MAXK = 6;       // largest truncation order supported
 constexpr int MAXB = 2 * MAXK + 1;  // 1D basis functions per axis: 1, cos, sin up to K
 
@@ -89,10 +90,12 @@ struct SlotDev {
   int max_iter;
   int pad_;
   // element operator in the per-axis Walsh-Hadamard basis, already scaled by
-  // 1/64: 24 diagonal entries [component][mode] then the couplings
-  // 4 lambda Mhat[s|d] / 64 and 4 mu Mhat[s|d] / 64
-  double kop64[28];
-  float kop32[28];
+  // 1/64: the diagonal entry of component c at mode m depends only on s_c and
+  // on the number of difference modes among the two other axes (6 classes,
+  // index 3 s_c + s_o1 + s_o2), then the couplings 4 lambda Mhat[s|d] / 64
+  // and 4 mu Mhat[s|d] / 64
+  double kop64[KOP_N];
+  float kop32[KOP_N];
   // buffers
   double *charges;      // [N][4]: x, y, z, q
   double *alpha;        // [(K+1)^3]

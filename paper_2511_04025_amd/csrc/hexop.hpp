@@ -11,6 +11,8 @@
 // pair of components (i, j), four couplings per mode of the third axis: 45
 // nonzeros instead of 576.  With Hhat the 8x8 (unnormalized) transform per
 // component, K_0 = Hhat^T Khat Hhat / 64; the 1/64 is folded into the constants.
+// By the symmetry of the cube under axis permutations the 21 nonzero diagonal
+// entries take 5 distinct values, so the operator needs 10 constants.
 //
 // Mode index m = s_x | s_y << 1 | s_z << 2 with s = 0 (sum) or 1 (difference).
 #pragma once
@@ -29,14 +31,18 @@ __device__ __forceinline__ void hex_apply(KP kop, const T (&h)[3][8], T (&y)[3][
   for (int c = 0; c < 3; ++c) {
     y[c][0] = T(0);
 #pragma unroll
-    for (int m = 1; m < 8; ++m) y[c][m] = kop[c * 8 + m] * h[c][m];
+    for (int m = 1; m < 8; ++m) {
+      const int sc = (m >> c) & 1;
+      const int so = ((m >> ((c + 1) % 3)) & 1) + ((m >> ((c + 2) % 3)) & 1);
+      y[c][m] = kop[sc * 3 + so] * h[c][m];
+    }
   }
   // couplings of components (i, j) with third axis k:
   //   y_i(i=d, j=s) += 4 lam M_k h_j(i=s, j=d)   y_i(i=s, j=d) += 4 mu M_k h_j(i=d, j=s)
   //   y_j(i=s, j=d) += 4 lam M_k h_i(i=d, j=s)   y_j(i=d, j=s) += 4 mu M_k h_i(i=s, j=d)
 #define SHH_COUPLE(I, J, KK)                                                   \
   _Pragma("unroll") for (int mk = 0; mk < 2; ++mk) {                           \
-    const T cl = kop[24 + mk], cm = kop[26 + mk];                              \
+    const T cl = kop[6 + mk], cm = kop[8 + mk];                                \
     const int a = (1 << (I)) | (mk << (KK));                                   \
     const int b = (1 << (J)) | (mk << (KK));                                   \
     y[I][a] += cl * h[J][b];                                                   \

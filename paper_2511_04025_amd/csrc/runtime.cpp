@@ -148,21 +148,20 @@ void copy_design(const shh_design *src, DesignCopy &dst) {
   dst.d.q = dst.q.data();
 }
 
-static void element_operator(double nu, double kop[28]) {
+static void element_operator(double nu, double kop[KOP_N]) {
   const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
   const double mu = 1.0 / (2.0 * (1.0 + nu));
   const double Mh[2] = {1.0, 1.0 / 3.0}, Sh[2] = {0.0, 4.0};
-  for (int c = 0; c < 3; ++c) {
-    const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
-    for (int m = 0; m < 8; ++m) {
-      const int sc = (m >> c) & 1, s1 = (m >> o1) & 1, s2 = (m >> o2) & 1;
-      kop[c * 8 + m] = ((lam + 2.0 * mu) * Sh[sc] * Mh[s1] * Mh[s2] +
-                        mu * Mh[sc] * (Sh[s1] * Mh[s2] + Mh[s1] * Sh[s2])) / 64.0;
+  // diagonal entry of component c at mode m depends on s_c and s_o1 + s_o2 only
+  for (int sc = 0; sc < 2; ++sc)
+    for (int so = 0; so < 3; ++so) {
+      const int s1 = so > 0 ? 1 : 0, s2 = so > 1 ? 1 : 0;
+      kop[sc * 3 + so] = ((lam + 2.0 * mu) * Sh[sc] * Mh[s1] * Mh[s2] +
+                          mu * Mh[sc] * (Sh[s1] * Mh[s2] + Mh[s1] * Sh[s2])) / 64.0;
     }
-  }
   for (int mk = 0; mk < 2; ++mk) {
-    kop[24 + mk] = 4.0 * lam * Mh[mk] / 64.0;
-    kop[26 + mk] = 4.0 * mu * Mh[mk] / 64.0;
+    kop[6 + mk] = 4.0 * lam * Mh[mk] / 64.0;
+    kop[8 + mk] = 4.0 * mu * Mh[mk] / 64.0;
   }
 }
 
@@ -201,7 +200,7 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.max_iter = s.opts.max_iter;
   h.ffloor = 1e-12 * d.E * std::sqrt(3.0 * double(h.nn));
   element_operator(d.nu, h.kop64);
-  for (int i = 0; i < 28; ++i) h.kop32[i] = (float)h.kop64[i];
+  for (int i = 0; i < KOP_N; ++i) h.kop32[i] = (float)h.kop64[i];
   h.charges = (double *)(base + L.charges);
   h.alpha = d.alpha ? (double *)(base + L.alpha) : nullptr;
   h.coef = (double *)(base + L.coef);

@@ -146,18 +146,22 @@ void stencil_kernel(LaunchArgs la) {
   const SHH_CONST TC *kop;
   if constexpr (sizeof(TC) == 8) kop = (const SHH_CONST TC *)s->kop64;
   else kop = (const SHH_CONST TC *)s->kop32;
-  rsrc_t rE;
-  if constexpr (sizeof(TC) == 8) rE = make_rsrc(s->E64, (uint64_t)nn * SC);
-  else rE = make_rsrc(s->E32, (uint64_t)nn * SC);
+  // one resource for the moduli and, in the CG pass, D^-1 behind them (the two
+  // arrays are adjacent in the slot, D^-1 at byte offset dOff)
+  const char *Ebase;
+  if constexpr (sizeof(TC) == 8) Ebase = (const char *)s->E64;
+  else Ebase = (const char *)s->E32;
+  const uint32_t dOff = MODE == MODE_PCG ? (uint32_t)((const char *)s->Dinv - Ebase) : 0u;
+  const rsrc_t rE = make_rsrc(Ebase, MODE == MODE_PCG ? (uint64_t)dOff + (uint64_t)nn * SS : (uint64_t)nn * SC);
 
   // component c of a load case's vector starts c * n^3 elements in
   const uint32_t cS[3] = {0u, (uint32_t)nn * SS, 2u * (uint32_t)nn * SS};
   const uint32_t cL[3] = {0u, (uint32_t)nn * SL, 2u * (uint32_t)nn * SL};
   const long long vbase = (long long)rhs * 3 * nn;
   const uint64_t vbytesS = 3ull * nn * SS, vbytesL = 3ull * nn * SL;
-  // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX, rD
+  // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX
   // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q.
-  rsrc_t rA, rB, rC, rR, rQ, rP, rX, rD;
+  rsrc_t rA, rB, rC, rR, rQ, rP, rX;
   TC alpha = TC(0), beta = TC(0);
   if constexpr (MODE == MODE_PCG) {
     const int pc = st->pcur[rhs];
@@ -168,7 +172,6 @@ void stencil_kernel(LaunchArgs la) {
     rQ = make_rsrc((const TS *)s->q[pc ^ 1] + vbase, vbytesS);
     rP = make_rsrc((const TS *)s->p[pc ^ 1] + vbase, vbytesS);
     rX = make_rsrc((const TS *)s->x + vbase, vbytesS);
-    rD = make_rsrc(s->Dinv, (uint64_t)nn * SS);
     alpha = (TC)st->alpha[rhs];
     beta = (TC)st->beta[rhs];
   } else if constexpr (MODE == MODE_RESID) {
@@ -204,7 +207,7 @@ void stencil_kernel(LaunchArgs la) {
       if (!hval[k]) continue;
       if (hel[k]) raw_e[k] = bload<TC>(rE, hoC[k], pe * SC);
       if constexpr (MODE == MODE_PCG) {
-        raw_d[k] = bload<TS>(rD, hoS[k], pz * SS);
+        raw_d[k] = bload<TS>(rE, hoS[k], dOff + pz * SS);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           raw_a[k][c] = bload<TS>(rA, hoS[k], pz * SS + cS[c]);
