@@ -210,7 +210,7 @@ static shh_design stiffness_design(int32_t n, double nu) {
 }
 
 int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *bytes) {
-  if (n < 2 || n > 1024 || !bytes) return SHH_INVALID_ARG;
+  if (n < 2 || n > 512 || !bytes) return SHH_INVALID_ARG;
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   o.save_for_backward = 0;

@@ -83,13 +83,16 @@ def test_field_sampled_at_128():
 
 
 def test_mixed_vs_fp64_at_128_served():
+    # the headline configuration: config-2 designs at 128^3 batched in the
+    # engine at the served CG tolerance 3e-6, every C^H entry against the FP64
+    # GPU path (tolerance 1e-10) to the 1e-4 bar
     from paper_2511_04025_amd import api, serving
-    designs = wl.config2_designs(n=128, count=2)
-    eng = serving.Engine(4 << 30, max_slots=2, precision="mixed", rtol=1e-6)
+    designs = wl.config2_designs(n=128, count=4)
+    eng = serving.Engine(8 << 30, max_slots=4, precision="mixed", rtol=3e-6)
     for i, d in enumerate(designs):
         eng.submit(d, i)
     res = {}
-    while len(res) < 2:
+    while len(res) < len(designs):
         eng.step(16)
         for rid, r in eng.poll():
             res[rid] = r
@@ -100,7 +103,7 @@ def test_mixed_vs_fp64_at_128_served():
         assert res[i]["V"] == ref[i]["V"]
         assert_ch_close(res[i]["C"], ref[i]["C"], 1e-4)
         _check_properties(res[i]["C"], res[i]["V"], d.E, d.E_void)
-        assert np.all(res[i]["rel_res"] <= 1e-6)
+        assert np.all(res[i]["rel_res"] <= 3e-6)
 
 
 def test_config3_at_256_mixed():
