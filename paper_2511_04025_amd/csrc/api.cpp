@@ -280,7 +280,7 @@ int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, dou
   g.first = 0;
   g.nrhs = nrhs;
   for (int r = 0; r < nrhs; ++r) g.rhs[r] = r;
-  g.nblocks = s.host.ntiles * nrhs;
+  g.nblocks = s.host.ntiles[precision == SHH_PREC_MIXED ? 1 : 0] * nrhs;
   SHH_HIP(hipMemcpyAsync(seg_mem, &g, sizeof(g), hipMemcpyHostToDevice, st));
   LaunchArgs la{(const Segment *)seg_mem, 1, g.nblocks};
   SHH_HIP(launch_stencil_apply(la, precision, st));
@@ -308,7 +308,7 @@ int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, v
   g.slot = s.d_slot;
   g.nrhs = NRHS;
   for (int r = 0; r < NRHS; ++r) g.rhs[r] = r;
-  g.nblocks = s.host.ntiles * NRHS;
+  g.nblocks = s.host.ntiles[0] * NRHS;  // FP64 residual kernel
   g.flag = RES_INIT;
   SHH_HIP(hipMemcpyAsync(seg_mem, &g, sizeof(g), hipMemcpyHostToDevice, st));
   LaunchArgs la{(const Segment *)seg_mem, 1, g.nblocks};

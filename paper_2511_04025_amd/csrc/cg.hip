@@ -82,7 +82,7 @@ __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int 
     // after CG pass j: the pass's sums r.z, r.r, p.q, q.z, q.D^-1 q
     if (!st->active[rhs]) return;
     double tot[5];
-    sum_partials<5, PSTRIDE>(parts, s->ntiles, tot, red, VEC_THREADS);
+    sum_partials<5, PSTRIDE>(parts, s->ntiles[s->prec], tot, red, VEC_THREADS);
     if (threadIdx.x != 0) return;
     const double rho = tot[0], rr = tot[1], sigma = tot[2], tau = tot[3], mu = tot[4];
     st->iters[rhs] += 1;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int 
     if (mode == RES_RECOMPUTE && !st->active[rhs]) return;
     if (mode == RES_FINAL && !(st->ff[rhs] > s->ffloor * s->ffloor)) return;
     double tot[3];
-    sum_partials<3, PSTRIDE>(parts, s->ntiles, tot, red, VEC_THREADS);
+    sum_partials<3, PSTRIDE>(parts, s->ntiles[0], tot, red, VEC_THREADS);  // FP64 residual tiles
     if (threadIdx.x == 0) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) st->mean[rhs][c] = tot[c] / double(s->nn);

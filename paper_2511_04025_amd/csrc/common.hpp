@@ -17,25 +17,47 @@ constexpr int KOP_N = 10;     // constants of the factored element operator
 constexpr int MAXK = 6;       // largest truncation order supported
 constexpr int MAXB = 2 * MAXK + 1;  // 1D basis functions per axis: 1, cos, sin up to K
 
-// ---- stencil tiling: output tile TX x TY nodes, z-marching over TZ planes ----
-#ifndef SHH_TILE_X
-#define SHH_TILE_X 32
+// ---- stencil tiling ----
+// A stencil workgroup owns an X x Y tile of nodes in the x-y plane and marches
+// up tz planes in z.  Kernels that compute in FP32 use a wide 64 x 6 tile: its
+// halo ring has 12 side-column nodes per 384 outputs (each of those pulls a
+// whole 128-byte line), 8 waves per workgroup, 2 workgroups per CU.  Kernels
+// that compute in FP64 hold twice the bytes in LDS per node and use 32 x 8.
+#ifndef SHH_F32_TILE_X
+#define SHH_F32_TILE_X 64
 #endif
-#ifndef SHH_TILE_Y
-#define SHH_TILE_Y 8
+#ifndef SHH_F32_TILE_Y
+#define SHH_F32_TILE_Y 6
 #endif
-constexpr int TX = SHH_TILE_X;
-constexpr int TY = SHH_TILE_Y;
-constexpr int HX = TX + 2;          // node halo tile width
-constexpr int HY = TY + 2;
-constexpr int EXC = TX + 1;         // element columns needed by the tile
-constexpr int EYC = TY + 1;
-constexpr int NHALO = HX * HY;      // 340 for 32 x 8
-constexpr int NELEMC = EXC * EYC;   // 297 for 32 x 8
-// one thread per element column, rounded up to whole waves (320 for 32 x 8)
-constexpr int STENCIL_THREADS = ((NELEMC + 63) / 64) * 64;
-static_assert(2 * STENCIL_THREADS >= NHALO, "each thread stages at most two halo nodes");
-static_assert(TX * TY <= STENCIL_THREADS, "one output node per thread");
+#ifndef SHH_F64_TILE_X
+#define SHH_F64_TILE_X 32
+#endif
+#ifndef SHH_F64_TILE_Y
+#define SHH_F64_TILE_Y 8
+#endif
+
+template <typename TC> struct TileDims;
+template <> struct TileDims<float> { static constexpr int X = SHH_F32_TILE_X, Y = SHH_F32_TILE_Y; };
+template <> struct TileDims<double> { static constexpr int X = SHH_F64_TILE_X, Y = SHH_F64_TILE_Y; };
+
+// Index of a compute precision's tiling in the per-slot tile counts.
+template <typename TC> constexpr int tiling_of() { return sizeof(TC) == 4 ? 1 : 0; }
+
+template <typename TC>
+struct Tile {
+  static constexpr int X = TileDims<TC>::X, Y = TileDims<TC>::Y;
+  static constexpr int HX = X + 2, HY = Y + 2;        // node halo tile
+  static constexpr int EXC = X + 1, EYC = Y + 1;      // element columns needed by the tile
+  static constexpr int NHALO = HX * HY;
+  static constexpr int NELEMC = EXC * EYC;
+  // one thread per element column, rounded up to whole waves
+  static constexpr int THREADS = ((NELEMC + 63) / 64) * 64;
+  static constexpr int NINT = X * Y;                  // interior (owned) nodes
+  static constexpr int NRING = NHALO - NINT;          // halo ring: 2 (X + 2) + 2 Y nodes
+  static_assert(2 * THREADS >= NHALO, "each thread stages at most two halo nodes");
+  static_assert(NINT <= THREADS, "one output node per thread");
+  static_assert(THREADS <= 1024, "one workgroup");
+};
 
 // ---- vector-update chunking ----
 constexpr int CHUNK = 1024;         // nodes per workgroup in the update kernels (4 per thread)
@@ -77,7 +99,8 @@ struct SlotDev {
   int n;
   int prec;             // 0 FP64, 1 mixed
   long long nn;         // n^3
-  int tiles_x, tiles_y, tiles_z, ntiles, tz;
+  int tiles_x[2], tiles_y[2], ntiles[2];  // by tiling: [0] FP64-compute, [1] FP32-compute kernels
+  int tiles_z, tz;
   int nchunks;
   int K, nb, N;
   int dist_mode;

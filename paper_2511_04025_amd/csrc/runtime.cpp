@@ -103,7 +103,10 @@ Layout make_layout(int n, int N, int K, int prec, bool save) {
   Layout L{};
   const long long nn = (long long)n * n * n;
   const int nb = 2 * K + 1;
-  const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY) * ((n + tz_for(n) - 1) / tz_for(n));
+  const int tz_runs = (n + tz_for(n) - 1) / tz_for(n);
+  const int tiles = std::max(((n + Tile<float>::X - 1) / Tile<float>::X) * ((n + Tile<float>::Y - 1) / Tile<float>::Y),
+                             ((n + Tile<double>::X - 1) / Tile<double>::X) * ((n + Tile<double>::Y - 1) / Tile<double>::Y)) *
+                    tz_runs;
   const int chunks = int((nn + CHUNK - 1) / CHUNK);
   L.maxparts = std::max(std::max(tiles, chunks), 1024);
   const size_t ts = prec == SHH_PREC_FP64 ? 8 : 4;
@@ -177,10 +180,12 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.prec = prec;
   h.nn = (long long)n * n * n;
   h.tz = tz_for(n);
-  h.tiles_x = (n + TX - 1) / TX;
-  h.tiles_y = (n + TY - 1) / TY;
   h.tiles_z = (n + h.tz - 1) / h.tz;
-  h.ntiles = h.tiles_x * h.tiles_y * h.tiles_z;
+  h.tiles_x[0] = (n + Tile<double>::X - 1) / Tile<double>::X;
+  h.tiles_y[0] = (n + Tile<double>::Y - 1) / Tile<double>::Y;
+  h.tiles_x[1] = (n + Tile<float>::X - 1) / Tile<float>::X;
+  h.tiles_y[1] = (n + Tile<float>::Y - 1) / Tile<float>::Y;
+  for (int w = 0; w < 2; ++w) h.ntiles[w] = h.tiles_x[w] * h.tiles_y[w] * h.tiles_z;
   h.nchunks = int((h.nn + CHUNK - 1) / CHUNK);
   h.K = d.K;
   h.nb = 2 * d.K + 1;
@@ -299,7 +304,9 @@ int Solver::build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_r
     g.flag = flag;
     const bool per_tile = (k == K_STENCIL || k == K_RESID);
     const bool scalar = (k == K_SCAL_IT || k == K_SCAL_RES);
-    const int units = scalar ? 1 : (per_tile ? s->host.ntiles : s->host.nchunks);
+    // the CG pass computes in the vector precision, the residual always in FP64
+    const int tiling = k == K_STENCIL ? s->host.prec : 0;
+    const int units = scalar ? 1 : (per_tile ? s->host.ntiles[tiling] : s->host.nchunks);
     if (k == K_FOLD || k == K_ZERO) {
       g.nrhs = 1;
       g.rhs[0] = 0;

@@ -1,8 +1,9 @@
 // Matrix-free periodic stiffness operator q = K p, K = sum_e E_e P_e^T K_0 P_e
 // (Sec. 4.1, Eq. (7)-(8)), for one load case per workgroup.
 //
-// A workgroup owns a TX x TY tile of nodes in the x-y plane and marches up a
-// run of tz planes in z.  Per element layer it
+// A workgroup owns a TX x TY tile of nodes in the x-y plane (64 x 6 for FP32
+// compute, 32 x 8 for FP64) and marches up a run of tz planes in z.  Per
+// element layer it
 //   1. stages the next node plane (tile + one-node periodic halo) in LDS,
 //   2. forms, for each of the (TX+1)(TY+1) element columns, the Hadamard
 //      coefficients of the element's 24 nodal values (x-y from the 2x2 node
@@ -58,11 +59,9 @@ enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2 };
 #define SHH_CARRY_DB 0
 #endif
 
-constexpr int NINT = TX * TY;        // interior (owned) nodes of a tile
-constexpr int NRING = NHALO - NINT;  // halo ring: 2 (TX + 2) + 2 TY nodes
-
 // Halo-tile index of ring node j: the bottom row, the top row, then the left
 // and right columns between them.
+template <int HX, int HY>
 __device__ __forceinline__ int ring_h(int j) {
   if (j < HX) return j;
   if (j < 2 * HX) return (HY - 1) * HX + (j - HX);
@@ -71,8 +70,14 @@ __device__ __forceinline__ int ring_h(int j) {
 }
 
 template <typename TC, typename TS, int MODE>
-__global__ __launch_bounds__(STENCIL_THREADS) __attribute__((amdgpu_waves_per_eu(SHH_STENCIL_WAVES_PER_EU)))
+__global__ __launch_bounds__(Tile<TC>::THREADS) __attribute__((amdgpu_waves_per_eu(SHH_STENCIL_WAVES_PER_EU)))
 void stencil_kernel(LaunchArgs la) {
+  // tile geometry of this compute precision
+  using TT = Tile<TC>;
+  constexpr int TX = TT::X, TY = TT::Y, HX = TT::HX, HY = TT::HY, EXC = TT::EXC, EYC = TT::EYC;
+  constexpr int NHALO = TT::NHALO, NELEMC = TT::NELEMC, STENCIL_THREADS = TT::THREADS;
+  constexpr int NINT = TT::NINT, NRING = TT::NRING;
+  constexpr int TW = tiling_of<TC>();
   __shared__ TC nbuf[2][3][NHALO];
   __shared__ TC ebuf[2][12][NELEMC];
   __shared__ TC mbuf[2][NHALO];  // element moduli, by the halo slot of the element's lower corner
@@ -96,9 +101,9 @@ void stencil_kernel(LaunchArgs la) {
   const uint32_t plane = (uint32_t)n * (uint32_t)n;
   const long long nn = s->nn;
   const int tile = w.tile;
-  const int tix = tile % s->tiles_x;
-  const int tiy = (tile / s->tiles_x) % s->tiles_y;
-  const int tiz = tile / (s->tiles_x * s->tiles_y);
+  const int tix = tile % s->tiles_x[TW];
+  const int tiy = (tile / s->tiles_x[TW]) % s->tiles_y[TW];
+  const int tiz = tile / (s->tiles_x[TW] * s->tiles_y[TW]);
   const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * s->tz;
   const int z1 = min(z0 + s->tz, n);
   const int tid = threadIdx.x;
@@ -132,7 +137,7 @@ void stencil_kernel(LaunchArgs la) {
     } else {
       const int j = k == 0 ? tid - NINT : tid + STENCIL_THREADS - NINT;
       hval[k] = j < NRING;
-      h = hval[k] ? ring_h(j) : 0;
+      h = hval[k] ? ring_h<HX, HY>(j) : 0;
     }
     hslot[k] = h;
     const int hx = h % HX, hy = h / HX;
@@ -461,24 +466,24 @@ static int padded_grid(int total) { return ((total + 7) / 8) * 8; }
 hipError_t launch_stencil_pcg(const LaunchArgs &la, int prec, hipStream_t st) {
   if (la.total == 0) return hipSuccess;
   const int g = padded_grid(la.total);
-  if (prec == 0) stencil_kernel<double, double, MODE_PCG><<<g, STENCIL_THREADS, 0, st>>>(la);
-  else stencil_kernel<float, float, MODE_PCG><<<g, STENCIL_THREADS, 0, st>>>(la);
+  if (prec == 0) stencil_kernel<double, double, MODE_PCG><<<g, Tile<double>::THREADS, 0, st>>>(la);
+  else stencil_kernel<float, float, MODE_PCG><<<g, Tile<float>::THREADS, 0, st>>>(la);
   return hipGetLastError();
 }
 
 hipError_t launch_stencil_resid(const LaunchArgs &la, int prec, hipStream_t st) {
   if (la.total == 0) return hipSuccess;
   const int g = padded_grid(la.total);
-  if (prec == 0) stencil_kernel<double, double, MODE_RESID><<<g, STENCIL_THREADS, 0, st>>>(la);
-  else stencil_kernel<double, float, MODE_RESID><<<g, STENCIL_THREADS, 0, st>>>(la);
+  if (prec == 0) stencil_kernel<double, double, MODE_RESID><<<g, Tile<double>::THREADS, 0, st>>>(la);
+  else stencil_kernel<double, float, MODE_RESID><<<g, Tile<double>::THREADS, 0, st>>>(la);
   return hipGetLastError();
 }
 
 hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st) {
   if (la.total == 0) return hipSuccess;
   const int g = padded_grid(la.total);
-  if (prec == 0) stencil_kernel<double, double, MODE_APPLY><<<g, STENCIL_THREADS, 0, st>>>(la);
-  else stencil_kernel<float, float, MODE_APPLY><<<g, STENCIL_THREADS, 0, st>>>(la);
+  if (prec == 0) stencil_kernel<double, double, MODE_APPLY><<<g, Tile<double>::THREADS, 0, st>>>(la);
+  else stencil_kernel<float, float, MODE_APPLY><<<g, Tile<float>::THREADS, 0, st>>>(la);
   return hipGetLastError();
 }
 
