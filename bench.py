@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # any change to them the bench reports null until the counters are taken again.
 PCG_TRAFFIC = {
     "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
-    "sha256": "1d15ae20bf2b468895d27a852011272dcd24f7167ca376926a0c4abae67d57d4",
-    "fetch_bytes_per_node_case": 91.37,
+    "sha256": "47e4e70a604b3b52c5860bc7a1faa397bdca5fc6bb84b18fc079f3339e8f6a79",
+    "fetch_bytes_per_node_case": 68.04,
     "write_bytes_per_node_case": 48.01,
 }
 # What a plain 1 GiB device-to-device copy sustains on this GPU (read + write,
@@ -92,7 +92,7 @@ def serving_trace(args):
     import numpy as np
     import torch
     from paper_2511_04025_amd import serving, workloads as wl
-    designs = wl.config4_trace(count=args.trace_count)
+    designs = wl.serving_trace(count=args.trace_count)
     engine = serving.Engine(int(args.arena_gb * (1 << 30)), max_slots=256, precision="mixed", rtol=args.rtol)
     rate = args.rate
     if rate <= 0:
@@ -121,7 +121,7 @@ def serving_trace(args):
         "metric": "serving trace: homogenized designs/s and latency (Poisson arrivals)",
         "value": round(len(designs) / wall, 4), "unit": "designs/s", "n_gpus": 1,
         "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": f"config4: {len(designs)} requests, n in {{64,96,128}}, N U{{16..64}}, "
+        "config": {"workload": f"serving trace: {len(designs)} requests, n in {{64,96,128}}, N U{{16..64}}, "
                                f"V U[0.03,0.2], void E 1e-6, mixed, rtol {args.rtol}", "rate": round(rate, 4)},
         "latency_p50_s": round(float(np.percentile(L, 50)), 4),
         "latency_p99_s": round(float(np.percentile(L, 99)), 4),
@@ -137,7 +137,7 @@ def inverse_step(args):
     import numpy as np
     import torch
     from paper_2511_04025_amd import autograd as AG, workloads as wl
-    designs = wl.config5_batch(n=args.inverse_n, count=args.inverse_batch)
+    designs = wl.smooth_shell_96_batch(n=args.inverse_n, count=args.inverse_batch)
     t = AG.initial_thickness(designs)
     spec = AG.Spec(n=args.inverse_n, thickness=t, kappa=designs[0].kappa, E_void=designs[0].E_void,
                    precision="mixed", rtol=args.rtol)
@@ -164,7 +164,7 @@ def inverse_step(args):
         "value": round(args.inverse_batch / (ms / 1e3), 4), "unit": "designs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 1), "higher_is_better": True,
         "data": "synthetic",
-        "config": {"workload": f"config5: batch {args.inverse_batch} at {args.inverse_n}^3, 32 charges +-1, "
+        "config": {"workload": f"smooth_shell_96: batch {args.inverse_batch} at {args.inverse_n}^3, 32 charges +-1, "
                                f"logistic shell kappa=4n, t from V=0.10, mixed, rtol {args.rtol}"},
         "grad_norm_pos": float(pos.grad.norm()), "grad_norm_q": float(q.grad.norm())}))
 
@@ -229,7 +229,7 @@ def cpu_baseline(design, gpu_iters, budget_s):
         "unit": "designs/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle (NumPy/SciPy FP64) on config-2 design seed {design.seed} at {m}^3: field+threshold+"
+        "sample": (f"oracle (NumPy/SciPy FP64) on the 48-charge shell design seed {design.seed} at {m}^3: field+threshold+"
                    f"assembly {t_setup:.2f} s, {k} Jacobi-PCG iterations {t_it * 1e3:.1f} ms each; scaled by "
                    f"({design.n}/{m})^3 and the GPU's {gpu_iters} iterations to one {design.n}^3 design; "
                    f"host os.cpu_count()={os.cpu_count()}, single-threaded SciPy/NumPy"),
@@ -258,7 +258,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    designs = wl.config2_designs(n=args.n, count=args.designs)
+    designs = wl.shell_128_designs(n=args.n, count=args.designs)
     eng_opts = dict(precision="mixed", rtol=args.rtol, max_iter=args.max_iter)
     probe = serving.Engine(1 << 20, max_slots=1, **eng_opts)
     fp = probe.footprint(designs[0])
@@ -358,7 +358,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 stencil/vectors, f64 dots/recompute/reduction",
         "data": "synthetic",
-        "config": {"workload": f"config2: {len(designs)} designs/step at {args.n}^3, 48 charges, "
+        "config": {"workload": f"shell_128: {len(designs)} designs/step at {args.n}^3, 48 charges, "
                                f"vf U[0.05,0.15], void E 1e-6, mixed precision, rtol {args.rtol}, "
                                f"continuous-batching engine",
                    "n": args.n, "designs_per_step": len(designs)},

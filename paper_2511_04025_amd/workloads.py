@@ -51,7 +51,7 @@ def plus_minus_charges(N):
     return np.concatenate([np.ones(N // 2), -np.ones(N - N // 2)])
 
 
-def config1(seed=1):
+def small_shell_24(seed=1):
     """24^3, 16 charges of +-1 at uniform positions, hard shell at V = 0.12,
     E = 1, nu = 0.3, void E = 1e-3 (solved in FP64 to 1e-10)."""
     rng = np.random.default_rng(seed)
@@ -60,7 +60,7 @@ def config1(seed=1):
                   E_void=1e-3, seed=seed, tag="c1")
 
 
-def config2(seed, n=128):
+def shell_128(seed, n=128):
     """128^3 (or n^3), 48 charges with magnitudes U[-1, 1] shifted to zero net
     charge, volume fraction U[0.05, 0.15], void E = 1e-6."""
     rng = np.random.default_rng(seed)
@@ -71,11 +71,11 @@ def config2(seed, n=128):
     return Design(pos=pos, q=q, n=n, target_vf=float(vf), E_void=1e-6, seed=seed, tag="c2")
 
 
-def config2_designs(n=128, count=8):
-    return [config2(2000 + i, n=n) for i in range(count)]
+def shell_128_designs(n=128, count=8):
+    return [shell_128(2000 + i, n=n) for i in range(count)]
 
 
-def config3(seed=3000, n=256):
+def large_shell_256(seed=3000, n=256):
     """256^3, 64 charges of +-1, volume fraction 0.05, void E = 1e-6."""
     rng = np.random.default_rng(seed)
     pos = rng.random((64, 3))
@@ -83,9 +83,9 @@ def config3(seed=3000, n=256):
                   E_void=1e-6, seed=seed, tag="c3")
 
 
-def config4_trace(count=512, seed=4000, resolutions=(64, 96, 128)):
+def serving_trace(count=512, seed=4000, resolutions=(64, 96, 128)):
     """Serving trace: resolution uniform over `resolutions`, charge count
-    U{16..64}, magnitudes as config2, volume fraction U[0.03, 0.2], void
+    U{16..64}, magnitudes as shell_128, volume fraction U[0.03, 0.2], void
     E = 1e-6.  Arrival times are drawn separately (poisson_arrivals)."""
     rng = np.random.default_rng(seed)
     out = []
@@ -106,7 +106,7 @@ def poisson_arrivals(count, rate, seed=4001):
     return np.cumsum(rng.exponential(1.0 / rate, count))
 
 
-def config5(seed, n=96):
+def smooth_shell_96(seed, n=96):
     """Differentiable design step: 32 charges of +-1, logistic occupancy whose
     transition spans one voxel (kappa = 4 n, see the transition-width reading),
     void E = 1e-6; t is set from V = 0.10 at the initial design."""
@@ -116,8 +116,8 @@ def config5(seed, n=96):
                   kappa=4.0 * n, E_void=1e-6, seed=seed, tag="c5")
 
 
-def config5_batch(n=96, count=32):
-    return [config5(5000 + i, n=n) for i in range(count)]
+def smooth_shell_96_batch(n=96, count=32):
+    return [smooth_shell_96(5000 + i, n=n) for i in range(count)]
 
 
 def random_design(seed, n, N=16, vf=0.12, E_void=1e-3, kappa=0.0, pm=True):

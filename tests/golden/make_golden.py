@@ -1,14 +1,14 @@
 """Write the stored expected values under tests/golden/ by running the FP64
 oracle (and nothing else) on the seeded workloads.
 
-    python tests/golden/make_golden.py [c1] [c2] [c5] [--procs 8]
+    python tests/golden/make_golden.py [small] [shell48] [smooth] [--procs 8]
 
-c1: 24^3, 16 charges of +-1, V = 0.12, void E 1e-3              -> c1_n24_seed1.json
-c2: 48^3 versions of the 128^3 designs (seeds 2000-2007), void 1e-6 -> c2_n48_seed<s>.json
-c5: 24^3 logistic designs (seeds 5000, 5001), kappa = 4n, t from V = 0.10,
+small: 24^3, 16 charges of +-1, V = 0.12, void E 1e-3              -> small_shell_n24_seed1.json
+shell48: 48^3 versions of the 128^3 designs (seeds 2000-2007), void 1e-6 -> shell_n48_seed<s>.json
+smooth: 24^3 logistic designs (seeds 5000, 5001), kappa = 4n, t from V = 0.10,
     void 1e-6, with the oracle's design gradients of two functionals of
     (C^H, V): the bulk/Poisson loss, and a fixed random linear functional
-    -> c5_n24_seed<s>.json
+    -> smooth_shell_n24_seed<s>.json
 All solves: Jacobi-PCG to ||r|| <= 1e-12 ||f|| (node 0 pinned).
 """
 import json
@@ -32,30 +32,30 @@ def _dump(path, obj):
         json.dump(obj, f, indent=1)
 
 
-def run_c1(_=None):
-    d = wl.config1()
+def run_small(_=None):
+    d = wl.small_shell_24()
     t0 = time.time()
     C, info = hom.homogenize_design(d.pos, d.q, d.n, target_vf=d.target_vf, E_void=d.E_void, rtol=1e-12)
-    _dump(os.path.join(HERE, "c1_n24_seed1.json"), {
-        "source": "oracle, make_golden.py c1", "seed": 1, "n": 24, "C": C.tolist(), "V": info["V"],
+    _dump(os.path.join(HERE, "small_shell_n24_seed1.json"), {
+        "source": "oracle, make_golden.py small", "seed": 1, "n": 24, "C": C.tolist(), "V": info["V"],
         "t": info["t"], "iters": info["iters"].tolist(), "rel_res": info["rel_res"].tolist(),
         "seconds": time.time() - t0})
-    return "c1"
+    return "small"
 
 
-def run_c2(seed):
-    d = wl.config2(seed, n=48)
+def run_shell48(seed):
+    d = wl.shell_128(seed, n=48)
     t0 = time.time()
     C, info = hom.homogenize_design(d.pos, d.q, 48, target_vf=d.target_vf, E_void=d.E_void, rtol=1e-12,
                                     maxiter=400000)
-    _dump(os.path.join(HERE, f"c2_n48_seed{seed}.json"), {
-        "source": "oracle, make_golden.py c2", "seed": seed, "n": 48, "target_vf": d.target_vf,
+    _dump(os.path.join(HERE, f"shell_n48_seed{seed}.json"), {
+        "source": "oracle, make_golden.py shell48", "seed": seed, "n": 48, "target_vf": d.target_vf,
         "C": C.tolist(), "V": info["V"], "t": info["t"], "iters": info["iters"].tolist(),
         "rel_res": info["rel_res"].tolist(), "seconds": time.time() - t0})
-    return f"c2 {seed}"
+    return f"shell48 {seed}"
 
 
-def c5_functionals(C, V):
+def smooth_functionals(C, V):
     """The bulk/Poisson loss with targets fixed from the design itself (half the
     Hashin-Shtrikman bulk bound at its V, Poisson ratio 0), and a fixed random
     symmetric linear functional with dL/dV = 0.7."""
@@ -70,25 +70,25 @@ def c5_functionals(C, V):
     return K_target, g_loss, 0.5 * (G + G.T)
 
 
-def run_c5(seed):
-    d = wl.config5(seed, n=24)
+def run_smooth(seed):
+    d = wl.smooth_shell_96(seed, n=24)
     t0 = time.time()
     F, G = fld.field_and_gradient(d.pos, d.q, 24)
     t = fld.thickness_for_volume(fld.distance(F, G), 0.10, d.kappa)
     C, info = hom.homogenize_design(d.pos, d.q, 24, thickness=t, kappa=d.kappa, E_void=d.E_void, rtol=1e-12,
                                     maxiter=400000)
-    K_target, g_loss, g_rand = c5_functionals(C, info["V"])
+    K_target, g_loss, g_rand = smooth_functionals(C, info["V"])
     gp_l, gq_l = adj.design_gradient(info, d.pos, d.q, 24, g_loss, 0.0, kappa=d.kappa, E_void=d.E_void)
     gp_r, gq_r = adj.design_gradient(info, d.pos, d.q, 24, g_rand, 0.7, kappa=d.kappa, E_void=d.E_void)
-    _dump(os.path.join(HERE, f"c5_n24_seed{seed}.json"), {
-        "source": "oracle, make_golden.py c5", "seed": seed, "n": 24, "kappa": d.kappa, "t": t,
+    _dump(os.path.join(HERE, f"smooth_shell_n24_seed{seed}.json"), {
+        "source": "oracle, make_golden.py smooth", "seed": seed, "n": 24, "kappa": d.kappa, "t": t,
         "C": C.tolist(), "V": info["V"], "iters": info["iters"].tolist(), "rel_res": info["rel_res"].tolist(),
         "K_target": K_target, "nu_target": 0.0,
         "loss": float(metrics.bulk_poisson_loss(C, K_target, 0.0)),
         "dL_dC_loss": g_loss.tolist(), "dpos_loss": gp_l.tolist(), "dq_loss": gq_l.tolist(),
         "dL_dC_rand": g_rand.tolist(), "dL_dV_rand": 0.7, "dpos_rand": gp_r.tolist(), "dq_rand": gq_r.tolist(),
         "seconds": time.time() - t0})
-    return f"c5 {seed}"
+    return f"smooth {seed}"
 
 
 def main():
@@ -96,14 +96,14 @@ def main():
     procs = 8
     if "--procs" in args:
         procs = int(args[args.index("--procs") + 1])
-    which = [a for a in args if a in ("c1", "c2", "c5")] or ["c1", "c2", "c5"]
+    which = [a for a in args if a in ("small", "shell48", "smooth")] or ["small", "shell48", "smooth"]
     jobs = []
-    if "c1" in which:
-        jobs.append((run_c1, 0))
-    if "c5" in which:
-        jobs += [(run_c5, s) for s in (5000, 5001)]
-    if "c2" in which:
-        jobs += [(run_c2, 2000 + i) for i in range(8)]
+    if "small" in which:
+        jobs.append((run_small, 0))
+    if "smooth" in which:
+        jobs += [(run_smooth, s) for s in (5000, 5001)]
+    if "shell48" in which:
+        jobs += [(run_shell48, 2000 + i) for i in range(8)]
     with Pool(procs) as pool:
         rs = [pool.apply_async(f, (a,)) for f, a in jobs]
         for r in rs:

@@ -28,8 +28,8 @@ def rel_err(a, b):
 @pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-11, 1e-7), ("mixed", 1e-7, 1e-4)])
 def test_gradient_matches_oracle_golden(seed, precision, rtol, tol):
     from paper_2511_04025_amd import api
-    g = golden(f"c5_n24_seed{seed}.json")
-    d = wl.config5(seed, n=24).with_(thickness=g["t"])
+    g = golden(f"smooth_shell_n24_seed{seed}.json")
+    d = wl.smooth_shell_96(seed, n=24).with_(thickness=g["t"])
     r = api.homogenize(d, precision=precision, rtol=rtol, save_for_backward=True, return_workspace=True)
     assert r["status"] == 0
     for tag, dV in (("loss", 0.0), ("rand", g["dL_dV_rand"])):

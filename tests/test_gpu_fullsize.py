@@ -22,13 +22,13 @@ def golden(name):
         return json.load(f)
 
 
-def test_config2_at_48_against_oracle():
+def test_shell_designs_at_48_against_oracle():
     from paper_2511_04025_amd import api
-    designs = wl.config2_designs(n=48, count=8)
+    designs = wl.shell_128_designs(n=48, count=8)
     mixed = api.homogenize_batch(designs, precision="mixed", rtol=1e-6)
     fp64 = api.homogenize_batch(designs, precision="fp64", rtol=1e-10)
     for d, rm, rd in zip(designs, mixed, fp64):
-        g = golden(f"c2_n48_seed{d.seed}.json")
+        g = golden(f"shell_n48_seed{d.seed}.json")
         Cg = np.array(g["C"])
         assert rm["status"] == 0 and rd["status"] == 0
         assert rm["V"] == g["V"] and rd["V"] == g["V"]
@@ -38,7 +38,7 @@ def test_config2_at_48_against_oracle():
 
 def test_batch_equals_single():
     from paper_2511_04025_amd import api
-    designs = [wl.config2(2001, n=40), wl.config1(), wl.random_design(9, 33, N=20, vf=0.1, E_void=1e-6)]
+    designs = [wl.shell_128(2001, n=40), wl.small_shell_24(), wl.random_design(9, 33, N=20, vf=0.1, E_void=1e-6)]
     batch = api.homogenize_batch(designs, precision="mixed")
     for d, rb in zip(designs, batch):
         rs = api.homogenize(d, precision="mixed")
@@ -57,7 +57,7 @@ def _check_properties(C, V, E, E_void, nu=0.3):
 
 def test_field_sampled_at_128():
     from paper_2511_04025_amd import api
-    d = wl.config2(2000)
+    d = wl.shell_128(2000)
     n = d.n
     out = api.field(d)
     rng = np.random.default_rng(128)
@@ -83,11 +83,11 @@ def test_field_sampled_at_128():
 
 
 def test_mixed_vs_fp64_at_128_served():
-    # the headline configuration: config-2 designs at 128^3 batched in the
+    # the headline workload: the 48-charge shell designs at 128^3 batched in the
     # engine at the served CG tolerance 3e-6, every C^H entry against the FP64
     # GPU path (tolerance 1e-10) to the 1e-4 bar
     from paper_2511_04025_amd import api, serving
-    designs = wl.config2_designs(n=128, count=4)
+    designs = wl.shell_128_designs(n=128, count=4)
     eng = serving.Engine(8 << 30, max_slots=4, precision="mixed", rtol=3e-6)
     for i, d in enumerate(designs):
         eng.submit(d, i)
@@ -106,11 +106,11 @@ def test_mixed_vs_fp64_at_128_served():
         assert np.all(res[i]["rel_res"] <= 3e-6)
 
 
-def test_config3_at_256_mixed():
+def test_large_shell_256_mixed():
     # 256^3, 64 charges +-1, V = 0.05, void E 1e-6, FP32 stencil with the FP64
     # residual replaced every 50 iterations: properties that hold at any size
     from paper_2511_04025_amd import api
-    d = wl.config3()
+    d = wl.large_shell_256()
     rm = api.homogenize(d, precision="mixed", rtol=1e-6, recompute_every=50)
     assert rm["status"] == 0
     assert rm["V"] == np.floor(0.05 * 256 ** 3 + 0.5) / 256 ** 3
@@ -120,17 +120,17 @@ def test_config3_at_256_mixed():
 
 @pytest.mark.skipif(os.environ.get("SHH_FULL_256") != "1",
                     reason="FP64 reference solve at 256^3 takes minutes; set SHH_FULL_256=1")
-def test_config3_at_256_mixed_vs_fp64():
+def test_large_shell_256_mixed_vs_fp64():
     from paper_2511_04025_amd import api
-    d = wl.config3()
+    d = wl.large_shell_256()
     rm = api.homogenize(d, precision="mixed", rtol=1e-6, recompute_every=50)
-    print(f"config3 256^3 mixed: status {rm['status']} iters {rm['iters'].tolist()} "
+    print(f"large_shell_256 256^3 mixed: status {rm['status']} iters {rm['iters'].tolist()} "
           f"rel_res {rm['rel_res'].tolist()} ms {rm['ms']}", flush=True)
     rd = api.homogenize(d, precision="fp64", rtol=1e-9, max_iter=100000)
-    print(f"config3 256^3 fp64: status {rd['status']} iters {rd['iters'].tolist()} "
+    print(f"large_shell_256 256^3 fp64: status {rd['status']} iters {rd['iters'].tolist()} "
           f"rel_res {rd['rel_res'].tolist()} ms {rd['ms']}", flush=True)
     assert rm["status"] == 0 and rd["status"] == 0
     assert rm["V"] == rd["V"]
     rel, small, frob = ch_errors(rm["C"], rd["C"])
-    print(f"config3 256^3: mixed vs fp64 max rel {rel:.2e} small {small:.2e} frob {frob:.2e}")
+    print(f"large_shell_256 256^3: mixed vs fp64 max rel {rel:.2e} small {small:.2e} frob {frob:.2e}")
     assert rel <= 1e-4 and small <= 1e-7, (rel, small, frob)

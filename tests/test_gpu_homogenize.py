@@ -58,11 +58,11 @@ def golden(name):
         return json.load(f)
 
 
-def test_config1_fp64_vs_oracle():
+def test_small_shell_fp64_vs_oracle():
     # 24^3, 16 charges of +-1, V = 0.12, void E = 1e-3, FP64 PCG to 1e-10
     A = api()
-    g = golden("c1_n24_seed1.json")
-    r = A.homogenize(wl.config1(), precision="fp64", rtol=1e-10)
+    g = golden("small_shell_n24_seed1.json")
+    r = A.homogenize(wl.small_shell_24(), precision="fp64", rtol=1e-10)
     assert r["status"] == 0 and np.all(r["rel_res"] <= 1e-10)
     assert r["V"] == g["V"]
     assert abs(r["t"] - g["t"]) <= 1e-12 * g["t"]
@@ -70,10 +70,10 @@ def test_config1_fp64_vs_oracle():
 
 
 @pytest.mark.parametrize("precision,tol", [("mixed", 1e-4), ("fp64", 1e-7)])
-def test_config1_mixed_and_fp64(precision, tol):
+def test_small_shell_mixed_and_fp64(precision, tol):
     A = api()
-    g = golden("c1_n24_seed1.json")
-    r = A.homogenize(wl.config1(), precision=precision)
+    g = golden("small_shell_n24_seed1.json")
+    r = A.homogenize(wl.small_shell_24(), precision=precision)
     assert r["status"] == 0
     assert_ch_close(r["C"], np.array(g["C"]), tol)
 
@@ -94,8 +94,8 @@ def test_mixed_path_matches_oracle(n, seed):
 def test_logistic_void_1e6_vs_golden(seed, precision, tol):
     # 24^3, 32 charges of +-1, logistic occupancy (kappa = 4n), void E = 1e-6
     A = api()
-    g = golden(f"c5_n24_seed{seed}.json")
-    d = wl.config5(seed, n=24).with_(thickness=g["t"])
+    g = golden(f"smooth_shell_n24_seed{seed}.json")
+    d = wl.smooth_shell_96(seed, n=24).with_(thickness=g["t"])
     r = A.homogenize(d, precision=precision)
     assert r["status"] == 0
     assert abs(r["V"] - g["V"]) <= 1e-13

@@ -69,7 +69,7 @@ def ws_bytes(lib, design, precision="mixed", **kw):
 
 def test_workspace_sizes(lib):
     for n in (2, 24, 64, 128):
-        d = wl.config2(2000, n=n)
+        d = wl.shell_128(2000, n=n)
         rc_m, bm = ws_bytes(lib, d, "mixed")
         rc_d, bd = ws_bytes(lib, d, "fp64")
         assert rc_m == B.SHH_OK and rc_d == B.SHH_OK
@@ -80,7 +80,7 @@ def test_workspace_sizes(lib):
             assert 600 < bm / n ** 3 < 700
             assert 980 < bd / n ** 3 < 1060
     # keeping the field for the adjoint adds F, grad F, d (40 B/voxel)
-    d = wl.config5(5000, n=24)
+    d = wl.smooth_shell_96(5000, n=24)
     _, b0 = ws_bytes(lib, d, "mixed")
     _, b1 = ws_bytes(lib, d, "mixed", save_for_backward=True)
     assert b1 - b0 >= 40 * 24 ** 3
@@ -92,7 +92,7 @@ def test_stiffness_and_engine_footprints(lib):
     assert lib.shh_workspace_bytes_stiffness(512, byref(o), byref(nb)) == B.SHH_OK and nb.value > 0
     assert lib.shh_workspace_bytes_stiffness(513, byref(o), byref(nb)) == B.SHH_INVALID_ARG
     assert lib.shh_workspace_bytes_stiffness(1, byref(o), byref(nb)) == B.SHH_INVALID_ARG
-    d = wl.config2(2001, n=96)
+    d = wl.shell_128(2001, n=96)
     a = B.DesignArgs(d)
     fp = c_size_t(0)
     assert lib.shh_engine_footprint(byref(a.c), byref(o), byref(fp)) == B.SHH_OK
@@ -102,7 +102,7 @@ def test_stiffness_and_engine_footprints(lib):
 
 
 def _invalid(**change):
-    d = wl.config1()
+    d = wl.small_shell_24()
     return d.with_(**change)
 
 
@@ -117,7 +117,7 @@ def test_design_validation(lib, change):
 
 
 def test_nonfinite_charges_and_bad_options(lib):
-    d = wl.config1()
+    d = wl.small_shell_24()
     pos = d.pos.copy()
     pos[3, 1] = np.nan
     assert ws_bytes(lib, d.with_(pos=pos))[0] == B.SHH_INVALID_ARG
@@ -142,18 +142,18 @@ def test_option_defaults():
 
 
 def test_workloads_are_seeded_and_shaped():
-    a, b = wl.config2(2003), wl.config2(2003)
+    a, b = wl.shell_128(2003), wl.shell_128(2003)
     assert np.array_equal(a.pos, b.pos) and np.array_equal(a.q, b.q)
     assert a.n == 128 and len(a.q) == 48 and abs(a.q.sum()) < 1e-12
     assert 0.05 <= a.target_vf <= 0.15 and a.E_void == 1e-6
-    c1 = wl.config1()
+    c1 = wl.small_shell_24()
     assert c1.n == 24 and sorted(set(c1.q.tolist())) == [-1.0, 1.0] and c1.q.sum() == 0
-    c3 = wl.config3()
+    c3 = wl.large_shell_256()
     assert c3.n == 256 and len(c3.q) == 64 and c3.q.sum() == 0
-    trace = wl.config4_trace(count=64)
+    trace = wl.serving_trace(count=64)
     assert {d.n for d in trace} <= {64, 96, 128}
     assert all(16 <= len(d.q) <= 64 and 0.03 <= d.target_vf <= 0.2 for d in trace)
     t = wl.poisson_arrivals(64, 2.0)
     assert np.all(np.diff(t) >= 0) and t[0] >= 0
-    c5 = wl.config5(5000)
+    c5 = wl.smooth_shell_96(5000)
     assert c5.n == 96 and c5.kappa == 4 * 96 and len(c5.q) == 32
