@@ -145,14 +145,23 @@ int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const 
 int32_t shh_field(const shh_design *design, void *d_ws, size_t ws_bytes, double *d_F,
                   double *d_G, double *d_d, double *d_beta, void *hip_stream, shh_result *out);
 
+/* Workspace of the operator calls below (shh_apply_stiffness,
+   shh_load_vectors, shh_energy): the moduli in the working precision, the
+   Jacobi diagonal, reduction partials and descriptors, about 16 B per node
+   (the callers' vectors are not part of it).  2 <= n <= 512;
+   precision SHH_PREC_FP64 or SHH_PREC_MIXED; SHH_INVALID_ARG otherwise.  A
+   shh_workspace_bytes_stiffness workspace of the same precision is larger and
+   serves as well. */
+int32_t shh_workspace_bytes_operator(int32_t n, int32_t precision, size_t *bytes);
+
 /* The matrix-free periodic stiffness operator: d_q = K d_p for `nrhs` nodal
    vector fields [nrhs][3][n^3], K = sum_e E_e P_e^T K_0 P_e (Sec. 4.1, K_0 the
    unit-voxel 8-node-hex matrix at E = 1 and Poisson ratio nu).  precision
    SHH_PREC_FP64: d_p, d_q are doubles; SHH_PREC_MIXED: floats (E rounded to
    float).  d_E: device n^3 doubles.  d_ws: device scratch of at least
-   shh_workspace_bytes_stiffness(n, opts) bytes for opts with this precision
-   (SHH_INVALID_ARG / SHH_WORKSPACE_TOO_SMALL otherwise).  Synchronizes the
-   stream before returning. */
+   shh_workspace_bytes_operator(n, precision) bytes (SHH_INVALID_ARG /
+   SHH_WORKSPACE_TOO_SMALL otherwise).  Synchronizes the stream before
+   returning. */
 int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, double nu,
                             int32_t nrhs, const void *d_p, void *d_q, void *d_ws, size_t ws_bytes,
                             void *hip_stream);

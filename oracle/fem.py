@@ -147,3 +147,28 @@ def load_vectors(Ee, nu, n):
     for k in range(6):
         np.add.at(f[:, k], dofs.ravel(), -(e[:, None] * g[None, :, k]).ravel())
     return f
+
+
+def stiffness_rows(Ee, nu, n, u_at, nodes):
+    """Rows of K u at selected nodes, straight from K = sum_e E_e P_e^T K_0 P_e
+    (Sec. 4.1): node v is corner a of exactly one element per corner a, the
+    element (v - a) mod n, which contributes E_e times the three rows of K_0
+    for corner a applied to that element's 24 displacements.
+
+    u_at(node_ids) returns the displacements of the given global nodes as an
+    array (len, 3, m); nodes are global node ids.  Returns (len(nodes), 3, m).
+    For sampling K u on grids too large to assemble."""
+    K0 = element_stiffness(nu)
+    E = np.asarray(Ee, dtype=np.float64).ravel()
+    v = np.asarray(nodes, dtype=np.int64)
+    vx, vy, vz = v % n, (v // n) % n, v // (n * n)
+    out = None
+    for a, (ax, ay, az) in enumerate(CORNERS):
+        ex, ey, ez = (vx - ax) % n, (vy - ay) % n, (vz - az) % n
+        ue = []
+        for bx, by, bz in CORNERS:
+            ue.append(u_at((((ez + bz) % n) * n + (ey + by) % n) * n + (ex + bx) % n))
+        ue = np.concatenate(ue, axis=1)  # (len, 24, m), dof 3 * corner + component
+        part = E[(ez * n + ey) * n + ex][:, None, None] * np.einsum("ij,pjm->pim", K0[3 * a:3 * a + 3], ue)
+        out = part if out is None else out + part
+    return out

@@ -100,6 +100,14 @@ def stiffness_workspace_bytes(n, precision="fp64"):
     return nb.value
 
 
+def operator_workspace_bytes(n, precision="fp64"):
+    """Device bytes the operator calls (apply_stiffness, load_vectors, energy) need."""
+    prec = B.PREC_FP64 if precision == "fp64" else B.PREC_MIXED
+    nb = c_size_t(0)
+    B.check(B.lib().shh_workspace_bytes_operator(int(n), prec, byref(nb)), "shh_workspace_bytes_operator")
+    return nb.value
+
+
 def _check_grid(E):
     if not (E.is_cuda and E.dtype == torch.float64 and E.dim() == 3 and E.is_contiguous()
             and E.shape[0] == E.shape[1] == E.shape[2]):
@@ -152,7 +160,7 @@ def apply_stiffness(E, p, nu, precision="fp64"):
         raise ValueError("p must be a contiguous CUDA tensor (m, 3, n, n, n) of the precision's dtype")
     m = p.shape[0]
     q = torch.empty_like(p)
-    ws = Workspace(stiffness_workspace_bytes(n, precision))
+    ws = Workspace(operator_workspace_bytes(n, precision))
     prec = B.PREC_FP64 if precision == "fp64" else B.PREC_MIXED
     rc = B.lib().shh_apply_stiffness(n, prec, _ptr(E), c_double(nu), m, _ptr(p), _ptr(q), ws.ptr,
                                      c_size_t(ws.nbytes), _stream())
@@ -165,7 +173,7 @@ def load_vectors(E, nu):
     _require_gpu()
     n = _check_grid(E)
     f = torch.empty((6, 3, n, n, n), dtype=torch.float64, device="cuda")
-    ws = Workspace(stiffness_workspace_bytes(n, "fp64"))
+    ws = Workspace(operator_workspace_bytes(n, "fp64"))
     rc = B.lib().shh_load_vectors(n, _ptr(E), c_double(nu), _ptr(f), ws.ptr, c_size_t(ws.nbytes), _stream())
     B.check(rc, "shh_load_vectors")
     return f
@@ -177,7 +185,7 @@ def energy(E, u, nu):
     n = _check_grid(E)
     if not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous() and u.shape == (6, 3, n, n, n)):
         raise ValueError("u must be a contiguous float64 CUDA tensor (6, 3, n, n, n)")
-    ws = Workspace(stiffness_workspace_bytes(n, "fp64"))
+    ws = Workspace(operator_workspace_bytes(n, "fp64"))
     C = (c_double * 36)()
     rc = B.lib().shh_energy(n, _ptr(E), c_double(nu), _ptr(u), C, ws.ptr, c_size_t(ws.nbytes), _stream())
     B.check(rc, "shh_energy")

@@ -55,10 +55,10 @@ struct Events {
 };
 
 int prepare_slot(Slot &s, const shh_design *d, const shh_opts *o, void *d_ws, size_t ws_bytes,
-                 char **seg_mem) {
+                 char **seg_mem, bool vectors = true) {
   copy_design(d, s.design);
   s.opts = *o;
-  s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0);
+  s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, vectors);
   if (!d_ws) return SHH_INVALID_ARG;
   char *base = aligned(d_ws);
   const size_t need = s.lay.total + seg_region() + size_t(base - (char *)d_ws);
@@ -219,14 +219,23 @@ int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *b
   return SHH_OK;
 }
 
+int32_t shh_workspace_bytes_operator(int32_t n, int32_t precision, size_t *bytes) {
+  if (n < 2 || n > 512 || !bytes || (precision != SHH_PREC_FP64 && precision != SHH_PREC_MIXED))
+    return SHH_INVALID_ARG;
+  const shh_design d = stiffness_design(n, 0.3);
+  const Layout L = make_layout(d.n, d.num_charges, d.K, precision, false, false);
+  *bytes = L.total + seg_region() + 256;
+  return SHH_OK;
+}
+
 // Slot over a workspace with moduli copied from d_E (scale taken from max E).
 static int moduli_slot(Slot &s, int32_t n, const double *d_E, double nu, const shh_opts *o, void *d_ws,
-                       size_t ws_bytes, hipStream_t st, char **seg_mem) {
+                       size_t ws_bytes, hipStream_t st, char **seg_mem, bool vectors) {
   if (n < 2 || n > 512 || !d_E || !(nu > -1.0 && nu < 0.5)) return SHH_INVALID_ARG;
   shh_opts oo = *o;
   oo.save_for_backward = 0;
   const shh_design d = stiffness_design(n, nu);
-  SHH_TRY(prepare_slot(s, &d, &oo, d_ws, ws_bytes, seg_mem));
+  SHH_TRY(prepare_slot(s, &d, &oo, d_ws, ws_bytes, seg_mem, vectors));
   SHH_TRY(slot_init(s, s.base, st));
   SHH_TRY(slot_setup_moduli(s, d_E, st));
   SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
@@ -250,7 +259,7 @@ int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const 
   char *seg_mem = nullptr;
   Events ev(&s);
   SHH_HIP(hipEventRecord(s.ev[0], st));
-  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true));
   Solver sv(st);
   sv.set_segment_memory(seg_mem, seg_region());
   SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
@@ -270,7 +279,7 @@ int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, dou
   hipStream_t st = (hipStream_t)hip_stream;
   Slot s;
   char *seg_mem = nullptr;
-  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, false));
   s.host.p[0] = const_cast<void *>(d_p);
   s.host.q[0] = d_q;
   SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
@@ -300,7 +309,7 @@ int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, v
   hipStream_t st = (hipStream_t)hip_stream;
   Slot s;
   char *seg_mem = nullptr;
-  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem));
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, false));
   s.host.r[0] = d_f;
   SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
   Segment g;
@@ -328,7 +337,7 @@ int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, d
   SHH_TRY(normalize_opts(&o, &o));
   hipStream_t st = (hipStream_t)hip_stream;
   Slot s;
-  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, nullptr));
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, nullptr, false));
   s.host.x64 = const_cast<double *>(d_u);
   SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
   SHH_HIP(launch_energy(s.d_slot, s.host.nn, st));

@@ -99,8 +99,9 @@ static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // z planes per stencil workgroup (the z-march length)
 static int tz_for(int n) { return n < SHH_TZ ? n : SHH_TZ; }
 
-Layout make_layout(int n, int N, int K, int prec, bool save) {
+Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors) {
   Layout L{};
+  L.vectors = vectors;
   const long long nn = (long long)n * n * n;
   const int nb = 2 * K + 1;
   const int tz_runs = (n + tz_for(n) - 1) / tz_for(n);
@@ -126,6 +127,10 @@ Layout make_layout(int n, int N, int K, int prec, bool save) {
   L.E64 = take(sizeof(double) * nn);
   L.E32 = prec == SHH_PREC_MIXED ? take(sizeof(float) * nn) : 0;
   L.Dinv = take(ts * nn);
+  if (!vectors) {  // the operator calls bring their own vectors
+    L.total = off;
+    return L;
+  }
   L.x64 = prec == SHH_PREC_MIXED ? take(sizeof(double) * NRHS * 3 * nn) : 0;
   L.vec_bytes = align256(ts * NRHS * 3 * nn);
   L.vec = take(7 * L.vec_bytes);  // r[2], p[2], q[2], x
@@ -209,19 +214,21 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.charges = (double *)(base + L.charges);
   h.alpha = d.alpha ? (double *)(base + L.alpha) : nullptr;
   h.coef = (double *)(base + L.coef);
-  h.F = (double *)(base + L.field);
-  h.G = h.F + h.nn;
-  h.d = h.F + 4 * h.nn;
+  h.F = L.vectors ? (double *)(base + L.field) : nullptr;
+  h.G = L.vectors ? h.F + h.nn : nullptr;
+  h.d = L.vectors ? h.F + 4 * h.nn : nullptr;
   h.E64 = (double *)(base + L.E64);
   h.E32 = prec == SHH_PREC_MIXED ? (float *)(base + L.E32) : nullptr;
   h.Dinv = base + L.Dinv;
-  for (int b = 0; b < 2; ++b) {
-    h.r[b] = base + L.vec + (0 + b) * L.vec_bytes;
-    h.p[b] = base + L.vec + (2 + b) * L.vec_bytes;
-    h.q[b] = base + L.vec + (4 + b) * L.vec_bytes;
-  }
-  h.x = base + L.vec + 6 * L.vec_bytes;
-  h.x64 = prec == SHH_PREC_MIXED ? (double *)(base + L.x64) : (double *)h.x;
+  if (L.vectors) {
+    for (int b = 0; b < 2; ++b) {
+      h.r[b] = base + L.vec + (0 + b) * L.vec_bytes;
+      h.p[b] = base + L.vec + (2 + b) * L.vec_bytes;
+      h.q[b] = base + L.vec + (4 + b) * L.vec_bytes;
+    }
+    h.x = base + L.vec + 6 * L.vec_bytes;
+    h.x64 = prec == SHH_PREC_MIXED ? (double *)(base + L.x64) : (double *)h.x;
+  }  // else: left null; each operator call sets the vectors it uses
   h.partials = (double *)(base + L.partials);
   h.st = (CgState *)(base + L.state);
   s.d_slot = (SlotDev *)(base + L.slotdev);

@@ -21,6 +21,7 @@ struct Layout {
   size_t vec_bytes;   // one [6][3][n^3] vector
   size_t total;
   int maxparts;
+  bool vectors;       // false: operator-only slot (no CG vectors, no field arrays)
 };
 
 struct DesignCopy {
@@ -50,7 +51,7 @@ struct Slot {
 
 int validate_design(const shh_design *d);
 int normalize_opts(const shh_opts *in, shh_opts *out);
-Layout make_layout(int n, int N, int K, int prec, bool save);
+Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors = true);
 void copy_design(const shh_design *src, DesignCopy &dst);
 
 // Fill the slot descriptor for a region and upload it (+ charges, alpha, zeroed state).

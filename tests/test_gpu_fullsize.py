@@ -134,3 +134,58 @@ def test_large_shell_256_mixed_vs_fp64():
     rel, small, frob = ch_errors(rm["C"], rd["C"])
     print(f"large_shell_256 256^3: mixed vs fp64 max rel {rel:.2e} small {small:.2e} frob {frob:.2e}")
     assert rel <= 1e-4 and small <= 1e-7, (rel, small, frob)
+
+
+def _boundary_nodes(n, seed, extra=200):
+    """Nodes on and around tile seams (64- and 32-wide x tiles, 6- and 8-high
+    y tiles, 32-plane z runs), the periodic wrap and a ragged last tile, plus
+    random ones."""
+    def near(cuts):
+        c = set()
+        for v in cuts:
+            c.update({v - 1, v, v + 1})
+        return sorted(x % n for x in c)
+    xs = near([0, 32, 64, 96, 128, n - 1, n // 2])
+    ys = near([0, 6, 8, 12, 24, n - 1, n - n % 6, n // 2])
+    zs = near([0, 32, 64, n - 1, n // 2])
+    X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+    rng = np.random.default_rng(seed)
+    r = rng.integers(0, n, (3, extra))
+    x = np.concatenate([X.ravel(), r[0]])
+    y = np.concatenate([Y.ravel(), r[1]])
+    z = np.concatenate([Z.ravel(), r[2]])
+    return x, y, z
+
+
+@pytest.mark.parametrize("n,m", [(97, 6), (130, 6), (512, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_operator_sampled_at_large_and_maximum_sizes(n, m, precision):
+    """K p at multi-tile grids with ragged last tiles and at the largest grid
+    the library accepts (512^3), against the oracle's rows of K p computed
+    from the element definition at sampled nodes."""
+    from paper_2511_04025_amd import api
+    print(f"operator sampled: n={n} m={m} {precision}", flush=True)
+    rng = np.random.default_rng(n)
+    E = np.where(rng.random((n, n, n)) < 0.35, 1.0, 1e-3) * rng.uniform(0.5, 1.0, (n, n, n))
+    dt = np.float64 if precision == "fp64" else np.float32
+    p = rng.standard_normal((m, 3, n, n, n), dtype=dt)
+    nu = 0.3
+    Eg = torch.tensor(E, device="cuda")
+    pg = torch.from_numpy(p).to("cuda")
+    q = api.apply_stiffness(Eg, pg, nu, precision)
+    del pg
+    x, y, z = _boundary_nodes(n, n + 1)
+    ix = [torch.tensor(a, device="cuda") for a in (z, y, x)]
+    qs = q[:, :, ix[0], ix[1], ix[2]].double().cpu().numpy()  # (m, 3, len)
+    del q
+    torch.cuda.empty_cache()
+    nodes = (z * n + y) * n + x
+    pf = p.reshape(m, 3, n ** 3)
+
+    def u_at(ids):
+        return np.ascontiguousarray(pf[:, :, ids].astype(np.float64).transpose(2, 1, 0))
+
+    ref = fem.stiffness_rows(E.ravel(), nu, n, u_at, nodes)  # (len, 3, m)
+    got = qs.transpose(2, 1, 0)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max()

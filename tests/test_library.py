@@ -157,3 +157,19 @@ def test_workloads_are_seeded_and_shaped():
     assert np.all(np.diff(t) >= 0) and t[0] >= 0
     c5 = wl.smooth_shell_96(5000)
     assert c5.n == 96 and c5.kappa == 4 * 96 and len(c5.q) == 32
+
+
+def test_operator_workspace(lib):
+    nb = c_size_t(0)
+    for n in (2, 130, 512):
+        for prec in (B.PREC_FP64, B.PREC_MIXED):
+            assert lib.shh_workspace_bytes_operator(n, prec, byref(nb)) == B.SHH_OK
+            # moduli + Jacobi diagonal (~16 B/node) plus fixed-size tables
+            if n >= 130:
+                assert 15.5 < nb.value / n ** 3 < 17.5
+            o = B.make_opts("fp64" if prec == B.PREC_FP64 else "mixed")
+            full = c_size_t(0)
+            assert lib.shh_workspace_bytes_stiffness(n, byref(o), byref(full)) == B.SHH_OK
+            assert nb.value < full.value
+    for bad in ((1, B.PREC_FP64), (513, B.PREC_FP64), (64, 2), (64, -1)):
+        assert lib.shh_workspace_bytes_operator(bad[0], bad[1], byref(nb)) == B.SHH_INVALID_ARG

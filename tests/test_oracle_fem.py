@@ -122,3 +122,30 @@ def test_cg_zero_rhs():
     Kp, fp = slv.pin_node0(K, np.zeros((3 * n ** 3, 6)))
     u, iters, res = slv.pcg_jacobi(Kp, fp)
     assert np.all(u == 0.0) and np.all(iters == 0)
+
+
+def test_stiffness_rows_match_assembly_and_rigid_modes():
+    # rows of K u by the per-node definition equal the assembled product
+    n, nu = 5, 0.27
+    rng = np.random.default_rng(31)
+    E = rng.uniform(1e-3, 1.0, n ** 3)
+    U = rng.standard_normal((3 * n ** 3, 2))
+    Q = fem.assemble(E, nu, n) @ U
+    nodes = np.array([0, 1, n - 1, n * n - 1, n ** 3 - 1, 37, 64, 99])
+    u_at = lambda ids: U.reshape(n ** 3, 3, 2)[ids]
+    rows = fem.stiffness_rows(E, nu, n, u_at, nodes)
+    assert np.max(np.abs(rows - Q.reshape(n ** 3, 3, 2)[nodes])) <= 1e-13 * np.abs(Q).max()
+    # a rigid translation has no force anywhere
+    t = np.tile(np.array([0.3, -1.2, 2.0])[None, :, None], (n ** 3, 1, 1))
+    rows = fem.stiffness_rows(E, nu, n, lambda ids: t[ids], np.arange(n ** 3))
+    assert np.abs(rows).max() <= 1e-14 * np.abs(E).max()
+    # a single displaced node pulls on itself with the diagonal closed form:
+    # (lambda + 4 mu) / 9 times the sum of its 8 incident E_e (E = 1 units)
+    lam, mu = fem.lame(1.0, nu)
+    k = 62
+    vx, vy, vz = k % n, (k // n) % n, k // (n * n)
+    s = sum(E[(((vz - az) % n) * n + (vy - ay) % n) * n + (vx - ax) % n] for ax, ay, az in fem.CORNERS)
+    e = np.zeros((n ** 3, 3, 1))
+    e[k, 1, 0] = 1.0
+    rows = fem.stiffness_rows(E, nu, n, lambda ids: e[ids], np.array([k]))
+    assert abs(rows[0, 1, 0] - (lam + 4 * mu) / 9 * s) <= 1e-14
