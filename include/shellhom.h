@@ -58,6 +58,9 @@ extern "C" {
 #define SHH_PREC_MIXED 1  /* FP32 stencil and CG vectors; FP64 dots, residual
                              recompute, solution accumulator and C^H reduction           */
 
+#define SHH_SOLVER_JACOBI 0  /* CG with the Jacobi preconditioner                        */
+#define SHH_SOLVER_MG     1  /* CG with a geometric multigrid V-cycle preconditioner     */
+
 /* One design (Eq. (6)-(7) parameters and material). */
 typedef struct {
   int32_t n;            /* voxels per axis, 2 <= n <= 512                               */
@@ -92,6 +95,11 @@ typedef struct {
                                the true residual is always recomputed at the end)        */
   int32_t save_for_backward;/* keep F, grad F and the solution for shh_grad               */
   int32_t check_every;      /* host polls convergence every this many iterations (0: 16) */
+  int32_t solver;           /* SHH_SOLVER_JACOBI (0): Jacobi-preconditioned CG, one fused
+                               pass per iteration; SHH_SOLVER_MG (1): CG preconditioned by
+                               a geometric multigrid V-cycle (Sec. 4.2's solver family:
+                               Galerkin coarse grids, Chebyshev smoothing), for n = m 2^k
+                               with k >= 1 and m <= 8 (SHH_UNSUPPORTED otherwise)       */
 } shh_opts;
 
 /* Result of one homogenization. */

@@ -52,11 +52,11 @@ def workspace_bytes(design, opts):
 
 
 def homogenize(design, precision="mixed", rtol=None, max_iter=20000, recompute_every=0,
-               save_for_backward=False, check_every=0, workspace=None, return_workspace=False):
+               save_for_backward=False, check_every=0, workspace=None, return_workspace=False, solver="jacobi"):
     """The whole path for one design; returns a dict with C (6x6), V, t,
     iters, rel_res, ms, status (and the workspace if asked)."""
     _require_gpu()
-    opts = B.make_opts(precision, rtol, max_iter, recompute_every, save_for_backward, check_every)
+    opts = B.make_opts(precision, rtol, max_iter, recompute_every, save_for_backward, check_every, solver)
     a = B.DesignArgs(design)
     need = workspace_bytes(design, opts)
     if workspace is None or workspace.nbytes < need:
@@ -73,10 +73,11 @@ def homogenize(design, precision="mixed", rtol=None, max_iter=20000, recompute_e
 
 
 def homogenize_batch(designs, precision="mixed", rtol=None, max_iter=20000, recompute_every=0,
-                     save_for_backward=False, check_every=0, workspaces=None, return_workspaces=False):
+                     save_for_backward=False, check_every=0, workspaces=None, return_workspaces=False,
+                     solver="jacobi"):
     """All designs at once, one batched launch per phase."""
     _require_gpu()
-    opts = B.make_opts(precision, rtol, max_iter, recompute_every, save_for_backward, check_every)
+    opts = B.make_opts(precision, rtol, max_iter, recompute_every, save_for_backward, check_every, solver)
     args = [B.DesignArgs(d) for d in designs]
     count = len(designs)
     arr = (B.ShhDesign * count)(*[a.c for a in args])
@@ -116,11 +117,11 @@ def _check_grid(E):
 
 
 def homogenize_stiffness(E, nu, precision="mixed", rtol=None, max_iter=20000, recompute_every=0,
-                         check_every=0):
+                         check_every=0, solver="jacobi"):
     """Steps 3-4 for a given voxel modulus field E (n, n, n) float64 on the GPU."""
     _require_gpu()
     n = _check_grid(E)
-    opts = B.make_opts(precision, rtol, max_iter, recompute_every, False, check_every)
+    opts = B.make_opts(precision, rtol, max_iter, recompute_every, False, check_every, solver)
     nb = c_size_t(0)
     B.check(B.lib().shh_workspace_bytes_stiffness(n, byref(opts), byref(nb)), "shh_workspace_bytes_stiffness")
     ws = Workspace(nb.value)

@@ -46,6 +46,7 @@ class ShhOpts(ctypes.Structure):
     _fields_ = [
         ("precision", c_int32), ("rtol", c_double), ("max_iter", c_int32),
         ("recompute_every", c_int32), ("save_for_backward", c_int32), ("check_every", c_int32),
+        ("solver", c_int32),
     ]
 
 
@@ -144,14 +145,18 @@ class DesignArgs:
             E=float(design.E), nu=float(design.nu), E_void=float(design.E_void))
 
 
+SOLVER_JACOBI, SOLVER_MG = 0, 1
+
+
 def make_opts(precision="mixed", rtol=None, max_iter=20000, recompute_every=0, save_for_backward=False,
-              check_every=0):
+              check_every=0, solver="jacobi"):
     prec = PREC_MIXED if precision in ("mixed", PREC_MIXED) else PREC_FP64
     if rtol is None:
         rtol = 1e-6 if prec == PREC_MIXED else 1e-10
+    sv = SOLVER_MG if solver in ("mg", SOLVER_MG) else SOLVER_JACOBI
     return ShhOpts(precision=prec, rtol=float(rtol), max_iter=int(max_iter),
                    recompute_every=int(recompute_every), save_for_backward=int(bool(save_for_backward)),
-                   check_every=int(check_every))
+                   check_every=int(check_every), solver=sv)
 
 
 def result_dict(r):

@@ -31,8 +31,15 @@ constexpr int MAX_BATCH = 64;
 // Segment tables of one solve live in a fixed block of the first workspace.
 size_t seg_region() { return Solver::seg_bytes(MAX_BATCH); }
 
+// The multigrid solver needs n = m 2^k, k >= 1, m <= 8.
+int check_solver(int n, const shh_opts *o) {
+  if (o->solver == SHH_SOLVER_MG && mg_num_levels(n) < 2) return SHH_UNSUPPORTED;
+  return SHH_OK;
+}
+
 size_t ws_bytes_for(const shh_design *d, const shh_opts *o) {
-  const Layout L = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0);
+  const Layout L = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, true,
+                               o->solver);
   return L.total + seg_region() + 256;
 }
 
@@ -58,7 +65,9 @@ int prepare_slot(Slot &s, const shh_design *d, const shh_opts *o, void *d_ws, si
                  char **seg_mem, bool vectors = true) {
   copy_design(d, s.design);
   s.opts = *o;
-  s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, vectors);
+  SHH_TRY(check_solver(d->n, o));
+  s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, vectors,
+                      vectors ? o->solver : SHH_SOLVER_JACOBI);
   if (!d_ws) return SHH_INVALID_ARG;
   char *base = aligned(d_ws);
   const size_t need = s.lay.total + seg_region() + size_t(base - (char *)d_ws);
@@ -105,7 +114,7 @@ const char *shh_strerror(int32_t code) {
     case SHH_WORKSPACE_TOO_SMALL: return "workspace too small";
     case SHH_HIP_ERROR: return "HIP runtime error";
     case SHH_OVER_BUDGET: return "request footprint exceeds the engine arena";
-    case SHH_UNSUPPORTED: return "unsupported (gradient of the hard step)";
+    case SHH_UNSUPPORTED: return "unsupported (hard-step gradient, or a grid the multigrid solver cannot coarsen)";
     case SHH_BREAKDOWN: return "CG breakdown (p^T K p <= 0 or NaN)";
     case SHH_NOT_FOUND: return "unknown request id";
     default: return "unknown status";
@@ -117,6 +126,7 @@ int32_t shh_workspace_bytes(const shh_design *design, const shh_opts *opts, size
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   if (!bytes) return SHH_INVALID_ARG;
+  SHH_TRY(check_solver(design->n, &o));
   *bytes = ws_bytes_for(design, &o);
   return SHH_OK;
 }
@@ -215,6 +225,7 @@ int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *b
   SHH_TRY(normalize_opts(opts, &o));
   o.save_for_backward = 0;
   const shh_design d = stiffness_design(n, 0.3);
+  SHH_TRY(check_solver(n, &o));
   *bytes = ws_bytes_for(&d, &o);
   return SHH_OK;
 }
@@ -487,7 +498,9 @@ int32_t shh_engine_footprint(const shh_design *design, const shh_opts *opts, siz
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   if (!bytes) return SHH_INVALID_ARG;
-  const Layout L = make_layout(design->n, design->num_charges, design->K, o.precision, o.save_for_backward != 0);
+  SHH_TRY(check_solver(design->n, &o));
+  const Layout L = make_layout(design->n, design->num_charges, design->K, o.precision, o.save_for_backward != 0,
+                               true, o.solver);
   *bytes = (L.total + 255) & ~size_t(255);
   return SHH_OK;
 }
@@ -540,7 +553,7 @@ static int engine_admit(shh_engine *eng, std::vector<Slot *> &fresh) {
   while (!eng->queue.empty() && (int)eng->resident.size() < eng->max_slots) {
     shh_engine::Pending &p = eng->queue.front();
     const Layout L = make_layout(p.design.d.n, p.design.d.num_charges, p.design.d.K, p.opts.precision,
-                                 p.opts.save_for_backward != 0);
+                                 p.opts.save_for_backward != 0, true, p.opts.solver);
     size_t off = 0;
     if (!eng->alloc(L.total, off)) break;  // first in line waits for memory
     std::unique_ptr<Slot> s(new Slot());

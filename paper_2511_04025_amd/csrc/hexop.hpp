@@ -26,7 +26,7 @@ namespace shh {
 // diagonal entry is zero (every term carries S along some axis) and no
 // coupling touches it, so h[c][0] is never read and y[c][0] is exactly zero.
 template <typename T, typename KP>
-__device__ __forceinline__ void hex_apply(KP kop, const T (&h)[3][8], T (&y)[3][8], T e) {
+__host__ __device__ __forceinline__ void hex_apply(KP kop, const T (&h)[3][8], T (&y)[3][8], T e) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     y[c][0] = T(0);

@@ -1,0 +1,581 @@
+// Kernels of the geometric multigrid preconditioner (see mg.hpp): setup
+// (Galerkin element matrices, nodal stencils, diagonals, power iteration) and
+// the V-cycle and CG sweeps.  T is the working precision of the slot.
+#include "kernels.hpp"
+#include "mg.hpp"
+
+namespace shh {
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+// Level-1 element matrices: K_E = sum_f E_f G_f over the 8 voxels of coarse
+// element E.  One thread per (element, row).
+template <typename T>
+__global__ __launch_bounds__(256) void mg_elem1_kernel(const SlotDev *s, const MgDev *mg) {
+  const MgLevel &c = mg->lv[1];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= c.nn * 24) return;
+  const long long E = t / 24;
+  const int i = int(t % 24);
+  const int nc = c.n, nf = s->n;
+  const int X = int(E % nc), Y = int((E / nc) % nc), Z = int(E / ((long long)nc * nc));
+  const double *Ef = s->E64;
+  const T *G = (const T *)mg->G;
+  double row[24];
+#pragma unroll
+  for (int j = 0; j < 24; ++j) row[j] = 0.0;
+  for (int f = 0; f < 8; ++f) {
+    const int fx = f & 1, fy = (f >> 1) & 1, fz = f >> 2;
+    const long long fe = ((long long)(2 * Z + fz) * nf + (2 * Y + fy)) * nf + (2 * X + fx);
+    const double e = Ef[fe];
+    const T *g = G + (f * 24 + i) * 24;
+#pragma unroll
+    for (int j = 0; j < 24; ++j) row[j] += e * (double)g[j];
+  }
+  T *K = (T *)c.Ke + E * 576 + i * 24;
+#pragma unroll
+  for (int j = 0; j < 24; ++j) K[j] = (T)row[j];
+}
+
+// Trilinear weight of coarse corner a at fine corner b of child f (per axis:
+// fine position (f + b) / 2 in the coarse element).
+__device__ __forceinline__ double qweight(int f, int b, int a) {
+  double w = 1.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int pos2 = ((f >> d) & 1) + ((b >> d) & 1);  // 0, 1 or 2 halves
+    const int ad = (a >> d) & 1;
+    const double p = 0.5 * pos2;
+    w *= ad ? p : 1.0 - p;
+  }
+  return w;
+}
+
+// Level l + 1 element matrices from level l: K_E = sum_f Q_f^T K_f Q_f.
+// One thread per (coarse element, row i = 3 a + c).
+template <typename T>
+__global__ __launch_bounds__(256) void mg_elemc_kernel(const MgDev *mg, int l) {
+  const MgLevel &fl = mg->lv[l];
+  const MgLevel &cl = mg->lv[l + 1];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cl.nn * 24) return;
+  const long long E = t / 24;
+  const int i = int(t % 24);
+  const int a = i / 3, ci = i % 3;
+  const int nc = cl.n, nf = fl.n;
+  const int X = int(E % nc), Y = int((E / nc) % nc), Z = int(E / ((long long)nc * nc));
+  const T *Kf = (const T *)fl.Ke;
+  double row[24];
+#pragma unroll
+  for (int j = 0; j < 24; ++j) row[j] = 0.0;
+  for (int f = 0; f < 8; ++f) {
+    const int fx = f & 1, fy = (f >> 1) & 1, fz = f >> 2;
+    const long long fe = ((long long)(2 * Z + fz) * nf + (2 * Y + fy)) * nf + (2 * X + fx);
+    const T *K = Kf + fe * 576;
+    // w = Q_f[:, i]^T K_f: rows 3 b' + ci of K_f weighted by q(f, b', a)
+    double w[24];
+#pragma unroll
+    for (int j = 0; j < 24; ++j) w[j] = 0.0;
+    for (int bp = 0; bp < 8; ++bp) {
+      const double q = qweight(f, bp, a);
+      if (q == 0.0) continue;
+      const T *kr = K + (3 * bp + ci) * 24;
+#pragma unroll
+      for (int j = 0; j < 24; ++j) w[j] += q * (double)kr[j];
+    }
+    // row += w Q_f: column 3 a' + c of the result sums w[3 b + c] q(f, b, a')
+    for (int ap = 0; ap < 8; ++ap) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const double q = qweight(f, b, ap);
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) row[3 * ap + cc] += q * w[3 * b + cc];
+      }
+    }
+  }
+  T *out = (T *)cl.Ke + E * 576 + i * 24;
+#pragma unroll
+  for (int j = 0; j < 24; ++j) out[j] = (T)row[j];
+}
+
+// Nodal 27-point stencil of level l from its element matrices, and D^-1.
+// Node v is corner a of element v - a; entry (v, v - a + b) gathers K_e[a][b].
+template <typename T>
+__global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l) {
+  const MgLevel &L = mg->lv[l];
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= L.nn) return;
+  const int n = L.n;
+  const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
+  const T *Ke = (const T *)L.Ke;
+  T *S = (T *)L.S;
+  for (int w = 0; w < 27; ++w)
+    for (int k = 0; k < 9; ++k) S[(w * 9 + k) * L.nn + v] = T(0);
+  double diag[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const long long e = ((long long)wrapi(z - az, n) * n + wrapi(y - ay, n)) * n + wrapi(x - ax, n);
+    const T *K = Ke + e * 576;
+    for (int b = 0; b < 8; ++b) {
+      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+      const int w = ((bz - az + 1) * 3 + (by - ay + 1)) * 3 + (bx - ax + 1);
+      for (int c = 0; c < 3; ++c)
+        for (int cp = 0; cp < 3; ++cp) {
+          const T kv = K[(3 * a + c) * 24 + 3 * b + cp];
+          T *dst = S + (w * 9 + 3 * c + cp) * L.nn + v;
+          *dst = *dst + kv;
+          if (b == a && cp == c) diag[c] += (double)kv;
+        }
+    }
+  }
+  T *Dinv = (T *)L.Dinv;
+  for (int c = 0; c < 3; ++c) Dinv[c * L.nn + v] = diag[c] > 0.0 ? (T)(1.0 / diag[c]) : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// operator, transfer and coarsest solve (levels >= 1)
+// ---------------------------------------------------------------------------
+
+// q = A_l v for all load cases (v = x or d of the level).  One thread per node.
+template <typename T>
+__global__ __launch_bounds__(256) void mg_apply_kernel(const MgDev *mg, int l, int src) {
+  const MgLevel &L = mg->lv[l];
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= L.nn) return;
+  const int n = L.n;
+  const long long nn = L.nn;
+  const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
+  const T *S = (const T *)L.S;
+  const T *in = (const T *)(src == 0 ? L.x : L.d);
+  T acc[NRHS][3];
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = T(0);
+  for (int w = 0; w < 27; ++w) {
+    const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
+    const long long u = ((long long)wrap1(z + dz, n) * n + wrap1(y + dy, n)) * n + wrap1(x + dx, n);
+    T blk[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) blk[k] = S[(w * 9 + k) * nn + v];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) {
+      const T *vr = in + (long long)r * 3 * nn;
+      const T u0 = vr[u], u1 = vr[nn + u], u2 = vr[2 * nn + u];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r][c] += blk[3 * c] * u0 + blk[3 * c + 1] * u1 + blk[3 * c + 2] * u2;
+    }
+  }
+  T *q = (T *)L.q;
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = acc[r][c];
+}
+
+// b_{l+1} = P^T r_l: coarse node I collects fine nodes 2I + o, o in {-1, 0, 1}^3,
+// with weight prod (o == 0 ? 1 : 1/2).
+template <typename T>
+__global__ __launch_bounds__(256) void mg_restrict_kernel(const MgDev *mg, int l) {
+  const MgLevel &F = mg->lv[l];
+  const MgLevel &C = mg->lv[l + 1];
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= C.nn) return;
+  const int nc = C.n, nf = F.n;
+  const int X = int(I % nc), Y = int((I / nc) % nc), Z = int(I / ((long long)nc * nc));
+  const T *r = (const T *)F.r;
+  double acc[NRHS][3];
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[k][c] = 0.0;
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const double w = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
+    const long long i = ((long long)wrap1(2 * Z + oz, nf) * nf + wrap1(2 * Y + oy, nf)) * nf + wrap1(2 * X + ox, nf);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[k][c] += w * (double)r[((long long)k * 3 + c) * F.nn + i];
+  }
+  T *b = (T *)C.b;
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[((long long)k * 3 + c) * C.nn + I] = (T)acc[k][c];
+}
+
+// x_l += P x_{l+1}: per axis an even fine index takes coarse node i / 2, an
+// odd one the mean of its two coarse neighbours.
+template <typename T>
+__global__ __launch_bounds__(256) void mg_prolong_kernel(const MgDev *mg, int l) {
+  const MgLevel &F = mg->lv[l];
+  const MgLevel &C = mg->lv[l + 1];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F.nn) return;
+  const int nf = F.n, nc = C.n;
+  const int x = int(i % nf), y = int((i / nf) % nf), z = int(i / ((long long)nf * nf));
+  int cx[2], cy[2], cz[2];
+  double wx[2], wy[2], wz[2];
+  auto axis = [&](int f, int (&ci)[2], double (&wi)[2]) {
+    ci[0] = f >> 1;
+    ci[1] = wrap1((f >> 1) + 1, nc);
+    if (f & 1) {
+      wi[0] = 0.5;
+      wi[1] = 0.5;
+    } else {
+      wi[0] = 1.0;
+      wi[1] = 0.0;
+    }
+  };
+  axis(x, cx, wx);
+  axis(y, cy, wy);
+  axis(z, cz, wz);
+  const T *xc = (const T *)C.x;
+  double acc[NRHS][3];
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[k][c] = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const double w = wx[a & 1] * wy[(a >> 1) & 1] * wz[a >> 2];
+    if (w == 0.0) continue;
+    const long long I = ((long long)cz[a >> 2] * nc + cy[(a >> 1) & 1]) * nc + cx[a & 1];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[k][c] += w * (double)xc[((long long)k * 3 + c) * C.nn + I];
+  }
+  T *xf = (T *)F.x;
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long j = ((long long)k * 3 + c) * F.nn + i;
+      xf[j] = (T)((double)xf[j] + acc[k][c]);
+    }
+}
+
+// Coarsest level: x = Mc b per load case (one workgroup per load case).
+template <typename T>
+__global__ __launch_bounds__(256) void mg_coarsest_kernel(const MgDev *mg) {
+  const MgLevel &L = mg->lv[mg->L];
+  const int k = blockIdx.x;
+  const int nd = mg->ndof_c;
+  const long long nn = L.nn;
+  const T *M = (const T *)mg->Mc;
+  const T *b = (const T *)L.b + (long long)k * 3 * nn;
+  T *x = (T *)L.x + (long long)k * 3 * nn;
+  for (int row = threadIdx.x; row < nd; row += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < nd; ++j) acc += (double)M[(long long)row * nd + j] * (double)b[(j % 3) * nn + j / 3];
+    x[(row % 3) * nn + row / 3] = (T)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle vector sweeps (any level) and CG sweeps (voxel level)
+// ---------------------------------------------------------------------------
+
+// Chebyshev smoothing steps on A x = b at level l (x starts at 0 in INIT):
+//   INIT:  d = D^-1 b / theta, x = d, r = b
+//   STEP:  r -= q (q = A d), d = c1 d + c2 D^-1 r, x += d
+//   RESID: r -= q            (r = b - A x after the pre-smoother)
+//   POST:  r = b - q (q = A x), d = D^-1 r / theta, x += d
+// STEP_FINAL (voxel level): STEP, then partial sums b . x and b . b for CG.
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, const MgDev *mg, int l, int op) {
+  __shared__ double red[2 * 16];
+  const MgLevel &L = mg->lv[l];
+  const int k = blockIdx.y;
+  const long long nn = L.nn;
+  const long long i0 = (long long)blockIdx.x * CHUNK;
+  const long long i1 = min(i0 + (long long)CHUNK, nn);
+  const T ith = (T)L.inv_theta, c1 = (T)L.c1, c2 = (T)L.c2;
+  const T *b = (const T *)L.b + (long long)k * 3 * nn;
+  T *x = (T *)L.x + (long long)k * 3 * nn;
+  T *r = (T *)L.r + (long long)k * 3 * nn;
+  T *d = (T *)L.d + (long long)k * 3 * nn;
+  const T *q = (const T *)L.q + (long long)k * 3 * nn;
+  const T *Dv = (const T *)L.Dinv;
+  double acc[2] = {0.0, 0.0};
+  for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long j = c * nn + i;
+      const T di = l == 0 ? Dv[i] : Dv[j];
+      if (op == MGV_INIT) {
+        const T bv = b[j];
+        const T dv = di * bv * ith;
+        d[j] = dv;
+        x[j] = dv;
+        r[j] = bv;
+      } else if (op == MGV_STEP || op == MGV_STEP_FINAL) {
+        const T rv = r[j] - q[j];
+        const T dv = c1 * d[j] + c2 * di * rv;
+        const T xv = x[j] + dv;
+        r[j] = rv;
+        d[j] = dv;
+        x[j] = xv;
+        if (op == MGV_STEP_FINAL) {
+          const double bv = (double)b[j];
+          acc[0] += bv * (double)xv;
+          acc[1] += bv * bv;
+        }
+      } else if (op == MGV_RESID) {
+        r[j] = r[j] - q[j];
+      } else {  // MGV_POST
+        const T rv = b[j] - q[j];
+        const T dv = di * rv * ith;
+        r[j] = rv;
+        d[j] = dv;
+        x[j] = x[j] + dv;
+      }
+    }
+  }
+  if (op == MGV_STEP_FINAL) {
+    block_sum<2>(acc, red, VEC_THREADS);
+    if (threadIdx.x == 0) {
+      double *parts = s->partials + ((long long)k * s->maxparts + blockIdx.x) * PSTRIDE;
+      parts[0] = acc[0];
+      parts[1] = acc[1];
+    }
+  }
+}
+
+// CG sweeps at the voxel level: p = p[0], q = q[0], r = r[0], z = r[1].
+//   DOT_PQ:   partial p . q
+//   UPDATE:   x += alpha p, r -= alpha q
+//   P_UPDATE: p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(const SlotDev *s, int op) {
+  __shared__ double red[16];
+  const int k = blockIdx.y;
+  const long long nn = s->nn;
+  const long long i0 = (long long)blockIdx.x * CHUNK;
+  const long long i1 = min(i0 + (long long)CHUNK, nn);
+  const long long vb = (long long)k * 3 * nn;
+  T *p = (T *)s->p[0] + vb;
+  const T *q = (const T *)s->q[0] + vb;
+  T *r = (T *)s->r[0] + vb;
+  const T *z = (const T *)s->r[1] + vb;
+  T *x = (T *)s->x + vb;
+  const CgState *st = s->st;
+  const T a = (T)st->alpha[k], bt = (T)st->beta[k];
+  double acc[1] = {0.0};
+  for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long j = c * nn + i;
+      if (op == MGC_DOT_PQ) {
+        acc[0] += (double)p[j] * (double)q[j];
+      } else if (op == MGC_UPDATE) {
+        if (a != T(0)) {
+          x[j] = x[j] + a * p[j];
+          r[j] = r[j] - a * q[j];
+        }
+      } else {
+        p[j] = z[j] + bt * p[j];
+      }
+    }
+  }
+  if (op == MGC_DOT_PQ) {
+    block_sum<1>(acc, red, VEC_THREADS);
+    if (threadIdx.x == 0) s->partials[((long long)k * s->maxparts + blockIdx.x) * PSTRIDE] = acc[0];
+  }
+}
+
+// CG scalars of the multigrid-preconditioned solve (one workgroup per load
+// case; partials over the voxel-level chunks).
+//   RESTART: rho = r . z after a (re)started V-cycle, beta = 0
+//   ALPHA:   alpha = rho / p . K p
+//   BETA:    rho' = r . z, ||r||^2 -> convergence; beta = rho' / rho
+__global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(SlotDev *s, int phase) {
+  __shared__ double red[2 * 16];
+  const int k = blockIdx.x;
+  CgState *st = s->st;
+  const double *parts = s->partials + (long long)k * s->maxparts * PSTRIDE;
+  double tot[2];
+  sum_partials<2, PSTRIDE>(parts, s->nchunks, tot, red, VEC_THREADS);
+  if (threadIdx.x != 0) return;
+  if (!st->active[k]) {
+    st->alpha[k] = 0.0;
+    st->beta[k] = 0.0;
+    return;
+  }
+  if (phase == MGS_RESTART) {
+    const double rho = tot[0];
+    st->rho[k] = rho;
+    st->beta[k] = 0.0;
+    st->alpha[k] = 0.0;
+    if (!(rho > 0.0) || !isfinite(rho)) {
+      st->status[k] = ST_BREAKDOWN;
+      st->active[k] = 0;
+    }
+  } else if (phase == MGS_ALPHA) {
+    const double sigma = tot[0], rho = st->rho[k];
+    const bool ok = isfinite(sigma) && sigma > 0.0 && rho > 0.0;
+    st->alpha[k] = ok ? rho / sigma : 0.0;
+    if (!ok) {
+      st->status[k] = ST_BREAKDOWN;
+      st->active[k] = 0;
+    }
+  } else {
+    const double rho_n = tot[0], rr = tot[1];
+    st->iters[k] += 1;
+    st->alpha[k] = 0.0;
+    st->rr[k] = rr;
+    const double rel = sqrt(rr / st->ff[k]);
+    st->rel[k] = rel;
+    const double rho = st->rho[k];
+    const bool ok = isfinite(rho_n) && rho_n >= 0.0;
+    st->beta[k] = ok && rho > 0.0 ? rho_n / rho : 0.0;
+    st->rho[k] = rho_n;
+    if (rel <= s->rtol) {
+      st->status[k] = ST_CONVERGED;
+      st->active[k] = 0;
+    } else if (!ok || !isfinite(rel)) {
+      st->status[k] = ST_BREAKDOWN;
+      st->active[k] = 0;
+    } else if (st->iters[k] >= s->max_iter) {
+      st->status[k] = ST_MAXIT;
+      st->active[k] = 0;
+    }
+  }
+}
+
+// Power iteration for lambda_max(D^-1 A) at level l, on load case 0 of x:
+//   phase 0: x = a fixed pseudo-random vector
+//   phase 1: partial x.q and x.D x (the Rayleigh quotient x.A x / x.D x of
+//            D^-1 A, self-adjoint in the D inner product), then x = D^-1 q
+//            (q = A x) and partial ||x||^2
+//   phase 2: x *= scale
+template <typename T>
+__global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s, const MgDev *mg, int l, int phase,
+                                                             double scale) {
+  __shared__ double red[3 * 16];
+  const MgLevel &L = mg->lv[l];
+  const long long nn = L.nn;
+  const long long i0 = (long long)blockIdx.x * CHUNK;
+  const long long i1 = min(i0 + (long long)CHUNK, nn);
+  T *x = (T *)L.x;
+  const T *q = (const T *)L.q;
+  const T *Dv = (const T *)L.Dinv;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long j = c * nn + i;
+      if (phase == 0) {
+        uint32_t h = (uint32_t)j * 2654435761u + 0x9e3779b9u;
+        h ^= h >> 16;
+        h *= 0x85ebca6bu;
+        h ^= h >> 13;
+        x[j] = (T)((double)(h & 0xffffff) / 16777216.0 - 0.5);
+      } else if (phase == 1) {
+        const T di = l == 0 ? Dv[i] : Dv[j];
+        const double xo = (double)x[j], qo = (double)q[j];
+        acc[1] += xo * qo;
+        acc[2] += di != T(0) ? xo * xo / (double)di : 0.0;
+        const T v = di * q[j];
+        x[j] = v;
+        acc[0] += (double)v * (double)v;
+      } else {
+        x[j] = (T)((double)x[j] * scale);
+      }
+    }
+  }
+  if (phase == 1) {
+    block_sum<3>(acc, red, VEC_THREADS);
+    if (threadIdx.x == 0) {
+      s->partials[blockIdx.x * PSTRIDE] = acc[0];
+      s->partials[blockIdx.x * PSTRIDE + 1] = acc[1];
+      s->partials[blockIdx.x * PSTRIDE + 2] = acc[2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static unsigned blocks_for(long long count, int per) { return (unsigned)((count + per - 1) / per); }
+
+hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long nn1, int prec, hipStream_t st) {
+  const unsigned g = blocks_for(nn1 * 24, 256);
+  if (prec == 0) mg_elem1_kernel<double><<<g, 256, 0, st>>>(d_slot, d_mg);
+  else mg_elem1_kernel<float><<<g, 256, 0, st>>>(d_slot, d_mg);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st) {
+  const unsigned g = blocks_for(nn_next * 24, 256);
+  if (prec == 0) mg_elemc_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
+  else mg_elemc_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st) {
+  const unsigned g = blocks_for(nn, 256);
+  if (prec == 0) mg_stencil_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
+  else mg_stencil_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_apply(const MgDev *d_mg, int l, int src, long long nn, int prec, hipStream_t st) {
+  const unsigned g = blocks_for(nn, 256);
+  if (prec == 0) mg_apply_kernel<double><<<g, 256, 0, st>>>(d_mg, l, src);
+  else mg_apply_kernel<float><<<g, 256, 0, st>>>(d_mg, l, src);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_restrict(const MgDev *d_mg, int l, long long nn_coarse, int prec, hipStream_t st) {
+  const unsigned g = blocks_for(nn_coarse, 256);
+  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
+  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_prolong(const MgDev *d_mg, int l, long long nn_fine, int prec, hipStream_t st) {
+  const unsigned g = blocks_for(nn_fine, 256);
+  if (prec == 0) mg_prolong_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
+  else mg_prolong_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_coarsest(const MgDev *d_mg, int prec, hipStream_t st) {
+  if (prec == 0) mg_coarsest_kernel<double><<<NRHS, 256, 0, st>>>(d_mg);
+  else mg_coarsest_kernel<float><<<NRHS, 256, 0, st>>>(d_mg);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_vec(const SlotDev *d_slot, const MgDev *d_mg, int l, int op, int nchunks, int prec,
+                         hipStream_t st) {
+  const dim3 g((unsigned)nchunks, NRHS);
+  if (prec == 0) mg_vec_kernel<double><<<g, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, op);
+  else mg_vec_kernel<float><<<g, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, op);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_cg(const SlotDev *d_slot, int op, int nchunks, int prec, hipStream_t st) {
+  const dim3 g((unsigned)nchunks, NRHS);
+  if (prec == 0) mg_cg_kernel<double><<<g, VEC_THREADS, 0, st>>>(d_slot, op);
+  else mg_cg_kernel<float><<<g, VEC_THREADS, 0, st>>>(d_slot, op);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_scalar(SlotDev *d_slot, int phase, hipStream_t st) {
+  mg_scalar_kernel<<<NRHS, VEC_THREADS, 0, st>>>(d_slot, phase);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_power(const SlotDev *d_slot, const MgDev *d_mg, int l, int phase, double scale, int nchunks,
+                           int prec, hipStream_t st) {
+  if (prec == 0) mg_power_kernel<double><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase, scale);
+  else mg_power_kernel<float><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase, scale);
+  return hipGetLastError();
+}
+
+}  // namespace shh

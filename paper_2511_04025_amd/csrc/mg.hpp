@@ -1,0 +1,70 @@
+// Geometric multigrid preconditioner for the periodic voxel elasticity system
+// (the solver family of Sec. 4.2, here as a V-cycle inside CG).
+//
+// Levels: level 0 is the voxel grid (matrix-free operator of the stencil
+// kernel); level l + 1 halves every axis of level l while it is even.  Coarse
+// operators are Galerkin products A_{l+1} = P^T A_l P with trilinear periodic
+// prolongation P.  Because P restricted to one coarse element is the
+// trilinear interpolation inside it, the product is element-local: a coarse
+// element matrix is the sum over its 8 children f of Q_f^T K_f Q_f (Q_f maps
+// the coarse element's 8 corner values to child f's corners), and on level 1
+// K_f = E_f K_0, so K_E = sum_f E_f G_f with G_f = Q_f^T K_0 Q_f.  Coarse
+// element matrices are assembled into 27-point nodal stencils of 3 x 3 blocks
+// for the smoother and residual sweeps.  Smoothing is Chebyshev (degree 2)
+// on D^-1 A over [lambda_max / 30, 1.1 lambda_max], lambda_max estimated by
+// power iteration; the coarsest level (at most 8^3 nodes) is solved with a
+// dense inverse of its operator made nonsingular on the three rigid
+// translations.
+#pragma once
+
+#include "common.hpp"
+
+namespace shh {
+
+constexpr int MG_MAXL = 10;          // levels including the voxel grid
+constexpr int MG_MAX_COARSE = 8;     // coarsest grid at most 8^3 nodes
+constexpr int MG_STENCIL = 27 * 9;   // values of one node's 27-point 3 x 3-block stencil
+
+struct MgLevel {
+  int n;
+  int nchunks;          // CHUNK-node chunks of the level (vector kernels)
+  long long nn;
+  // levels >= 1: nodal stencil [27 * 9][nn] (entry (w, c, c') at (w * 9 + 3 c + c') * nn),
+  // inverse diagonal [3][nn]; level 0 uses the slot's matrix-free operator and D^-1 [nn]
+  void *S, *Dinv;
+  // V-cycle vectors [NRHS][3][nn]: right-hand side, iterate, residual,
+  // Chebyshev direction, operator output.  Level 0 aliases the slot's CG
+  // vectors (b = r[0], x = r[1] (z), r = q[1], d = p[1], q = q[0]).
+  void *b, *x, *r, *d, *q;
+  void *Ke;             // setup only: element matrices [nn][24][24] (levels >= 1)
+  double inv_theta, c1, c2;  // Chebyshev coefficients
+  double lmax;
+};
+
+struct MgDev {
+  int L;                // index of the coarsest level
+  int ndof_c;           // 3 n_L^3
+  void *G;              // [8][24][24] child Galerkin matrices of K_0 (T)
+  void *Mc;             // [ndof_c][ndof_c] coarsest inverse (T), dof 3 node + c
+  MgLevel lv[MG_MAXL];
+};
+
+// V-cycle vector operations at one level (grid: chunks x NRHS)
+enum { MGV_INIT = 0, MGV_STEP = 1, MGV_RESID = 2, MGV_POST = 3, MGV_STEP_FINAL = 4 };
+// CG operations at the voxel level
+enum { MGC_DOT_PQ = 0, MGC_UPDATE = 1, MGC_P_UPDATE = 2 };
+// CG scalar phases
+enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2 };
+
+// Number of levels for an n^3 grid (coarsening while even and >= 4), or 0 when
+// the coarsest grid would exceed MG_MAX_COARSE.
+inline int mg_num_levels(int n) {
+  int L = 1;
+  while (n % 2 == 0 && n >= 4 && L < MG_MAXL) {
+    n /= 2;
+    ++L;
+  }
+  return n <= MG_MAX_COARSE ? L : 0;
+}
+
+}  // namespace shh

@@ -1,0 +1,408 @@
+// Host side of the multigrid-preconditioned CG (see mg.hpp): memory carving,
+// setup (Galerkin hierarchy, coarsest inverse, Chebyshev bounds) and the
+// V-cycle / CG launch sequence of one iteration.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "hexop.hpp"
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+namespace shh {
+
+#define SHH_HIP(call)                                \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return SHH_HIP_ERROR;      \
+  } while (0)
+
+hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long nn1, int prec, hipStream_t st);
+hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st);
+hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
+hipError_t mg_launch_apply(const MgDev *d_mg, int l, int src, long long nn, int prec, hipStream_t st);
+hipError_t mg_launch_restrict(const MgDev *d_mg, int l, long long nn_coarse, int prec, hipStream_t st);
+hipError_t mg_launch_prolong(const MgDev *d_mg, int l, long long nn_fine, int prec, hipStream_t st);
+hipError_t mg_launch_coarsest(const MgDev *d_mg, int prec, hipStream_t st);
+hipError_t mg_launch_vec(const SlotDev *d_slot, const MgDev *d_mg, int l, int op, int nchunks, int prec,
+                         hipStream_t st);
+hipError_t mg_launch_cg(const SlotDev *d_slot, int op, int nchunks, int prec, hipStream_t st);
+hipError_t mg_launch_scalar(SlotDev *d_slot, int phase, hipStream_t st);
+hipError_t mg_launch_power(const SlotDev *d_slot, const MgDev *d_mg, int l, int phase, double scale, int nchunks,
+                           int prec, hipStream_t st);
+
+namespace {
+
+size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+
+constexpr int SEG_PQ = 0, SEG_ZQ = 1, SEG_DQ = 2, SEG_POW = 3, NSEG = 4;
+constexpr int POWER_ITERS = 30;  // power steps per level
+
+// Lay out the multigrid region at `base` (nullptr: sizing only).  Fills the
+// level-1.. descriptors' persistent buffers, G, Mc and the segment table.
+size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mgdev) {
+  const size_t ts = prec == SHH_PREC_FP64 ? 8 : 4;
+  const int count = mg_num_levels(n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = a256(off + bytes);
+    return base ? base + o : nullptr;
+  };
+  char *dev = take(sizeof(MgDev));
+  char *sg = take(NSEG * sizeof(Segment));
+  char *G = take(8 * 576 * ts);
+  if (mg) {
+    mg->L = count - 1;
+    mg->G = G;
+  }
+  if (d_mgdev) *d_mgdev = dev;
+  if (segs) *segs = (Segment *)sg;
+  long long nl = n;
+  for (int l = 1; l < count; ++l) {
+    nl /= 2;
+    const long long nn = nl * nl * nl;
+    char *S = take(MG_STENCIL * nn * ts);
+    char *D = take(3 * nn * ts);
+    char *v[5];
+    for (int k = 0; k < 5; ++k) v[k] = take((size_t)NRHS * 3 * nn * ts);
+    if (mg) {
+      MgLevel &L = mg->lv[l];
+      L.n = int(nl);
+      L.nn = nn;
+      L.nchunks = int((nn + CHUNK - 1) / CHUNK);
+      L.S = S;
+      L.Dinv = D;
+      L.b = v[0];
+      L.x = v[1];
+      L.r = v[2];
+      L.d = v[3];
+      L.q = v[4];
+    }
+  }
+  const long long nc = nl * nl * nl;
+  char *Mc = take((size_t)(3 * nc) * (3 * nc) * ts);
+  if (mg) {
+    mg->ndof_c = int(3 * nc);
+    mg->Mc = Mc;
+  }
+  return off;
+}
+
+// Dense K_0 (DOF 3 a + c, corner a = ax + 2 ay + 4 az) of the factored operator:
+// K_0 v = H^T hex_apply(H v) with H[m][a] = prod_axis (m bit ? 2 a bit - 1 : 1).
+void dense_k0(const double kop[KOP_N], double K0[24][24]) {
+  auto H = [](int m, int a) {
+    int s = 1;
+    for (int d = 0; d < 3; ++d)
+      if ((m >> d) & 1) s *= ((a >> d) & 1) ? 1 : -1;
+    return double(s);
+  };
+  for (int j = 0; j < 24; ++j) {
+    double h[3][8] = {}, y[3][8] = {};
+    const int aj = j / 3, cj = j % 3;
+    for (int m = 0; m < 8; ++m) h[cj][m] = H(m, aj);
+    hex_apply<double>(kop, h, y, 1.0);
+    for (int a = 0; a < 8; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double v = 0.0;
+        for (int m = 0; m < 8; ++m) v += H(m, a) * y[c][m];
+        K0[3 * a + c][j] = v;
+      }
+  }
+}
+
+double qweight(int f, int b, int a) {
+  double w = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    const double p = 0.5 * (((f >> d) & 1) + ((b >> d) & 1));
+    w *= ((a >> d) & 1) ? p : 1.0 - p;
+  }
+  return w;
+}
+
+// G_f = Q_f^T K_0 Q_f for the 8 children f of a coarse element.
+void child_galerkin(const double K0[24][24], std::vector<double> &G) {
+  G.assign(8 * 576, 0.0);
+  for (int f = 0; f < 8; ++f) {
+    double Q[24][24] = {};
+    for (int b = 0; b < 8; ++b)
+      for (int a = 0; a < 8; ++a)
+        for (int c = 0; c < 3; ++c) Q[3 * b + c][3 * a + c] = qweight(f, b, a);
+    double T[24][24] = {};
+    for (int i = 0; i < 24; ++i)
+      for (int k = 0; k < 24; ++k) {
+        double v = 0.0;
+        for (int j = 0; j < 24; ++j) v += K0[i][j] * Q[j][k];
+        T[i][k] = v;
+      }
+    for (int i = 0; i < 24; ++i)
+      for (int k = 0; k < 24; ++k) {
+        double v = 0.0;
+        for (int j = 0; j < 24; ++j) v += Q[j][i] * T[j][k];
+        G[(f * 24 + i) * 24 + k] = v;
+      }
+  }
+}
+
+// In-place inverse of a dense SPD-made matrix (Gauss-Jordan, partial pivoting).
+bool invert(std::vector<double> &A, int m) {
+  std::vector<double> I((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[(size_t)r * m + c]) > std::fabs(A[(size_t)piv * m + c])) piv = r;
+    if (!(std::fabs(A[(size_t)piv * m + c]) > 0.0)) return false;
+    if (piv != c)
+      for (int k = 0; k < m; ++k) {
+        std::swap(A[(size_t)c * m + k], A[(size_t)piv * m + k]);
+        std::swap(I[(size_t)c * m + k], I[(size_t)piv * m + k]);
+      }
+    const double inv = 1.0 / A[(size_t)c * m + c];
+    for (int k = 0; k < m; ++k) {
+      A[(size_t)c * m + k] *= inv;
+      I[(size_t)c * m + k] *= inv;
+    }
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * m + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < m; ++k) {
+        A[(size_t)r * m + k] -= f * A[(size_t)c * m + k];
+        I[(size_t)r * m + k] -= f * I[(size_t)c * m + k];
+      }
+    }
+  }
+  A.swap(I);
+  return true;
+}
+
+template <typename T>
+int upload_as(const std::vector<double> &src, void *dst, hipStream_t st) {
+  std::vector<T> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+  SHH_HIP(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+int upload(const std::vector<double> &src, void *dst, int prec, hipStream_t st) {
+  return prec == SHH_PREC_FP64 ? upload_as<double>(src, dst, st) : upload_as<float>(src, dst, st);
+}
+
+// Dense operator of the coarsest level from its nodal stencil, made
+// nonsingular on the rigid translations (+ gamma / nn on each component's
+// constant block), inverted on the host.
+int coarsest_inverse(Slot &s, hipStream_t st) {
+  MgDev &mg = s.mg;
+  const MgLevel &L = mg.lv[mg.L];
+  const int prec = s.host.prec;
+  const long long nn = L.nn;
+  const int n = L.n, m = mg.ndof_c;
+  const size_t cnt = (size_t)MG_STENCIL * nn;
+  std::vector<double> S(cnt);
+  if (prec == SHH_PREC_FP64) {
+    SHH_HIP(hipMemcpyAsync(S.data(), L.S, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+    SHH_HIP(hipStreamSynchronize(st));
+  } else {
+    std::vector<float> Sf(cnt);
+    SHH_HIP(hipMemcpyAsync(Sf.data(), L.S, cnt * sizeof(float), hipMemcpyDeviceToHost, st));
+    SHH_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < cnt; ++i) S[i] = Sf[i];
+  }
+  std::vector<double> A((size_t)m * m, 0.0);
+  double dsum = 0.0;
+  for (long long v = 0; v < nn; ++v) {
+    const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
+    for (int w = 0; w < 27; ++w) {
+      const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
+      const long long u = ((long long)((z + dz + n) % n) * n + (y + dy + n) % n) * n + (x + dx + n) % n;
+      for (int c = 0; c < 3; ++c)
+        for (int cp = 0; cp < 3; ++cp)
+          A[(size_t)(3 * v + c) * m + 3 * u + cp] += S[(size_t)(w * 9 + 3 * c + cp) * nn + v];
+    }
+  }
+  for (int i = 0; i < m; ++i) dsum += A[(size_t)i * m + i];
+  const double gamma = dsum / m / double(nn);
+  for (long long v = 0; v < nn; ++v)
+    for (long long u = 0; u < nn; ++u)
+      for (int c = 0; c < 3; ++c) A[(size_t)(3 * v + c) * m + 3 * u + c] += gamma;
+  if (!invert(A, m)) return SHH_BREAKDOWN;
+  return upload(A, mg.Mc, prec, st);
+}
+
+int apply(Slot &s, int l, int src, hipStream_t st) {
+  const int prec = s.host.prec;
+  if (l == 0) {
+    const int seg = src == 0 ? SEG_ZQ : SEG_DQ;
+    const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
+    LaunchArgs la{s.d_mgsegs + seg, 1, s.host.ntiles[tiling] * NRHS};
+    SHH_HIP(launch_stencil_apply(la, prec, st));
+    return SHH_OK;
+  }
+  SHH_HIP(mg_launch_apply(s.d_mg, l, src, s.mg.lv[l].nn, prec, st));
+  return SHH_OK;
+}
+
+int vcycle(Slot &s, int l, hipStream_t st) {
+  const int prec = s.host.prec;
+  const MgLevel &L = s.mg.lv[l];
+  if (l == s.mg.L) {
+    SHH_HIP(mg_launch_coarsest(s.d_mg, prec, st));
+    return SHH_OK;
+  }
+  auto vec = [&](int op) { return mg_launch_vec(s.d_slot, s.d_mg, l, op, L.nchunks, prec, st); };
+  int rc;
+  SHH_HIP(vec(MGV_INIT));
+  if ((rc = apply(s, l, 1, st))) return rc;
+  SHH_HIP(vec(MGV_STEP));
+  if ((rc = apply(s, l, 1, st))) return rc;
+  SHH_HIP(vec(MGV_RESID));
+  SHH_HIP(mg_launch_restrict(s.d_mg, l, s.mg.lv[l + 1].nn, prec, st));
+  if ((rc = vcycle(s, l + 1, st))) return rc;
+  SHH_HIP(mg_launch_prolong(s.d_mg, l, L.nn, prec, st));
+  if ((rc = apply(s, l, 0, st))) return rc;
+  SHH_HIP(vec(MGV_POST));
+  if ((rc = apply(s, l, 1, st))) return rc;
+  SHH_HIP(vec(l == 0 ? MGV_STEP_FINAL : MGV_STEP));
+  return SHH_OK;
+}
+
+}  // namespace
+
+size_t mg_region_bytes(int n, int prec) {
+  if (mg_num_levels(n) < 2) return 0;
+  return carve(nullptr, n, prec, nullptr, nullptr, nullptr);
+}
+
+int mg_setup(Slot &s, hipStream_t st) {
+  SlotDev &h = s.host;
+  const int n = h.n, prec = h.prec;
+  const int count = mg_num_levels(n);
+  if (count < 2 || s.lay.mg == 0 || !s.lay.vectors) return SHH_UNSUPPORTED;
+  const size_t ts = prec == SHH_PREC_FP64 ? 8 : 4;
+  std::memset(&s.mg, 0, sizeof(s.mg));
+  char *dev = nullptr;
+  carve(s.base + s.lay.mg, n, prec, &s.mg, &s.d_mgsegs, &dev);
+  s.d_mg = (MgDev *)dev;
+  MgDev &mg = s.mg;
+  MgLevel &L0 = mg.lv[0];
+  L0.n = n;
+  L0.nn = h.nn;
+  L0.nchunks = h.nchunks;
+  L0.Dinv = h.Dinv;
+  L0.b = h.r[0];
+  L0.x = h.r[1];
+  L0.r = h.q[1];
+  L0.d = h.p[1];
+  L0.q = h.q[0];
+  // element matrices of levels >= 1 live in the (not yet used) CG vector region
+  {
+    char *ke = s.base + s.lay.vec;
+    size_t used = 0;
+    for (int l = 1; l < count; ++l) {
+      mg.lv[l].Ke = ke + used;
+      used = a256(used + (size_t)mg.lv[l].nn * 576 * ts);
+    }
+    if (used > 7 * s.lay.vec_bytes) return SHH_WORKSPACE_TOO_SMALL;
+  }
+  // child Galerkin matrices of this Poisson ratio's K_0
+  double K0[24][24];
+  dense_k0(h.kop64, K0);
+  std::vector<double> G;
+  child_galerkin(K0, G);
+  int rc;
+  if ((rc = upload(G, mg.G, prec, st))) return rc;
+  SHH_HIP(hipMemcpyAsync(s.d_mg, &mg, sizeof(MgDev), hipMemcpyHostToDevice, st));
+  SHH_HIP(mg_launch_elem1(s.d_slot, s.d_mg, mg.lv[1].nn, prec, st));
+  for (int l = 1; l + 1 < count; ++l) SHH_HIP(mg_launch_elemc(s.d_mg, l, mg.lv[l + 1].nn, prec, st));
+  for (int l = 1; l < count; ++l) SHH_HIP(mg_launch_stencil(s.d_mg, l, mg.lv[l].nn, prec, st));
+  if ((rc = coarsest_inverse(s, st))) return rc;
+  // voxel-level operator launches: flag 0 is p[0] -> q[0], else 1 + src + 8 dst
+  // over (r0, r1, p0, p1, q0, q1, x)
+  Segment sg[NSEG];
+  std::memset(sg, 0, sizeof(sg));
+  const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
+  const int flags[NSEG] = {0, 1 + 1 + 8 * 4, 1 + 3 + 8 * 4, 1 + 1 + 8 * 4};
+  for (int k = 0; k < NSEG; ++k) {
+    sg[k].slot = s.d_slot;
+    sg[k].first = 0;
+    sg[k].nrhs = k == SEG_POW ? 1 : NRHS;
+    for (int r = 0; r < sg[k].nrhs; ++r) sg[k].rhs[r] = r;
+    sg[k].nblocks = h.ntiles[tiling] * sg[k].nrhs;
+    sg[k].flag = flags[k];
+  }
+  SHH_HIP(hipMemcpyAsync(s.d_mgsegs, sg, sizeof(sg), hipMemcpyHostToDevice, st));
+  // lambda_max(D^-1 A) of every smoothing level by power iteration on load case 0
+  std::vector<double> parts;
+  for (int l = 0; l < mg.L; ++l) {
+    const MgLevel &L = mg.lv[l];
+    SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 0, 1.0, L.nchunks, prec, st));
+    parts.resize((size_t)L.nchunks * PSTRIDE);
+    double lam = 0.0;
+    for (int it = 0; it < POWER_ITERS; ++it) {
+      if (l == 0) {
+        LaunchArgs la{s.d_mgsegs + SEG_POW, 1, h.ntiles[tiling]};
+        SHH_HIP(launch_stencil_apply(la, prec, st));
+      } else {
+        SHH_HIP(mg_launch_apply(s.d_mg, l, 0, L.nn, prec, st));
+      }
+      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 1, 1.0, L.nchunks, prec, st));
+      SHH_HIP(hipMemcpyAsync(parts.data(), h.partials, parts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      SHH_HIP(hipStreamSynchronize(st));
+      double sum = 0.0, xax = 0.0, xdx = 0.0;
+      for (int c = 0; c < L.nchunks; ++c) {
+        sum += parts[(size_t)c * PSTRIDE];
+        xax += parts[(size_t)c * PSTRIDE + 1];
+        xdx += parts[(size_t)c * PSTRIDE + 2];
+      }
+      const double nrm = std::sqrt(sum);
+      if (!(nrm > 0.0) || !std::isfinite(nrm) || !(xdx > 0.0)) return SHH_BREAKDOWN;
+      // the Rayleigh quotient is a lower bound of lambda_max that converges
+      // twice as fast as the norm ratio
+      lam = std::max(lam, xax / xdx);
+      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 2, 1.0 / nrm, L.nchunks, prec, st));
+    }
+    MgLevel &W = mg.lv[l];
+    W.lmax = lam;
+    if (std::getenv("SHH_MG_VERBOSE"))
+      std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f\n", n, l, W.n, lam);
+    const double hi = 1.1 * lam, lo = lam / 30.0;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    W.inv_theta = 1.0 / theta;
+    W.c1 = rho1 * rho0;
+    W.c2 = 2.0 * rho1 / delta;
+  }
+  SHH_HIP(hipMemcpyAsync(s.d_mg, &mg, sizeof(MgDev), hipMemcpyHostToDevice, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  s.mg_restart = true;
+  return SHH_OK;
+}
+
+int mg_iteration(Slot &s, hipStream_t st) {
+  const int prec = s.host.prec;
+  const int nch = s.host.nchunks;
+  int rc;
+  if (s.mg_restart) {
+    if ((rc = vcycle(s, 0, st))) return rc;
+    SHH_HIP(mg_launch_scalar(s.d_slot, MGS_RESTART, st));
+    SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));  // beta = 0: p = z
+    s.mg_restart = false;
+  }
+  const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
+  LaunchArgs la{s.d_mgsegs + SEG_PQ, 1, s.host.ntiles[tiling] * NRHS};
+  SHH_HIP(launch_stencil_apply(la, prec, st));
+  SHH_HIP(mg_launch_cg(s.d_slot, MGC_DOT_PQ, nch, prec, st));
+  SHH_HIP(mg_launch_scalar(s.d_slot, MGS_ALPHA, st));
+  SHH_HIP(mg_launch_cg(s.d_slot, MGC_UPDATE, nch, prec, st));
+  if ((rc = vcycle(s, 0, st))) return rc;
+  SHH_HIP(mg_launch_scalar(s.d_slot, MGS_BETA, st));
+  SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));
+  return SHH_OK;
+}
+
+}  // namespace shh

@@ -86,6 +86,7 @@ int normalize_opts(const shh_opts *in, shh_opts *out) {
   if (out->precision != SHH_PREC_FP64 && out->precision != SHH_PREC_MIXED) return SHH_INVALID_ARG;
   if (!(out->rtol > 0.0 && out->rtol < 1.0)) return SHH_INVALID_ARG;
   if (out->max_iter < 0 || out->recompute_every < 0 || out->check_every < 0) return SHH_INVALID_ARG;
+  if (out->solver != SHH_SOLVER_JACOBI && out->solver != SHH_SOLVER_MG) return SHH_INVALID_ARG;
   if (out->recompute_every == 0 && out->precision == SHH_PREC_MIXED) out->recompute_every = 50;
   if (out->check_every == 0) out->check_every = 16;
   return SHH_OK;
@@ -99,7 +100,7 @@ static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // z planes per stencil workgroup (the z-march length)
 static int tz_for(int n) { return n < SHH_TZ ? n : SHH_TZ; }
 
-Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors) {
+Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors, int solver) {
   Layout L{};
   L.vectors = vectors;
   const long long nn = (long long)n * n * n;
@@ -135,6 +136,7 @@ Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors) {
   L.vec_bytes = align256(ts * NRHS * 3 * nn);
   L.vec = take(7 * L.vec_bytes);  // r[2], p[2], q[2], x
   L.field = save ? take(sizeof(double) * 5 * nn) : L.vec;  // F, G[3], d (aliased unless saved)
+  if (solver == SHH_SOLVER_MG) L.mg = take(mg_region_bytes(n, prec));
   L.total = off;
   return L;
 }
@@ -369,6 +371,8 @@ int Solver::residual(const std::vector<Slot *> &slots, int mode) {
   if ((rc = build(K_FINISH, slots, mode, all, la))) return rc;
   SHH_HIP(launch_finish_resid(la, prec, st_));
   SHH_HIP(launch_scalar(ls, PH_RESID, st_));
+  // a multigrid-preconditioned CG restarts from the new residual
+  for (Slot *s : slots) s->mg_restart = true;
   return SHH_OK;
 }
 
@@ -377,6 +381,9 @@ int Solver::start(const std::vector<Slot *> &slots) {
   const int prec = slots[0]->host.prec;
   LaunchArgs la;
   int rc;
+  // multigrid hierarchies first: their setup borrows the CG vector region
+  for (Slot *s : slots)
+    if (s->opts.solver == SHH_SOLVER_MG && (rc = mg_setup(*s, st_))) return rc;
   if ((rc = build(K_ZERO, slots, 0, true, la))) return rc;
   SHH_HIP(launch_zero_vectors(la, prec, st_));
   for (Slot *s : slots) SHH_HIP(hipEventRecord(s->ev[1], st_));
@@ -416,11 +423,15 @@ void Solver::resolve_events() {
   ev_pending_.clear();
 }
 
-int Solver::iterate(const std::vector<Slot *> &slots, int iters) {
+int Solver::iterate(const std::vector<Slot *> &all, int iters) {
+  if (all.empty()) return SHH_OK;
+  std::vector<Slot *> slots, mgs;
+  for (Slot *s : all) (s->opts.solver == SHH_SOLVER_MG ? mgs : slots).push_back(s);
+  int rc;
+  if (!mgs.empty() && (rc = iterate_mg(mgs, iters))) return rc;
   if (slots.empty()) return SHH_OK;
   const int prec = slots[0]->host.prec;
   LaunchArgs la_s;
-  int rc;
   if ((rc = build(K_STENCIL, slots, 0, false, la_s))) return rc;
   const bool prof = profile_on();
   LaunchArgs la_c;
@@ -446,6 +457,32 @@ int Solver::iterate(const std::vector<Slot *> &slots, int iters) {
     if (!due.empty()) {
       if ((rc = residual(due, RES_RECOMPUTE))) return rc;
     }
+  }
+  return SHH_OK;
+}
+
+// Multigrid-preconditioned CG: one launch sequence per slot and iteration.
+int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
+  int rc;
+  const bool prof = profile_on();
+  for (int it = 0; it < iters; ++it) {
+    std::vector<Slot *> due;
+    for (Slot *s : slots) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof) {
+        e0 = get_event();
+        e1 = get_event();
+        if (e0) SHH_HIP(hipEventRecord(e0, st_));
+      }
+      if ((rc = mg_iteration(*s, st_))) return rc;
+      if (e0 && e1) {
+        SHH_HIP(hipEventRecord(e1, st_));
+        ev_pending_.emplace_back(e0, e1);
+      }
+      s->launched += 1;
+      if (s->R > 0 && s->launched % s->R == 0) due.push_back(s);
+    }
+    if (!due.empty() && (rc = residual(due, RES_RECOMPUTE))) return rc;
   }
   return SHH_OK;
 }

@@ -11,6 +11,7 @@
 
 #include "shellhom.h"
 #include "common.hpp"
+#include "mg.hpp"
 
 namespace shh {
 
@@ -19,6 +20,7 @@ struct Layout {
   size_t slotdev, state, charges, alpha, coef, partials, segs;
   size_t E64, E32, Dinv, x64, vec, field;
   size_t vec_bytes;   // one [6][3][n^3] vector
+  size_t mg;          // multigrid region (0 bytes unless the multigrid solver is used)
   size_t total;
   int maxparts;
   bool vectors;       // false: operator-only slot (no CG vectors, no field arrays)
@@ -47,11 +49,23 @@ struct Slot {
   double t_arrive_ms = 0.0;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double ms[5] = {0, 0, 0, 0, 0};
+  // multigrid solver (opts.solver == SHH_SOLVER_MG)
+  MgDev mg;                     // host image of the level descriptors
+  MgDev *d_mg = nullptr;
+  Segment *d_mgsegs = nullptr;  // voxel-level operator launches: p->q, z->q, d->q, power
+  bool mg_restart = false;      // next iteration starts from z = V r, p = z
 };
 
 int validate_design(const shh_design *d);
 int normalize_opts(const shh_opts *in, shh_opts *out);
-Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors = true);
+Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors = true, int solver = 0);
+// bytes of the multigrid region of an n^3 slot (levels >= 1, coarsest inverse, descriptors)
+size_t mg_region_bytes(int n, int prec);
+// multigrid setup of a slot whose moduli and D^-1 are in place (before the CG
+// vectors are zeroed: the element matrices use the vector region as scratch)
+int mg_setup(Slot &s, hipStream_t st);
+// one multigrid-preconditioned CG iteration of every load case of the slot
+int mg_iteration(Slot &s, hipStream_t st);
 void copy_design(const shh_design *src, DesignCopy &dst);
 
 // Fill the slot descriptor for a region and upload it (+ charges, alpha, zeroed state).
@@ -80,6 +94,7 @@ class Solver {
  private:
   enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_NKIND };
   int residual(const std::vector<Slot *> &slots, int mode);
+  int iterate_mg(const std::vector<Slot *> &slots, int iters);
   int build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_rhs, LaunchArgs &la);
   int read_states(const std::vector<Slot *> &slots);
   int final_check(const std::vector<Slot *> &slots);

@@ -165,7 +165,7 @@ void stencil_kernel(LaunchArgs la) {
   const long long vbase = (long long)rhs * 3 * nn;
   const uint64_t vbytesS = 3ull * nn * SS, vbytesL = 3ull * nn * SL;
   // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX
-  // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q.
+  // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q (or the pair the flag names).
   rsrc_t rA, rB, rC, rR, rQ, rP, rX;
   TC alpha = TC(0), beta = TC(0);
   if constexpr (MODE == MODE_PCG) {
@@ -183,8 +183,26 @@ void stencil_kernel(LaunchArgs la) {
     rA = make_rsrc(s->x64 + vbase, vbytesL);
     rQ = make_rsrc((const TS *)s->r[st->pcur[rhs]] + vbase, vbytesS);
   } else {
-    rA = make_rsrc((const TS *)s->p[0] + vbase, vbytesL);
-    rQ = make_rsrc((const TS *)s->q[0] + vbase, vbytesS);
+    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x)
+    const void *src = s->p[0];
+    void *dst = s->q[0];
+    if (w.flag > 0) {
+      auto pick = [&](int i) -> void * {
+        switch (i) {
+          case 0: return s->r[0];
+          case 1: return s->r[1];
+          case 2: return s->p[0];
+          case 3: return s->p[1];
+          case 4: return s->q[0];
+          case 5: return s->q[1];
+          default: return s->x;
+        }
+      };
+      src = pick((w.flag - 1) & 7);
+      dst = pick(((w.flag - 1) >> 3) & 7);
+    }
+    rA = make_rsrc((const TS *)src + vbase, vbytesL);
+    rQ = make_rsrc((const TS *)dst + vbase, vbytesS);
   }
   const bool zero_x = (MODE == MODE_RESID) && (w.flag == RES_INIT);
 

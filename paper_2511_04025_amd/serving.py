@@ -21,11 +21,11 @@ from . import binding as B
 
 class Engine:
     def __init__(self, arena_bytes, max_slots=64, precision="mixed", rtol=None, max_iter=20000,
-                 recompute_every=0, check_every=0):
+                 recompute_every=0, check_every=0, solver="jacobi"):
         if not torch.cuda.is_available():
             raise RuntimeError("the engine needs a HIP GPU")
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
-        self.opts = B.make_opts(precision, rtol, max_iter, recompute_every, False, check_every)
+        self.opts = B.make_opts(precision, rtol, max_iter, recompute_every, False, check_every, solver)
         self.stream = torch.cuda.current_stream()
         h = c_void_p()
         B.check(B.lib().shh_engine_create(c_void_p(self.arena.data_ptr()), c_size_t(self.arena.numel()),

@@ -45,7 +45,7 @@ def test_every_declared_function_is_exported(lib):
 def test_struct_layouts_match_the_header():
     # shh_design: 2 int32, 2 pointers, int32 (+pad), pointer, 4 doubles, int32 (+pad), 3 doubles
     assert ctypes.sizeof(B.ShhDesign) == 104
-    assert ctypes.sizeof(B.ShhOpts) == 32
+    assert ctypes.sizeof(B.ShhOpts) == 40
     assert ctypes.sizeof(B.ShhResult) == 36 * 8 + 2 * 8 + 6 * 4 + 6 * 8 + 5 * 8 + 8
     assert B.ShhResult.status.offset == ctypes.sizeof(B.ShhResult) - 8
 
@@ -173,3 +173,19 @@ def test_operator_workspace(lib):
             assert nb.value < full.value
     for bad in ((1, B.PREC_FP64), (513, B.PREC_FP64), (64, 2), (64, -1)):
         assert lib.shh_workspace_bytes_operator(bad[0], bad[1], byref(nb)) == B.SHH_INVALID_ARG
+
+
+def test_multigrid_solver_option(lib):
+    # n = m 2^k with k >= 1 and m <= 8 coarsens; others are refused up front
+    for n, ok in ((128, True), (96, True), (24, True), (20, True), (37, False), (50, False), (2, False)):
+        d = wl.shell_128(2000, n=n)
+        rc, nb = ws_bytes(lib, d, "mixed", solver="mg")
+        assert rc == (B.SHH_OK if ok else B.SHH_UNSUPPORTED), n
+        if ok:
+            _, nj = ws_bytes(lib, d, "mixed")
+            # the hierarchy adds its stencils and vectors (~1/8 of the voxel level's per level)
+            assert nj < nb < 2 * nj
+    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=2)
+    a = B.DesignArgs(wl.small_shell_24())
+    nb = c_size_t(0)
+    assert lib.shh_workspace_bytes(byref(a.c), byref(o), byref(nb)) == B.SHH_INVALID_ARG
