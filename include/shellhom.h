@@ -99,7 +99,7 @@ typedef struct {
                                pass per iteration; SHH_SOLVER_MG (1): CG preconditioned by
                                a geometric multigrid V-cycle (Sec. 4.2's solver family:
                                Galerkin coarse grids, Chebyshev smoothing), for n = m 2^k
-                               with k >= 1 and m <= 8 (SHH_UNSUPPORTED otherwise)       */
+                               with k >= 1, m <= 8 and n >= 6 (SHH_UNSUPPORTED otherwise) */
 } shh_opts;
 
 /* Result of one homogenization. */
@@ -202,13 +202,19 @@ int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts 
                        const double *dL_dV, double *dL_dpos, double *dL_dq, void *hip_stream);
 
 /* ---- instrumentation ------------------------------------------------------
-   When enabled, every launch of the CG pass kernel (one whole PCG iteration:
-   q = K p fused with the vector updates, the dominant kernel) is bracketed by
-   two HIP events on the stream it runs on; elapsed times are accumulated
-   process-wide when the solver next synchronizes.  shh_profile_read returns the number of timed
-   launches and their total milliseconds; shh_profile_enable(1) also resets. */
+   When enabled, every launch of the solver's dominant kernel is bracketed by
+   two HIP events on the stream it runs on: with SHH_SOLVER_JACOBI the CG pass
+   kernel (one whole PCG iteration: q = K p fused with the vector updates),
+   with SHH_SOLVER_MG the V-cycle vector sweep kernel (Chebyshev steps and
+   residual updates at every level), whose launches also add their algorithmic
+   bytes (the values the sweep must read and write).  Elapsed times are
+   accumulated process-wide when the solver next synchronizes.
+   shh_profile_read returns the number of timed launches and their total
+   milliseconds, shh_profile_read_bytes also the bytes (0 for CG pass
+   launches); shh_profile_enable(1) also resets. */
 int32_t shh_profile_enable(int32_t on);
 int32_t shh_profile_read(int64_t *launches, double *ms_total);
+int32_t shh_profile_read_bytes(int64_t *launches, double *ms_total, double *bytes);
 
 /* ---- serving engine: continuous batching ------------------------------
    Requests are admitted into slots while a free slot and enough arena memory

@@ -83,6 +83,7 @@ EXPORTS = {
                                  POINTER(c_double), c_void_p]),
     "shh_profile_enable": (c_int32, [c_int32]),
     "shh_profile_read": (c_int32, [POINTER(ctypes.c_int64), POINTER(c_double)]),
+    "shh_profile_read_bytes": (c_int32, [POINTER(ctypes.c_int64), POINTER(c_double), POINTER(c_double)]),
     "shh_engine_create": (c_int32, [c_void_p, c_size_t, c_int32, c_void_p, POINTER(c_void_p)]),
     "shh_engine_footprint": (c_int32, [POINTER(ShhDesign), POINTER(ShhOpts), POINTER(c_size_t)]),
     "shh_engine_submit": (c_int32, [c_void_p, POINTER(ShhDesign), POINTER(ShhOpts), c_uint64]),

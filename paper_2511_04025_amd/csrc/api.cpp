@@ -31,7 +31,7 @@ constexpr int MAX_BATCH = 64;
 // Segment tables of one solve live in a fixed block of the first workspace.
 size_t seg_region() { return Solver::seg_bytes(MAX_BATCH); }
 
-// The multigrid solver needs n = m 2^k, k >= 1, m <= 8.
+// The multigrid solver needs n = m 2^k, k >= 1, m <= 8, n >= 6.
 int check_solver(int n, const shh_opts *o) {
   if (o->solver == SHH_SOLVER_MG && mg_num_levels(n) < 2) return SHH_UNSUPPORTED;
   return SHH_OK;
@@ -427,11 +427,16 @@ int32_t shh_profile_enable(int32_t on) {
 }
 
 int32_t shh_profile_read(int64_t *launches, double *ms_total) {
+  return shh_profile_read_bytes(launches, ms_total, nullptr);
+}
+
+int32_t shh_profile_read_bytes(int64_t *launches, double *ms_total, double *bytes) {
   long long l = 0;
-  double m = 0.0;
-  profile_read(&l, &m);
+  double m = 0.0, b = 0.0;
+  profile_read(&l, &m, &b);
   if (launches) *launches = l;
   if (ms_total) *ms_total = m;
+  if (bytes) *bytes = b;
   return SHH_OK;
 }
 

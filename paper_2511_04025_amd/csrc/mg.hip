@@ -138,20 +138,25 @@ __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l)
 // operator, transfer and coarsest solve (levels >= 1)
 // ---------------------------------------------------------------------------
 
-// q = A_l v for all load cases (v = x or d of the level).  One thread per node.
-template <typename T>
+// q = A_l v (v = x or d of the level) for RHS load cases per thread: RHS =
+// NRHS (one thread per node; the stencil is read once for all load cases) on
+// large levels, RHS = 1 (one thread per node and load case: six times the
+// threads, so latency overlaps) on small ones.
+template <typename T, int RHS>
 __global__ __launch_bounds__(256) void mg_apply_kernel(const MgDev *mg, int l, int src) {
   const MgLevel &L = mg->lv[l];
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= L.nn) return;
-  const int n = L.n;
   const long long nn = L.nn;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn * (NRHS / RHS)) return;
+  const long long v = t % nn;
+  const int r0 = int(t / nn) * RHS;
+  const int n = L.n;
   const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
   const T *S = (const T *)L.S;
-  const T *in = (const T *)(src == 0 ? L.x : L.d);
-  T acc[NRHS][3];
+  const T *in = (const T *)(src == 0 ? L.x : L.d) + (long long)r0 * 3 * nn;
+  T acc[RHS][3];
 #pragma unroll
-  for (int r = 0; r < NRHS; ++r)
+  for (int r = 0; r < RHS; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[r][c] = T(0);
   for (int w = 0; w < 27; ++w) {
@@ -161,16 +166,16 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(const MgDev *mg, int l, i
 #pragma unroll
     for (int k = 0; k < 9; ++k) blk[k] = S[(w * 9 + k) * nn + v];
 #pragma unroll
-    for (int r = 0; r < NRHS; ++r) {
+    for (int r = 0; r < RHS; ++r) {
       const T *vr = in + (long long)r * 3 * nn;
       const T u0 = vr[u], u1 = vr[nn + u], u2 = vr[2 * nn + u];
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[r][c] += blk[3 * c] * u0 + blk[3 * c + 1] * u1 + blk[3 * c + 2] * u2;
     }
   }
-  T *q = (T *)L.q;
+  T *q = (T *)L.q + (long long)r0 * 3 * nn;
 #pragma unroll
-  for (int r = 0; r < NRHS; ++r)
+  for (int r = 0; r < RHS; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = acc[r][c];
 }
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, c
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long j = c * nn + i;
-      const T di = l == 0 ? Dv[i] : Dv[j];
+      const T di = op == MGV_RESID ? T(0) : (l == 0 ? Dv[i] : Dv[j]);
       if (op == MGV_INIT) {
         const T bv = b[j];
         const T dv = di * bv * ith;
@@ -525,9 +530,15 @@ hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, h
 }
 
 hipError_t mg_launch_apply(const MgDev *d_mg, int l, int src, long long nn, int prec, hipStream_t st) {
-  const unsigned g = blocks_for(nn, 256);
-  if (prec == 0) mg_apply_kernel<double><<<g, 256, 0, st>>>(d_mg, l, src);
-  else mg_apply_kernel<float><<<g, 256, 0, st>>>(d_mg, l, src);
+  if (nn > 32768) {
+    const unsigned g = blocks_for(nn, 256);
+    if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(d_mg, l, src);
+    else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(d_mg, l, src);
+  } else {
+    const unsigned g = blocks_for(nn * NRHS, 256);
+    if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(d_mg, l, src);
+    else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(d_mg, l, src);
+  }
   return hipGetLastError();
 }
 

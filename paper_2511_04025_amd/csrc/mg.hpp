@@ -56,11 +56,12 @@ enum { MGC_DOT_PQ = 0, MGC_UPDATE = 1, MGC_P_UPDATE = 2 };
 // CG scalar phases
 enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2 };
 
-// Number of levels for an n^3 grid (coarsening while even and >= 4), or 0 when
-// the coarsest grid would exceed MG_MAX_COARSE.
+// Number of levels for an n^3 grid (coarsening while even and above 4^3, so
+// the dense coarsest solve stays at most 8^3 and usually 3^3 or 4^3), or 0
+// when the coarsest grid would exceed MG_MAX_COARSE.
 inline int mg_num_levels(int n) {
   int L = 1;
-  while (n % 2 == 0 && n >= 4 && L < MG_MAXL) {
+  while (n % 2 == 0 && n > 4 && L < MG_MAXL) {
     n /= 2;
     ++L;
   }

@@ -247,27 +247,51 @@ int apply(Slot &s, int l, int src, hipStream_t st) {
   return SHH_OK;
 }
 
-int vcycle(Slot &s, int l, hipStream_t st) {
+// Algorithmic bytes of one vector sweep at a level: values per node and load
+// case read and written (3 components each), plus the inverse diagonal (one
+// value per node at the voxel level, three on coarse levels) per load case.
+double vec_bytes(const Slot &s, int l, int op) {
+  const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
+  const double nn = double(s.mg.lv[l].nn);
+  const double dv = l == 0 ? 1.0 : 3.0;
+  double vals = 0.0, dvals = dv;
+  switch (op) {
+    case MGV_INIT: vals = 3 * (1 + 3); break;        // b -> d, x, r
+    case MGV_STEP: vals = 3 * (4 + 3); break;        // r, q, d, x -> r, d, x
+    case MGV_RESID: vals = 3 * (2 + 1); dvals = 0; break;  // r, q -> r
+    case MGV_POST: vals = 3 * (3 + 3); break;        // b, q, x -> r, d, x
+    default: vals = 3 * (5 + 3); break;              // STEP_FINAL also reads b
+  }
+  return NRHS * nn * (vals + dvals) * ts;
+}
+
+int vcycle(Slot &s, int l, hipStream_t st, Solver *timer) {
   const int prec = s.host.prec;
   const MgLevel &L = s.mg.lv[l];
   if (l == s.mg.L) {
     SHH_HIP(mg_launch_coarsest(s.d_mg, prec, st));
     return SHH_OK;
   }
-  auto vec = [&](int op) { return mg_launch_vec(s.d_slot, s.d_mg, l, op, L.nchunks, prec, st); };
   int rc;
-  SHH_HIP(vec(MGV_INIT));
+  auto vec = [&](int op) -> int {
+    hipEvent_t e0 = nullptr;
+    if (timer && (rc = timer->timed_begin(&e0))) return rc;
+    SHH_HIP(mg_launch_vec(s.d_slot, s.d_mg, l, op, L.nchunks, prec, st));
+    if (timer) return timer->timed_end(e0, vec_bytes(s, l, op));
+    return SHH_OK;
+  };
+  if ((rc = vec(MGV_INIT))) return rc;
   if ((rc = apply(s, l, 1, st))) return rc;
-  SHH_HIP(vec(MGV_STEP));
+  if ((rc = vec(MGV_STEP))) return rc;
   if ((rc = apply(s, l, 1, st))) return rc;
-  SHH_HIP(vec(MGV_RESID));
+  if ((rc = vec(MGV_RESID))) return rc;
   SHH_HIP(mg_launch_restrict(s.d_mg, l, s.mg.lv[l + 1].nn, prec, st));
-  if ((rc = vcycle(s, l + 1, st))) return rc;
+  if ((rc = vcycle(s, l + 1, st, timer))) return rc;
   SHH_HIP(mg_launch_prolong(s.d_mg, l, L.nn, prec, st));
   if ((rc = apply(s, l, 0, st))) return rc;
-  SHH_HIP(vec(MGV_POST));
+  if ((rc = vec(MGV_POST))) return rc;
   if ((rc = apply(s, l, 1, st))) return rc;
-  SHH_HIP(vec(l == 0 ? MGV_STEP_FINAL : MGV_STEP));
+  if ((rc = vec(l == 0 ? MGV_STEP_FINAL : MGV_STEP))) return rc;
   return SHH_OK;
 }
 
@@ -383,12 +407,12 @@ int mg_setup(Slot &s, hipStream_t st) {
   return SHH_OK;
 }
 
-int mg_iteration(Slot &s, hipStream_t st) {
+int mg_iteration(Slot &s, hipStream_t st, Solver *timer) {
   const int prec = s.host.prec;
   const int nch = s.host.nchunks;
   int rc;
   if (s.mg_restart) {
-    if ((rc = vcycle(s, 0, st))) return rc;
+    if ((rc = vcycle(s, 0, st, timer))) return rc;
     SHH_HIP(mg_launch_scalar(s.d_slot, MGS_RESTART, st));
     SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));  // beta = 0: p = z
     s.mg_restart = false;
@@ -399,7 +423,7 @@ int mg_iteration(Slot &s, hipStream_t st) {
   SHH_HIP(mg_launch_cg(s.d_slot, MGC_DOT_PQ, nch, prec, st));
   SHH_HIP(mg_launch_scalar(s.d_slot, MGS_ALPHA, st));
   SHH_HIP(mg_launch_cg(s.d_slot, MGC_UPDATE, nch, prec, st));
-  if ((rc = vcycle(s, 0, st))) return rc;
+  if ((rc = vcycle(s, 0, st, timer))) return rc;
   SHH_HIP(mg_launch_scalar(s.d_slot, MGS_BETA, st));
   SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));
   return SHH_OK;

@@ -25,6 +25,7 @@ std::atomic<bool> g_prof_on{false};
 std::mutex g_prof_mu;
 long long g_prof_launches = 0;
 double g_prof_ms = 0.0;
+double g_prof_bytes = 0.0;
 }  // namespace
 
 void profile_enable(bool on) {
@@ -33,18 +34,21 @@ void profile_enable(bool on) {
   if (on) {
     g_prof_launches = 0;
     g_prof_ms = 0.0;
+    g_prof_bytes = 0.0;
   }
 }
 bool profile_on() { return g_prof_on.load(); }
-void profile_read(long long *launches, double *ms) {
+void profile_read(long long *launches, double *ms, double *bytes) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (launches) *launches = g_prof_launches;
   if (ms) *ms = g_prof_ms;
+  if (bytes) *bytes = g_prof_bytes;
 }
-void profile_add(double ms) {
+void profile_add(double ms, double bytes) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_launches += 1;
   g_prof_ms += ms;
+  g_prof_bytes += bytes;
 }
 
 double now_ms() {
@@ -416,11 +420,18 @@ hipEvent_t Solver::get_event() {
 void Solver::resolve_events() {
   for (auto &pr : ev_pending_) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) profile_add(ms);
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) profile_add(ms, 0.0);
     ev_pool_.push_back(pr.first);
     ev_pool_.push_back(pr.second);
   }
   ev_pending_.clear();
+  for (auto &tb : ev_bytes_) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, tb.e0, tb.e1) == hipSuccess) profile_add(ms, tb.bytes);
+    ev_pool_.push_back(tb.e0);
+    ev_pool_.push_back(tb.e1);
+  }
+  ev_bytes_.clear();
 }
 
 int Solver::iterate(const std::vector<Slot *> &all, int iters) {
@@ -464,26 +475,30 @@ int Solver::iterate(const std::vector<Slot *> &all, int iters) {
 // Multigrid-preconditioned CG: one launch sequence per slot and iteration.
 int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
-  const bool prof = profile_on();
   for (int it = 0; it < iters; ++it) {
     std::vector<Slot *> due;
     for (Slot *s : slots) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (prof) {
-        e0 = get_event();
-        e1 = get_event();
-        if (e0) SHH_HIP(hipEventRecord(e0, st_));
-      }
-      if ((rc = mg_iteration(*s, st_))) return rc;
-      if (e0 && e1) {
-        SHH_HIP(hipEventRecord(e1, st_));
-        ev_pending_.emplace_back(e0, e1);
-      }
+      if ((rc = mg_iteration(*s, st_, profile_on() ? this : nullptr))) return rc;
       s->launched += 1;
       if (s->R > 0 && s->launched % s->R == 0) due.push_back(s);
     }
     if (!due.empty() && (rc = residual(due, RES_RECOMPUTE))) return rc;
   }
+  return SHH_OK;
+}
+
+int Solver::timed_begin(hipEvent_t *e0) {
+  *e0 = get_event();
+  if (*e0) SHH_HIP(hipEventRecord(*e0, st_));
+  return SHH_OK;
+}
+
+int Solver::timed_end(hipEvent_t e0, double bytes) {
+  if (!e0) return SHH_OK;
+  hipEvent_t e1 = get_event();
+  if (!e1) return SHH_OK;
+  SHH_HIP(hipEventRecord(e1, st_));
+  ev_bytes_.push_back({e0, e1, bytes});
   return SHH_OK;
 }
 

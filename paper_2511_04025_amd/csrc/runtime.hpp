@@ -65,7 +65,10 @@ size_t mg_region_bytes(int n, int prec);
 // vectors are zeroed: the element matrices use the vector region as scratch)
 int mg_setup(Slot &s, hipStream_t st);
 // one multigrid-preconditioned CG iteration of every load case of the slot
-int mg_iteration(Slot &s, hipStream_t st);
+// (timer: when profiling, the voxel- and coarse-level vector sweeps are timed
+// with their algorithmic bytes)
+class Solver;
+int mg_iteration(Slot &s, hipStream_t st, Solver *timer);
 void copy_design(const shh_design *src, DesignCopy &dst);
 
 // Fill the slot descriptor for a region and upload it (+ charges, alpha, zeroed state).
@@ -90,6 +93,10 @@ class Solver {
   // residual check and, if it holds, the C^H reduction. Returns slots finished now.
   int poll(const std::vector<Slot *> &slots, std::vector<Slot *> &done);
   int sync();
+  // bracket one launch on the solver's stream with events; `bytes` is its
+  // algorithmic traffic (profiling only)
+  int timed_begin(hipEvent_t *e0);
+  int timed_end(hipEvent_t e0, double bytes);
 
  private:
   enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_NKIND };
@@ -105,6 +112,11 @@ class Solver {
   // events bracketing stencil launches, resolved at the next synchronization
   std::vector<hipEvent_t> ev_pool_;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending_;
+  struct TimedBytes {
+    hipEvent_t e0, e1;
+    double bytes;
+  };
+  std::vector<TimedBytes> ev_bytes_;
   hipEvent_t get_event();
   void resolve_events();
 
@@ -115,8 +127,8 @@ class Solver {
 // process-wide stencil-launch timing (shh_profile_*)
 void profile_enable(bool on);
 bool profile_on();
-void profile_read(long long *launches, double *ms);
-void profile_add(double ms);
+void profile_read(long long *launches, double *ms, double *bytes);
+void profile_add(double ms, double bytes);
 
 double now_ms();
 void fill_result(const Slot &s, shh_result *out);

@@ -176,8 +176,8 @@ def test_operator_workspace(lib):
 
 
 def test_multigrid_solver_option(lib):
-    # n = m 2^k with k >= 1 and m <= 8 coarsens; others are refused up front
-    for n, ok in ((128, True), (96, True), (24, True), (20, True), (37, False), (50, False), (2, False)):
+    # n = m 2^k with k >= 1, m <= 8 and n >= 6 coarsens; others are refused up front
+    for n, ok in ((128, True), (96, True), (24, True), (20, True), (6, True), (37, False), (50, False), (4, False), (2, False)):
         d = wl.shell_128(2000, n=n)
         rc, nb = ws_bytes(lib, d, "mixed", solver="mg")
         assert rc == (B.SHH_OK if ok else B.SHH_UNSUPPORTED), n
