@@ -180,90 +180,78 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(const MgDev *mg, int l, i
     for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = acc[r][c];
 }
 
-// b_{l+1} = P^T r_l: coarse node I collects fine nodes 2I + o, o in {-1, 0, 1}^3,
-// with weight prod (o == 0 ? 1 : 1/2).
+// b_{l+1} = P^T (r_l - q_l), the residual after the pre-smoother (q = A d of
+// its last step): coarse node I collects fine nodes 2I + o, o in {-1, 0, 1}^3,
+// with weight prod (o == 0 ? 1 : 1/2).  One thread per (coarse node, load case).
 template <typename T>
 __global__ __launch_bounds__(256) void mg_restrict_kernel(const MgDev *mg, int l) {
   const MgLevel &F = mg->lv[l];
   const MgLevel &C = mg->lv[l + 1];
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= C.nn) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C.nn * NRHS) return;
+  const long long I = t % C.nn;
+  const int k = int(t / C.nn);
   const int nc = C.n, nf = F.n;
   const int X = int(I % nc), Y = int((I / nc) % nc), Z = int(I / ((long long)nc * nc));
-  const T *r = (const T *)F.r;
-  double acc[NRHS][3];
+  const T *r = (const T *)F.r + (long long)k * 3 * F.nn;
+  const T *qf = (const T *)F.q + (long long)k * 3 * F.nn;
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int oz = -1; oz <= 1; ++oz) {
+    const long long pz = (long long)wrap1(2 * Z + oz, nf) * nf;
+    for (int oy = -1; oy <= 1; ++oy) {
+      const long long py = (pz + wrap1(2 * Y + oy, nf)) * nf;
+      const T wyz = T((oz ? 0.5 : 1.0) * (oy ? 0.5 : 1.0));
 #pragma unroll
-  for (int k = 0; k < NRHS; ++k)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const long long i = py + wrap1(2 * X + ox, nf);
+        const T w = ox ? T(0.5) * wyz : wyz;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[k][c] = 0.0;
-  for (int o = 0; o < 27; ++o) {
-    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-    const double w = (ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0);
-    const long long i = ((long long)wrap1(2 * Z + oz, nf) * nf + wrap1(2 * Y + oy, nf)) * nf + wrap1(2 * X + ox, nf);
-#pragma unroll
-    for (int k = 0; k < NRHS; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[k][c] += w * (double)r[((long long)k * 3 + c) * F.nn + i];
+        for (int c = 0; c < 3; ++c) {
+          const long long j = (long long)c * F.nn + i;
+          acc[c] += w * (r[j] - qf[j]);
+        }
+      }
+    }
   }
-  T *b = (T *)C.b;
+  T *b = (T *)C.b + (long long)k * 3 * C.nn;
 #pragma unroll
-  for (int k = 0; k < NRHS; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) b[((long long)k * 3 + c) * C.nn + I] = (T)acc[k][c];
+  for (int c = 0; c < 3; ++c) b[(long long)c * C.nn + I] = acc[c];
 }
 
 // x_l += P x_{l+1}: per axis an even fine index takes coarse node i / 2, an
-// odd one the mean of its two coarse neighbours.
+// odd one the mean of its two coarse neighbours.  One thread per (fine node,
+// load case).
 template <typename T>
 __global__ __launch_bounds__(256) void mg_prolong_kernel(const MgDev *mg, int l) {
   const MgLevel &F = mg->lv[l];
   const MgLevel &C = mg->lv[l + 1];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F.nn) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F.nn * NRHS) return;
+  const long long i = t % F.nn;
+  const int k = int(t / F.nn);
   const int nf = F.n, nc = C.n;
   const int x = int(i % nf), y = int((i / nf) % nf), z = int(i / ((long long)nf * nf));
-  int cx[2], cy[2], cz[2];
-  double wx[2], wy[2], wz[2];
-  auto axis = [&](int f, int (&ci)[2], double (&wi)[2]) {
-    ci[0] = f >> 1;
-    ci[1] = wrap1((f >> 1) + 1, nc);
-    if (f & 1) {
-      wi[0] = 0.5;
-      wi[1] = 0.5;
-    } else {
-      wi[0] = 1.0;
-      wi[1] = 0.0;
-    }
-  };
-  axis(x, cx, wx);
-  axis(y, cy, wy);
-  axis(z, cz, wz);
-  const T *xc = (const T *)C.x;
-  double acc[NRHS][3];
+  const int cx0 = x >> 1, cy0 = y >> 1, cz0 = z >> 1;
+  const int cx1 = (x & 1) ? wrap1(cx0 + 1, nc) : cx0;
+  const int cy1 = (y & 1) ? wrap1(cy0 + 1, nc) : cy0;
+  const int cz1 = (z & 1) ? wrap1(cz0 + 1, nc) : cz0;
+  // odd index: mean of the two neighbours; even: the coincident node twice at 1/2
+  const T *xc = (const T *)C.x + (long long)k * 3 * C.nn;
+  const long long p00 = ((long long)cz0 * nc + cy0) * nc, p01 = ((long long)cz0 * nc + cy1) * nc;
+  const long long p10 = ((long long)cz1 * nc + cy0) * nc, p11 = ((long long)cz1 * nc + cy1) * nc;
+  T *xf = (T *)F.x + (long long)k * 3 * F.nn;
 #pragma unroll
-  for (int k = 0; k < NRHS; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[k][c] = 0.0;
-  for (int a = 0; a < 8; ++a) {
-    const double w = wx[a & 1] * wy[(a >> 1) & 1] * wz[a >> 2];
-    if (w == 0.0) continue;
-    const long long I = ((long long)cz[a >> 2] * nc + cy[(a >> 1) & 1]) * nc + cx[a & 1];
-#pragma unroll
-    for (int k = 0; k < NRHS; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[k][c] += w * (double)xc[((long long)k * 3 + c) * C.nn + I];
+  for (int c = 0; c < 3; ++c) {
+    const T *v = xc + (long long)c * C.nn;
+    const T s = (v[p00 + cx0] + v[p00 + cx1]) + (v[p01 + cx0] + v[p01 + cx1]) +
+                (v[p10 + cx0] + v[p10 + cx1]) + (v[p11 + cx0] + v[p11 + cx1]);
+    const long long j = (long long)c * F.nn + i;
+    xf[j] = xf[j] + T(0.125) * s;
   }
-  T *xf = (T *)F.x;
-#pragma unroll
-  for (int k = 0; k < NRHS; ++k)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const long long j = ((long long)k * 3 + c) * F.nn + i;
-      xf[j] = (T)((double)xf[j] + acc[k][c]);
-    }
 }
 
-// Coarsest level: x = Mc b per load case (one workgroup per load case).
+// Coarsest level: x = Mc b per load case (one workgroup per load case; four
+// lanes share a row and combine their partial sums by shuffles).
 template <typename T>
 __global__ __launch_bounds__(256) void mg_coarsest_kernel(const MgDev *mg) {
   const MgLevel &L = mg->lv[mg->L];
@@ -273,23 +261,29 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(const MgDev *mg) {
   const T *M = (const T *)mg->Mc;
   const T *b = (const T *)L.b + (long long)k * 3 * nn;
   T *x = (T *)L.x + (long long)k * 3 * nn;
-  for (int row = threadIdx.x; row < nd; row += blockDim.x) {
+  const int part = threadIdx.x & 3;
+  for (int row0 = 0; row0 < nd; row0 += 64) {
+    const int row = row0 + (threadIdx.x >> 2);
     double acc = 0.0;
-    for (int j = 0; j < nd; ++j) acc += (double)M[(long long)row * nd + j] * (double)b[(j % 3) * nn + j / 3];
-    x[(row % 3) * nn + row / 3] = (T)acc;
+    if (row < nd)
+      for (int j = part; j < nd; j += 4) acc += (double)M[(long long)row * nd + j] * (double)b[(j % 3) * nn + j / 3];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (row < nd && part == 0) x[(row % 3) * nn + row / 3] = (T)acc;
   }
 }
 
-// ---------------------------------------------------------------------------
-// V-cycle vector sweeps (any level) and CG sweeps (voxel level)
-// ---------------------------------------------------------------------------
-
-// Chebyshev smoothing steps on A x = b at level l (x starts at 0 in INIT):
-//   INIT:  d = D^-1 b / theta, x = d, r = b
-//   STEP:  r -= q (q = A d), d = c1 d + c2 D^-1 r, x += d
-//   RESID: r -= q            (r = b - A x after the pre-smoother)
+// Degree-2 Chebyshev smoothing of A x = b at level l, in four sweeps around
+// the operator applications (q = A d or A x from the launch before):
+//   INIT:  d = D^-1 b / theta                    (x = d is implied)
+//          at the voxel level first the CG update x_cg += alpha p,
+//          b = r -= alpha q (q = K p), so that b is the new CG residual
+//   STEP1: r = b - q, d' = c1 d + c2 D^-1 r, x = d + d', d = d'
 //   POST:  r = b - q (q = A x), d = D^-1 r / theta, x += d
-// STEP_FINAL (voxel level): STEP, then partial sums b . x and b . b for CG.
+//   LAST:  x += c1 d + c2 D^-1 (r - q); at the voxel level partial sums
+//          b . x and b . b for the CG scalars
+// (the pre-smoother is INIT, STEP1; the restriction takes r - q after it;
+// the post-smoother is POST, LAST).
 template <typename T>
 __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, const MgDev *mg, int l, int op) {
   __shared__ double red[2 * 16];
@@ -299,48 +293,61 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, c
   const long long i0 = (long long)blockIdx.x * CHUNK;
   const long long i1 = min(i0 + (long long)CHUNK, nn);
   const T ith = (T)L.inv_theta, c1 = (T)L.c1, c2 = (T)L.c2;
-  const T *b = (const T *)L.b + (long long)k * 3 * nn;
-  T *x = (T *)L.x + (long long)k * 3 * nn;
-  T *r = (T *)L.r + (long long)k * 3 * nn;
-  T *d = (T *)L.d + (long long)k * 3 * nn;
-  const T *q = (const T *)L.q + (long long)k * 3 * nn;
+  const long long vb = (long long)k * 3 * nn;
+  T *b = (T *)L.b + vb;
+  T *x = (T *)L.x + vb;
+  T *r = (T *)L.r + vb;
+  T *d = (T *)L.d + vb;
+  const T *q = (const T *)L.q + vb;
   const T *Dv = (const T *)L.Dinv;
+  // voxel-level CG update folded into INIT
+  T a = T(0);
+  T *xcg = nullptr;
+  const T *pcg = nullptr;
+  if (l == 0 && op == MGV_INIT) {
+    a = (T)s->st->alpha[k];
+    xcg = (T *)s->x + vb;
+    pcg = (const T *)s->p[0] + vb;
+  }
   double acc[2] = {0.0, 0.0};
   for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long j = c * nn + i;
-      const T di = op == MGV_RESID ? T(0) : (l == 0 ? Dv[i] : Dv[j]);
+      const T di = l == 0 ? Dv[i] : Dv[j];
       if (op == MGV_INIT) {
-        const T bv = b[j];
-        const T dv = di * bv * ith;
-        d[j] = dv;
-        x[j] = dv;
-        r[j] = bv;
-      } else if (op == MGV_STEP || op == MGV_STEP_FINAL) {
-        const T rv = r[j] - q[j];
-        const T dv = c1 * d[j] + c2 * di * rv;
-        const T xv = x[j] + dv;
-        r[j] = rv;
-        d[j] = dv;
-        x[j] = xv;
-        if (op == MGV_STEP_FINAL) {
-          const double bv = (double)b[j];
-          acc[0] += bv * (double)xv;
-          acc[1] += bv * bv;
+        T bv = b[j];
+        if (a != T(0)) {
+          xcg[j] = xcg[j] + a * pcg[j];
+          bv = bv - a * q[j];
+          b[j] = bv;
         }
-      } else if (op == MGV_RESID) {
-        r[j] = r[j] - q[j];
-      } else {  // MGV_POST
+        d[j] = di * bv * ith;
+      } else if (op == MGV_STEP1) {
+        const T rv = b[j] - q[j];
+        const T d0 = d[j];
+        const T d1 = c1 * d0 + c2 * di * rv;
+        r[j] = rv;
+        d[j] = d1;
+        x[j] = d0 + d1;
+      } else if (op == MGV_POST) {
         const T rv = b[j] - q[j];
         const T dv = di * rv * ith;
         r[j] = rv;
         d[j] = dv;
         x[j] = x[j] + dv;
+      } else {  // MGV_LAST
+        const T xv = x[j] + c1 * d[j] + c2 * di * (r[j] - q[j]);
+        x[j] = xv;
+        if (l == 0) {
+          const double bv = (double)b[j];
+          acc[0] += bv * (double)xv;
+          acc[1] += bv * bv;
+        }
       }
     }
   }
-  if (op == MGV_STEP_FINAL) {
+  if (l == 0 && op == MGV_LAST) {
     block_sum<2>(acc, red, VEC_THREADS);
     if (threadIdx.x == 0) {
       double *parts = s->partials + ((long long)k * s->maxparts + blockIdx.x) * PSTRIDE;
@@ -350,9 +357,9 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, c
   }
 }
 
-// CG sweeps at the voxel level: p = p[0], q = q[0], r = r[0], z = r[1].
+// CG sweeps at the voxel level: p = p[0], q = q[0], z = r[1] (the update of x
+// and r is folded into the V-cycle's first sweep).
 //   DOT_PQ:   partial p . q
-//   UPDATE:   x += alpha p, r -= alpha q
 //   P_UPDATE: p = z + beta p
 template <typename T>
 __global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(const SlotDev *s, int op) {
@@ -364,11 +371,8 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(const SlotDev *s, in
   const long long vb = (long long)k * 3 * nn;
   T *p = (T *)s->p[0] + vb;
   const T *q = (const T *)s->q[0] + vb;
-  T *r = (T *)s->r[0] + vb;
   const T *z = (const T *)s->r[1] + vb;
-  T *x = (T *)s->x + vb;
-  const CgState *st = s->st;
-  const T a = (T)st->alpha[k], bt = (T)st->beta[k];
+  const T bt = (T)s->st->beta[k];
   double acc[1] = {0.0};
   for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
 #pragma unroll
@@ -376,11 +380,6 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(const SlotDev *s, in
       const long long j = c * nn + i;
       if (op == MGC_DOT_PQ) {
         acc[0] += (double)p[j] * (double)q[j];
-      } else if (op == MGC_UPDATE) {
-        if (a != T(0)) {
-          x[j] = x[j] + a * p[j];
-          r[j] = r[j] - a * q[j];
-        }
       } else {
         p[j] = z[j] + bt * p[j];
       }
@@ -543,14 +542,14 @@ hipError_t mg_launch_apply(const MgDev *d_mg, int l, int src, long long nn, int 
 }
 
 hipError_t mg_launch_restrict(const MgDev *d_mg, int l, long long nn_coarse, int prec, hipStream_t st) {
-  const unsigned g = blocks_for(nn_coarse, 256);
+  const unsigned g = blocks_for(nn_coarse * NRHS, 256);
   if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
   else mg_restrict_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
   return hipGetLastError();
 }
 
 hipError_t mg_launch_prolong(const MgDev *d_mg, int l, long long nn_fine, int prec, hipStream_t st) {
-  const unsigned g = blocks_for(nn_fine, 256);
+  const unsigned g = blocks_for(nn_fine * NRHS, 256);
   if (prec == 0) mg_prolong_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
   else mg_prolong_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
   return hipGetLastError();

@@ -49,10 +49,10 @@ struct MgDev {
   MgLevel lv[MG_MAXL];
 };
 
-// V-cycle vector operations at one level (grid: chunks x NRHS)
-enum { MGV_INIT = 0, MGV_STEP = 1, MGV_RESID = 2, MGV_POST = 3, MGV_STEP_FINAL = 4 };
+// V-cycle vector sweeps at one level (grid: chunks x NRHS); see mg_vec_kernel
+enum { MGV_INIT = 0, MGV_STEP1 = 1, MGV_POST = 2, MGV_LAST = 3 };
 // CG operations at the voxel level
-enum { MGC_DOT_PQ = 0, MGC_UPDATE = 1, MGC_P_UPDATE = 2 };
+enum { MGC_DOT_PQ = 0, MGC_P_UPDATE = 2 };
 // CG scalar phases
 enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2 };
 

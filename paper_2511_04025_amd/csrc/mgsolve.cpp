@@ -247,22 +247,21 @@ int apply(Slot &s, int l, int src, hipStream_t st) {
   return SHH_OK;
 }
 
-// Algorithmic bytes of one vector sweep at a level: values per node and load
-// case read and written (3 components each), plus the inverse diagonal (one
+// Algorithmic bytes of one vector sweep at a level: vectors read and written
+// per node and load case (3 components each) plus the inverse diagonal (one
 // value per node at the voxel level, three on coarse levels) per load case.
 double vec_bytes(const Slot &s, int l, int op) {
   const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
   const double nn = double(s.mg.lv[l].nn);
   const double dv = l == 0 ? 1.0 : 3.0;
-  double vals = 0.0, dvals = dv;
+  double vals = 0.0;
   switch (op) {
-    case MGV_INIT: vals = 3 * (1 + 3); break;        // b -> d, x, r
-    case MGV_STEP: vals = 3 * (4 + 3); break;        // r, q, d, x -> r, d, x
-    case MGV_RESID: vals = 3 * (2 + 1); dvals = 0; break;  // r, q -> r
-    case MGV_POST: vals = 3 * (3 + 3); break;        // b, q, x -> r, d, x
-    default: vals = 3 * (5 + 3); break;              // STEP_FINAL also reads b
+    case MGV_INIT: vals = l == 0 ? 3 * (4 + 3) : 3 * (1 + 1); break;  // voxel: x, p, r, q -> x, r, d
+    case MGV_STEP1: vals = 3 * (3 + 3); break;                       // b, q, d -> r, d, x
+    case MGV_POST: vals = 3 * (3 + 3); break;                        // b, q, x -> r, d, x
+    default: vals = l == 0 ? 3 * (5 + 1) : 3 * (4 + 1); break;       // r, q, d, x (, b) -> x
   }
-  return NRHS * nn * (vals + dvals) * ts;
+  return NRHS * nn * (vals + dv) * ts;
 }
 
 int vcycle(Slot &s, int l, hipStream_t st, Solver *timer) {
@@ -280,18 +279,20 @@ int vcycle(Slot &s, int l, hipStream_t st, Solver *timer) {
     if (timer) return timer->timed_end(e0, vec_bytes(s, l, op));
     return SHH_OK;
   };
+  // pre-smoother (at the voxel level INIT also applies the pending CG update)
   if ((rc = vec(MGV_INIT))) return rc;
   if ((rc = apply(s, l, 1, st))) return rc;
-  if ((rc = vec(MGV_STEP))) return rc;
+  if ((rc = vec(MGV_STEP1))) return rc;
   if ((rc = apply(s, l, 1, st))) return rc;
-  if ((rc = vec(MGV_RESID))) return rc;
+  // coarse-grid correction of the residual r - A d
   SHH_HIP(mg_launch_restrict(s.d_mg, l, s.mg.lv[l + 1].nn, prec, st));
   if ((rc = vcycle(s, l + 1, st, timer))) return rc;
   SHH_HIP(mg_launch_prolong(s.d_mg, l, L.nn, prec, st));
+  // post-smoother
   if ((rc = apply(s, l, 0, st))) return rc;
   if ((rc = vec(MGV_POST))) return rc;
   if ((rc = apply(s, l, 1, st))) return rc;
-  if ((rc = vec(l == 0 ? MGV_STEP_FINAL : MGV_STEP))) return rc;
+  if ((rc = vec(MGV_LAST))) return rc;
   return SHH_OK;
 }
 
@@ -422,7 +423,7 @@ int mg_iteration(Slot &s, hipStream_t st, Solver *timer) {
   SHH_HIP(launch_stencil_apply(la, prec, st));
   SHH_HIP(mg_launch_cg(s.d_slot, MGC_DOT_PQ, nch, prec, st));
   SHH_HIP(mg_launch_scalar(s.d_slot, MGS_ALPHA, st));
-  SHH_HIP(mg_launch_cg(s.d_slot, MGC_UPDATE, nch, prec, st));
+  // the V-cycle's first sweep applies x += alpha p, r -= alpha q
   if ((rc = vcycle(s, 0, st, timer))) return rc;
   SHH_HIP(mg_launch_scalar(s.d_slot, MGS_BETA, st));
   SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));
