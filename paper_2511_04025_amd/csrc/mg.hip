@@ -143,8 +143,8 @@ __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l)
 // large levels, RHS = 1 (one thread per node and load case: six times the
 // threads, so latency overlaps) on small ones.
 template <typename T, int RHS>
-__global__ __launch_bounds__(256) void mg_apply_kernel(const MgDev *mg, int l, int src) {
-  const MgLevel &L = mg->lv[l];
+__global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src) {
+  const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const long long nn = L.nn;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nn * (NRHS / RHS)) return;
@@ -184,7 +184,8 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(const MgDev *mg, int l, i
 // its last step): coarse node I collects fine nodes 2I + o, o in {-1, 0, 1}^3,
 // with weight prod (o == 0 ? 1 : 1/2).  One thread per (coarse node, load case).
 template <typename T>
-__global__ __launch_bounds__(256) void mg_restrict_kernel(const MgDev *mg, int l) {
+__global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l) {
+  const MgDev *mg = B.mg[blockIdx.z];
   const MgLevel &F = mg->lv[l];
   const MgLevel &C = mg->lv[l + 1];
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(const MgDev *mg, int l
 // odd one the mean of its two coarse neighbours.  One thread per (fine node,
 // load case).
 template <typename T>
-__global__ __launch_bounds__(256) void mg_prolong_kernel(const MgDev *mg, int l) {
+__global__ __launch_bounds__(256) void mg_prolong_kernel(MgBatch B, int l) {
+  const MgDev *mg = B.mg[blockIdx.z];
   const MgLevel &F = mg->lv[l];
   const MgLevel &C = mg->lv[l + 1];
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -253,7 +255,8 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(const MgDev *mg, int l)
 // Coarsest level: x = Mc b per load case (one workgroup per load case; four
 // lanes share a row and combine their partial sums by shuffles).
 template <typename T>
-__global__ __launch_bounds__(256) void mg_coarsest_kernel(const MgDev *mg) {
+__global__ __launch_bounds__(256) void mg_coarsest_kernel(MgBatch B) {
+  const MgDev *mg = B.mg[blockIdx.z];
   const MgLevel &L = mg->lv[mg->L];
   const int k = blockIdx.x;
   const int nd = mg->ndof_c;
@@ -285,11 +288,13 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(const MgDev *mg) {
 // (the pre-smoother is INIT, STEP1; the restriction takes r - q after it;
 // the post-smoother is POST, LAST).
 template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, const MgDev *mg, int l, int op) {
+__global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, int op) {
   __shared__ double red[2 * 16];
-  const MgLevel &L = mg->lv[l];
+  const SlotDev *s = B.slot[blockIdx.z];
+  const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const int k = blockIdx.y;
   const long long nn = L.nn;
+  if (blockIdx.x >= (unsigned)L.nchunks) return;
   const long long i0 = (long long)blockIdx.x * CHUNK;
   const long long i1 = min(i0 + (long long)CHUNK, nn);
   const T ith = (T)L.inv_theta, c1 = (T)L.c1, c2 = (T)L.c2;
@@ -362,10 +367,12 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(const SlotDev *s, c
 //   DOT_PQ:   partial p . q
 //   P_UPDATE: p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(const SlotDev *s, int op) {
+__global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(MgBatch B, int op) {
   __shared__ double red[16];
+  const SlotDev *s = B.slot[blockIdx.z];
   const int k = blockIdx.y;
   const long long nn = s->nn;
+  if (blockIdx.x >= (unsigned)s->nchunks) return;
   const long long i0 = (long long)blockIdx.x * CHUNK;
   const long long i1 = min(i0 + (long long)CHUNK, nn);
   const long long vb = (long long)k * 3 * nn;
@@ -396,8 +403,9 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(const SlotDev *s, in
 //   RESTART: rho = r . z after a (re)started V-cycle, beta = 0
 //   ALPHA:   alpha = rho / p . K p
 //   BETA:    rho' = r . z, ||r||^2 -> convergence; beta = rho' / rho
-__global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(SlotDev *s, int phase) {
+__global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int phase) {
   __shared__ double red[2 * 16];
+  const SlotDev *s = B.slot[blockIdx.z];
   const int k = blockIdx.x;
   CgState *st = s->st;
   const double *parts = s->partials + (long long)k * s->maxparts * PSTRIDE;
@@ -455,10 +463,9 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(SlotDev *s, int 
 //   phase 1: partial x.q and x.D x (the Rayleigh quotient x.A x / x.D x of
 //            D^-1 A, self-adjoint in the D inner product), then x = D^-1 q
 //            (q = A x) and partial ||x||^2
-//   phase 2: x *= scale
+//   phase 2: x *= the level's pw_scale
 template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s, const MgDev *mg, int l, int phase,
-                                                             double scale) {
+__global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s, const MgDev *mg, int l, int phase) {
   __shared__ double red[3 * 16];
   const MgLevel &L = mg->lv[l];
   const long long nn = L.nn;
@@ -487,7 +494,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s,
         x[j] = v;
         acc[0] += (double)v * (double)v;
       } else {
-        x[j] = (T)((double)x[j] * scale);
+        x[j] = (T)((double)x[j] * L.pw_scale);
       }
     }
   }
@@ -499,6 +506,26 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s,
       s->partials[blockIdx.x * PSTRIDE + 2] = acc[2];
     }
   }
+}
+
+// After power phase 1: reduce the partials (one workgroup), keep the largest
+// Rayleigh quotient in lmax and the normalization for phase 2 (a vanishing or
+// non-finite step leaves lmax = -1, which the host reports as a breakdown).
+__global__ __launch_bounds__(VEC_THREADS) void mg_power_reduce_kernel(const SlotDev *s, MgDev *mg, int l,
+                                                                    int nchunks) {
+  __shared__ double red[3 * 16];
+  double tot[3];
+  sum_partials<3, PSTRIDE>(s->partials, nchunks, tot, red, VEC_THREADS);
+  if (threadIdx.x != 0) return;
+  MgLevel &L = mg->lv[l];
+  const double nrm = sqrt(tot[0]);
+  if (!(nrm > 0.0) || !isfinite(nrm) || !(tot[2] > 0.0) || L.lmax < 0.0) {
+    L.lmax = -1.0;
+    L.pw_scale = 0.0;
+    return;
+  }
+  L.lmax = fmax(L.lmax, tot[1] / tot[2]);
+  L.pw_scale = 1.0 / nrm;
 }
 
 // ---------------------------------------------------------------------------
@@ -528,63 +555,68 @@ hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, h
   return hipGetLastError();
 }
 
-hipError_t mg_launch_apply(const MgDev *d_mg, int l, int src, long long nn, int prec, hipStream_t st) {
-  if (nn > 32768) {
-    const unsigned g = blocks_for(nn, 256);
-    if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(d_mg, l, src);
-    else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(d_mg, l, src);
+hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st) {
+  if (nn_max > 32768) {
+    const dim3 g(blocks_for(nn_max, 256), 1, B.count);
+    if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(B, l, src);
+    else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(B, l, src);
   } else {
-    const unsigned g = blocks_for(nn * NRHS, 256);
-    if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(d_mg, l, src);
-    else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(d_mg, l, src);
+    const dim3 g(blocks_for(nn_max * NRHS, 256), 1, B.count);
+    if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, src);
+    else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, src);
   }
   return hipGetLastError();
 }
 
-hipError_t mg_launch_restrict(const MgDev *d_mg, int l, long long nn_coarse, int prec, hipStream_t st) {
-  const unsigned g = blocks_for(nn_coarse * NRHS, 256);
-  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
-  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st) {
+  const dim3 g(blocks_for(nn_coarse_max * NRHS, 256), 1, B.count);
+  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(B, l);
+  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(B, l);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_prolong(const MgDev *d_mg, int l, long long nn_fine, int prec, hipStream_t st) {
-  const unsigned g = blocks_for(nn_fine * NRHS, 256);
-  if (prec == 0) mg_prolong_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
-  else mg_prolong_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st) {
+  const dim3 g(blocks_for(nn_fine_max * NRHS, 256), 1, B.count);
+  if (prec == 0) mg_prolong_kernel<double><<<g, 256, 0, st>>>(B, l);
+  else mg_prolong_kernel<float><<<g, 256, 0, st>>>(B, l);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_coarsest(const MgDev *d_mg, int prec, hipStream_t st) {
-  if (prec == 0) mg_coarsest_kernel<double><<<NRHS, 256, 0, st>>>(d_mg);
-  else mg_coarsest_kernel<float><<<NRHS, 256, 0, st>>>(d_mg);
+hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st) {
+  const dim3 g(NRHS, 1, B.count);
+  if (prec == 0) mg_coarsest_kernel<double><<<g, 256, 0, st>>>(B);
+  else mg_coarsest_kernel<float><<<g, 256, 0, st>>>(B);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_vec(const SlotDev *d_slot, const MgDev *d_mg, int l, int op, int nchunks, int prec,
-                         hipStream_t st) {
-  const dim3 g((unsigned)nchunks, NRHS);
-  if (prec == 0) mg_vec_kernel<double><<<g, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, op);
-  else mg_vec_kernel<float><<<g, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, op);
+hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st) {
+  const dim3 g((unsigned)nchunks_max, NRHS, B.count);
+  if (prec == 0) mg_vec_kernel<double><<<g, VEC_THREADS, 0, st>>>(B, l, op);
+  else mg_vec_kernel<float><<<g, VEC_THREADS, 0, st>>>(B, l, op);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_cg(const SlotDev *d_slot, int op, int nchunks, int prec, hipStream_t st) {
-  const dim3 g((unsigned)nchunks, NRHS);
-  if (prec == 0) mg_cg_kernel<double><<<g, VEC_THREADS, 0, st>>>(d_slot, op);
-  else mg_cg_kernel<float><<<g, VEC_THREADS, 0, st>>>(d_slot, op);
+hipError_t mg_launch_cg(const MgBatch &B, int op, int nchunks_max, int prec, hipStream_t st) {
+  const dim3 g((unsigned)nchunks_max, NRHS, B.count);
+  if (prec == 0) mg_cg_kernel<double><<<g, VEC_THREADS, 0, st>>>(B, op);
+  else mg_cg_kernel<float><<<g, VEC_THREADS, 0, st>>>(B, op);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_scalar(SlotDev *d_slot, int phase, hipStream_t st) {
-  mg_scalar_kernel<<<NRHS, VEC_THREADS, 0, st>>>(d_slot, phase);
+hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st) {
+  mg_scalar_kernel<<<dim3(NRHS, 1, B.count), VEC_THREADS, 0, st>>>(B, phase);
   return hipGetLastError();
 }
 
-hipError_t mg_launch_power(const SlotDev *d_slot, const MgDev *d_mg, int l, int phase, double scale, int nchunks,
-                           int prec, hipStream_t st) {
-  if (prec == 0) mg_power_kernel<double><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase, scale);
-  else mg_power_kernel<float><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase, scale);
+hipError_t mg_launch_power(const SlotDev *d_slot, MgDev *d_mg, int l, int phase, int nchunks, int prec,
+                           hipStream_t st) {
+  if (phase == 3) {
+    mg_power_reduce_kernel<<<1, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, nchunks);
+  } else if (prec == 0) {
+    mg_power_kernel<double><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase);
+  } else {
+    mg_power_kernel<float><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase);
+  }
   return hipGetLastError();
 }
 

@@ -38,7 +38,8 @@ struct MgLevel {
   void *b, *x, *r, *d, *q;
   void *Ke;             // setup only: element matrices [nn][24][24] (levels >= 1)
   double inv_theta, c1, c2;  // Chebyshev coefficients
-  double lmax;
+  double lmax;               // lambda_max(D^-1 A) estimate (setup: running max of Rayleigh quotients)
+  double pw_scale;           // setup: 1 / ||D^-1 A x|| of the last power step
 };
 
 struct MgDev {
@@ -47,6 +48,14 @@ struct MgDev {
   void *G;              // [8][24][24] child Galerkin matrices of K_0 (T)
   void *Mc;             // [ndof_c][ndof_c] coarsest inverse (T), dof 3 node + c
   MgLevel lv[MG_MAXL];
+};
+
+// One launch of a V-cycle kernel covers up to MG_MAXB slots (grid z = slot).
+constexpr int MG_MAXB = 16;
+struct MgBatch {
+  const SlotDev *slot[MG_MAXB];
+  const MgDev *mg[MG_MAXB];
+  int count;
 };
 
 // V-cycle vector sweeps at one level (grid: chunks x NRHS); see mg_vec_kernel

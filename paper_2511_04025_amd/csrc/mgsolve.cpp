@@ -22,16 +22,15 @@ namespace shh {
 hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long nn1, int prec, hipStream_t st);
 hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st);
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
-hipError_t mg_launch_apply(const MgDev *d_mg, int l, int src, long long nn, int prec, hipStream_t st);
-hipError_t mg_launch_restrict(const MgDev *d_mg, int l, long long nn_coarse, int prec, hipStream_t st);
-hipError_t mg_launch_prolong(const MgDev *d_mg, int l, long long nn_fine, int prec, hipStream_t st);
-hipError_t mg_launch_coarsest(const MgDev *d_mg, int prec, hipStream_t st);
-hipError_t mg_launch_vec(const SlotDev *d_slot, const MgDev *d_mg, int l, int op, int nchunks, int prec,
-                         hipStream_t st);
-hipError_t mg_launch_cg(const SlotDev *d_slot, int op, int nchunks, int prec, hipStream_t st);
-hipError_t mg_launch_scalar(SlotDev *d_slot, int phase, hipStream_t st);
-hipError_t mg_launch_power(const SlotDev *d_slot, const MgDev *d_mg, int l, int phase, double scale, int nchunks,
-                           int prec, hipStream_t st);
+hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st);
+hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
+hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
+hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
+hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st);
+hipError_t mg_launch_cg(const MgBatch &B, int op, int nchunks_max, int prec, hipStream_t st);
+hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st);
+hipError_t mg_launch_power(const SlotDev *d_slot, MgDev *d_mg, int l, int phase, int nchunks, int prec,
+                           hipStream_t st);
 
 namespace {
 
@@ -234,22 +233,20 @@ int coarsest_inverse(Slot &s, hipStream_t st) {
   return upload(A, mg.Mc, prec, st);
 }
 
-int apply(Slot &s, int l, int src, hipStream_t st) {
-  const int prec = s.host.prec;
-  if (l == 0) {
-    const int seg = src == 0 ? SEG_ZQ : SEG_DQ;
-    const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
-    LaunchArgs la{s.d_mgsegs + seg, 1, s.host.ntiles[tiling] * NRHS};
-    SHH_HIP(launch_stencil_apply(la, prec, st));
-    return SHH_OK;
+MgBatch batch_of(const std::vector<Slot *> &slots) {
+  MgBatch B;
+  std::memset(&B, 0, sizeof(B));
+  B.count = int(slots.size());
+  for (int i = 0; i < B.count; ++i) {
+    B.slot[i] = slots[i]->d_slot;
+    B.mg[i] = slots[i]->d_mg;
   }
-  SHH_HIP(mg_launch_apply(s.d_mg, l, src, s.mg.lv[l].nn, prec, st));
-  return SHH_OK;
+  return B;
 }
 
 // Algorithmic bytes of one vector sweep at a level: vectors read and written
-// per node and load case (3 components each) plus the inverse diagonal (one
-// value per node at the voxel level, three on coarse levels) per load case.
+// per node and load case (3 components each) plus the inverse diagonal, once
+// per node (one value at the voxel level, three on coarse levels).
 double vec_bytes(const Slot &s, int l, int op) {
   const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
   const double nn = double(s.mg.lv[l].nn);
@@ -261,38 +258,48 @@ double vec_bytes(const Slot &s, int l, int op) {
     case MGV_POST: vals = 3 * (3 + 3); break;                        // b, q, x -> r, d, x
     default: vals = l == 0 ? 3 * (5 + 1) : 3 * (4 + 1); break;       // r, q, d, x (, b) -> x
   }
-  return NRHS * nn * (vals + dv) * ts;
+  return nn * (NRHS * vals + dv) * ts;
 }
 
-int vcycle(Slot &s, int l, hipStream_t st, Solver *timer) {
-  const int prec = s.host.prec;
-  const MgLevel &L = s.mg.lv[l];
-  if (l == s.mg.L) {
-    SHH_HIP(mg_launch_coarsest(s.d_mg, prec, st));
-    return SHH_OK;
+// One V-cycle from level l down, for slots that all have at least l + 1
+// levels; slots whose coarsest level is l take the dense solve there.
+int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *timer, const MgApply0 &apply0) {
+  const int prec = slots[0]->host.prec;
+  std::vector<Slot *> coarse, smooth;
+  for (Slot *s : slots) (s->mg.L == l ? coarse : smooth).push_back(s);
+  if (!coarse.empty()) SHH_HIP(mg_launch_coarsest(batch_of(coarse), prec, st));
+  if (smooth.empty()) return SHH_OK;
+  const MgBatch B = batch_of(smooth);
+  long long nn_max = 0, nn_next_max = 0;
+  int nch_max = 0;
+  for (Slot *s : smooth) {
+    nn_max = std::max(nn_max, s->mg.lv[l].nn);
+    nn_next_max = std::max(nn_next_max, s->mg.lv[l + 1].nn);
+    nch_max = std::max(nch_max, s->mg.lv[l].nchunks);
   }
   int rc;
   auto vec = [&](int op) -> int {
     hipEvent_t e0 = nullptr;
     if (timer && (rc = timer->timed_begin(&e0))) return rc;
-    SHH_HIP(mg_launch_vec(s.d_slot, s.d_mg, l, op, L.nchunks, prec, st));
-    if (timer) return timer->timed_end(e0, vec_bytes(s, l, op));
+    SHH_HIP(mg_launch_vec(B, l, op, nch_max, prec, st));
+    if (!timer) return SHH_OK;
+    double bytes = 0.0;
+    for (Slot *s : smooth) bytes += vec_bytes(*s, l, op);
+    return timer->timed_end(e0, bytes);
+  };
+  auto app = [&](int src) -> int {
+    if (l == 0) return apply0(smooth, src == 0 ? MG_SRC_Z : MG_SRC_D);
+    SHH_HIP(mg_launch_apply(B, l, src, nn_max, prec, st));
     return SHH_OK;
   };
   // pre-smoother (at the voxel level INIT also applies the pending CG update)
-  if ((rc = vec(MGV_INIT))) return rc;
-  if ((rc = apply(s, l, 1, st))) return rc;
-  if ((rc = vec(MGV_STEP1))) return rc;
-  if ((rc = apply(s, l, 1, st))) return rc;
+  if ((rc = vec(MGV_INIT)) || (rc = app(1)) || (rc = vec(MGV_STEP1)) || (rc = app(1))) return rc;
   // coarse-grid correction of the residual r - A d
-  SHH_HIP(mg_launch_restrict(s.d_mg, l, s.mg.lv[l + 1].nn, prec, st));
-  if ((rc = vcycle(s, l + 1, st, timer))) return rc;
-  SHH_HIP(mg_launch_prolong(s.d_mg, l, L.nn, prec, st));
+  SHH_HIP(mg_launch_restrict(B, l, nn_next_max, prec, st));
+  if ((rc = vcycle(smooth, l + 1, st, timer, apply0))) return rc;
+  SHH_HIP(mg_launch_prolong(B, l, nn_max, prec, st));
   // post-smoother
-  if ((rc = apply(s, l, 0, st))) return rc;
-  if ((rc = vec(MGV_POST))) return rc;
-  if ((rc = apply(s, l, 1, st))) return rc;
-  if ((rc = vec(MGV_LAST))) return rc;
+  if ((rc = app(0)) || (rc = vec(MGV_POST)) || (rc = app(1)) || (rc = vec(MGV_LAST))) return rc;
   return SHH_OK;
 }
 
@@ -351,7 +358,7 @@ int mg_setup(Slot &s, hipStream_t st) {
   Segment sg[NSEG];
   std::memset(sg, 0, sizeof(sg));
   const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
-  const int flags[NSEG] = {0, 1 + 1 + 8 * 4, 1 + 3 + 8 * 4, 1 + 1 + 8 * 4};
+  const int flags[NSEG] = {0, MG_FLAG_ZQ, MG_FLAG_DQ, MG_FLAG_ZQ};
   for (int k = 0; k < NSEG; ++k) {
     sg[k].slot = s.d_slot;
     sg[k].first = 0;
@@ -361,40 +368,35 @@ int mg_setup(Slot &s, hipStream_t st) {
     sg[k].flag = flags[k];
   }
   SHH_HIP(hipMemcpyAsync(s.d_mgsegs, sg, sizeof(sg), hipMemcpyHostToDevice, st));
-  // lambda_max(D^-1 A) of every smoothing level by power iteration on load case 0
-  std::vector<double> parts;
+  // lambda_max(D^-1 A) of every smoothing level by power iteration on load
+  // case 0, entirely on the device (phase 0 start, then per step: apply,
+  // phase 1 sweep, reduction, phase 2 normalization); one read-back at the end
   for (int l = 0; l < mg.L; ++l) {
     const MgLevel &L = mg.lv[l];
-    SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 0, 1.0, L.nchunks, prec, st));
-    parts.resize((size_t)L.nchunks * PSTRIDE);
-    double lam = 0.0;
+    SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 0, L.nchunks, prec, st));
     for (int it = 0; it < POWER_ITERS; ++it) {
       if (l == 0) {
         LaunchArgs la{s.d_mgsegs + SEG_POW, 1, h.ntiles[tiling]};
         SHH_HIP(launch_stencil_apply(la, prec, st));
       } else {
-        SHH_HIP(mg_launch_apply(s.d_mg, l, 0, L.nn, prec, st));
+        SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, prec, st));
       }
-      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 1, 1.0, L.nchunks, prec, st));
-      SHH_HIP(hipMemcpyAsync(parts.data(), h.partials, parts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-      SHH_HIP(hipStreamSynchronize(st));
-      double sum = 0.0, xax = 0.0, xdx = 0.0;
-      for (int c = 0; c < L.nchunks; ++c) {
-        sum += parts[(size_t)c * PSTRIDE];
-        xax += parts[(size_t)c * PSTRIDE + 1];
-        xdx += parts[(size_t)c * PSTRIDE + 2];
-      }
-      const double nrm = std::sqrt(sum);
-      if (!(nrm > 0.0) || !std::isfinite(nrm) || !(xdx > 0.0)) return SHH_BREAKDOWN;
-      // the Rayleigh quotient is a lower bound of lambda_max that converges
-      // twice as fast as the norm ratio
-      lam = std::max(lam, xax / xdx);
-      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 2, 1.0 / nrm, L.nchunks, prec, st));
+      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 1, L.nchunks, prec, st));
+      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 3, L.nchunks, prec, st));
+      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 2, L.nchunks, prec, st));
     }
+  }
+  MgDev est;
+  SHH_HIP(hipMemcpyAsync(&est, s.d_mg, sizeof(MgDev), hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  for (int l = 0; l < mg.L; ++l) {
     MgLevel &W = mg.lv[l];
+    const double lam = est.lv[l].lmax;
+    if (!(lam > 0.0) || !std::isfinite(lam)) return SHH_BREAKDOWN;
     W.lmax = lam;
     if (std::getenv("SHH_MG_VERBOSE"))
       std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f\n", n, l, W.n, lam);
+    // Chebyshev interval [lambda/30, 1.1 lambda] (the Rayleigh quotients bound lambda_max from below)
     const double hi = 1.1 * lam, lo = lam / 30.0;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
     const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
@@ -408,25 +410,36 @@ int mg_setup(Slot &s, hipStream_t st) {
   return SHH_OK;
 }
 
-int mg_iteration(Slot &s, hipStream_t st, Solver *timer) {
-  const int prec = s.host.prec;
-  const int nch = s.host.nchunks;
+int mg_iterate(const std::vector<Slot *> &all, hipStream_t st, Solver *timer, const MgApply0 &apply0) {
+  if (all.empty()) return SHH_OK;
+  const int prec = all[0]->host.prec;
   int rc;
-  if (s.mg_restart) {
-    if ((rc = vcycle(s, 0, st, timer))) return rc;
-    SHH_HIP(mg_launch_scalar(s.d_slot, MGS_RESTART, st));
-    SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));  // beta = 0: p = z
-    s.mg_restart = false;
+  for (size_t b0 = 0; b0 < all.size(); b0 += MG_MAXB) {
+    const std::vector<Slot *> slots(all.begin() + b0, all.begin() + std::min(all.size(), b0 + MG_MAXB));
+    int nch = 0;
+    for (Slot *s : slots) nch = std::max(nch, s->host.nchunks);
+    // (re)started slots: z = V r, rho = r . z, p = z
+    std::vector<Slot *> rs;
+    for (Slot *s : slots)
+      if (s->mg_restart) rs.push_back(s);
+    if (!rs.empty()) {
+      int nchr = 0;
+      for (Slot *s : rs) nchr = std::max(nchr, s->host.nchunks);
+      if ((rc = vcycle(rs, 0, st, timer, apply0))) return rc;
+      const MgBatch R = batch_of(rs);
+      SHH_HIP(mg_launch_scalar(R, MGS_RESTART, st));
+      SHH_HIP(mg_launch_cg(R, MGC_P_UPDATE, nchr, prec, st));  // beta = 0: p = z
+      for (Slot *s : rs) s->mg_restart = false;
+    }
+    const MgBatch B = batch_of(slots);
+    if ((rc = apply0(slots, MG_SRC_P))) return rc;
+    SHH_HIP(mg_launch_cg(B, MGC_DOT_PQ, nch, prec, st));
+    SHH_HIP(mg_launch_scalar(B, MGS_ALPHA, st));
+    // the V-cycle's first sweep applies x += alpha p, r -= alpha q
+    if ((rc = vcycle(slots, 0, st, timer, apply0))) return rc;
+    SHH_HIP(mg_launch_scalar(B, MGS_BETA, st));
+    SHH_HIP(mg_launch_cg(B, MGC_P_UPDATE, nch, prec, st));
   }
-  const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
-  LaunchArgs la{s.d_mgsegs + SEG_PQ, 1, s.host.ntiles[tiling] * NRHS};
-  SHH_HIP(launch_stencil_apply(la, prec, st));
-  SHH_HIP(mg_launch_cg(s.d_slot, MGC_DOT_PQ, nch, prec, st));
-  SHH_HIP(mg_launch_scalar(s.d_slot, MGS_ALPHA, st));
-  // the V-cycle's first sweep applies x += alpha p, r -= alpha q
-  if ((rc = vcycle(s, 0, st, timer))) return rc;
-  SHH_HIP(mg_launch_scalar(s.d_slot, MGS_BETA, st));
-  SHH_HIP(mg_launch_cg(s.d_slot, MGC_P_UPDATE, nch, prec, st));
   return SHH_OK;
 }
 

@@ -315,10 +315,11 @@ int Solver::build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_r
     g.slot = s->d_slot;
     g.first = first;
     g.flag = flag;
-    const bool per_tile = (k == K_STENCIL || k == K_RESID);
+    const bool mg_apply = (k == K_MG_P || k == K_MG_Z || k == K_MG_D);
+    const bool per_tile = (k == K_STENCIL || k == K_RESID || mg_apply);
     const bool scalar = (k == K_SCAL_IT || k == K_SCAL_RES);
-    // the CG pass computes in the vector precision, the residual always in FP64
-    const int tiling = k == K_STENCIL ? s->host.prec : 0;
+    // the CG pass and the operator compute in the vector precision, the residual always in FP64
+    const int tiling = (k == K_STENCIL || mg_apply) ? s->host.prec : 0;
     const int units = scalar ? 1 : (per_tile ? s->host.ntiles[tiling] : s->host.nchunks);
     if (k == K_FOLD || k == K_ZERO) {
       g.nrhs = 1;
@@ -475,10 +476,20 @@ int Solver::iterate(const std::vector<Slot *> &all, int iters) {
 // Multigrid-preconditioned CG: one launch sequence per slot and iteration.
 int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
+  // voxel-level operator over all the given slots, one launch
+  MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
+    const Kind k = src == MG_SRC_P ? K_MG_P : (src == MG_SRC_Z ? K_MG_Z : K_MG_D);
+    const int flag = src == MG_SRC_P ? 0 : (src == MG_SRC_Z ? MG_FLAG_ZQ : MG_FLAG_DQ);
+    LaunchArgs la;
+    int r;
+    if ((r = build(k, ss, flag, true, la))) return r;
+    SHH_HIP(launch_stencil_apply(la, ss[0]->host.prec, st_));
+    return SHH_OK;
+  };
   for (int it = 0; it < iters; ++it) {
+    if ((rc = mg_iterate(slots, st_, profile_on() ? this : nullptr, apply0))) return rc;
     std::vector<Slot *> due;
     for (Slot *s : slots) {
-      if ((rc = mg_iteration(*s, st_, profile_on() ? this : nullptr))) return rc;
       s->launched += 1;
       if (s->R > 0 && s->launched % s->R == 0) due.push_back(s);
     }
