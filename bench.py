@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # any change to them the bench reports null until the counters are taken again.
 PCG_TRAFFIC = {
     "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
-    "sha256": "47e4e70a604b3b52c5860bc7a1faa397bdca5fc6bb84b18fc079f3339e8f6a79",
-    "fetch_bytes_per_node_case": 68.04,
+    "sha256": "dba9d9a889525ba5257ae20f79f2ee94972700dbceb05a873709852d4bf93771",
+    "fetch_bytes_per_node_case": 66.62,
     "write_bytes_per_node_case": 48.01,
 }
 # What a plain 1 GiB device-to-device copy sustains on this GPU (read + write,
@@ -57,12 +57,14 @@ def pcg_traffic_per_node_case():
 
 
 # HBM traffic of the V-cycle vector sweep kernel relative to its algorithmic
-# bytes (FETCH_SIZE x2.0 + WRITE_SIZE x1.0 over the algorithmic bytes of the
-# same launches); null until counters are taken on these sources.
+# bytes: FETCH_SIZE x2.0 + WRITE_SIZE x1.0 summed over every launch of one
+# timed step of the default workload, over the algorithmic bytes the library
+# reported for the same launches (profiles/mg_vcycle_128_hbm_traffic.md).  It
+# holds only for the sources it was measured on (digest); null otherwise.
 MG_VEC_TRAFFIC = {
-    "sources": ("mg.hip", "mg.hpp", "common.hpp"),
-    "sha256": None,
-    "traffic_per_algorithmic_byte": None,
+    "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
+    "sha256": "2db2efd341ce142a5921ed028ec8a0ff1049e8148b2220c0b83281ad557b72a7",
+    "traffic_per_algorithmic_byte": 0.9726,
 }
 
 
@@ -123,7 +125,8 @@ def serving_trace(args):
     import torch
     from paper_2511_04025_amd import serving, workloads as wl
     designs = wl.serving_trace(count=args.trace_count)
-    engine = serving.Engine(int(args.arena_gb * (1 << 30)), max_slots=256, precision="mixed", rtol=args.rtol)
+    engine = serving.Engine(int(args.arena_gb * (1 << 30)), max_slots=256, precision="mixed", rtol=args.rtol,
+                            solver=args.solver)
     rate = args.rate
     if rate <= 0:
         # saturated throughput of a closed batch of the first 16 requests
@@ -152,7 +155,8 @@ def serving_trace(args):
         "value": round(len(designs) / wall, 4), "unit": "designs/s", "n_gpus": 1,
         "higher_is_better": True, "data": "synthetic",
         "config": {"workload": f"serving trace: {len(designs)} requests, n in {{64,96,128}}, N U{{16..64}}, "
-                               f"V U[0.03,0.2], void E 1e-6, mixed, rtol {args.rtol}", "rate": round(rate, 4)},
+                               f"V U[0.03,0.2], void E 1e-6, mixed, rtol {args.rtol}, solver {args.solver}",
+                   "rate": round(rate, 4)},
         "latency_p50_s": round(float(np.percentile(L, 50)), 4),
         "latency_p99_s": round(float(np.percentile(L, 99)), 4),
         "latency_p50_by_n": {str(k): round(float(np.percentile(v, 50)), 4) for k, v in sorted(by_n.items())},
@@ -170,7 +174,7 @@ def inverse_step(args):
     designs = wl.smooth_shell_96_batch(n=args.inverse_n, count=args.inverse_batch)
     t = AG.initial_thickness(designs)
     spec = AG.Spec(n=args.inverse_n, thickness=t, kappa=designs[0].kappa, E_void=designs[0].E_void,
-                   precision="mixed", rtol=args.rtol)
+                   precision="mixed", rtol=args.rtol, solver=args.solver)
     pos = torch.tensor(np.stack([d.pos for d in designs]), dtype=torch.float64, requires_grad=True)
     q = torch.tensor(np.stack([d.q for d in designs]), dtype=torch.float64, requires_grad=True)
     times = []
@@ -195,7 +199,7 @@ def inverse_step(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 1), "higher_is_better": True,
         "data": "synthetic",
         "config": {"workload": f"smooth_shell_96: batch {args.inverse_batch} at {args.inverse_n}^3, 32 charges +-1, "
-                               f"logistic shell kappa=4n, t from V=0.10, mixed, rtol {args.rtol}"},
+                               f"logistic shell kappa=4n, t from V=0.10, mixed, rtol {args.rtol}, solver {args.solver}"},
         "grad_norm_pos": float(pos.grad.norm()), "grad_norm_q": float(q.grad.norm())}))
 
 

@@ -35,6 +35,7 @@ class Spec:
     precision: str = "mixed"
     rtol: Optional[float] = None
     max_iter: int = 20000
+    solver: str = "jacobi"
     state: dict = dc_field(default_factory=dict)
 
     def designs(self, pos, q):
@@ -61,7 +62,7 @@ class Homogenize(torch.autograd.Function):
         designs = spec.designs(P, Q)
         outs, ws, opts = api.homogenize_batch(designs, precision=spec.precision, rtol=spec.rtol,
                                               max_iter=spec.max_iter, save_for_backward=True,
-                                              return_workspaces=True)
+                                              return_workspaces=True, solver=spec.solver)
         spec.state["last"] = outs
         ctx.spec = spec
         ctx.designs = designs

@@ -113,6 +113,31 @@ void dense_k0(const double kop[KOP_N], double K0[24][24]) {
   }
 }
 
+// lambda_max(diag(K_0)^-1 K_0): since K = sum_e E_e K_0 with D = sum_e E_e
+// diag(K_0), x^T K x <= this value times x^T D x, so it bounds
+// lambda_max(D^-1 K) on the voxel grid whatever the moduli.  Power iteration
+// on the symmetric D_0^-1/2 K_0 D_0^-1/2 with Rayleigh quotients.
+double element_bound(const double K0[24][24]) {
+  double v[24], w[24], lam = 0.0;
+  for (int i = 0; i < 24; ++i) v[i] = 1.0 + 0.01 * i * ((i & 1) ? -1.0 : 1.0);
+  for (int it = 0; it < 4000; ++it) {
+    double nv = 0.0;
+    for (int i = 0; i < 24; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    for (int i = 0; i < 24; ++i) v[i] /= nv;
+    double rq = 0.0;
+    for (int i = 0; i < 24; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < 24; ++j) a += K0[i][j] / std::sqrt(K0[i][i] * K0[j][j]) * v[j];
+      w[i] = a;
+      rq += v[i] * a;
+    }
+    lam = rq;
+    for (int i = 0; i < 24; ++i) v[i] = w[i];
+  }
+  return lam;
+}
+
 double qweight(int f, int b, int a) {
   double w = 1.0;
   for (int d = 0; d < 3; ++d) {
@@ -344,6 +369,7 @@ int mg_setup(Slot &s, hipStream_t st) {
   // child Galerkin matrices of this Poisson ratio's K_0
   double K0[24][24];
   dense_k0(h.kop64, K0);
+  const double bound0 = element_bound(K0);
   std::vector<double> G;
   child_galerkin(K0, G);
   int rc;
@@ -396,8 +422,12 @@ int mg_setup(Slot &s, hipStream_t st) {
     W.lmax = lam;
     if (std::getenv("SHH_MG_VERBOSE"))
       std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f\n", n, l, W.n, lam);
-    // Chebyshev interval [lambda/30, 1.1 lambda] (the Rayleigh quotients bound lambda_max from below)
-    const double hi = 1.1 * lam, lo = lam / 30.0;
+    // Chebyshev interval [hi/33, hi]: above lambda_max, or the smoother
+    // amplifies the top of the spectrum and the V-cycle stops being positive
+    // definite.  The Rayleigh quotients bound lambda_max from below, so the
+    // voxel level takes the rigorous element bound and coarse levels a
+    // generous 1.5 x the estimate.
+    const double hi = l == 0 ? std::max(bound0, 1.1 * lam) : 1.5 * lam, lo = hi / 33.0;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
     const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
     W.inv_theta = 1.0 / theta;

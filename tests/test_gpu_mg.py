@@ -108,3 +108,21 @@ def test_mixed_vs_fp64_at_128_served():
         rel, small, _ = ch_errors(a["C"], b["C"])
         print("mg 128 iters", a["iters"], "fp64", b["iters"], "rel", rel, "small", small, flush=True)
         assert rel <= 1e-4 and small <= 1e-7
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-11, 1e-7), ("mixed", 1e-7, 1e-4)])
+def test_adjoint_after_multigrid_solve(precision, rtol, tol):
+    # the adjoint reads the solution the multigrid solver left; against the
+    # oracle's stored design gradients
+    A = api()
+    g = golden("smooth_shell_n24_seed5000.json")
+    d = wl.smooth_shell_96(5000, n=24).with_(thickness=g["t"])
+    r = A.homogenize(d, precision=precision, rtol=rtol, save_for_backward=True, return_workspace=True,
+                     solver="mg")
+    assert r["status"] == 0
+    for tag, dV in (("loss", 0.0), ("rand", g["dL_dV_rand"])):
+        dpos, dq = A.grad(d, r["opts"], r["workspace"], np.array(g[f"dL_dC_{tag}"]), dV)
+        ref_p, ref_q = np.array(g[f"dpos_{tag}"]), np.array(g[f"dq_{tag}"])
+        scale = max(np.abs(ref_p).max(), np.abs(ref_q).max())
+        assert np.max(np.abs(dpos - ref_p)) <= tol * scale, tag
+        assert np.max(np.abs(dq - ref_q)) <= tol * scale, tag
