@@ -126,3 +126,13 @@ def test_adjoint_after_multigrid_solve(precision, rtol, tol):
         scale = max(np.abs(ref_p).max(), np.abs(ref_q).max())
         assert np.max(np.abs(dpos - ref_p)) <= tol * scale, tag
         assert np.max(np.abs(dq - ref_q)) <= tol * scale, tag
+
+
+def test_serving_trace_design_that_broke_down():
+    # a 128^3 design whose power estimate of lambda_max(D^-1 K) fell short:
+    # with the rigorous voxel-level bound the V-cycle stays positive definite
+    A = api()
+    d = wl.serving_trace(count=64)[14]
+    assert d.n == 128
+    r = A.homogenize(d, precision="mixed", rtol=1e-5, solver="mg")
+    assert r["status"] == 0 and r["iters"].max() < 200
