@@ -174,6 +174,19 @@ int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, dou
                             int32_t nrhs, const void *d_p, void *d_q, void *d_ws, size_t ws_bytes,
                             void *hip_stream);
 
+/* The Galerkin coarse operator of level `level` (1 <= level < number of
+   levels; level l halves each axis l times) of the multigrid solver's
+   hierarchy for the moduli d_E (device n^3 doubles) at Poisson ratio nu:
+   d_q = A_l d_v with A_l = P_l^T ... P_1^T K P_1 ... P_l, P trilinear periodic
+   prolongation (Sec. 4.2's coarse grids).  d_v, d_q: device [6][3][(n/2^l)^3]
+   in the precision's type (doubles for SHH_PREC_FP64, floats for MIXED).
+   d_ws: at least shh_workspace_bytes_stiffness(n, opts) bytes for opts with
+   this precision and solver = SHH_SOLVER_MG.  SHH_UNSUPPORTED for grids the
+   hierarchy cannot coarsen, SHH_INVALID_ARG for other levels.  Builds the
+   hierarchy, so it costs a solver setup; synchronizes the stream. */
+int32_t shh_mg_operator(int32_t n, int32_t precision, const double *d_E, double nu, int32_t level,
+                        const void *d_v, void *d_q, void *d_ws, size_t ws_bytes, void *hip_stream);
+
 /* Right-hand sides f^(k) = -sum_e E_e P_e^T K_0 chi^k of the six load cases
    (Eq. (8)) in FP64: d_f [6][3][n^3].  d_ws as for shh_apply_stiffness with
    precision SHH_PREC_FP64. */

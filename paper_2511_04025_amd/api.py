@@ -94,8 +94,8 @@ def homogenize_batch(designs, precision="mixed", rtol=None, max_iter=20000, reco
     return outs
 
 
-def stiffness_workspace_bytes(n, precision="fp64"):
-    opts = B.make_opts(precision)
+def stiffness_workspace_bytes(n, precision="fp64", solver="jacobi"):
+    opts = B.make_opts(precision, solver=solver)
     nb = c_size_t(0)
     B.check(B.lib().shh_workspace_bytes_stiffness(int(n), byref(opts), byref(nb)), "shh_workspace_bytes_stiffness")
     return nb.value
@@ -166,6 +166,24 @@ def apply_stiffness(E, p, nu, precision="fp64"):
     rc = B.lib().shh_apply_stiffness(n, prec, _ptr(E), c_double(nu), m, _ptr(p), _ptr(q), ws.ptr,
                                      c_size_t(ws.nbytes), _stream())
     B.check(rc, "shh_apply_stiffness")
+    return q
+
+
+def mg_operator(E, v, nu, level, precision="fp64"):
+    """q = A_level v for the multigrid hierarchy's Galerkin operator of level
+    `level` >= 1; v (6, 3, m, m, m) with m = n / 2^level."""
+    _require_gpu()
+    n = _check_grid(E)
+    want = torch.float64 if precision == "fp64" else torch.float32
+    m = n >> level
+    if not (v.is_cuda and v.dtype == want and v.is_contiguous() and tuple(v.shape) == (6, 3, m, m, m)):
+        raise ValueError("v must be a contiguous CUDA tensor (6, 3, m, m, m) of the precision's dtype")
+    q = torch.empty_like(v)
+    ws = Workspace(stiffness_workspace_bytes(n, precision, solver="mg"))
+    prec = B.PREC_FP64 if precision == "fp64" else B.PREC_MIXED
+    rc = B.lib().shh_mg_operator(n, prec, _ptr(E), c_double(nu), int(level), _ptr(v), _ptr(q), ws.ptr,
+                                 c_size_t(ws.nbytes), _stream())
+    B.check(rc, "shh_mg_operator")
     return q
 
 

@@ -67,6 +67,8 @@ EXPORTS = {
                                        POINTER(c_size_t), c_void_p, POINTER(ShhResult)]),
     "shh_workspace_bytes_stiffness": (c_int32, [c_int32, POINTER(ShhOpts), POINTER(c_size_t)]),
     "shh_workspace_bytes_operator": (c_int32, [c_int32, c_int32, POINTER(c_size_t)]),
+    "shh_mg_operator": (c_int32, [c_int32, c_int32, c_void_p, c_double, c_int32, c_void_p, c_void_p, c_void_p,
+                                  c_size_t, c_void_p]),
     "shh_homogenize_stiffness": (c_int32, [c_int32, c_void_p, c_double, POINTER(ShhOpts), c_void_p, c_size_t,
                                            c_void_p, POINTER(ShhResult)]),
     "shh_field": (c_int32, [POINTER(ShhDesign), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p,

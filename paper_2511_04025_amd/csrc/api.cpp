@@ -308,6 +308,26 @@ int32_t shh_apply_stiffness(int32_t n, int32_t precision, const double *d_E, dou
   return SHH_OK;
 }
 
+int32_t shh_mg_operator(int32_t n, int32_t precision, const double *d_E, double nu, int32_t level,
+                        const void *d_v, void *d_q, void *d_ws, size_t ws_bytes, void *hip_stream) {
+  if (!d_v || !d_q) return SHH_INVALID_ARG;
+  shh_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = precision;
+  o.rtol = 1e-10;
+  o.max_iter = 1;
+  o.solver = SHH_SOLVER_MG;
+  SHH_TRY(normalize_opts(&o, &o));
+  SHH_TRY(check_solver(n, &o));
+  if (level < 1 || level >= mg_num_levels(n)) return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  char *seg_mem = nullptr;
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true));
+  SHH_TRY(mg_setup(s, st));
+  return mg_apply_level(s, level, d_v, d_q, st);
+}
+
 int32_t shh_load_vectors(int32_t n, const double *d_E, double nu, double *d_f, void *d_ws, size_t ws_bytes,
                          void *hip_stream) {
   if (!d_f) return SHH_INVALID_ARG;

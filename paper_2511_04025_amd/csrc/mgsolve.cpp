@@ -440,6 +440,17 @@ int mg_setup(Slot &s, hipStream_t st) {
   return SHH_OK;
 }
 
+int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
+  if (l < 1 || l > s.mg.L) return SHH_INVALID_ARG;
+  const MgLevel &L = s.mg.lv[l];
+  const size_t bytes = (size_t)NRHS * 3 * L.nn * (s.host.prec == SHH_PREC_FP64 ? 8 : 4);
+  SHH_HIP(hipMemcpyAsync(L.x, d_v, bytes, hipMemcpyDeviceToDevice, st));
+  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, s.host.prec, st));
+  SHH_HIP(hipMemcpyAsync(d_q, L.q, bytes, hipMemcpyDeviceToDevice, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
 int mg_iterate(const std::vector<Slot *> &all, hipStream_t st, Solver *timer, const MgApply0 &apply0) {
   if (all.empty()) return SHH_OK;
   const int prec = all[0]->host.prec;

@@ -77,6 +77,9 @@ using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // (timer: when profiling, the V-cycle vector sweeps are timed with their
 // algorithmic bytes)
 int mg_iterate(const std::vector<Slot *> &slots, hipStream_t st, Solver *timer, const MgApply0 &apply0);
+// q = A_l v for the Galerkin operator of level l >= 1 of a set-up slot (all six
+// load cases, [6][3][n_l^3] in the slot's precision)
+int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st);
 void copy_design(const shh_design *src, DesignCopy &dst);
 
 // Fill the slot descriptor for a region and upload it (+ charges, alpha, zeroed state).

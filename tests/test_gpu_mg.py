@@ -136,3 +136,27 @@ def test_serving_trace_design_that_broke_down():
     assert d.n == 128
     r = A.homogenize(d, precision="mixed", rtol=1e-5, solver="mg")
     assert r["status"] == 0 and r["iters"].max() < 200
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+def test_coarse_operators_are_galerkin_products(precision, tol):
+    # levels 1 and 2 of the hierarchy against P^T K P and P^T (P^T K P) P
+    from oracle import fem, multigrid as omg
+    from gpu_helpers import nodal_to_oracle, oracle_to_nodal
+    A = api()
+    n, nu = 16, 0.3
+    rng = np.random.default_rng(16)
+    E = np.where(rng.random((n, n, n)) < 0.35, 1.0, 1e-3) * rng.uniform(0.5, 1.0, (n, n, n))
+    K1 = omg.galerkin(fem.assemble(E, nu, n), n)
+    K2 = omg.galerkin(K1, n // 2)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    for level, Kl in ((1, K1), (2, K2)):
+        m = n >> level
+        U = rng.standard_normal((3 * m ** 3, 6))
+        if precision == "mixed":
+            U = U.astype(np.float32).astype(np.float64)
+        Q = Kl @ U
+        v = torch.tensor(oracle_to_nodal(U, m), dtype=dt, device="cuda")
+        q = A.mg_operator(torch.tensor(E, device="cuda"), v, nu, level, precision)
+        Qg = nodal_to_oracle(q.double().cpu().numpy(), m)
+        assert np.max(np.abs(Qg - Q)) <= tol * np.abs(Q).max(), level
