@@ -100,8 +100,9 @@ __global__ __launch_bounds__(256) void mg_elemc_kernel(const MgDev *mg, int l) {
   for (int j = 0; j < 24; ++j) out[j] = (T)row[j];
 }
 
-// Nodal 27-point stencil of level l from its element matrices, and D^-1.
-// Node v is corner a of element v - a; entry (v, v - a + b) gathers K_e[a][b].
+// Nodal stencil of level l from its element matrices (the 14 stored offsets),
+// and D^-1.  Node v is corner a of element v - a; entry (v, v - a + b)
+// gathers K_e[a][b].
 template <typename T>
 __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l) {
   const MgLevel &L = mg->lv[l];
@@ -111,8 +112,7 @@ __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l)
   const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
   const T *Ke = (const T *)L.Ke;
   T *S = (T *)L.S;
-  for (int w = 0; w < 27; ++w)
-    for (int k = 0; k < 9; ++k) S[(w * 9 + k) * L.nn + v] = T(0);
+  for (int k = 0; k < MG_STENCIL; ++k) S[k * L.nn + v] = T(0);
   double diag[3] = {0.0, 0.0, 0.0};
   for (int a = 0; a < 8; ++a) {
     const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
@@ -121,10 +121,11 @@ __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l)
     for (int b = 0; b < 8; ++b) {
       const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
       const int w = ((bz - az + 1) * 3 + (by - ay + 1)) * 3 + (bx - ax + 1);
+      if (w < 13) continue;  // stored by the neighbour, transposed
       for (int c = 0; c < 3; ++c)
         for (int cp = 0; cp < 3; ++cp) {
           const T kv = K[(3 * a + c) * 24 + 3 * b + cp];
-          T *dst = S + (w * 9 + 3 * c + cp) * L.nn + v;
+          T *dst = S + ((w - 13) * 9 + 3 * c + cp) * L.nn + v;
           *dst = *dst + kv;
           if (b == a && cp == c) diag[c] += (double)kv;
         }
@@ -163,8 +164,16 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
     const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
     const long long u = ((long long)wrap1(z + dz, n) * n + wrap1(y + dy, n)) * n + wrap1(x + dx, n);
     T blk[9];
+    if (w >= 13) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) blk[k] = S[(w * 9 + k) * nn + v];
+      for (int k = 0; k < 9; ++k) blk[k] = S[((w - 13) * 9 + k) * nn + v];
+    } else {
+      // A[v][u] = A[u][v]^T, stored at u for offset 26 - w
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int cp = 0; cp < 3; ++cp) blk[3 * c + cp] = S[((13 - w) * 9 + 3 * cp + c) * nn + u];
+    }
 #pragma unroll
     for (int r = 0; r < RHS; ++r) {
       const T *vr = in + (long long)r * 3 * nn;

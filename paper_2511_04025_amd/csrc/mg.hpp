@@ -23,13 +23,19 @@ namespace shh {
 
 constexpr int MG_MAXL = 10;          // levels including the voxel grid
 constexpr int MG_MAX_COARSE = 8;     // coarsest grid at most 8^3 nodes
-constexpr int MG_STENCIL = 27 * 9;   // values of one node's 27-point 3 x 3-block stencil
+// A coarse operator is symmetric, so a node stores the 3 x 3 blocks of the 14
+// neighbour offsets w = 13..26 of the 27 (w = 9 (dz + 1) + 3 (dy + 1) + dx + 1;
+// 13 is the node itself); the block of offset w < 13 is the transpose of the
+// block the neighbour at that offset stores for offset 26 - w.
+constexpr int MG_HALF = 14;
+constexpr int MG_STENCIL = MG_HALF * 9;  // stored values per node
 
 struct MgLevel {
   int n;
   int nchunks;          // CHUNK-node chunks of the level (vector kernels)
   long long nn;
-  // levels >= 1: nodal stencil [27 * 9][nn] (entry (w, c, c') at (w * 9 + 3 c + c') * nn),
+  // levels >= 1: nodal stencil [14 * 9][nn] (block of offset w >= 13, entry (c, c')
+  // at ((w - 13) * 9 + 3 c + c') * nn),
   // inverse diagonal [3][nn]; level 0 uses the slot's matrix-free operator and D^-1 [nn]
   void *S, *Dinv;
   // V-cycle vectors [NRHS][3][nn]: right-hand side, iterate, residual,

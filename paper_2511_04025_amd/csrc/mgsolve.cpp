@@ -241,12 +241,15 @@ int coarsest_inverse(Slot &s, hipStream_t st) {
   double dsum = 0.0;
   for (long long v = 0; v < nn; ++v) {
     const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
-    for (int w = 0; w < 27; ++w) {
+    for (int w = 13; w < 27; ++w) {  // stored offsets; the others by symmetry
       const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
       const long long u = ((long long)((z + dz + n) % n) * n + (y + dy + n) % n) * n + (x + dx + n) % n;
       for (int c = 0; c < 3; ++c)
-        for (int cp = 0; cp < 3; ++cp)
-          A[(size_t)(3 * v + c) * m + 3 * u + cp] += S[(size_t)(w * 9 + 3 * c + cp) * nn + v];
+        for (int cp = 0; cp < 3; ++cp) {
+          const double a = S[(size_t)((w - 13) * 9 + 3 * c + cp) * nn + v];
+          A[(size_t)(3 * v + c) * m + 3 * u + cp] += a;
+          if (w != 13) A[(size_t)(3 * u + cp) * m + 3 * v + c] += a;
+        }
     }
   }
   for (int i = 0; i < m; ++i) dsum += A[(size_t)i * m + i];
