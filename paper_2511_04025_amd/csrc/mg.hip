@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(MgBatch B) {
   const int k = blockIdx.x;
   const int nd = mg->ndof_c;
   const long long nn = L.nn;
-  const T *M = (const T *)mg->Mc;
+  const double *M = mg->Mc;
   const T *b = (const T *)L.b + (long long)k * 3 * nn;
   T *x = (T *)L.x + (long long)k * 3 * nn;
   const int part = threadIdx.x & 3;
@@ -537,6 +537,72 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_power_reduce_kernel(const Slot
   L.pw_scale = 1.0 / nrm;
 }
 
+// The coarsest level's dense inverse, in one workgroup: assemble the
+// operator from the stored stencil blocks (row 3 v + c gathers every block of
+// node v, the lower offsets transposed from the neighbours), add gamma / nn to
+// each component's constant block (gamma = mean diagonal; this makes the
+// operator nonsingular on the rigid translations and leaves its inverse on
+// the range equal to the pseudo-inverse), then invert in place by
+// Gauss-Jordan elimination (the matrix is symmetric positive definite, so no
+// pivoting).  FP64 throughout.
+template <typename T>
+__global__ __launch_bounds__(1024) void mg_coarse_inverse_kernel(MgDev *mg) {
+  __shared__ double red[16];
+  const MgLevel &L = mg->lv[mg->L];
+  const int n = L.n, m = mg->ndof_c;
+  const long long nn = L.nn;
+  const T *S = (const T *)L.S;
+  double *A = mg->Mc;
+  for (long long k = threadIdx.x; k < (long long)m * m; k += blockDim.x) A[k] = 0.0;
+  __syncthreads();
+  for (int row = threadIdx.x; row < m; row += blockDim.x) {
+    const long long v = row / 3;
+    const int c = row % 3;
+    const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
+    for (int w = 0; w < 27; ++w) {
+      const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
+      const long long u = ((long long)wrap1(z + dz, n) * n + wrap1(y + dy, n)) * n + wrap1(x + dx, n);
+#pragma unroll
+      for (int cp = 0; cp < 3; ++cp) {
+        const double a = w >= 13 ? (double)S[((w - 13) * 9 + 3 * c + cp) * nn + v]
+                                  : (double)S[((13 - w) * 9 + 3 * cp + c) * nn + u];
+        A[(long long)row * m + 3 * u + cp] += a;
+      }
+    }
+  }
+  __syncthreads();
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < m; i += blockDim.x) acc[0] += A[(long long)i * m + i];
+  block_sum<1>(acc, red, blockDim.x);
+  if (threadIdx.x == 0) red[0] = acc[0];
+  __syncthreads();
+  const double add = red[0] / m / double(nn);
+  for (long long k = threadIdx.x; k < (long long)m * m; k += blockDim.x) {
+    const int i = int(k / m), j = int(k % m);
+    if (i % 3 == j % 3) A[k] += add;
+  }
+  __syncthreads();
+  // column k of the current matrix, kept while the rows are updated
+  __shared__ double colk[3 * MG_MAX_COARSE * MG_MAX_COARSE * MG_MAX_COARSE];
+  for (int k = 0; k < m; ++k) {
+    const double piv = A[(long long)k * m + k];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) colk[i] = A[(long long)i * m + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      const long long kj = (long long)k * m + j;
+      A[kj] = j == k ? 1.0 / piv : A[kj] / piv;
+    }
+    __syncthreads();
+    // rows i != k: A[i][j] -= f_i A[k][j] (j != k), A[i][k] = -f_i / piv
+    for (long long t = threadIdx.x; t < (long long)m * m; t += blockDim.x) {
+      const int i = int(t / m), j = int(t % m);
+      if (i == k) continue;
+      A[t] = (j == k ? 0.0 : A[t]) - colk[i] * A[(long long)k * m + j];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -554,6 +620,12 @@ hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec
   const unsigned g = blocks_for(nn_next * 24, 256);
   if (prec == 0) mg_elemc_kernel<double><<<g, 256, 0, st>>>(d_mg, l);
   else mg_elemc_kernel<float><<<g, 256, 0, st>>>(d_mg, l);
+  return hipGetLastError();
+}
+
+hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st) {
+  if (prec == 0) mg_coarse_inverse_kernel<double><<<1, 1024, 0, st>>>(d_mg);
+  else mg_coarse_inverse_kernel<float><<<1, 1024, 0, st>>>(d_mg);
   return hipGetLastError();
 }
 

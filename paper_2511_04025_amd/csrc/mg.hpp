@@ -14,7 +14,7 @@
 // on D^-1 A over [lambda_max / 30, 1.1 lambda_max], lambda_max estimated by
 // power iteration; the coarsest level (at most 8^3 nodes) is solved with a
 // dense inverse of its operator made nonsingular on the three rigid
-// translations.
+// translations, assembled and inverted on the device.
 #pragma once
 
 #include "common.hpp"
@@ -52,7 +52,7 @@ struct MgDev {
   int L;                // index of the coarsest level
   int ndof_c;           // 3 n_L^3
   void *G;              // [8][24][24] child Galerkin matrices of K_0 (T)
-  void *Mc;             // [ndof_c][ndof_c] coarsest inverse (T), dof 3 node + c
+  double *Mc;           // [ndof_c][ndof_c] coarsest inverse (FP64), dof 3 node + c
   MgLevel lv[MG_MAXL];
 };
 

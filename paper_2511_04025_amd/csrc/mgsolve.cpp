@@ -22,6 +22,7 @@ namespace shh {
 hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long nn1, int prec, hipStream_t st);
 hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st);
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
+hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st);
 hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
 hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
@@ -36,7 +37,9 @@ namespace {
 
 size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 
-constexpr int SEG_PQ = 0, SEG_ZQ = 1, SEG_DQ = 2, SEG_POW = 3, NSEG = 4;
+// the slot's own segment table: the power iteration's voxel-level operator
+// on load case 0 (the iteration's operator launches use the solver's tables)
+constexpr int NSEG = 1;
 constexpr int POWER_ITERS = 30;  // power steps per level
 
 // Lay out the multigrid region at `base` (nullptr: sizing only).  Fills the
@@ -82,10 +85,10 @@ size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mg
     }
   }
   const long long nc = nl * nl * nl;
-  char *Mc = take((size_t)(3 * nc) * (3 * nc) * ts);
+  char *Mc = take((size_t)(3 * nc) * (3 * nc) * sizeof(double));
   if (mg) {
     mg->ndof_c = int(3 * nc);
-    mg->Mc = Mc;
+    mg->Mc = (double *)Mc;
   }
   return off;
 }
@@ -171,39 +174,6 @@ void child_galerkin(const double K0[24][24], std::vector<double> &G) {
   }
 }
 
-// In-place inverse of a dense SPD-made matrix (Gauss-Jordan, partial pivoting).
-bool invert(std::vector<double> &A, int m) {
-  std::vector<double> I((size_t)m * m, 0.0);
-  for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
-  for (int c = 0; c < m; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < m; ++r)
-      if (std::fabs(A[(size_t)r * m + c]) > std::fabs(A[(size_t)piv * m + c])) piv = r;
-    if (!(std::fabs(A[(size_t)piv * m + c]) > 0.0)) return false;
-    if (piv != c)
-      for (int k = 0; k < m; ++k) {
-        std::swap(A[(size_t)c * m + k], A[(size_t)piv * m + k]);
-        std::swap(I[(size_t)c * m + k], I[(size_t)piv * m + k]);
-      }
-    const double inv = 1.0 / A[(size_t)c * m + c];
-    for (int k = 0; k < m; ++k) {
-      A[(size_t)c * m + k] *= inv;
-      I[(size_t)c * m + k] *= inv;
-    }
-    for (int r = 0; r < m; ++r) {
-      if (r == c) continue;
-      const double f = A[(size_t)r * m + c];
-      if (f == 0.0) continue;
-      for (int k = 0; k < m; ++k) {
-        A[(size_t)r * m + k] -= f * A[(size_t)c * m + k];
-        I[(size_t)r * m + k] -= f * I[(size_t)c * m + k];
-      }
-    }
-  }
-  A.swap(I);
-  return true;
-}
-
 template <typename T>
 int upload_as(const std::vector<double> &src, void *dst, hipStream_t st) {
   std::vector<T> tmp(src.size());
@@ -215,50 +185,6 @@ int upload_as(const std::vector<double> &src, void *dst, hipStream_t st) {
 
 int upload(const std::vector<double> &src, void *dst, int prec, hipStream_t st) {
   return prec == SHH_PREC_FP64 ? upload_as<double>(src, dst, st) : upload_as<float>(src, dst, st);
-}
-
-// Dense operator of the coarsest level from its nodal stencil, made
-// nonsingular on the rigid translations (+ gamma / nn on each component's
-// constant block), inverted on the host.
-int coarsest_inverse(Slot &s, hipStream_t st) {
-  MgDev &mg = s.mg;
-  const MgLevel &L = mg.lv[mg.L];
-  const int prec = s.host.prec;
-  const long long nn = L.nn;
-  const int n = L.n, m = mg.ndof_c;
-  const size_t cnt = (size_t)MG_STENCIL * nn;
-  std::vector<double> S(cnt);
-  if (prec == SHH_PREC_FP64) {
-    SHH_HIP(hipMemcpyAsync(S.data(), L.S, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
-    SHH_HIP(hipStreamSynchronize(st));
-  } else {
-    std::vector<float> Sf(cnt);
-    SHH_HIP(hipMemcpyAsync(Sf.data(), L.S, cnt * sizeof(float), hipMemcpyDeviceToHost, st));
-    SHH_HIP(hipStreamSynchronize(st));
-    for (size_t i = 0; i < cnt; ++i) S[i] = Sf[i];
-  }
-  std::vector<double> A((size_t)m * m, 0.0);
-  double dsum = 0.0;
-  for (long long v = 0; v < nn; ++v) {
-    const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
-    for (int w = 13; w < 27; ++w) {  // stored offsets; the others by symmetry
-      const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
-      const long long u = ((long long)((z + dz + n) % n) * n + (y + dy + n) % n) * n + (x + dx + n) % n;
-      for (int c = 0; c < 3; ++c)
-        for (int cp = 0; cp < 3; ++cp) {
-          const double a = S[(size_t)((w - 13) * 9 + 3 * c + cp) * nn + v];
-          A[(size_t)(3 * v + c) * m + 3 * u + cp] += a;
-          if (w != 13) A[(size_t)(3 * u + cp) * m + 3 * v + c] += a;
-        }
-    }
-  }
-  for (int i = 0; i < m; ++i) dsum += A[(size_t)i * m + i];
-  const double gamma = dsum / m / double(nn);
-  for (long long v = 0; v < nn; ++v)
-    for (long long u = 0; u < nn; ++u)
-      for (int c = 0; c < 3; ++c) A[(size_t)(3 * v + c) * m + 3 * u + c] += gamma;
-  if (!invert(A, m)) return SHH_BREAKDOWN;
-  return upload(A, mg.Mc, prec, st);
 }
 
 MgBatch batch_of(const std::vector<Slot *> &slots) {
@@ -381,22 +307,18 @@ int mg_setup(Slot &s, hipStream_t st) {
   SHH_HIP(mg_launch_elem1(s.d_slot, s.d_mg, mg.lv[1].nn, prec, st));
   for (int l = 1; l + 1 < count; ++l) SHH_HIP(mg_launch_elemc(s.d_mg, l, mg.lv[l + 1].nn, prec, st));
   for (int l = 1; l < count; ++l) SHH_HIP(mg_launch_stencil(s.d_mg, l, mg.lv[l].nn, prec, st));
-  if ((rc = coarsest_inverse(s, st))) return rc;
-  // voxel-level operator launches: flag 0 is p[0] -> q[0], else 1 + src + 8 dst
-  // over (r0, r1, p0, p1, q0, q1, x)
-  Segment sg[NSEG];
-  std::memset(sg, 0, sizeof(sg));
+  SHH_HIP(mg_launch_coarse_inverse(s.d_mg, prec, st));
+  // the power iteration's voxel-level operator: z (r[1]) -> q[0], load case 0
+  Segment sg;
+  std::memset(&sg, 0, sizeof(sg));
   const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
-  const int flags[NSEG] = {0, MG_FLAG_ZQ, MG_FLAG_DQ, MG_FLAG_ZQ};
-  for (int k = 0; k < NSEG; ++k) {
-    sg[k].slot = s.d_slot;
-    sg[k].first = 0;
-    sg[k].nrhs = k == SEG_POW ? 1 : NRHS;
-    for (int r = 0; r < sg[k].nrhs; ++r) sg[k].rhs[r] = r;
-    sg[k].nblocks = h.ntiles[tiling] * sg[k].nrhs;
-    sg[k].flag = flags[k];
-  }
-  SHH_HIP(hipMemcpyAsync(s.d_mgsegs, sg, sizeof(sg), hipMemcpyHostToDevice, st));
+  sg.slot = s.d_slot;
+  sg.first = 0;
+  sg.nrhs = 1;
+  sg.rhs[0] = 0;
+  sg.nblocks = h.ntiles[tiling];
+  sg.flag = MG_FLAG_ZQ;
+  SHH_HIP(hipMemcpyAsync(s.d_mgsegs, &sg, sizeof(sg), hipMemcpyHostToDevice, st));
   // lambda_max(D^-1 A) of every smoothing level by power iteration on load
   // case 0, entirely on the device (phase 0 start, then per step: apply,
   // phase 1 sweep, reduction, phase 2 normalization); one read-back at the end
@@ -405,7 +327,7 @@ int mg_setup(Slot &s, hipStream_t st) {
     SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 0, L.nchunks, prec, st));
     for (int it = 0; it < POWER_ITERS; ++it) {
       if (l == 0) {
-        LaunchArgs la{s.d_mgsegs + SEG_POW, 1, h.ntiles[tiling]};
+        LaunchArgs la{s.d_mgsegs, 1, h.ntiles[tiling]};
         SHH_HIP(launch_stencil_apply(la, prec, st));
       } else {
         SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, prec, st));

@@ -53,7 +53,7 @@ struct Slot {
   // multigrid solver (opts.solver == SHH_SOLVER_MG)
   MgDev mg;                     // host image of the level descriptors
   MgDev *d_mg = nullptr;
-  Segment *d_mgsegs = nullptr;  // voxel-level operator launches: p->q, z->q, d->q, power
+  Segment *d_mgsegs = nullptr;  // the power iteration's voxel-level operator launch
   bool mg_restart = false;      // next iteration starts from z = V r, p = z
 };
 
