@@ -160,3 +160,22 @@ def test_coarse_operators_are_galerkin_products(precision, tol):
         q = A.mg_operator(torch.tensor(E, device="cuda"), v, nu, level, precision)
         Qg = nodal_to_oracle(q.double().cpu().numpy(), m)
         assert np.max(np.abs(Qg - Q)) <= tol * np.abs(Q).max(), level
+
+
+def test_random_designs_converge():
+    # a spread of resolutions, charge counts, volume fractions (down to thin
+    # 3 % shells), void moduli and Poisson ratios: every design converges, and
+    # the multigrid needs far fewer iterations than Jacobi would
+    A = api()
+    rng = np.random.default_rng(4242)
+    iters = []
+    for i in range(16):
+        n = int(rng.choice([16, 24, 32, 40, 48]))
+        d = wl.random_design(20000 + i, n, N=int(rng.integers(8, 64)), vf=float(rng.uniform(0.03, 0.3)),
+                             E_void=float(rng.choice([1e-6, 1e-4, 1e-3])), pm=bool(rng.random() < 0.5))
+        d = d.with_(nu=float(rng.choice([0.0, 0.2, 0.3, 0.45, -0.3])))
+        r = A.homogenize(d, precision="mixed", rtol=1e-5, solver="mg")
+        assert r["status"] == 0, (i, n, r["iters"], r["rel_res"])
+        iters.append(int(r["iters"].max()))
+    print("mg iterations over the random designs:", iters, flush=True)
+    assert np.median(iters) < 100
