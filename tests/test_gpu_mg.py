@@ -179,3 +179,41 @@ def test_random_designs_converge():
         iters.append(int(r["iters"].max()))
     print("mg iterations over the random designs:", iters, flush=True)
     assert np.median(iters) < 100
+
+
+def test_closed_forms_through_the_stiffness_entry_point():
+    # shh_homogenize_stiffness with the multigrid solver: a full solid (zero
+    # loads, u = 0, C^H = D) and a z laminate (Backus averages, exact)
+    from oracle import fem
+    from test_oracle_homogenize import backus_z
+    A = api()
+    n = 16
+    for prec in ("fp64", "mixed"):
+        r = A.homogenize_stiffness(torch.full((n, n, n), 2.0, dtype=torch.float64, device="cuda"), 0.3,
+                                   precision=prec, solver="mg")
+        assert r["status"] == 0
+        assert np.max(np.abs(r["C"] - fem.isotropic_D(2.0, 0.3))) <= 1e-12 * 2.0
+    E = np.full((n, n, n), 1e-3)
+    E[: n // 4] = 1.0
+    E[n // 2: n // 2 + 2] = 0.4
+    phases = []
+    for e in sorted(set(E[:, 0, 0])):
+        lam, mu = fem.lame(e, 0.3)
+        phases.append((np.mean(E[:, 0, 0] == e), lam, mu))
+    ref = backus_z(phases)
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-5)):
+        r = A.homogenize_stiffness(torch.tensor(E, device="cuda"), 0.3, precision=prec,
+                                   rtol=1e-11 if prec == "fp64" else 1e-7, solver="mg")
+        assert r["status"] == 0
+        assert np.max(np.abs(r["C"] - ref)) <= tol * np.abs(ref).max(), prec
+
+
+@pytest.mark.parametrize("n", [6, 8, 10, 12])
+def test_smallest_hierarchies_match_jacobi(n):
+    # one coarse level (6 -> 3, 8 -> 4, 10 -> 5) and two (12 -> 6 -> 3)
+    A = api()
+    d = wl.random_design(300 + n, n, N=12, vf=0.25, E_void=1e-3)
+    rm = A.homogenize(d, precision="fp64", rtol=1e-11, solver="mg")
+    rj = A.homogenize(d, precision="fp64", rtol=1e-11)
+    assert rm["status"] == 0 and rj["status"] == 0
+    assert_ch_close(rm["C"], rj["C"], 1e-8)
