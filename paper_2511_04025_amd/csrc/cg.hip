@@ -136,6 +136,7 @@ __global__ __launch_bounds__(VEC_THREADS) void scalar_kernel(LaunchArgs la, int 
       st->alpha[rhs] = 0.0;
       st->iters[rhs] = 0;
       st->pcur[rhs] = 0;
+      st->mgpar[rhs] = 0;
       st->rr[rhs] = rr;
       if (sqrt(rr) <= s->ffloor) {  // zero load: u = 0 solves it
         st->active[rhs] = 0;

@@ -81,6 +81,7 @@ struct CgState {
   int status[NRHS];
   int iters[NRHS];
   int pcur[NRHS];         // which of the two r, p, q buffer sets is current
+  int mgpar[NRHS];        // multigrid CG: which p buffer holds the current direction
   unsigned cnt[8];        // last-workgroup counters (0..5 per load case, 6, 7 misc)
   double V;               // volume fraction
   double t;               // half-thickness used
@@ -130,6 +131,7 @@ struct SlotDev {
   // CG vectors [6][3][nn] (float mixed / double FP64).  r, p and q are double
   // buffered: a CG pass reads set pcur[k] of load case k and writes the other
   void *r[2], *p[2], *q[2], *x;
+  void *mgd;            // multigrid: the voxel level's Chebyshev direction [6][3][nn]
   double *x64;          // FP64 solution accumulator (mixed); == x for FP64
   double *partials;     // [NRHS][maxparts][PSTRIDE]
   CgState *st;

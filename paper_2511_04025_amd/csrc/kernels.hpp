@@ -23,6 +23,7 @@ hipError_t launch_dinv(SlotDev *d_slot, long long nn, int prec, hipStream_t st);
 hipError_t launch_stencil_pcg(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_stencil_resid(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st);
+hipError_t launch_stencil_mgdir(const LaunchArgs &la, int prec, hipStream_t st);
 
 // cg.hip (segments of (slot, load case, chunk); fold/zero use one case per slot)
 hipError_t launch_finish_resid(const LaunchArgs &la, int prec, hipStream_t st);

@@ -321,7 +321,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
   if (l == 0 && op == MGV_INIT) {
     a = (T)s->st->alpha[k];
     xcg = (T *)s->x + vb;
-    pcg = (const T *)s->p[0] + vb;
+    pcg = (const T *)s->p[s->st->mgpar[k]] + vb;
   }
   double acc[2] = {0.0, 0.0};
   for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
@@ -371,46 +371,11 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
   }
 }
 
-// CG sweeps at the voxel level: p = p[0], q = q[0], z = r[1] (the update of x
-// and r is folded into the V-cycle's first sweep).
-//   DOT_PQ:   partial p . q
-//   P_UPDATE: p = z + beta p
-template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void mg_cg_kernel(MgBatch B, int op) {
-  __shared__ double red[16];
-  const SlotDev *s = B.slot[blockIdx.z];
-  const int k = blockIdx.y;
-  const long long nn = s->nn;
-  if (blockIdx.x >= (unsigned)s->nchunks) return;
-  const long long i0 = (long long)blockIdx.x * CHUNK;
-  const long long i1 = min(i0 + (long long)CHUNK, nn);
-  const long long vb = (long long)k * 3 * nn;
-  T *p = (T *)s->p[0] + vb;
-  const T *q = (const T *)s->q[0] + vb;
-  const T *z = (const T *)s->r[1] + vb;
-  const T bt = (T)s->st->beta[k];
-  double acc[1] = {0.0};
-  for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const long long j = c * nn + i;
-      if (op == MGC_DOT_PQ) {
-        acc[0] += (double)p[j] * (double)q[j];
-      } else {
-        p[j] = z[j] + bt * p[j];
-      }
-    }
-  }
-  if (op == MGC_DOT_PQ) {
-    block_sum<1>(acc, red, VEC_THREADS);
-    if (threadIdx.x == 0) s->partials[((long long)k * s->maxparts + blockIdx.x) * PSTRIDE] = acc[0];
-  }
-}
-
 // CG scalars of the multigrid-preconditioned solve (one workgroup per load
-// case; partials over the voxel-level chunks).
+// case; partials over the voxel-level chunks, for ALPHA over the direction
+// pass's tiles).
 //   RESTART: rho = r . z after a (re)started V-cycle, beta = 0
-//   ALPHA:   alpha = rho / p . K p
+//   ALPHA:   alpha = rho / p . K p; the new direction becomes current
 //   BETA:    rho' = r . z, ||r||^2 -> convergence; beta = rho' / rho
 __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int phase) {
   __shared__ double red[2 * 16];
@@ -419,8 +384,10 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
   CgState *st = s->st;
   const double *parts = s->partials + (long long)k * s->maxparts * PSTRIDE;
   double tot[2];
-  sum_partials<2, PSTRIDE>(parts, s->nchunks, tot, red, VEC_THREADS);
+  sum_partials<2, PSTRIDE>(parts, phase == MGS_ALPHA ? s->ntiles[s->prec] : s->nchunks, tot, red, VEC_THREADS);
   if (threadIdx.x != 0) return;
+  // the direction pass ran for every load case, active or not
+  if (phase == MGS_ALPHA) st->mgpar[k] ^= 1;
   if (!st->active[k]) {
     st->alpha[k] = 0.0;
     st->beta[k] = 0.0;
@@ -677,12 +644,6 @@ hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int p
   return hipGetLastError();
 }
 
-hipError_t mg_launch_cg(const MgBatch &B, int op, int nchunks_max, int prec, hipStream_t st) {
-  const dim3 g((unsigned)nchunks_max, NRHS, B.count);
-  if (prec == 0) mg_cg_kernel<double><<<g, VEC_THREADS, 0, st>>>(B, op);
-  else mg_cg_kernel<float><<<g, VEC_THREADS, 0, st>>>(B, op);
-  return hipGetLastError();
-}
 
 hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st) {
   mg_scalar_kernel<<<dim3(NRHS, 1, B.count), VEC_THREADS, 0, st>>>(B, phase);

@@ -40,7 +40,8 @@ struct MgLevel {
   void *S, *Dinv;
   // V-cycle vectors [NRHS][3][nn]: right-hand side, iterate, residual,
   // Chebyshev direction, operator output.  Level 0 aliases the slot's CG
-  // vectors (b = r[0], x = r[1] (z), r = q[1], d = p[1], q = q[0]).
+  // vectors (b = r[0], x = r[1] (z), r = q[1], q = q[0]) except d, which
+  // has a buffer of its own (the CG direction alternates between p[0] and p[1]).
   void *b, *x, *r, *d, *q;
   void *Ke;             // setup only: element matrices [nn][24][24] (levels >= 1)
   double inv_theta, c1, c2;  // Chebyshev coefficients
@@ -66,8 +67,6 @@ struct MgBatch {
 
 // V-cycle vector sweeps at one level (grid: chunks x NRHS); see mg_vec_kernel
 enum { MGV_INIT = 0, MGV_STEP1 = 1, MGV_POST = 2, MGV_LAST = 3 };
-// CG operations at the voxel level
-enum { MGC_DOT_PQ = 0, MGC_P_UPDATE = 2 };
 // CG scalar phases
 enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2 };
 

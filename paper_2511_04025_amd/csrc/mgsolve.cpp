@@ -28,7 +28,6 @@ hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, 
 hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
 hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
 hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st);
-hipError_t mg_launch_cg(const MgBatch &B, int op, int nchunks_max, int prec, hipStream_t st);
 hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st);
 hipError_t mg_launch_power(const SlotDev *d_slot, MgDev *d_mg, int l, int phase, int nchunks, int prec,
                            hipStream_t st);
@@ -56,9 +55,12 @@ size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mg
   char *dev = take(sizeof(MgDev));
   char *sg = take(NSEG * sizeof(Segment));
   char *G = take(8 * 576 * ts);
+  // the voxel level's Chebyshev direction (its other V-cycle vectors alias CG vectors)
+  char *d0 = take((size_t)NRHS * 3 * (size_t)n * n * n * ts);
   if (mg) {
     mg->L = count - 1;
     mg->G = G;
+    mg->lv[0].d = d0;
   }
   if (d_mgdev) *d_mgdev = dev;
   if (segs) *segs = (Segment *)sg;
@@ -283,8 +285,9 @@ int mg_setup(Slot &s, hipStream_t st) {
   L0.b = h.r[0];
   L0.x = h.r[1];
   L0.r = h.q[1];
-  L0.d = h.p[1];
   L0.q = h.q[0];
+  h.mgd = L0.d;
+  SHH_HIP(hipMemcpyAsync(&s.d_slot->mgd, &h.mgd, sizeof(h.mgd), hipMemcpyHostToDevice, st));
   // element matrices of levels >= 1 live in the (not yet used) CG vector region
   {
     char *ke = s.base + s.lay.vec;
@@ -378,33 +381,26 @@ int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
 
 int mg_iterate(const std::vector<Slot *> &all, hipStream_t st, Solver *timer, const MgApply0 &apply0) {
   if (all.empty()) return SHH_OK;
-  const int prec = all[0]->host.prec;
   int rc;
   for (size_t b0 = 0; b0 < all.size(); b0 += MG_MAXB) {
     const std::vector<Slot *> slots(all.begin() + b0, all.begin() + std::min(all.size(), b0 + MG_MAXB));
-    int nch = 0;
-    for (Slot *s : slots) nch = std::max(nch, s->host.nchunks);
-    // (re)started slots: z = V r, rho = r . z, p = z
+    // (re)started slots: z = V r, rho = r . z, beta = 0 (the direction pass
+    // then starts from p = z)
     std::vector<Slot *> rs;
     for (Slot *s : slots)
       if (s->mg_restart) rs.push_back(s);
     if (!rs.empty()) {
-      int nchr = 0;
-      for (Slot *s : rs) nchr = std::max(nchr, s->host.nchunks);
       if ((rc = vcycle(rs, 0, st, timer, apply0))) return rc;
-      const MgBatch R = batch_of(rs);
-      SHH_HIP(mg_launch_scalar(R, MGS_RESTART, st));
-      SHH_HIP(mg_launch_cg(R, MGC_P_UPDATE, nchr, prec, st));  // beta = 0: p = z
+      SHH_HIP(mg_launch_scalar(batch_of(rs), MGS_RESTART, st));
       for (Slot *s : rs) s->mg_restart = false;
     }
     const MgBatch B = batch_of(slots);
-    if ((rc = apply0(slots, MG_SRC_P))) return rc;
-    SHH_HIP(mg_launch_cg(B, MGC_DOT_PQ, nch, prec, st));
+    // p = z + beta p, q = K p, partials p . q in one pass; alpha
+    if ((rc = apply0(slots, MG_SRC_DIR))) return rc;
     SHH_HIP(mg_launch_scalar(B, MGS_ALPHA, st));
     // the V-cycle's first sweep applies x += alpha p, r -= alpha q
     if ((rc = vcycle(slots, 0, st, timer, apply0))) return rc;
     SHH_HIP(mg_launch_scalar(B, MGS_BETA, st));
-    SHH_HIP(mg_launch_cg(B, MGC_P_UPDATE, nch, prec, st));
   }
   return SHH_OK;
 }

@@ -315,7 +315,7 @@ int Solver::build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_r
     g.slot = s->d_slot;
     g.first = first;
     g.flag = flag;
-    const bool mg_apply = (k == K_MG_P || k == K_MG_Z || k == K_MG_D);
+    const bool mg_apply = (k == K_MG_DIR || k == K_MG_Z || k == K_MG_D);
     const bool per_tile = (k == K_STENCIL || k == K_RESID || mg_apply);
     const bool scalar = (k == K_SCAL_IT || k == K_SCAL_RES);
     // the CG pass and the operator compute in the vector precision, the residual always in FP64
@@ -478,12 +478,13 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
   // voxel-level operator over all the given slots, one launch
   MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
-    const Kind k = src == MG_SRC_P ? K_MG_P : (src == MG_SRC_Z ? K_MG_Z : K_MG_D);
-    const int flag = src == MG_SRC_P ? 0 : (src == MG_SRC_Z ? MG_FLAG_ZQ : MG_FLAG_DQ);
+    const Kind k = src == MG_SRC_DIR ? K_MG_DIR : (src == MG_SRC_Z ? K_MG_Z : K_MG_D);
+    const int flag = src == MG_SRC_DIR ? 0 : (src == MG_SRC_Z ? MG_FLAG_ZQ : MG_FLAG_DQ);
     LaunchArgs la;
     int r;
     if ((r = build(k, ss, flag, true, la))) return r;
-    SHH_HIP(launch_stencil_apply(la, ss[0]->host.prec, st_));
+    if (src == MG_SRC_DIR) SHH_HIP(launch_stencil_mgdir(la, ss[0]->host.prec, st_));
+    else SHH_HIP(launch_stencil_apply(la, ss[0]->host.prec, st_));
     return SHH_OK;
   };
   for (int it = 0; it < iters; ++it) {

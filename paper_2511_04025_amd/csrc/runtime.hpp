@@ -66,11 +66,13 @@ size_t mg_region_bytes(int n, int prec);
 // vectors are zeroed: the element matrices use the vector region as scratch)
 int mg_setup(Slot &s, hipStream_t st);
 // one multigrid-preconditioned CG iteration of every load case of the slot
-// Voxel-level operator launches of the multigrid iteration: q[0] = K v for v
-// = p[0] (CG direction), r[1] (z, the V-cycle iterate) or p[1] (Chebyshev
-// direction); stencil flags 0 / 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x)
-enum { MG_SRC_P = 0, MG_SRC_Z = 1, MG_SRC_D = 2 };
-constexpr int MG_FLAG_ZQ = 1 + 1 + 8 * 4, MG_FLAG_DQ = 1 + 3 + 8 * 4;
+// Voxel-level operator launches of the multigrid iteration: the CG direction
+// pass (p_j = z + beta p_{j-1} into the other p buffer, q[0] = K p_j, partials
+// p_j . q), or q[0] = K v for v = r[1] (z, the V-cycle iterate) or the
+// Chebyshev direction mgd; stencil flags 1 + src + 8 dst over (r0, r1, p0, p1,
+// q0, q1, x, mgd)
+enum { MG_SRC_DIR = 0, MG_SRC_Z = 1, MG_SRC_D = 2 };
+constexpr int MG_FLAG_ZQ = 1 + 1 + 8 * 4, MG_FLAG_DQ = 1 + 7 + 8 * 4;
 class Solver;
 using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // one multigrid-preconditioned CG iteration of every load case of the slots
@@ -110,7 +112,7 @@ class Solver {
   int timed_end(hipEvent_t e0, double bytes);
 
  private:
-  enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_MG_P, K_MG_Z, K_MG_D,
+  enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_MG_DIR, K_MG_Z, K_MG_D,
               K_NKIND };
   int residual(const std::vector<Slot *> &slots, int mode);
   int iterate_mg(const std::vector<Slot *> &slots, int iters);

@@ -50,7 +50,7 @@
 
 namespace shh {
 
-enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2 };
+enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2, MODE_MGDIR = 3 };
 
 #ifndef SHH_STENCIL_WAVES_PER_EU
 #define SHH_STENCIL_WAVES_PER_EU 1
@@ -166,9 +166,17 @@ void stencil_kernel(LaunchArgs la) {
   const uint64_t vbytesS = 3ull * nn * SS, vbytesL = 3ull * nn * SL;
   // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX
   // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q (or the pair the flag names).
+  // MGDIR (the multigrid CG's direction pass): rA = z, rC = p_{j-1}, rP = p_j, rQ = q.
   rsrc_t rA, rB, rC, rR, rQ, rP, rX;
   TC alpha = TC(0), beta = TC(0);
-  if constexpr (MODE == MODE_PCG) {
+  if constexpr (MODE == MODE_MGDIR) {
+    const int pc = st->mgpar[rhs];
+    rA = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+    rC = make_rsrc((const TS *)s->p[pc] + vbase, vbytesS);
+    rP = make_rsrc((const TS *)s->p[pc ^ 1] + vbase, vbytesS);
+    rQ = make_rsrc((const TS *)s->q[0] + vbase, vbytesS);
+    beta = (TC)st->beta[rhs];
+  } else if constexpr (MODE == MODE_PCG) {
     const int pc = st->pcur[rhs];
     rA = make_rsrc((const TS *)s->r[pc] + vbase, vbytesS);
     rB = make_rsrc((const TS *)s->q[pc] + vbase, vbytesS);
@@ -183,7 +191,7 @@ void stencil_kernel(LaunchArgs la) {
     rA = make_rsrc(s->x64 + vbase, vbytesL);
     rQ = make_rsrc((const TS *)s->r[st->pcur[rhs]] + vbase, vbytesS);
   } else {
-    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x)
+    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x, mgd)
     const void *src = s->p[0];
     void *dst = s->q[0];
     if (w.flag > 0) {
@@ -195,7 +203,8 @@ void stencil_kernel(LaunchArgs la) {
           case 3: return s->p[1];
           case 4: return s->q[0];
           case 5: return s->q[1];
-          default: return s->x;
+          case 6: return s->x;
+          default: return s->mgd;
         }
       };
       src = pick((w.flag - 1) & 7);
@@ -244,6 +253,13 @@ void stencil_kernel(LaunchArgs la) {
       } else if constexpr (MODE == MODE_RESID) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = zero_x ? 0.0 : bload<TL>(rA, hoL[k], pz * SL + cL[c]);
+      } else if constexpr (MODE == MODE_MGDIR) {
+        // beta = 0 starts a new direction: the old one is not read
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          raw_a[k][c] = bload<TS>(rA, hoS[k], pz * SS + cS[c]);
+          raw_c[k][c] = beta != TC(0) ? bload<TS>(rC, hoS[k], pz * SS + cS[c]) : TS(0);
+        }
       } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = bload<TL>(rA, hoL[k], pz * SL + cL[c]);
@@ -266,6 +282,13 @@ void stencil_kernel(LaunchArgs la) {
           bstore<TS>(out_p[c], rP, hoS[0], so);
           bstore<TS>(out_x[c], rX, hoS[0], so);
         }
+      }
+    } else if constexpr (MODE == MODE_MGDIR) {
+      const uint32_t pz = (uint32_t)wrap1(z, n) * plane;
+      const bool ownz = z >= z0 && z < z1;
+      if (is_out && ownz) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bstore<TS>(out_p[c], rP, hoS[0], pz * SS + cS[c]);
       }
     }
   };
@@ -300,6 +323,20 @@ void stencil_kernel(LaunchArgs la) {
             own_p[b][c] = pn[c];
           }
           own_d[b] = dk;
+        }
+      } else if constexpr (MODE == MODE_MGDIR) {
+        TC pn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pn[c] = (TC)raw_a[k][c] + beta * (TC)raw_c[k][c];
+          nbuf[b][c][hslot[k]] = pn[c];
+        }
+        if (k == 0 && is_out && ownz) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            out_p[c] = (TS)pn[c];
+            own_p[b][c] = pn[c];
+          }
         }
       } else {
 #pragma unroll
@@ -370,6 +407,9 @@ void stencil_kernel(LaunchArgs la) {
         op[c] = own_p[b][c];
       }
       od = own_d[b];
+    } else if constexpr (MODE == MODE_MGDIR) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) op[c] = own_p[b][c];
     }
     if (is_elem) {
       constexpr int ib = NB == 2 ? b : 0, ibn = NB == 2 ? bn : 0;
@@ -441,6 +481,12 @@ void stencil_kernel(LaunchArgs la) {
           acc[3] += (double)oz[c] * q64;
           acc[4] += d64 * q64 * q64;
         }
+      } else if constexpr (MODE == MODE_MGDIR) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          bstore<TS>((TS)qv[c], rQ, ooff, pk + cS[c]);
+          acc[0] += (double)op[c] * (double)qv[c];
+        }
       } else if constexpr (MODE == MODE_RESID) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -469,6 +515,10 @@ void stencil_kernel(LaunchArgs la) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) parts[i] = acc[i];
     }
+  } else if constexpr (MODE == MODE_MGDIR) {
+    double a1[1] = {acc[0]};
+    block_sum<1>(a1, red, STENCIL_THREADS);
+    if (tid == 0) parts[0] = a1[0];
   } else if constexpr (MODE == MODE_RESID) {
     double a3[3] = {acc[0], acc[1], acc[2]};
     block_sum<3>(a3, red, STENCIL_THREADS);
@@ -502,6 +552,16 @@ hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st) 
   const int g = padded_grid(la.total);
   if (prec == 0) stencil_kernel<double, double, MODE_APPLY><<<g, Tile<double>::THREADS, 0, st>>>(la);
   else stencil_kernel<float, float, MODE_APPLY><<<g, Tile<float>::THREADS, 0, st>>>(la);
+  return hipGetLastError();
+}
+
+// Multigrid CG direction: p_j = z + beta p_{j-1} (into the other p buffer),
+// q = K p_j and per-tile partials p_j . q, in the vector precision.
+hipError_t launch_stencil_mgdir(const LaunchArgs &la, int prec, hipStream_t st) {
+  if (la.total == 0) return hipSuccess;
+  const int g = padded_grid(la.total);
+  if (prec == 0) stencil_kernel<double, double, MODE_MGDIR><<<g, Tile<double>::THREADS, 0, st>>>(la);
+  else stencil_kernel<float, float, MODE_MGDIR><<<g, Tile<float>::THREADS, 0, st>>>(la);
   return hipGetLastError();
 }
 
