@@ -131,7 +131,11 @@ struct SlotDev {
   // CG vectors [6][3][nn] (float mixed / double FP64).  r, p and q are double
   // buffered: a CG pass reads set pcur[k] of load case k and writes the other
   void *r[2], *p[2], *q[2], *x;
-  void *mgd;            // multigrid: the voxel level's Chebyshev direction [6][3][nn]
+  // multigrid, voxel level: the two Chebyshev direction buffers [6][3][nn]
+  // (the second one also holds the post-smoother's iterate) and the Chebyshev
+  // coefficients 1 / theta, c1, c2
+  void *mgd[2];
+  double mgc[3];
   double *x64;          // FP64 solution accumulator (mixed); == x for FP64
   double *partials;     // [NRHS][maxparts][PSTRIDE]
   CgState *st;
@@ -149,6 +153,9 @@ struct Segment {
   int flag;             // kernel-specific (e.g. recompute mode)
   int pad_;
 };
+
+// Fused voxel-level passes of the multigrid-preconditioned CG (stencil kernel)
+enum { SMG_DIR = 0, SMG_STEP1 = 1, SMG_POST = 2, SMG_LAST = 3 };
 
 struct LaunchArgs {
   const Segment *segs;

@@ -292,13 +292,13 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(MgBatch B) {
 //          b = r -= alpha q (q = K p), so that b is the new CG residual
 //   STEP1: r = b - q, d' = c1 d + c2 D^-1 r, x = d + d', d = d'
 //   POST:  r = b - q (q = A x), d = D^-1 r / theta, x += d
-//   LAST:  x += c1 d + c2 D^-1 (r - q); at the voxel level partial sums
-//          b . x and b . b for the CG scalars
+//   LAST:  x += c1 d + c2 D^-1 (r - q)
 // (the pre-smoother is INIT, STEP1; the restriction takes r - q after it;
-// the post-smoother is POST, LAST).
+// the post-smoother is POST, LAST).  At the voxel level only INIT runs here:
+// STEP1, POST and LAST run inside the stencil kernel's operator pass, which
+// also leaves the partial sums b . x and b . b for the CG scalars.
 template <typename T>
 __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, int op) {
-  __shared__ double red[2 * 16];
   const SlotDev *s = B.slot[blockIdx.z];
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const int k = blockIdx.y;
@@ -323,7 +323,6 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
     xcg = (T *)s->x + vb;
     pcg = (const T *)s->p[s->st->mgpar[k]] + vb;
   }
-  double acc[2] = {0.0, 0.0};
   for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -351,29 +350,15 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
         d[j] = dv;
         x[j] = x[j] + dv;
       } else {  // MGV_LAST
-        const T xv = x[j] + c1 * d[j] + c2 * di * (r[j] - q[j]);
-        x[j] = xv;
-        if (l == 0) {
-          const double bv = (double)b[j];
-          acc[0] += bv * (double)xv;
-          acc[1] += bv * bv;
-        }
+        x[j] = x[j] + c1 * d[j] + c2 * di * (r[j] - q[j]);
       }
-    }
-  }
-  if (l == 0 && op == MGV_LAST) {
-    block_sum<2>(acc, red, VEC_THREADS);
-    if (threadIdx.x == 0) {
-      double *parts = s->partials + ((long long)k * s->maxparts + blockIdx.x) * PSTRIDE;
-      parts[0] = acc[0];
-      parts[1] = acc[1];
     }
   }
 }
 
 // CG scalars of the multigrid-preconditioned solve (one workgroup per load
-// case; partials over the voxel-level chunks, for ALPHA over the direction
-// pass's tiles).
+// case; per-tile partials of the voxel-level stencil passes: the direction
+// pass for ALPHA, the last post-smoothing sweep for RESTART and BETA).
 //   RESTART: rho = r . z after a (re)started V-cycle, beta = 0
 //   ALPHA:   alpha = rho / p . K p; the new direction becomes current
 //   BETA:    rho' = r . z, ||r||^2 -> convergence; beta = rho' / rho
@@ -384,7 +369,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
   CgState *st = s->st;
   const double *parts = s->partials + (long long)k * s->maxparts * PSTRIDE;
   double tot[2];
-  sum_partials<2, PSTRIDE>(parts, phase == MGS_ALPHA ? s->ntiles[s->prec] : s->nchunks, tot, red, VEC_THREADS);
+  sum_partials<2, PSTRIDE>(parts, s->ntiles[s->prec], tot, red, VEC_THREADS);
   if (threadIdx.x != 0) return;
   // the direction pass ran for every load case, active or not
   if (phase == MGS_ALPHA) st->mgpar[k] ^= 1;

@@ -55,8 +55,9 @@ size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mg
   char *dev = take(sizeof(MgDev));
   char *sg = take(NSEG * sizeof(Segment));
   char *G = take(8 * 576 * ts);
-  // the voxel level's Chebyshev direction (its other V-cycle vectors alias CG vectors)
-  char *d0 = take((size_t)NRHS * 3 * (size_t)n * n * n * ts);
+  // the voxel level's two Chebyshev direction buffers (its other V-cycle
+  // vectors alias CG vectors)
+  char *d0 = take(2 * (size_t)NRHS * 3 * (size_t)n * n * n * ts);
   if (mg) {
     mg->L = count - 1;
     mg->G = G;
@@ -202,7 +203,8 @@ MgBatch batch_of(const std::vector<Slot *> &slots) {
 
 // Algorithmic bytes of one vector sweep at a level: vectors read and written
 // per node and load case (3 components each) plus the inverse diagonal, once
-// per node (one value at the voxel level, three on coarse levels).
+// per node (one value at the voxel level, three on coarse levels).  At the
+// voxel level only INIT runs as a vector sweep.
 double vec_bytes(const Slot &s, int l, int op) {
   const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
   const double nn = double(s.mg.lv[l].nn);
@@ -212,7 +214,7 @@ double vec_bytes(const Slot &s, int l, int op) {
     case MGV_INIT: vals = l == 0 ? 3 * (4 + 3) : 3 * (1 + 1); break;  // voxel: x, p, r, q -> x, r, d
     case MGV_STEP1: vals = 3 * (3 + 3); break;                       // b, q, d -> r, d, x
     case MGV_POST: vals = 3 * (3 + 3); break;                        // b, q, x -> r, d, x
-    default: vals = l == 0 ? 3 * (5 + 1) : 3 * (4 + 1); break;       // r, q, d, x (, b) -> x
+    default: vals = 3 * (4 + 1); break;                              // r, q, d, x -> x
   }
   return nn * (NRHS * vals + dv) * ts;
 }
@@ -244,18 +246,26 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
     return timer->timed_end(e0, bytes);
   };
   auto app = [&](int src) -> int {
-    if (l == 0) return apply0(smooth, src == 0 ? MG_SRC_Z : MG_SRC_D);
+    if (l == 0) return apply0(smooth, MG_SRC_D);  // only the direction is applied bare
     SHH_HIP(mg_launch_apply(B, l, src, nn_max, prec, st));
     return SHH_OK;
   };
-  // pre-smoother (at the voxel level INIT also applies the pending CG update)
-  if ((rc = vec(MGV_INIT)) || (rc = app(1)) || (rc = vec(MGV_STEP1)) || (rc = app(1))) return rc;
+  // pre-smoother (at the voxel level INIT also applies the pending CG
+  // update, and the operator runs fused with the sweep after it)
+  if ((rc = vec(MGV_INIT))) return rc;
+  if (l == 0) rc = apply0(smooth, MG_SRC_STEP1);
+  else if (!(rc = app(1))) rc = vec(MGV_STEP1);
+  if (rc || (rc = app(1))) return rc;
   // coarse-grid correction of the residual r - A d
   SHH_HIP(mg_launch_restrict(B, l, nn_next_max, prec, st));
   if ((rc = vcycle(smooth, l + 1, st, timer, apply0))) return rc;
   SHH_HIP(mg_launch_prolong(B, l, nn_max, prec, st));
   // post-smoother
-  if ((rc = app(0)) || (rc = vec(MGV_POST)) || (rc = app(1)) || (rc = vec(MGV_LAST))) return rc;
+  if (l == 0) {
+    if ((rc = apply0(smooth, MG_SRC_POST)) || (rc = apply0(smooth, MG_SRC_LAST))) return rc;
+  } else if ((rc = app(0)) || (rc = vec(MGV_POST)) || (rc = app(1)) || (rc = vec(MGV_LAST))) {
+    return rc;
+  }
   return SHH_OK;
 }
 
@@ -286,8 +296,9 @@ int mg_setup(Slot &s, hipStream_t st) {
   L0.x = h.r[1];
   L0.r = h.q[1];
   L0.q = h.q[0];
-  h.mgd = L0.d;
-  SHH_HIP(hipMemcpyAsync(&s.d_slot->mgd, &h.mgd, sizeof(h.mgd), hipMemcpyHostToDevice, st));
+  h.mgd[0] = L0.d;
+  h.mgd[1] = (char *)L0.d + (size_t)NRHS * 3 * h.nn * ts;
+  SHH_HIP(hipMemcpyAsync(&s.d_slot->mgd, h.mgd, sizeof(h.mgd), hipMemcpyHostToDevice, st));
   // element matrices of levels >= 1 live in the (not yet used) CG vector region
   {
     char *ke = s.base + s.lay.vec;
@@ -362,6 +373,11 @@ int mg_setup(Slot &s, hipStream_t st) {
     W.c1 = rho1 * rho0;
     W.c2 = 2.0 * rho1 / delta;
   }
+  // the fused voxel-level sweeps read the coefficients from the slot
+  h.mgc[0] = L0.inv_theta;
+  h.mgc[1] = L0.c1;
+  h.mgc[2] = L0.c2;
+  SHH_HIP(hipMemcpyAsync(&s.d_slot->mgc, h.mgc, sizeof(h.mgc), hipMemcpyHostToDevice, st));
   SHH_HIP(hipMemcpyAsync(s.d_mg, &mg, sizeof(MgDev), hipMemcpyHostToDevice, st));
   SHH_HIP(hipStreamSynchronize(st));
   s.mg_restart = true;

@@ -315,7 +315,7 @@ int Solver::build(Kind k, const std::vector<Slot *> &slots, int flag, bool all_r
     g.slot = s->d_slot;
     g.first = first;
     g.flag = flag;
-    const bool mg_apply = (k == K_MG_DIR || k == K_MG_Z || k == K_MG_D);
+    const bool mg_apply = (k >= K_MG_DIR && k <= K_MG_LAST);
     const bool per_tile = (k == K_STENCIL || k == K_RESID || mg_apply);
     const bool scalar = (k == K_SCAL_IT || k == K_SCAL_RES);
     // the CG pass and the operator compute in the vector precision, the residual always in FP64
@@ -478,13 +478,15 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
   // voxel-level operator over all the given slots, one launch
   MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
-    const Kind k = src == MG_SRC_DIR ? K_MG_DIR : (src == MG_SRC_Z ? K_MG_Z : K_MG_D);
-    const int flag = src == MG_SRC_DIR ? 0 : (src == MG_SRC_Z ? MG_FLAG_ZQ : MG_FLAG_DQ);
+    static const Kind kinds[6] = {K_MG_DIR, K_MG_Z, K_MG_D, K_MG_STEP1, K_MG_POST, K_MG_LAST};
+    static const int ops[6] = {SMG_DIR, -1, -1, SMG_STEP1, SMG_POST, SMG_LAST};
+    if (src < 0 || src > MG_SRC_LAST) return SHH_INVALID_ARG;
+    const int flag = src == MG_SRC_Z ? MG_FLAG_ZQ : (src == MG_SRC_D ? MG_FLAG_DQ : 0);
     LaunchArgs la;
     int r;
-    if ((r = build(k, ss, flag, true, la))) return r;
-    if (src == MG_SRC_DIR) SHH_HIP(launch_stencil_mgdir(la, ss[0]->host.prec, st_));
-    else SHH_HIP(launch_stencil_apply(la, ss[0]->host.prec, st_));
+    if ((r = build(kinds[src], ss, flag, true, la))) return r;
+    if (ops[src] < 0) SHH_HIP(launch_stencil_apply(la, ss[0]->host.prec, st_));
+    else SHH_HIP(launch_stencil_mg(la, ss[0]->host.prec, ops[src], st_));
     return SHH_OK;
   };
   for (int it = 0; it < iters; ++it) {

@@ -50,7 +50,8 @@
 
 namespace shh {
 
-enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2, MODE_MGDIR = 3 };
+enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2, MODE_MGDIR = 3, MODE_MGSTEP1 = 4, MODE_MGPOST = 5,
+       MODE_MGLAST = 6 };
 
 #ifndef SHH_STENCIL_WAVES_PER_EU
 #define SHH_STENCIL_WAVES_PER_EU 1
@@ -156,8 +157,10 @@ void stencil_kernel(LaunchArgs la) {
   const char *Ebase;
   if constexpr (sizeof(TC) == 8) Ebase = (const char *)s->E64;
   else Ebase = (const char *)s->E32;
-  const uint32_t dOff = MODE == MODE_PCG ? (uint32_t)((const char *)s->Dinv - Ebase) : 0u;
-  const rsrc_t rE = make_rsrc(Ebase, MODE == MODE_PCG ? (uint64_t)dOff + (uint64_t)nn * SS : (uint64_t)nn * SC);
+  constexpr bool MGF = MODE >= MODE_MGSTEP1;  // a Chebyshev sweep fused behind the operator
+  constexpr bool WITH_D = MODE == MODE_PCG || MGF;
+  const uint32_t dOff = WITH_D ? (uint32_t)((const char *)s->Dinv - Ebase) : 0u;
+  const rsrc_t rE = make_rsrc(Ebase, WITH_D ? (uint64_t)dOff + (uint64_t)nn * SS : (uint64_t)nn * SC);
 
   // component c of a load case's vector starts c * n^3 elements in
   const uint32_t cS[3] = {0u, (uint32_t)nn * SS, 2u * (uint32_t)nn * SS};
@@ -167,9 +170,34 @@ void stencil_kernel(LaunchArgs la) {
   // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX
   // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q (or the pair the flag names).
   // MGDIR (the multigrid CG's direction pass): rA = z, rC = p_{j-1}, rP = p_j, rQ = q.
-  rsrc_t rA, rB, rC, rR, rQ, rP, rX;
+  // Fused voxel-level Chebyshev sweeps: rA the operand v (q = K v is not
+  // stored), rAux the owned-node inputs, rR, rP, rX the outputs:
+  //   STEP1: v = d0 (mgd[0]); aux b;       r = b - q, d1 = c1 d0 + c2 D r,
+  //          x = d0 + d1 -> r (q[1]), d1 (mgd[1]), x (r[1])
+  //   POST:  v = x (r[1]); aux b;          r = b - q, d = D r / theta, x + d
+  //          -> r (q[1]), d (mgd[0]), x (mgd[1])
+  //   LAST:  v = d (mgd[0]); aux b, x, r;  x + c1 d + c2 D (r - q) -> r[1],
+  //          partials b . x, b . b
+  constexpr int NAUX = MODE == MODE_MGLAST ? 3 : 1;
+  rsrc_t rA, rB, rC, rR, rQ, rP, rX, rAux[NAUX];
   TC alpha = TC(0), beta = TC(0);
-  if constexpr (MODE == MODE_MGDIR) {
+  TC ith = TC(0), c1 = TC(0), c2 = TC(0);
+  if constexpr (MGF) {
+    ith = (TC)s->mgc[0];
+    c1 = (TC)s->mgc[1];
+    c2 = (TC)s->mgc[2];
+    rA = make_rsrc((const TS *)(MODE == MODE_MGPOST ? s->r[1] : s->mgd[0]) + vbase, vbytesS);
+    rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
+    if constexpr (MODE == MODE_MGLAST) {
+      rAux[NAUX - 2] = make_rsrc((const TS *)s->mgd[1] + vbase, vbytesS);
+      rAux[NAUX - 1] = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
+      rX = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+    } else {
+      rR = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
+      rP = make_rsrc((const TS *)s->mgd[MODE == MODE_MGSTEP1 ? 1 : 0] + vbase, vbytesS);
+      rX = make_rsrc((const TS *)(MODE == MODE_MGSTEP1 ? s->r[1] : s->mgd[1]) + vbase, vbytesS);
+    }
+  } else if constexpr (MODE == MODE_MGDIR) {
     const int pc = st->mgpar[rhs];
     rA = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
     rC = make_rsrc((const TS *)s->p[pc] + vbase, vbytesS);
@@ -191,7 +219,7 @@ void stencil_kernel(LaunchArgs la) {
     rA = make_rsrc(s->x64 + vbase, vbytesL);
     rQ = make_rsrc((const TS *)s->r[st->pcur[rhs]] + vbase, vbytesS);
   } else {
-    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x, mgd)
+    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x, mgd[1])
     const void *src = s->p[0];
     void *dst = s->q[0];
     if (w.flag > 0) {
@@ -204,7 +232,7 @@ void stencil_kernel(LaunchArgs la) {
           case 4: return s->q[0];
           case 5: return s->q[1];
           case 6: return s->x;
-          default: return s->mgd;
+          default: return s->mgd[1];
         }
       };
       src = pick((w.flag - 1) & 7);
@@ -220,6 +248,8 @@ void stencil_kernel(LaunchArgs la) {
   // owned-node values kept from staging to output (two steps later), by
   // parity of the step that staged them: z, D^-1 and p of the node
   TC own_z[2][3], own_p[2][3], own_d[2];
+  // fused sweeps: the owned node's auxiliary inputs, by the same parity
+  TC own_aux[2][NAUX][3];
 
   // ---- plane staging, split into issue (loads into registers), finish
   //      (combine, store to LDS) and commit (store owned values) so that the
@@ -227,7 +257,7 @@ void stencil_kernel(LaunchArgs la) {
   //      work.
   //      Node planes z0-1 .. z1 are touched, so a single wrap suffices.
   TL raw_a[2][3];
-  TS raw_b[2][3], raw_c[2][3], raw_d[2], raw_x[3];
+  TS raw_b[2][3], raw_c[2][3], raw_d[2], raw_x[3], raw_aux[NAUX][3];
   TC raw_e[2];
   // node plane z, and the element layer z - 1 below it
   auto issue = [&](int z) {
@@ -253,6 +283,16 @@ void stencil_kernel(LaunchArgs la) {
       } else if constexpr (MODE == MODE_RESID) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = zero_x ? 0.0 : bload<TL>(rA, hoL[k], pz * SL + cL[c]);
+      } else if constexpr (MGF) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) raw_a[k][c] = bload<TS>(rA, hoS[k], pz * SS + cS[c]);
+        if (k == 0 && is_out && ownz) {
+          raw_d[0] = bload<TS>(rE, hoS[0], dOff + pz * SS);
+#pragma unroll
+          for (int a = 0; a < NAUX; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) raw_aux[a][c] = bload<TS>(rAux[a], hoS[0], pz * SS + cS[c]);
+        }
       } else if constexpr (MODE == MODE_MGDIR) {
         // beta = 0 starts a new direction: the old one is not read
 #pragma unroll
@@ -323,6 +363,18 @@ void stencil_kernel(LaunchArgs la) {
             own_p[b][c] = pn[c];
           }
           own_d[b] = dk;
+        }
+      } else if constexpr (MGF) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nbuf[b][c][hslot[k]] = (TC)raw_a[k][c];
+        if (k == 0 && is_out && ownz) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) own_p[b][c] = (TC)raw_a[0][c];
+          own_d[b] = (TC)raw_d[0];
+#pragma unroll
+          for (int a = 0; a < NAUX; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) own_aux[b][a][c] = (TC)raw_aux[a][c];
         }
       } else if constexpr (MODE == MODE_MGDIR) {
         TC pn[3];
@@ -399,7 +451,7 @@ void stencil_kernel(LaunchArgs la) {
     const int kk = z0 - 1 + sl;
     // the owned values of output plane kk (staged two steps ago, same parity)
     // before this step's staging replaces them
-    TC oz[3], op[3], od = TC(0);
+    TC oz[3], op[3], od = TC(0), oa[NAUX][3];
     if constexpr (MODE == MODE_PCG) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -410,6 +462,14 @@ void stencil_kernel(LaunchArgs la) {
     } else if constexpr (MODE == MODE_MGDIR) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) op[c] = own_p[b][c];
+    } else if constexpr (MGF) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) op[c] = own_p[b][c];
+      od = own_d[b];
+#pragma unroll
+      for (int a = 0; a < NAUX; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) oa[a][c] = own_aux[b][a][c];
     }
     if (is_elem) {
       constexpr int ib = NB == 2 ? b : 0, ibn = NB == 2 ? bn : 0;
@@ -487,6 +547,33 @@ void stencil_kernel(LaunchArgs la) {
           bstore<TS>((TS)qv[c], rQ, ooff, pk + cS[c]);
           acc[0] += (double)op[c] * (double)qv[c];
         }
+      } else if constexpr (MODE == MODE_MGSTEP1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const TC rv = oa[0][c] - qv[c];
+          const TC d1 = c1 * op[c] + c2 * od * rv;
+          bstore<TS>((TS)rv, rR, ooff, pk + cS[c]);
+          bstore<TS>((TS)d1, rP, ooff, pk + cS[c]);
+          bstore<TS>((TS)(op[c] + d1), rX, ooff, pk + cS[c]);
+        }
+      } else if constexpr (MODE == MODE_MGPOST) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const TC rv = oa[0][c] - qv[c];
+          const TC dv = od * rv * ith;
+          bstore<TS>((TS)rv, rR, ooff, pk + cS[c]);
+          bstore<TS>((TS)dv, rP, ooff, pk + cS[c]);
+          bstore<TS>((TS)(op[c] + dv), rX, ooff, pk + cS[c]);
+        }
+      } else if constexpr (MODE == MODE_MGLAST) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const TC xv = oa[1][c] + c1 * op[c] + c2 * od * (oa[2][c] - qv[c]);
+          bstore<TS>((TS)xv, rX, ooff, pk + cS[c]);
+          const double b64 = (double)oa[0][c];
+          acc[0] += b64 * (double)xv;
+          acc[1] += b64 * b64;
+        }
       } else if constexpr (MODE == MODE_RESID) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -514,6 +601,13 @@ void stencil_kernel(LaunchArgs la) {
     if (tid == 0) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) parts[i] = acc[i];
+    }
+  } else if constexpr (MODE == MODE_MGLAST) {
+    double a2[2] = {acc[0], acc[1]};
+    block_sum<2>(a2, red, STENCIL_THREADS);
+    if (tid == 0) {
+      parts[0] = a2[0];
+      parts[1] = a2[1];
     }
   } else if constexpr (MODE == MODE_MGDIR) {
     double a1[1] = {acc[0]};
@@ -555,13 +649,27 @@ hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st) 
   return hipGetLastError();
 }
 
-// Multigrid CG direction: p_j = z + beta p_{j-1} (into the other p buffer),
-// q = K p_j and per-tile partials p_j . q, in the vector precision.
-hipError_t launch_stencil_mgdir(const LaunchArgs &la, int prec, hipStream_t st) {
-  if (la.total == 0) return hipSuccess;
+template <int MODE>
+static void launch_mg_mode(const LaunchArgs &la, int prec, hipStream_t st) {
   const int g = padded_grid(la.total);
-  if (prec == 0) stencil_kernel<double, double, MODE_MGDIR><<<g, Tile<double>::THREADS, 0, st>>>(la);
-  else stencil_kernel<float, float, MODE_MGDIR><<<g, Tile<float>::THREADS, 0, st>>>(la);
+  if (prec == 0) stencil_kernel<double, double, MODE><<<g, Tile<double>::THREADS, 0, st>>>(la);
+  else stencil_kernel<float, float, MODE><<<g, Tile<float>::THREADS, 0, st>>>(la);
+}
+
+// Voxel-level passes of the multigrid-preconditioned CG, in the vector
+// precision: SMG_DIR the CG direction p_j = z + beta p_{j-1} (into the other
+// p buffer), q = K p_j and per-tile partials p_j . q; SMG_STEP1 / SMG_POST /
+// SMG_LAST the operator with the Chebyshev sweep that consumes its output
+// (LAST: per-tile partials b . x, b . b).
+hipError_t launch_stencil_mg(const LaunchArgs &la, int prec, int op, hipStream_t st) {
+  if (la.total == 0) return hipSuccess;
+  switch (op) {
+    case SMG_DIR: launch_mg_mode<MODE_MGDIR>(la, prec, st); break;
+    case SMG_STEP1: launch_mg_mode<MODE_MGSTEP1>(la, prec, st); break;
+    case SMG_POST: launch_mg_mode<MODE_MGPOST>(la, prec, st); break;
+    case SMG_LAST: launch_mg_mode<MODE_MGLAST>(la, prec, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
