@@ -131,10 +131,9 @@ struct SlotDev {
   // CG vectors [6][3][nn] (float mixed / double FP64).  r, p and q are double
   // buffered: a CG pass reads set pcur[k] of load case k and writes the other
   void *r[2], *p[2], *q[2], *x;
-  // multigrid, voxel level: the two Chebyshev direction buffers [6][3][nn]
-  // (the second one also holds the post-smoother's iterate) and the Chebyshev
-  // coefficients 1 / theta, c1, c2
-  void *mgd[2];
+  // multigrid, voxel level: the pre-smoother's second Chebyshev direction
+  // [6][3][nn] (the only one stored) and the coefficients 1 / theta, c1, c2
+  void *mgd;
   double mgc[3];
   double *x64;          // FP64 solution accumulator (mixed); == x for FP64
   double *partials;     // [NRHS][maxparts][PSTRIDE]

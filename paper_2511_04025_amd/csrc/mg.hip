@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(MgBatch B) {
 // Degree-2 Chebyshev smoothing of A x = b at level l, in four sweeps around
 // the operator applications (q = A d or A x from the launch before):
 //   INIT:  d = D^-1 b / theta                    (x = d is implied)
-//          at the voxel level first the CG update x_cg += alpha p,
+//          at the voxel level instead the CG update x_cg += alpha p,
 //          b = r -= alpha q (q = K p), so that b is the new CG residual
 //   STEP1: r = b - q, d' = c1 d + c2 D^-1 r, x = d + d', d = d'
 //   POST:  r = b - q (q = A x), d = D^-1 r / theta, x += d
@@ -327,16 +327,20 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long j = c * nn + i;
-      const T di = l == 0 ? Dv[i] : Dv[j];
       if (op == MGV_INIT) {
-        T bv = b[j];
-        if (a != T(0)) {
-          xcg[j] = xcg[j] + a * pcg[j];
-          bv = bv - a * q[j];
-          b[j] = bv;
+        if (l == 0) {
+          // the Chebyshev direction d = D^-1 b / theta is formed by the operator pass after this
+          if (a != T(0)) {
+            xcg[j] = xcg[j] + a * pcg[j];
+            b[j] = b[j] - a * q[j];
+          }
+        } else {
+          d[j] = Dv[j] * b[j] * ith;
         }
-        d[j] = di * bv * ith;
-      } else if (op == MGV_STEP1) {
+        continue;
+      }
+      const T di = l == 0 ? Dv[i] : Dv[j];
+      if (op == MGV_STEP1) {
         const T rv = b[j] - q[j];
         const T d0 = d[j];
         const T d1 = c1 * d0 + c2 * di * rv;

@@ -55,9 +55,9 @@ size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mg
   char *dev = take(sizeof(MgDev));
   char *sg = take(NSEG * sizeof(Segment));
   char *G = take(8 * 576 * ts);
-  // the voxel level's two Chebyshev direction buffers (its other V-cycle
-  // vectors alias CG vectors)
-  char *d0 = take(2 * (size_t)NRHS * 3 * (size_t)n * n * n * ts);
+  // the voxel level's stored Chebyshev direction (its other V-cycle vectors
+  // alias CG vectors)
+  char *d0 = take((size_t)NRHS * 3 * (size_t)n * n * n * ts);
   if (mg) {
     mg->L = count - 1;
     mg->G = G;
@@ -202,16 +202,16 @@ MgBatch batch_of(const std::vector<Slot *> &slots) {
 }
 
 // Algorithmic bytes of one vector sweep at a level: vectors read and written
-// per node and load case (3 components each) plus the inverse diagonal, once
-// per node (one value at the voxel level, three on coarse levels).  At the
-// voxel level only INIT runs as a vector sweep.
+// per node and load case (3 components each) plus the inverse diagonal (three
+// values per node), once per node.  At the voxel level only INIT runs as a
+// vector sweep, the CG update, which does not read the diagonal.
 double vec_bytes(const Slot &s, int l, int op) {
   const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
   const double nn = double(s.mg.lv[l].nn);
-  const double dv = l == 0 ? 1.0 : 3.0;
+  const double dv = l == 0 ? 0.0 : 3.0;
   double vals = 0.0;
   switch (op) {
-    case MGV_INIT: vals = l == 0 ? 3 * (4 + 3) : 3 * (1 + 1); break;  // voxel: x, p, r, q -> x, r, d
+    case MGV_INIT: vals = l == 0 ? 3 * (4 + 2) : 3 * (1 + 1); break;  // voxel: x, p, r, q -> x, r
     case MGV_STEP1: vals = 3 * (3 + 3); break;                       // b, q, d -> r, d, x
     case MGV_POST: vals = 3 * (3 + 3); break;                        // b, q, x -> r, d, x
     default: vals = 3 * (4 + 1); break;                              // r, q, d, x -> x
@@ -296,9 +296,8 @@ int mg_setup(Slot &s, hipStream_t st) {
   L0.x = h.r[1];
   L0.r = h.q[1];
   L0.q = h.q[0];
-  h.mgd[0] = L0.d;
-  h.mgd[1] = (char *)L0.d + (size_t)NRHS * 3 * h.nn * ts;
-  SHH_HIP(hipMemcpyAsync(&s.d_slot->mgd, h.mgd, sizeof(h.mgd), hipMemcpyHostToDevice, st));
+  h.mgd = L0.d;
+  SHH_HIP(hipMemcpyAsync(&s.d_slot->mgd, &h.mgd, sizeof(h.mgd), hipMemcpyHostToDevice, st));
   // element matrices of levels >= 1 live in the (not yet used) CG vector region
   {
     char *ke = s.base + s.lay.vec;

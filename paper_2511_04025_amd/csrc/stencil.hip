@@ -158,7 +158,9 @@ void stencil_kernel(LaunchArgs la) {
   if constexpr (sizeof(TC) == 8) Ebase = (const char *)s->E64;
   else Ebase = (const char *)s->E32;
   constexpr bool MGF = MODE >= MODE_MGSTEP1;  // a Chebyshev sweep fused behind the operator
-  constexpr bool WITH_D = MODE == MODE_PCG || MGF;
+  // operand staged as D^-1 v / theta (v = b or r: the direction is not stored)
+  constexpr bool MG_SCALED = MODE == MODE_MGSTEP1 || MODE == MODE_MGLAST;
+  constexpr bool WITH_D = MODE == MODE_PCG || MG_SCALED;
   const uint32_t dOff = WITH_D ? (uint32_t)((const char *)s->Dinv - Ebase) : 0u;
   const rsrc_t rE = make_rsrc(Ebase, WITH_D ? (uint64_t)dOff + (uint64_t)nn * SS : (uint64_t)nn * SC);
 
@@ -170,15 +172,17 @@ void stencil_kernel(LaunchArgs la) {
   // PCG: rA = r_{j-1}, rB = q_{j-1}, rC = p_{j-1}; rR, rQ, rP the new set; rX
   // RESID: rA = FP64 x, rQ = current r.  APPLY: rA = p, rQ = q (or the pair the flag names).
   // MGDIR (the multigrid CG's direction pass): rA = z, rC = p_{j-1}, rP = p_j, rQ = q.
-  // Fused voxel-level Chebyshev sweeps: rA the operand v (q = K v is not
-  // stored), rAux the owned-node inputs, rR, rP, rX the outputs:
-  //   STEP1: v = d0 (mgd[0]); aux b;       r = b - q, d1 = c1 d0 + c2 D r,
-  //          x = d0 + d1 -> r (q[1]), d1 (mgd[1]), x (r[1])
-  //   POST:  v = x (r[1]); aux b;          r = b - q, d = D r / theta, x + d
-  //          -> r (q[1]), d (mgd[0]), x (mgd[1])
-  //   LAST:  v = d (mgd[0]); aux b, x, r;  x + c1 d + c2 D (r - q) -> r[1],
-  //          partials b . x, b . b
-  constexpr int NAUX = MODE == MODE_MGLAST ? 3 : 1;
+  // Fused voxel-level Chebyshev sweeps (q = K v is consumed, not stored); rA
+  // the vector staged over the halo, rAux the owned-node inputs, rR, rP, rX
+  // the outputs:
+  //   STEP1: b (r[0]) staged as d0 = D b / theta;  r = b - q,
+  //          d1 = c1 d0 + c2 D r, x = d0 + d1 -> r (q[1]), d1 (mgd), x (r[1])
+  //   POST:  x (r[1]) staged as is; aux b;  r = b - q -> q[1]
+  //   LAST:  r (q[1]) staged as d = D r / theta; aux b, x;
+  //          x + (1 + c1) d + c2 D (r - q) -> r[1], partials b . x, b . b
+  //          (the post-smoother's x + d folded into the last update)
+  constexpr int NAUX = MODE == MODE_MGLAST ? 2 : 1;
+  constexpr int NLOAD = MODE == MODE_MGSTEP1 ? 0 : NAUX;  // auxiliary vectors read
   rsrc_t rA, rB, rC, rR, rQ, rP, rX, rAux[NAUX];
   TC alpha = TC(0), beta = TC(0);
   TC ith = TC(0), c1 = TC(0), c2 = TC(0);
@@ -186,16 +190,20 @@ void stencil_kernel(LaunchArgs la) {
     ith = (TC)s->mgc[0];
     c1 = (TC)s->mgc[1];
     c2 = (TC)s->mgc[2];
-    rA = make_rsrc((const TS *)(MODE == MODE_MGPOST ? s->r[1] : s->mgd[0]) + vbase, vbytesS);
-    rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
-    if constexpr (MODE == MODE_MGLAST) {
-      rAux[NAUX - 2] = make_rsrc((const TS *)s->mgd[1] + vbase, vbytesS);
-      rAux[NAUX - 1] = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
-      rX = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
-    } else {
+    if constexpr (MODE == MODE_MGSTEP1) {
+      rA = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
       rR = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
-      rP = make_rsrc((const TS *)s->mgd[MODE == MODE_MGSTEP1 ? 1 : 0] + vbase, vbytesS);
-      rX = make_rsrc((const TS *)(MODE == MODE_MGSTEP1 ? s->r[1] : s->mgd[1]) + vbase, vbytesS);
+      rP = make_rsrc((const TS *)s->mgd + vbase, vbytesS);
+      rX = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+    } else if constexpr (MODE == MODE_MGPOST) {
+      rA = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+      rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
+      rR = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
+    } else {
+      rA = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
+      rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
+      rAux[NAUX - 1] = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+      rX = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
     }
   } else if constexpr (MODE == MODE_MGDIR) {
     const int pc = st->mgpar[rhs];
@@ -219,7 +227,7 @@ void stencil_kernel(LaunchArgs la) {
     rA = make_rsrc(s->x64 + vbase, vbytesL);
     rQ = make_rsrc((const TS *)s->r[st->pcur[rhs]] + vbase, vbytesS);
   } else {
-    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x, mgd[1])
+    // flag 0: p[0] -> q[0]; otherwise 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x, mgd)
     const void *src = s->p[0];
     void *dst = s->q[0];
     if (w.flag > 0) {
@@ -232,7 +240,7 @@ void stencil_kernel(LaunchArgs la) {
           case 4: return s->q[0];
           case 5: return s->q[1];
           case 6: return s->x;
-          default: return s->mgd[1];
+          default: return s->mgd;
         }
       };
       src = pick((w.flag - 1) & 7);
@@ -284,12 +292,12 @@ void stencil_kernel(LaunchArgs la) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = zero_x ? 0.0 : bload<TL>(rA, hoL[k], pz * SL + cL[c]);
       } else if constexpr (MGF) {
+        if constexpr (MG_SCALED) raw_d[k] = bload<TS>(rE, hoS[k], dOff + pz * SS);
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = bload<TS>(rA, hoS[k], pz * SS + cS[c]);
         if (k == 0 && is_out && ownz) {
-          raw_d[0] = bload<TS>(rE, hoS[0], dOff + pz * SS);
 #pragma unroll
-          for (int a = 0; a < NAUX; ++a)
+          for (int a = 0; a < NLOAD; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) raw_aux[a][c] = bload<TS>(rAux[a], hoS[0], pz * SS + cS[c]);
         }
@@ -365,14 +373,23 @@ void stencil_kernel(LaunchArgs la) {
           own_d[b] = dk;
         }
       } else if constexpr (MGF) {
+        TC v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) nbuf[b][c][hslot[k]] = (TC)raw_a[k][c];
+        for (int c = 0; c < 3; ++c) {
+          v[c] = (TC)raw_a[k][c];
+          if constexpr (MG_SCALED) v[c] = (TC)raw_d[k] * v[c] * ith;
+          nbuf[b][c][hslot[k]] = v[c];
+        }
         if (k == 0 && is_out && ownz) {
+          // own_p: the staged value, own_z: the vector it came from
 #pragma unroll
-          for (int c = 0; c < 3; ++c) own_p[b][c] = (TC)raw_a[0][c];
-          own_d[b] = (TC)raw_d[0];
+          for (int c = 0; c < 3; ++c) {
+            own_p[b][c] = v[c];
+            own_z[b][c] = (TC)raw_a[0][c];
+          }
+          if constexpr (MG_SCALED) own_d[b] = (TC)raw_d[0];
 #pragma unroll
-          for (int a = 0; a < NAUX; ++a)
+          for (int a = 0; a < NLOAD; ++a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) own_aux[b][a][c] = (TC)raw_aux[a][c];
         }
@@ -464,10 +481,13 @@ void stencil_kernel(LaunchArgs la) {
       for (int c = 0; c < 3; ++c) op[c] = own_p[b][c];
     } else if constexpr (MGF) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) op[c] = own_p[b][c];
-      od = own_d[b];
+      for (int c = 0; c < 3; ++c) {
+        op[c] = own_p[b][c];
+        oz[c] = own_z[b][c];
+      }
+      if constexpr (MG_SCALED) od = own_d[b];
 #pragma unroll
-      for (int a = 0; a < NAUX; ++a)
+      for (int a = 0; a < NLOAD; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) oa[a][c] = own_aux[b][a][c];
     }
@@ -548,27 +568,25 @@ void stencil_kernel(LaunchArgs la) {
           acc[0] += (double)op[c] * (double)qv[c];
         }
       } else if constexpr (MODE == MODE_MGSTEP1) {
+        // op = d0, oz = b
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const TC rv = oa[0][c] - qv[c];
+          const TC rv = oz[c] - qv[c];
           const TC d1 = c1 * op[c] + c2 * od * rv;
           bstore<TS>((TS)rv, rR, ooff, pk + cS[c]);
           bstore<TS>((TS)d1, rP, ooff, pk + cS[c]);
           bstore<TS>((TS)(op[c] + d1), rX, ooff, pk + cS[c]);
         }
       } else if constexpr (MODE == MODE_MGPOST) {
+        // oa[0] = b
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const TC rv = oa[0][c] - qv[c];
-          const TC dv = od * rv * ith;
-          bstore<TS>((TS)rv, rR, ooff, pk + cS[c]);
-          bstore<TS>((TS)dv, rP, ooff, pk + cS[c]);
-          bstore<TS>((TS)(op[c] + dv), rX, ooff, pk + cS[c]);
-        }
+        for (int c = 0; c < 3; ++c) bstore<TS>((TS)(oa[0][c] - qv[c]), rR, ooff, pk + cS[c]);
       } else if constexpr (MODE == MODE_MGLAST) {
+        // op = d, oz = r, oa = b, x
+        const TC c1p = TC(1) + c1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const TC xv = oa[1][c] + c1 * op[c] + c2 * od * (oa[2][c] - qv[c]);
+          const TC xv = oa[1][c] + c1p * op[c] + c2 * od * (oz[c] - qv[c]);
           bstore<TS>((TS)xv, rX, ooff, pk + cS[c]);
           const double b64 = (double)oa[0][c];
           acc[0] += b64 * (double)xv;
