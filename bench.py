@@ -56,30 +56,30 @@ def pcg_traffic_per_node_case():
     return PCG_TRAFFIC["fetch_bytes_per_node_case"] + PCG_TRAFFIC["write_bytes_per_node_case"]
 
 
-# HBM traffic of the V-cycle vector sweep kernel relative to its algorithmic
-# bytes: FETCH_SIZE x2.0 + WRITE_SIZE x1.0 summed over every launch of one
-# timed step of the default workload, over the algorithmic bytes the library
-# reported for the same launches (profiles/mg_vcycle_128_hbm_traffic.md).  It
-# holds only for the sources it was measured on (digest); null otherwise.
-MG_VEC_TRAFFIC = {
+# HBM traffic of the first coarse level's operator kernel relative to its
+# algorithmic bytes: FETCH_SIZE x2.0 + WRITE_SIZE x1.0 summed over every launch
+# of the kernel in one step of the default workload, over the algorithmic bytes
+# of the same launches (profiles/mg_apply_128_hbm_traffic.md).  It holds only
+# for the sources it was measured on (digest); null otherwise.
+MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "7eae8e5093338ae812b856edae51197eaa87497365e4e820f2fe56077b0a656d",
-    "traffic_per_algorithmic_byte": 0.9794,
+    "sha256": None,
+    "traffic_per_algorithmic_byte": None,
 }
 
 
-def mg_vec_traffic_per_byte():
+def mg_apply_traffic_per_byte():
     import hashlib
-    if MG_VEC_TRAFFIC["sha256"] is None:
+    if MG_APPLY_TRAFFIC["sha256"] is None:
         return None
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_04025_amd", "csrc")
-    for f in MG_VEC_TRAFFIC["sources"]:
+    for f in MG_APPLY_TRAFFIC["sources"]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != MG_VEC_TRAFFIC["sha256"]:
+    if h.hexdigest() != MG_APPLY_TRAFFIC["sha256"]:
         return None
-    return MG_VEC_TRAFFIC["traffic_per_algorithmic_byte"]
+    return MG_APPLY_TRAFFIC["traffic_per_algorithmic_byte"]
 
 
 def parse():
@@ -353,13 +353,14 @@ def main():
         traffic = int(per_nc * node_cases / max(n_launch, 1)) if per_nc is not None else None
         kname = "stencil_kernel<float,float,PCG>"
     else:
-        # roofline of the V-cycle vector sweep kernel (the largest share of the
-        # multigrid iteration): the library adds each timed launch's
-        # algorithmic bytes
+        # roofline of the first coarse level's operator q = A_1 v (27-point
+        # 3x3-block stencil, all six load cases per thread; the kernel with the
+        # largest share of the multigrid iteration): the library adds each
+        # timed launch's algorithmic bytes
         nbytes = timed_bytes.value
-        per_launch = mg_vec_traffic_per_byte()
+        per_launch = mg_apply_traffic_per_byte()
         traffic = int(per_launch * nbytes / max(n_launch, 1)) if per_launch is not None else None
-        kname = "mg_vec_kernel<float>"
+        kname = "mg_apply_kernel<float,6>"
     achieved = nbytes / t_kernel / 1e9 if t_kernel > 0 else 0.0
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

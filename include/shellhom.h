@@ -218,9 +218,10 @@ int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts 
    When enabled, every launch of the solver's dominant kernel is bracketed by
    two HIP events on the stream it runs on: with SHH_SOLVER_JACOBI the CG pass
    kernel (one whole PCG iteration: q = K p fused with the vector updates),
-   with SHH_SOLVER_MG the V-cycle vector sweep kernel (Chebyshev steps and
-   residual updates at every level), whose launches also add their algorithmic
-   bytes (the values the sweep must read and write).  Elapsed times are
+   with SHH_SOLVER_MG the coarse-grid operator q = A_1 v of the first coarse
+   level (the 27-point block stencil, all six load cases per launch), whose
+   launches also add their algorithmic bytes (the stored stencil once, v read
+   and q written per load case).  Elapsed times are
    accumulated process-wide when the solver next synchronizes.
    shh_profile_read returns the number of timed launches and their total
    milliseconds, shh_profile_read_bytes also the bytes (0 for CG pass

@@ -160,6 +160,10 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
   for (int r = 0; r < RHS; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[r][c] = T(0);
+  // three offsets per trip: their loads are in flight together (measured
+  // faster than one; more waves per SIMD or fewer load cases per thread are
+  // slower, the stencil reads then miss the caches more)
+#pragma unroll 3
   for (int w = 0; w < 27; ++w) {
     const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
     const long long u = ((long long)wrap1(z + dz, n) * n + wrap1(y + dy, n)) * n + wrap1(x + dx, n);
@@ -592,8 +596,11 @@ hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, h
   return hipGetLastError();
 }
 
+// whether mg_launch_apply takes the all-load-cases-per-thread variant
+bool mg_apply_wide(long long nn_max) { return nn_max > 32768; }
+
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st) {
-  if (nn_max > 32768) {
+  if (mg_apply_wide(nn_max)) {
     const dim3 g(blocks_for(nn_max, 256), 1, B.count);
     if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(B, l, src);
     else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(B, l, src);

@@ -24,6 +24,7 @@ hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
 hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st);
+bool mg_apply_wide(long long nn_max);
 hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
 hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
 hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
@@ -201,22 +202,12 @@ MgBatch batch_of(const std::vector<Slot *> &slots) {
   return B;
 }
 
-// Algorithmic bytes of one vector sweep at a level: vectors read and written
-// per node and load case (3 components each) plus the inverse diagonal (three
-// values per node), once per node.  At the voxel level only INIT runs as a
-// vector sweep, the CG update, which does not read the diagonal.
-double vec_bytes(const Slot &s, int l, int op) {
+// Algorithmic bytes of one coarse-level operator application q = A_l v: the
+// stored half stencil (MG_STENCIL values per node, read once for all load
+// cases) and, per load case, v read and q written (3 components each).
+double apply_bytes(const Slot &s, int l) {
   const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
-  const double nn = double(s.mg.lv[l].nn);
-  const double dv = l == 0 ? 0.0 : 3.0;
-  double vals = 0.0;
-  switch (op) {
-    case MGV_INIT: vals = l == 0 ? 3 * (4 + 2) : 3 * (1 + 1); break;  // voxel: x, p, r, q -> x, r
-    case MGV_STEP1: vals = 3 * (3 + 3); break;                       // b, q, d -> r, d, x
-    case MGV_POST: vals = 3 * (3 + 3); break;                        // b, q, x -> r, d, x
-    default: vals = 3 * (4 + 1); break;                              // r, q, d, x -> x
-  }
-  return nn * (NRHS * vals + dv) * ts;
+  return double(s.mg.lv[l].nn) * (MG_STENCIL + NRHS * 3 * 2) * ts;
 }
 
 // One V-cycle from level l down, for slots that all have at least l + 1
@@ -237,18 +228,22 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   }
   int rc;
   auto vec = [&](int op) -> int {
-    hipEvent_t e0 = nullptr;
-    if (timer && (rc = timer->timed_begin(&e0))) return rc;
     SHH_HIP(mg_launch_vec(B, l, op, nch_max, prec, st));
-    if (!timer) return SHH_OK;
-    double bytes = 0.0;
-    for (Slot *s : smooth) bytes += vec_bytes(*s, l, op);
-    return timer->timed_end(e0, bytes);
+    return SHH_OK;
   };
+  // when profiling, the coarse operator launches that take a node per thread
+  // for all load cases (the largest coarse level) are timed with their
+  // algorithmic bytes
   auto app = [&](int src) -> int {
     if (l == 0) return apply0(smooth, MG_SRC_D);  // only the direction is applied bare
+    const bool timed = timer && mg_apply_wide(nn_max);
+    hipEvent_t e0 = nullptr;
+    if (timed && (rc = timer->timed_begin(&e0))) return rc;
     SHH_HIP(mg_launch_apply(B, l, src, nn_max, prec, st));
-    return SHH_OK;
+    if (!timed) return SHH_OK;
+    double bytes = 0.0;
+    for (Slot *s : smooth) bytes += apply_bytes(*s, l);
+    return timer->timed_end(e0, bytes);
   };
   // pre-smoother (at the voxel level INIT also applies the pending CG
   // update, and the operator runs fused with the sweep after it)

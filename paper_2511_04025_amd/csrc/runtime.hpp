@@ -76,8 +76,8 @@ constexpr int MG_FLAG_ZQ = 1 + 1 + 8 * 4, MG_FLAG_DQ = 1 + 7 + 8 * 4;
 class Solver;
 using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // one multigrid-preconditioned CG iteration of every load case of the slots
-// (timer: when profiling, the V-cycle vector sweeps are timed with their
-// algorithmic bytes)
+// (timer: when profiling, the largest coarse level's operator launches are
+// timed with their algorithmic bytes)
 int mg_iterate(const std::vector<Slot *> &slots, hipStream_t st, Solver *timer, const MgApply0 &apply0);
 // q = A_l v for the Galerkin operator of level l >= 1 of a set-up slot (all six
 // load cases, [6][3][n_l^3] in the slot's precision)
