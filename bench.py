@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # any change to them the bench reports null until the counters are taken again.
 PCG_TRAFFIC = {
     "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
-    "sha256": "dba9d9a889525ba5257ae20f79f2ee94972700dbceb05a873709852d4bf93771",
-    "fetch_bytes_per_node_case": 66.62,
+    "sha256": "0801c1795af03fbcaffed560b704341c0c5a6128133017ff1042dd49d4170f20",
+    "fetch_bytes_per_node_case": 67.11,
     "write_bytes_per_node_case": 48.01,
 }
 # What a plain 1 GiB device-to-device copy sustains on this GPU (read + write,
@@ -63,8 +63,8 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": None,
-    "traffic_per_algorithmic_byte": None,
+    "sha256": "970e88d4bab01d792ebb2a00cce41267854c545756a95786c759c2e5a2298529",
+    "traffic_per_algorithmic_byte": 2.1313,
 }
 
 
