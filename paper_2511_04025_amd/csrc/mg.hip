@@ -542,22 +542,29 @@ __global__ __launch_bounds__(1024) void mg_coarse_inverse_kernel(MgDev *mg) {
     if (i % 3 == j % 3) A[k] += add;
   }
   __syncthreads();
-  // column k of the current matrix, kept while the rows are updated
+  // column k of the current matrix and the normalized pivot row, kept in LDS
+  // while the other rows are updated (each wave sweeps rows, its lanes the
+  // columns)
   __shared__ double colk[3 * MG_MAX_COARSE * MG_MAX_COARSE * MG_MAX_COARSE];
+  __shared__ double rowk[3 * MG_MAX_COARSE * MG_MAX_COARSE * MG_MAX_COARSE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   for (int k = 0; k < m; ++k) {
     const double piv = A[(long long)k * m + k];
     for (int i = threadIdx.x; i < m; i += blockDim.x) colk[i] = A[(long long)i * m + k];
     __syncthreads();
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
       const long long kj = (long long)k * m + j;
-      A[kj] = j == k ? 1.0 / piv : A[kj] / piv;
+      const double v = j == k ? 1.0 / piv : A[kj] / piv;
+      A[kj] = v;
+      rowk[j] = v;
     }
     __syncthreads();
     // rows i != k: A[i][j] -= f_i A[k][j] (j != k), A[i][k] = -f_i / piv
-    for (long long t = threadIdx.x; t < (long long)m * m; t += blockDim.x) {
-      const int i = int(t / m), j = int(t % m);
+    for (int i = wave; i < m; i += nwaves) {
       if (i == k) continue;
-      A[t] = (j == k ? 0.0 : A[t]) - colk[i] * A[(long long)k * m + j];
+      const double f = colk[i];
+      double *Ai = A + (long long)i * m;
+      for (int j = lane; j < m; j += 64) Ai[j] = (j == k ? 0.0 : Ai[j]) - f * rowk[j];
     }
     __syncthreads();
   }
@@ -609,6 +616,14 @@ hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, i
     if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, src);
     else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, src);
   }
+  return hipGetLastError();
+}
+
+// q = A_l v for load case 0 only (the setup's power iteration)
+hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st) {
+  const dim3 g(blocks_for(nn_max, 256), 1, B.count);
+  if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, 0);
+  else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, 0);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
 hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st);
+hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st);
 bool mg_apply_wide(long long nn_max);
 hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
 hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
@@ -37,14 +38,11 @@ namespace {
 
 size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// the slot's own segment table: the power iteration's voxel-level operator
-// on load case 0 (the iteration's operator launches use the solver's tables)
-constexpr int NSEG = 1;
-constexpr int POWER_ITERS = 30;  // power steps per level
+constexpr int POWER_ITERS = 30;  // power steps per coarse level
 
 // Lay out the multigrid region at `base` (nullptr: sizing only).  Fills the
-// level-1.. descriptors' persistent buffers, G, Mc and the segment table.
-size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mgdev) {
+// level descriptors' persistent buffers, G and Mc.
+size_t carve(char *base, int n, int prec, MgDev *mg, char **d_mgdev) {
   const size_t ts = prec == SHH_PREC_FP64 ? 8 : 4;
   const int count = mg_num_levels(n);
   size_t off = 0;
@@ -54,7 +52,6 @@ size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mg
     return base ? base + o : nullptr;
   };
   char *dev = take(sizeof(MgDev));
-  char *sg = take(NSEG * sizeof(Segment));
   char *G = take(8 * 576 * ts);
   // the voxel level's stored Chebyshev direction (its other V-cycle vectors
   // alias CG vectors)
@@ -65,7 +62,6 @@ size_t carve(char *base, int n, int prec, MgDev *mg, Segment **segs, char **d_mg
     mg->lv[0].d = d0;
   }
   if (d_mgdev) *d_mgdev = dev;
-  if (segs) *segs = (Segment *)sg;
   long long nl = n;
   for (int l = 1; l < count; ++l) {
     nl /= 2;
@@ -268,7 +264,7 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
 
 size_t mg_region_bytes(int n, int prec) {
   if (mg_num_levels(n) < 2) return 0;
-  return carve(nullptr, n, prec, nullptr, nullptr, nullptr);
+  return carve(nullptr, n, prec, nullptr, nullptr);
 }
 
 int mg_setup(Slot &s, hipStream_t st) {
@@ -279,7 +275,7 @@ int mg_setup(Slot &s, hipStream_t st) {
   const size_t ts = prec == SHH_PREC_FP64 ? 8 : 4;
   std::memset(&s.mg, 0, sizeof(s.mg));
   char *dev = nullptr;
-  carve(s.base + s.lay.mg, n, prec, &s.mg, &s.d_mgsegs, &dev);
+  carve(s.base + s.lay.mg, n, prec, &s.mg, &dev);
   s.d_mg = (MgDev *)dev;
   MgDev &mg = s.mg;
   MgLevel &L0 = mg.lv[0];
@@ -316,30 +312,15 @@ int mg_setup(Slot &s, hipStream_t st) {
   for (int l = 1; l + 1 < count; ++l) SHH_HIP(mg_launch_elemc(s.d_mg, l, mg.lv[l + 1].nn, prec, st));
   for (int l = 1; l < count; ++l) SHH_HIP(mg_launch_stencil(s.d_mg, l, mg.lv[l].nn, prec, st));
   SHH_HIP(mg_launch_coarse_inverse(s.d_mg, prec, st));
-  // the power iteration's voxel-level operator: z (r[1]) -> q[0], load case 0
-  Segment sg;
-  std::memset(&sg, 0, sizeof(sg));
-  const int tiling = prec == SHH_PREC_MIXED ? 1 : 0;
-  sg.slot = s.d_slot;
-  sg.first = 0;
-  sg.nrhs = 1;
-  sg.rhs[0] = 0;
-  sg.nblocks = h.ntiles[tiling];
-  sg.flag = MG_FLAG_ZQ;
-  SHH_HIP(hipMemcpyAsync(s.d_mgsegs, &sg, sizeof(sg), hipMemcpyHostToDevice, st));
-  // lambda_max(D^-1 A) of every smoothing level by power iteration on load
-  // case 0, entirely on the device (phase 0 start, then per step: apply,
-  // phase 1 sweep, reduction, phase 2 normalization); one read-back at the end
-  for (int l = 0; l < mg.L; ++l) {
+  // lambda_max(D^-1 A) of every coarse smoothing level by power iteration
+  // on load case 0, entirely on the device (phase 0 start, then per step:
+  // apply, phase 1 sweep, reduction, phase 2 normalization); one read-back at
+  // the end.  The voxel level needs none: it takes the rigorous bound.
+  for (int l = 1; l < mg.L; ++l) {
     const MgLevel &L = mg.lv[l];
     SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 0, L.nchunks, prec, st));
     for (int it = 0; it < POWER_ITERS; ++it) {
-      if (l == 0) {
-        LaunchArgs la{s.d_mgsegs, 1, h.ntiles[tiling]};
-        SHH_HIP(launch_stencil_apply(la, prec, st));
-      } else {
-        SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, prec, st));
-      }
+      SHH_HIP(mg_launch_apply_case0(batch_of({&s}), l, L.nn, prec, st));
       SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 1, L.nchunks, prec, st));
       SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 3, L.nchunks, prec, st));
       SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 2, L.nchunks, prec, st));
@@ -350,17 +331,20 @@ int mg_setup(Slot &s, hipStream_t st) {
   SHH_HIP(hipStreamSynchronize(st));
   for (int l = 0; l < mg.L; ++l) {
     MgLevel &W = mg.lv[l];
-    const double lam = est.lv[l].lmax;
+    // Chebyshev interval [hi/33, hi]: above lambda_max, or the smoother
+    // amplifies the top of the spectrum and the V-cycle stops being positive
+    // definite.  The voxel level takes the rigorous element bound
+    // lambda_max(diag(K_0)^-1 K_0) >= lambda_max(D^-1 K) (its power estimates
+    // on the headline designs, 3.0 to 4.2, sit well below it); the Rayleigh
+    // quotients of a coarse level bound its lambda_max from below, so those
+    // levels take a generous 1.5 x the estimate.
+    const double lam = l == 0 ? bound0 : est.lv[l].lmax;
     if (!(lam > 0.0) || !std::isfinite(lam)) return SHH_BREAKDOWN;
     W.lmax = lam;
     if (std::getenv("SHH_MG_VERBOSE"))
-      std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f\n", n, l, W.n, lam);
-    // Chebyshev interval [hi/33, hi]: above lambda_max, or the smoother
-    // amplifies the top of the spectrum and the V-cycle stops being positive
-    // definite.  The Rayleigh quotients bound lambda_max from below, so the
-    // voxel level takes the rigorous element bound and coarse levels a
-    // generous 1.5 x the estimate.
-    const double hi = l == 0 ? std::max(bound0, 1.1 * lam) : 1.5 * lam, lo = hi / 33.0;
+      std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f%s\n", n, l, W.n, lam,
+                   l == 0 ? " (bound)" : "");
+    const double hi = l == 0 ? bound0 : 1.5 * lam, lo = hi / 33.0;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
     const double sigma = theta / delta, rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
     W.inv_theta = 1.0 / theta;

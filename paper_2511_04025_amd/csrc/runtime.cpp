@@ -478,10 +478,10 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
   // voxel-level operator over all the given slots, one launch
   MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
-    static const Kind kinds[6] = {K_MG_DIR, K_MG_Z, K_MG_D, K_MG_STEP1, K_MG_POST, K_MG_LAST};
-    static const int ops[6] = {SMG_DIR, -1, -1, SMG_STEP1, SMG_POST, SMG_LAST};
+    static const Kind kinds[5] = {K_MG_DIR, K_MG_D, K_MG_STEP1, K_MG_POST, K_MG_LAST};
+    static const int ops[5] = {SMG_DIR, -1, SMG_STEP1, SMG_POST, SMG_LAST};
     if (src < 0 || src > MG_SRC_LAST) return SHH_INVALID_ARG;
-    const int flag = src == MG_SRC_Z ? MG_FLAG_ZQ : (src == MG_SRC_D ? MG_FLAG_DQ : 0);
+    const int flag = src == MG_SRC_D ? MG_FLAG_DQ : 0;
     LaunchArgs la;
     int r;
     if ((r = build(kinds[src], ss, flag, true, la))) return r;
