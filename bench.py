@@ -63,8 +63,8 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "970e88d4bab01d792ebb2a00cce41267854c545756a95786c759c2e5a2298529",
-    "traffic_per_algorithmic_byte": 2.1313,
+    "sha256": "a1277e69fb37e59eb9bf16a0b838dc807b796f5dc67505e0ecce7658fe174214",
+    "traffic_per_algorithmic_byte": 2.146,
 }
 
 
