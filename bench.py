@@ -63,7 +63,7 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "a1277e69fb37e59eb9bf16a0b838dc807b796f5dc67505e0ecce7658fe174214",
+    "sha256": "5d928426d45e989d7dbdd56ebd8e8f836700f633fcfeae9661ef1bf46a50709d",
     "traffic_per_algorithmic_byte": 2.146,
 }
 

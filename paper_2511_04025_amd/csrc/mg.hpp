@@ -11,10 +11,11 @@
 // K_f = E_f K_0, so K_E = sum_f E_f G_f with G_f = Q_f^T K_0 Q_f.  Coarse
 // element matrices are assembled into 27-point nodal stencils of 3 x 3 blocks
 // for the smoother and residual sweeps.  Smoothing is Chebyshev (degree 2)
-// on D^-1 A over [lambda_max / 30, 1.1 lambda_max], lambda_max estimated by
-// power iteration; the coarsest level (at most 8^3 nodes) is solved with a
-// dense inverse of its operator made nonsingular on the three rigid
-// translations, assembled and inverted on the device.
+// on D^-1 A over [h / 33, h], h an upper bound of lambda_max: on the voxel
+// level the element bound lambda_max(diag(K_0)^-1 K_0), on coarse levels
+// 1.5 x a power-iteration estimate; the coarsest level (at most 8^3 nodes) is
+// solved with a dense inverse of its operator made nonsingular on the three
+// rigid translations, assembled and inverted on the device.
 #pragma once
 
 #include "common.hpp"
