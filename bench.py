@@ -63,8 +63,8 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "5d928426d45e989d7dbdd56ebd8e8f836700f633fcfeae9661ef1bf46a50709d",
-    "traffic_per_algorithmic_byte": 2.146,
+    "sha256": "5483d45de88ca29756012a7028bb8e2ffe6c28911e62c53366ef138078359d40",
+    "traffic_per_algorithmic_byte": 2.1437,
 }
 
 

@@ -1,10 +1,13 @@
 // Host side of the multigrid-preconditioned CG (see mg.hpp): memory carving,
 // setup (Galerkin hierarchy, coarsest inverse, Chebyshev bounds) and the
 // V-cycle / CG launch sequence of one iteration.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <vector>
 
 #include "hexop.hpp"
@@ -118,26 +121,43 @@ void dense_k0(const double kop[KOP_N], double K0[24][24]) {
 
 // lambda_max(diag(K_0)^-1 K_0): since K = sum_e E_e K_0 with D = sum_e E_e
 // diag(K_0), x^T K x <= this value times x^T D x, so it bounds
-// lambda_max(D^-1 K) on the voxel grid whatever the moduli.  Power iteration
-// on the symmetric D_0^-1/2 K_0 D_0^-1/2 with Rayleigh quotients.
+// lambda_max(D^-1 K) on the voxel grid whatever the moduli.  It is the
+// largest eigenvalue of the symmetric D_0^-1/2 K_0 D_0^-1/2, found by cyclic
+// Jacobi rotations (converged to rounding; a power iteration's Rayleigh
+// quotient would only approach it from below).
 double element_bound(const double K0[24][24]) {
-  double v[24], w[24], lam = 0.0;
-  for (int i = 0; i < 24; ++i) v[i] = 1.0 + 0.01 * i * ((i & 1) ? -1.0 : 1.0);
-  for (int it = 0; it < 4000; ++it) {
-    double nv = 0.0;
-    for (int i = 0; i < 24; ++i) nv += v[i] * v[i];
-    nv = std::sqrt(nv);
-    for (int i = 0; i < 24; ++i) v[i] /= nv;
-    double rq = 0.0;
-    for (int i = 0; i < 24; ++i) {
-      double a = 0.0;
-      for (int j = 0; j < 24; ++j) a += K0[i][j] / std::sqrt(K0[i][i] * K0[j][j]) * v[j];
-      w[i] = a;
-      rq += v[i] * a;
+  constexpr int N = 24;
+  double A[N][N];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) A[i][j] = K0[i][j] / std::sqrt(K0[i][i] * K0[j][j]);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < N; ++i) {
+      diag += A[i][i] * A[i][i];
+      for (int j = i + 1; j < N; ++j) off += A[i][j] * A[i][j];
     }
-    lam = rq;
-    for (int i = 0; i < 24; ++i) v[i] = w[i];
+    if (off <= 1e-30 * diag) break;
+    for (int p = 0; p < N; ++p)
+      for (int q = p + 1; q < N; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation that zeroes A[p][q] (Golub & Van Loan, symmetric Schur)
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < N; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+      }
   }
+  double lam = A[0][0];
+  for (int i = 1; i < N; ++i) lam = std::max(lam, A[i][i]);
   return lam;
 }
 
@@ -172,6 +192,39 @@ void child_galerkin(const double K0[24][24], std::vector<double> &G) {
         G[(f * 24 + i) * 24 + k] = v;
       }
   }
+}
+
+// The constants of one element operator (a Poisson ratio): the voxel-level
+// bound and the child Galerkin matrices, computed once per process and kept
+// for the last few operators seen.
+void nu_constants(const double kop[KOP_N], double &bound0, std::vector<double> &G) {
+  struct Entry {
+    double kop[KOP_N];
+    double bound0;
+    std::vector<double> G;
+  };
+  static std::mutex mu;
+  static std::deque<Entry> cache;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry &e : cache)
+      if (std::memcmp(e.kop, kop, sizeof(e.kop)) == 0) {
+        bound0 = e.bound0;
+        G = e.G;
+        return;
+      }
+  }
+  double K0[24][24];
+  dense_k0(kop, K0);
+  bound0 = element_bound(K0);
+  child_galerkin(K0, G);
+  std::lock_guard<std::mutex> lock(mu);
+  Entry e;
+  std::memcpy(e.kop, kop, sizeof(e.kop));
+  e.bound0 = bound0;
+  e.G = G;
+  cache.push_back(std::move(e));
+  if (cache.size() > 8) cache.pop_front();
 }
 
 template <typename T>
@@ -299,12 +352,11 @@ int mg_setup(Slot &s, hipStream_t st) {
     }
     if (used > 7 * s.lay.vec_bytes) return SHH_WORKSPACE_TOO_SMALL;
   }
-  // child Galerkin matrices of this Poisson ratio's K_0
-  double K0[24][24];
-  dense_k0(h.kop64, K0);
-  const double bound0 = element_bound(K0);
+  // child Galerkin matrices of this Poisson ratio's K_0 and the voxel-level
+  // Chebyshev bound (host work of about 1 ms, kept per element operator)
+  double bound0;
   std::vector<double> G;
-  child_galerkin(K0, G);
+  nu_constants(h.kop64, bound0, G);
   int rc;
   if ((rc = upload(G, mg.G, prec, st))) return rc;
   SHH_HIP(hipMemcpyAsync(s.d_mg, &mg, sizeof(MgDev), hipMemcpyHostToDevice, st));
