@@ -427,17 +427,20 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
   }
 }
 
-// Power iteration for lambda_max(D^-1 A) at level l, on load case 0 of x:
+// Power iteration for lambda_max(D^-1 A) at a coarse level l, on load case 0
+// of x, for a batch of slots (grid z = slot):
 //   phase 0: x = a fixed pseudo-random vector
 //   phase 1: partial x.q and x.D x (the Rayleigh quotient x.A x / x.D x of
 //            D^-1 A, self-adjoint in the D inner product), then x = D^-1 q
 //            (q = A x) and partial ||x||^2
 //   phase 2: x *= the level's pw_scale
 template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s, const MgDev *mg, int l, int phase) {
+__global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(MgBatch B, int l, int phase) {
   __shared__ double red[3 * 16];
-  const MgLevel &L = mg->lv[l];
+  const SlotDev *s = B.slot[blockIdx.z];
+  const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const long long nn = L.nn;
+  if (blockIdx.x >= (unsigned)L.nchunks) return;
   const long long i0 = (long long)blockIdx.x * CHUNK;
   const long long i1 = min(i0 + (long long)CHUNK, nn);
   T *x = (T *)L.x;
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s,
         h ^= h >> 13;
         x[j] = (T)((double)(h & 0xffffff) / 16777216.0 - 0.5);
       } else if (phase == 1) {
-        const T di = l == 0 ? Dv[i] : Dv[j];
+        const T di = Dv[j];
         const double xo = (double)x[j], qo = (double)q[j];
         acc[1] += xo * qo;
         acc[2] += di != T(0) ? xo * xo / (double)di : 0.0;
@@ -477,16 +480,18 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_power_kernel(const SlotDev *s,
   }
 }
 
-// After power phase 1: reduce the partials (one workgroup), keep the largest
-// Rayleigh quotient in lmax and the normalization for phase 2 (a vanishing or
-// non-finite step leaves lmax = -1, which the host reports as a breakdown).
-__global__ __launch_bounds__(VEC_THREADS) void mg_power_reduce_kernel(const SlotDev *s, MgDev *mg, int l,
-                                                                    int nchunks) {
+// After power phase 1: reduce the partials (one workgroup per slot), keep the
+// largest Rayleigh quotient in lmax and the normalization for phase 2 (a
+// vanishing or non-finite step leaves lmax = -1, which the host reports as a
+// breakdown).
+__global__ __launch_bounds__(VEC_THREADS) void mg_power_reduce_kernel(MgBatch B, int l) {
   __shared__ double red[3 * 16];
+  const SlotDev *s = B.slot[blockIdx.z];
+  // the slot's own descriptor in device memory, written only here
+  MgLevel &L = const_cast<MgDev *>(B.mg[blockIdx.z])->lv[l];
   double tot[3];
-  sum_partials<3, PSTRIDE>(s->partials, nchunks, tot, red, VEC_THREADS);
+  sum_partials<3, PSTRIDE>(s->partials, L.nchunks, tot, red, VEC_THREADS);
   if (threadIdx.x != 0) return;
-  MgLevel &L = mg->lv[l];
   const double nrm = sqrt(tot[0]);
   if (!(nrm > 0.0) || !isfinite(nrm) || !(tot[2] > 0.0) || L.lmax < 0.0) {
     L.lmax = -1.0;
@@ -661,14 +666,13 @@ hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t mg_launch_power(const SlotDev *d_slot, MgDev *d_mg, int l, int phase, int nchunks, int prec,
-                           hipStream_t st) {
+hipError_t mg_launch_power(const MgBatch &B, int l, int phase, int nchunks_max, int prec, hipStream_t st) {
   if (phase == 3) {
-    mg_power_reduce_kernel<<<1, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, nchunks);
+    mg_power_reduce_kernel<<<dim3(1, 1, B.count), VEC_THREADS, 0, st>>>(B, l);
   } else if (prec == 0) {
-    mg_power_kernel<double><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase);
+    mg_power_kernel<double><<<dim3((unsigned)nchunks_max, 1, B.count), VEC_THREADS, 0, st>>>(B, l, phase);
   } else {
-    mg_power_kernel<float><<<(unsigned)nchunks, VEC_THREADS, 0, st>>>(d_slot, d_mg, l, phase);
+    mg_power_kernel<float><<<dim3((unsigned)nchunks_max, 1, B.count), VEC_THREADS, 0, st>>>(B, l, phase);
   }
   return hipGetLastError();
 }

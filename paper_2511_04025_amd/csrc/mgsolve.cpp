@@ -34,8 +34,7 @@ hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int
 hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
 hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st);
 hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st);
-hipError_t mg_launch_power(const SlotDev *d_slot, MgDev *d_mg, int l, int phase, int nchunks, int prec,
-                           hipStream_t st);
+hipError_t mg_launch_power(const MgBatch &B, int l, int phase, int nchunks_max, int prec, hipStream_t st);
 
 namespace {
 
@@ -320,7 +319,12 @@ size_t mg_region_bytes(int n, int prec) {
   return carve(nullptr, n, prec, nullptr, nullptr);
 }
 
-int mg_setup(Slot &s, hipStream_t st) {
+namespace {
+
+// Setup of one slot up to the power iteration: level descriptors, the
+// nu-dependent constants, element matrices, stencils, D^-1 of every coarse
+// level and the coarsest inverse (all on the stream, no read-back).
+int mg_setup_levels(Slot &s, hipStream_t st, double &bound0) {
   SlotDev &h = s.host;
   const int n = h.n, prec = h.prec;
   const int count = mg_num_levels(n);
@@ -354,7 +358,6 @@ int mg_setup(Slot &s, hipStream_t st) {
   }
   // child Galerkin matrices of this Poisson ratio's K_0 and the voxel-level
   // Chebyshev bound (host work of about 1 ms, kept per element operator)
-  double bound0;
   std::vector<double> G;
   nu_constants(h.kop64, bound0, G);
   int rc;
@@ -364,23 +367,14 @@ int mg_setup(Slot &s, hipStream_t st) {
   for (int l = 1; l + 1 < count; ++l) SHH_HIP(mg_launch_elemc(s.d_mg, l, mg.lv[l + 1].nn, prec, st));
   for (int l = 1; l < count; ++l) SHH_HIP(mg_launch_stencil(s.d_mg, l, mg.lv[l].nn, prec, st));
   SHH_HIP(mg_launch_coarse_inverse(s.d_mg, prec, st));
-  // lambda_max(D^-1 A) of every coarse smoothing level by power iteration
-  // on load case 0, entirely on the device (phase 0 start, then per step:
-  // apply, phase 1 sweep, reduction, phase 2 normalization); one read-back at
-  // the end.  The voxel level needs none: it takes the rigorous bound.
-  for (int l = 1; l < mg.L; ++l) {
-    const MgLevel &L = mg.lv[l];
-    SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 0, L.nchunks, prec, st));
-    for (int it = 0; it < POWER_ITERS; ++it) {
-      SHH_HIP(mg_launch_apply_case0(batch_of({&s}), l, L.nn, prec, st));
-      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 1, L.nchunks, prec, st));
-      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 3, L.nchunks, prec, st));
-      SHH_HIP(mg_launch_power(s.d_slot, s.d_mg, l, 2, L.nchunks, prec, st));
-    }
-  }
-  MgDev est;
-  SHH_HIP(hipMemcpyAsync(&est, s.d_mg, sizeof(MgDev), hipMemcpyDeviceToHost, st));
-  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+// Chebyshev coefficients of every smoothing level from the estimates, and
+// their upload.
+int mg_setup_coefficients(Slot &s, const MgDev &est, double bound0, hipStream_t st) {
+  SlotDev &h = s.host;
+  MgDev &mg = s.mg;
   for (int l = 0; l < mg.L; ++l) {
     MgLevel &W = mg.lv[l];
     // Chebyshev interval [hi/33, hi]: above lambda_max, or the smoother
@@ -394,7 +388,7 @@ int mg_setup(Slot &s, hipStream_t st) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return SHH_BREAKDOWN;
     W.lmax = lam;
     if (std::getenv("SHH_MG_VERBOSE"))
-      std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f%s\n", n, l, W.n, lam,
+      std::fprintf(stderr, "mg setup: n=%d level %d (n=%d) lambda_max %.5f%s\n", h.n, l, W.n, lam,
                    l == 0 ? " (bound)" : "");
     const double hi = l == 0 ? bound0 : 1.5 * lam, lo = hi / 33.0;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
@@ -404,15 +398,65 @@ int mg_setup(Slot &s, hipStream_t st) {
     W.c2 = 2.0 * rho1 / delta;
   }
   // the fused voxel-level sweeps read the coefficients from the slot
-  h.mgc[0] = L0.inv_theta;
-  h.mgc[1] = L0.c1;
-  h.mgc[2] = L0.c2;
+  h.mgc[0] = mg.lv[0].inv_theta;
+  h.mgc[1] = mg.lv[0].c1;
+  h.mgc[2] = mg.lv[0].c2;
   SHH_HIP(hipMemcpyAsync(&s.d_slot->mgc, h.mgc, sizeof(h.mgc), hipMemcpyHostToDevice, st));
   SHH_HIP(hipMemcpyAsync(s.d_mg, &mg, sizeof(MgDev), hipMemcpyHostToDevice, st));
-  SHH_HIP(hipStreamSynchronize(st));
   s.mg_restart = true;
   return SHH_OK;
 }
+
+}  // namespace
+
+int mg_setup(const std::vector<Slot *> &slots, hipStream_t st) {
+  if (slots.empty()) return SHH_OK;
+  const int prec = slots[0]->host.prec;
+  std::vector<double> bound0(slots.size());
+  int rc;
+  int max_l = 0;
+  for (size_t i = 0; i < slots.size(); ++i) {
+    if ((rc = mg_setup_levels(*slots[i], st, bound0[i]))) return rc;
+    max_l = std::max(max_l, slots[i]->mg.L);
+  }
+  // lambda_max(D^-1 A) of every coarse smoothing level by power iteration
+  // on load case 0, entirely on the device and batched over the slots that
+  // have the level (phase 0 start, then per step: apply, phase 1 sweep,
+  // reduction, phase 2 normalization); one read-back at the end.  The voxel
+  // level needs none: it takes the rigorous bound.
+  for (int l = 1; l < max_l; ++l) {
+    std::vector<Slot *> at;
+    for (Slot *s : slots)
+      if (s->mg.L > l) at.push_back(s);
+    for (size_t b0 = 0; b0 < at.size(); b0 += MG_MAXB) {
+      const std::vector<Slot *> part(at.begin() + b0, at.begin() + std::min(at.size(), b0 + MG_MAXB));
+      const MgBatch B = batch_of(part);
+      long long nn = 0;
+      int nch = 0;
+      for (Slot *s : part) {
+        nn = std::max(nn, s->mg.lv[l].nn);
+        nch = std::max(nch, s->mg.lv[l].nchunks);
+      }
+      SHH_HIP(mg_launch_power(B, l, 0, nch, prec, st));
+      for (int it = 0; it < POWER_ITERS; ++it) {
+        SHH_HIP(mg_launch_apply_case0(B, l, nn, prec, st));
+        SHH_HIP(mg_launch_power(B, l, 1, nch, prec, st));
+        SHH_HIP(mg_launch_power(B, l, 3, nch, prec, st));
+        SHH_HIP(mg_launch_power(B, l, 2, nch, prec, st));
+      }
+    }
+  }
+  std::vector<MgDev> est(slots.size());
+  for (size_t i = 0; i < slots.size(); ++i)
+    SHH_HIP(hipMemcpyAsync(&est[i], slots[i]->d_mg, sizeof(MgDev), hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  for (size_t i = 0; i < slots.size(); ++i)
+    if ((rc = mg_setup_coefficients(*slots[i], est[i], bound0[i], st))) return rc;
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+int mg_setup(Slot &s, hipStream_t st) { return mg_setup({&s}, st); }
 
 int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
   if (l < 1 || l > s.mg.L) return SHH_INVALID_ARG;

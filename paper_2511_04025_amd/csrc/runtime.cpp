@@ -387,8 +387,10 @@ int Solver::start(const std::vector<Slot *> &slots) {
   LaunchArgs la;
   int rc;
   // multigrid hierarchies first: their setup borrows the CG vector region
+  std::vector<Slot *> mgs;
   for (Slot *s : slots)
-    if (s->opts.solver == SHH_SOLVER_MG && (rc = mg_setup(*s, st_))) return rc;
+    if (s->opts.solver == SHH_SOLVER_MG) mgs.push_back(s);
+  if ((rc = mg_setup(mgs, st_))) return rc;
   if ((rc = build(K_ZERO, slots, 0, true, la))) return rc;
   SHH_HIP(launch_zero_vectors(la, prec, st_));
   for (Slot *s : slots) SHH_HIP(hipEventRecord(s->ev[1], st_));

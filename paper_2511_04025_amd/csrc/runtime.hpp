@@ -64,6 +64,8 @@ size_t mg_region_bytes(int n, int prec);
 // multigrid setup of a slot whose moduli and D^-1 are in place (before the CG
 // vectors are zeroed: the element matrices use the vector region as scratch)
 int mg_setup(Slot &s, hipStream_t st);
+// the same for several slots at once (their power iterations batched)
+int mg_setup(const std::vector<Slot *> &slots, hipStream_t st);
 // Voxel-level operator launches of the multigrid iteration: the CG direction
 // pass (p_j = z + beta p_{j-1} into the other p buffer, q[0] = K p_j, partials
 // p_j . q); q[0] = K d for the stored Chebyshev direction mgd (stencil flag
