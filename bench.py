@@ -63,7 +63,7 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "5483d45de88ca29756012a7028bb8e2ffe6c28911e62c53366ef138078359d40",
+    "sha256": "ba81c06b4138f0e6b5734c337e81ea721164a8173e22e750683d33619d2c9660",
     "traffic_per_algorithmic_byte": 2.1437,
 }
 
