@@ -217,3 +217,38 @@ def test_smallest_hierarchies_match_jacobi(n):
     rj = A.homogenize(d, precision="fp64", rtol=1e-11)
     assert rm["status"] == 0 and rj["status"] == 0
     assert_ch_close(rm["C"], rj["C"], 1e-8)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 2e-5)])
+def test_wide_coarse_operator_sampled_against_galerkin_product(precision, tol):
+    # the first coarse level of an 80^3 grid has 40^3 nodes, enough for the
+    # operator form that reads a node's stencil once for all six load cases
+    # (the form the served 128^3 designs use): A_1 v against P^T K (P v) at
+    # sampled coarse nodes, with P the oracle's prolongation and K's rows from
+    # the oracle's element sum
+    from oracle import fem, multigrid as omg
+    A = api()
+    n, m, nu = 80, 40, 0.3
+    rng = np.random.default_rng(8040)
+    E = np.where(rng.random((n, n, n)) < 0.3, 1.0, 1e-3) * rng.uniform(0.5, 1.0, (n, n, n))
+    V = rng.standard_normal((6, 3, m, m, m))
+    if precision == "mixed":
+        V = V.astype(np.float32).astype(np.float64)
+    Pv = omg.prolongation(m) @ V.reshape(6, 3, m ** 3).transpose(2, 1, 0).reshape(3 * m ** 3, 6)
+    U = Pv.reshape(n ** 3, 3, 6)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    print(f"wide coarse operator 80^3 level 1 {precision}", flush=True)
+    q = A.mg_operator(torch.tensor(E, device="cuda"), torch.tensor(V, dtype=dt, device="cuda"), nu, 1,
+                      precision).double().cpu().numpy().reshape(6, 3, m ** 3)
+    sample = np.concatenate([[0, m ** 3 - 1, m - 1, m * m * (m - 1)], rng.integers(0, m ** 3, 60)])
+    X, Y, Z = sample % m, (sample // m) % m, sample // (m * m)
+    ref = np.zeros((len(sample), 3, 6))
+    for oz in (-1, 0, 1):
+        for oy in (-1, 0, 1):
+            for ox in (-1, 0, 1):
+                w = (0.5 if ox else 1.0) * (0.5 if oy else 1.0) * (0.5 if oz else 1.0)
+                fine = (((2 * Z + oz) % n) * n + (2 * Y + oy) % n) * n + (2 * X + ox) % n
+                ref += w * fem.stiffness_rows(E.ravel(), nu, n, lambda ids: U[ids], fine)
+    got = q[:, :, sample].transpose(2, 1, 0)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(got - ref)) <= tol * scale, np.max(np.abs(got - ref)) / scale
