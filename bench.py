@@ -63,8 +63,8 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "ba81c06b4138f0e6b5734c337e81ea721164a8173e22e750683d33619d2c9660",
-    "traffic_per_algorithmic_byte": 2.1437,
+    "sha256": "fddb670bf574677bf90b5ed1ecb4b1df8b048a549adfa85cfbe60fe6d3746f1c",
+    "traffic_per_algorithmic_byte": 2.0963,
 }
 
 
@@ -354,13 +354,13 @@ def main():
         kname = "stencil_kernel<float,float,PCG>"
     else:
         # roofline of the first coarse level's operator q = A_1 v (27-point
-        # 3x3-block stencil, all six load cases per thread; the kernel with the
-        # largest share of the multigrid iteration): the library adds each
-        # timed launch's algorithmic bytes
+        # 3x3-block stencil, all six load cases and two z-adjacent nodes per
+        # thread; the kernel with the largest share of the multigrid
+        # iteration): the library adds each timed launch's algorithmic bytes
         nbytes = timed_bytes.value
         per_launch = mg_apply_traffic_per_byte()
         traffic = int(per_launch * nbytes / max(n_launch, 1)) if per_launch is not None else None
-        kname = "mg_apply_kernel<float,6>"
+        kname = "mg_apply_pair_kernel<float>"
     achieved = nbytes / t_kernel / 1e9 if t_kernel > 0 else 0.0
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -26,7 +26,8 @@ hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long n
 hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st);
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
 hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
-hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, int prec, hipStream_t st);
+hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
+                           hipStream_t st);
 hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st);
 bool mg_apply_wide(long long nn_max);
 hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
@@ -269,10 +270,12 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   const MgBatch B = batch_of(smooth);
   long long nn_max = 0, nn_next_max = 0;
   int nch_max = 0;
+  bool all_even = true;  // the two-nodes-per-thread operator form needs even n
   for (Slot *s : smooth) {
     nn_max = std::max(nn_max, s->mg.lv[l].nn);
     nn_next_max = std::max(nn_next_max, s->mg.lv[l + 1].nn);
     nch_max = std::max(nch_max, s->mg.lv[l].nchunks);
+    all_even = all_even && s->mg.lv[l].n % 2 == 0;
   }
   int rc;
   auto vec = [&](int op) -> int {
@@ -287,7 +290,7 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
     const bool timed = timer && mg_apply_wide(nn_max);
     hipEvent_t e0 = nullptr;
     if (timed && (rc = timer->timed_begin(&e0))) return rc;
-    SHH_HIP(mg_launch_apply(B, l, src, nn_max, prec, st));
+    SHH_HIP(mg_launch_apply(B, l, src, nn_max, all_even, prec, st));
     if (!timed) return SHH_OK;
     double bytes = 0.0;
     for (Slot *s : smooth) bytes += apply_bytes(*s, l);
@@ -463,7 +466,7 @@ int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
   const MgLevel &L = s.mg.lv[l];
   const size_t bytes = (size_t)NRHS * 3 * L.nn * (s.host.prec == SHH_PREC_FP64 ? 8 : 4);
   SHH_HIP(hipMemcpyAsync(L.x, d_v, bytes, hipMemcpyDeviceToDevice, st));
-  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, s.host.prec, st));
+  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, L.n % 2 == 0, s.host.prec, st));
   SHH_HIP(hipMemcpyAsync(d_q, L.q, bytes, hipMemcpyDeviceToDevice, st));
   SHH_HIP(hipStreamSynchronize(st));
   return SHH_OK;
