@@ -154,7 +154,7 @@ struct Segment {
 };
 
 // Fused voxel-level passes of the multigrid-preconditioned CG (stencil kernel)
-enum { SMG_DIR = 0, SMG_STEP1 = 1, SMG_POST = 2, SMG_LAST = 3 };
+enum { SMG_DIR = 0, SMG_STEP1 = 1, SMG_POST = 2, SMG_LAST = 3, SMG_RES = 4 };
 
 struct LaunchArgs {
   const Segment *segs;

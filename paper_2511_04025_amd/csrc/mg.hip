@@ -265,10 +265,11 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
 }
 
 // b_{l+1} = P^T (r_l - q_l), the residual after the pre-smoother (q = A d of
-// its last step): coarse node I collects fine nodes 2I + o, o in {-1, 0, 1}^3,
-// with weight prod (o == 0 ? 1 : 1/2).  One thread per (coarse node, load case).
+// its last step; at the voxel level r already holds r - q): coarse node I
+// collects fine nodes 2I + o, o in {-1, 0, 1}^3, with weight
+// prod (o == 0 ? 1 : 1/2).  One thread per (coarse node, load case).
 template <typename T>
-__global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l) {
+__global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l, int formed) {
   const MgDev *mg = B.mg[blockIdx.z];
   const MgLevel &F = mg->lv[l];
   const MgLevel &C = mg->lv[l + 1];
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const long long j = (long long)c * F.nn + i;
-          acc[c] += w * (r[j] - qf[j]);
+          acc[c] += w * (formed ? r[j] : r[j] - qf[j]);
         }
       }
     }
@@ -708,10 +709,12 @@ hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int 
   return hipGetLastError();
 }
 
-hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st) {
+// formed: r already holds r - q (the voxel level's operator pass wrote it)
+hipError_t mg_launch_restrict(const MgBatch &B, int l, bool formed, long long nn_coarse_max, int prec,
+                              hipStream_t st) {
   const dim3 g(blocks_for(nn_coarse_max * NRHS, 256), 1, B.count);
-  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(B, l);
-  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(B, l);
+  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(B, l, formed ? 1 : 0);
+  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(B, l, formed ? 1 : 0);
   return hipGetLastError();
 }
 

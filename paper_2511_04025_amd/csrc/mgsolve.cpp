@@ -30,7 +30,8 @@ hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, b
                            hipStream_t st);
 hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st);
 bool mg_apply_wide(long long nn_max);
-hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
+hipError_t mg_launch_restrict(const MgBatch &B, int l, bool formed, long long nn_coarse_max, int prec,
+                              hipStream_t st);
 hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
 hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
 hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st);
@@ -286,7 +287,7 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   // for all load cases (the largest coarse level) are timed with their
   // algorithmic bytes
   auto app = [&](int src) -> int {
-    if (l == 0) return apply0(smooth, MG_SRC_D);  // only the direction is applied bare
+    if (l == 0) return apply0(smooth, MG_SRC_RES);  // r - K d1 in place of r
     const bool timed = timer && mg_apply_wide(nn_max);
     hipEvent_t e0 = nullptr;
     if (timed && (rc = timer->timed_begin(&e0))) return rc;
@@ -303,7 +304,7 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   else if (!(rc = app(1))) rc = vec(MGV_STEP1);
   if (rc || (rc = app(1))) return rc;
   // coarse-grid correction of the residual r - A d
-  SHH_HIP(mg_launch_restrict(B, l, nn_next_max, prec, st));
+  SHH_HIP(mg_launch_restrict(B, l, l == 0, nn_next_max, prec, st));
   if ((rc = vcycle(smooth, l + 1, st, timer, apply0))) return rc;
   SHH_HIP(mg_launch_prolong(B, l, nn_max, prec, st));
   // post-smoother

@@ -480,15 +480,13 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
   // voxel-level operator over all the given slots, one launch
   MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
-    static const Kind kinds[5] = {K_MG_DIR, K_MG_D, K_MG_STEP1, K_MG_POST, K_MG_LAST};
-    static const int ops[5] = {SMG_DIR, -1, SMG_STEP1, SMG_POST, SMG_LAST};
+    static const Kind kinds[5] = {K_MG_DIR, K_MG_RES, K_MG_STEP1, K_MG_POST, K_MG_LAST};
+    static const int ops[5] = {SMG_DIR, SMG_RES, SMG_STEP1, SMG_POST, SMG_LAST};
     if (src < 0 || src > MG_SRC_LAST) return SHH_INVALID_ARG;
-    const int flag = src == MG_SRC_D ? MG_FLAG_DQ : 0;
     LaunchArgs la;
     int r;
-    if ((r = build(kinds[src], ss, flag, true, la))) return r;
-    if (ops[src] < 0) SHH_HIP(launch_stencil_apply(la, ss[0]->host.prec, st_));
-    else SHH_HIP(launch_stencil_mg(la, ss[0]->host.prec, ops[src], st_));
+    if ((r = build(kinds[src], ss, 0, true, la))) return r;
+    SHH_HIP(launch_stencil_mg(la, ss[0]->host.prec, ops[src], st_));
     return SHH_OK;
   };
   for (int it = 0; it < iters; ++it) {

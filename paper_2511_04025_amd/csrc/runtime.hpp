@@ -68,12 +68,10 @@ int mg_setup(Slot &s, hipStream_t st);
 int mg_setup(const std::vector<Slot *> &slots, hipStream_t st);
 // Voxel-level operator launches of the multigrid iteration: the CG direction
 // pass (p_j = z + beta p_{j-1} into the other p buffer, q[0] = K p_j, partials
-// p_j . q); q[0] = K d for the stored Chebyshev direction mgd (stencil flag
-// 1 + src + 8 dst over (r0, r1, p0, p1, q0, q1, x, mgd)); the operator fused
-// with the Chebyshev sweep after it (pre-smoother step 1, post-smoother steps
-// 1 and 2)
-enum { MG_SRC_DIR = 0, MG_SRC_D = 1, MG_SRC_STEP1 = 2, MG_SRC_POST = 3, MG_SRC_LAST = 4 };
-constexpr int MG_FLAG_DQ = 1 + 7 + 8 * 4;
+// p_j . q); r - K d for the stored Chebyshev direction (the residual the
+// restriction takes, in place of r); the operator fused with the Chebyshev
+// sweep after it (pre-smoother step 1, post-smoother steps 1 and 2)
+enum { MG_SRC_DIR = 0, MG_SRC_RES = 1, MG_SRC_STEP1 = 2, MG_SRC_POST = 3, MG_SRC_LAST = 4 };
 class Solver;
 using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // one multigrid-preconditioned CG iteration of every load case of the slots
@@ -113,7 +111,7 @@ class Solver {
   int timed_end(hipEvent_t e0, double bytes);
 
  private:
-  enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_MG_DIR, K_MG_D,
+  enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_MG_DIR, K_MG_RES,
               K_MG_STEP1, K_MG_POST, K_MG_LAST,
               K_NKIND };
   int residual(const std::vector<Slot *> &slots, int mode);

@@ -51,7 +51,7 @@
 namespace shh {
 
 enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2, MODE_MGDIR = 3, MODE_MGSTEP1 = 4, MODE_MGPOST = 5,
-       MODE_MGLAST = 6 };
+       MODE_MGLAST = 6, MODE_MGRES = 7 };
 
 #ifndef SHH_STENCIL_WAVES_PER_EU
 #define SHH_STENCIL_WAVES_PER_EU 1
@@ -178,6 +178,8 @@ void stencil_kernel(LaunchArgs la) {
   //   STEP1: b (r[0]) staged as d0 = D b / theta;  r = b - q,
   //          d1 = c1 d0 + c2 D r, x = d0 + d1 -> r (q[1]), d1 (mgd), x (r[1])
   //   POST:  x (r[1]) staged as is; aux b;  r = b - q -> q[1]
+  //   RES:   d1 (mgd) staged as is; aux r (q[1]);  r - q -> q[1] (the
+  //          residual the restriction takes)
   //   LAST:  r (q[1]) staged as d = D r / theta; aux b, x;
   //          x + (1 + c1) d + c2 D (r - q) -> r[1], partials b . x, b . b
   //          (the post-smoother's x + d folded into the last update)
@@ -195,9 +197,9 @@ void stencil_kernel(LaunchArgs la) {
       rR = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
       rP = make_rsrc((const TS *)s->mgd + vbase, vbytesS);
       rX = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
-    } else if constexpr (MODE == MODE_MGPOST) {
-      rA = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
-      rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
+    } else if constexpr (MODE == MODE_MGPOST || MODE == MODE_MGRES) {
+      rA = make_rsrc((const TS *)(MODE == MODE_MGPOST ? s->r[1] : s->mgd) + vbase, vbytesS);
+      rAux[0] = make_rsrc((const TS *)(MODE == MODE_MGPOST ? s->r[0] : s->q[1]) + vbase, vbytesS);
       rR = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
     } else {
       rA = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
@@ -577,8 +579,8 @@ void stencil_kernel(LaunchArgs la) {
           bstore<TS>((TS)d1, rP, ooff, pk + cS[c]);
           bstore<TS>((TS)(op[c] + d1), rX, ooff, pk + cS[c]);
         }
-      } else if constexpr (MODE == MODE_MGPOST) {
-        // oa[0] = b
+      } else if constexpr (MODE == MODE_MGPOST || MODE == MODE_MGRES) {
+        // oa[0] = b (POST) or r (RES)
 #pragma unroll
         for (int c = 0; c < 3; ++c) bstore<TS>((TS)(oa[0][c] - qv[c]), rR, ooff, pk + cS[c]);
       } else if constexpr (MODE == MODE_MGLAST) {
@@ -686,6 +688,7 @@ hipError_t launch_stencil_mg(const LaunchArgs &la, int prec, int op, hipStream_t
     case SMG_STEP1: launch_mg_mode<MODE_MGSTEP1>(la, prec, st); break;
     case SMG_POST: launch_mg_mode<MODE_MGPOST>(la, prec, st); break;
     case SMG_LAST: launch_mg_mode<MODE_MGLAST>(la, prec, st); break;
+    case SMG_RES: launch_mg_mode<MODE_MGRES>(la, prec, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
