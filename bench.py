@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # any change to them the bench reports null until the counters are taken again.
 PCG_TRAFFIC = {
     "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
-    "sha256": "0801c1795af03fbcaffed560b704341c0c5a6128133017ff1042dd49d4170f20",
-    "fetch_bytes_per_node_case": 67.11,
+    "sha256": "548616e66795f56036fddfad1b68ca60527e0088c015c9f263ed644fbb9b0ac8",
+    "fetch_bytes_per_node_case": 66.17,
     "write_bytes_per_node_case": 48.01,
 }
 # What a plain 1 GiB device-to-device copy sustains on this GPU (read + write,
@@ -63,8 +63,8 @@ def pcg_traffic_per_node_case():
 # for the sources it was measured on (digest); null otherwise.
 MG_APPLY_TRAFFIC = {
     "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "fddb670bf574677bf90b5ed1ecb4b1df8b048a549adfa85cfbe60fe6d3746f1c",
-    "traffic_per_algorithmic_byte": 2.0963,
+    "sha256": "8b7ab882304002413021a7c87535a83f40d0ed1f962a3a4242251ee954c104d2",
+    "traffic_per_algorithmic_byte": 2.0970,
 }
 
 
