@@ -146,6 +146,26 @@ int32_t shh_workspace_bytes_stiffness(int32_t n, const shh_opts *opts, size_t *b
 int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const shh_opts *opts,
                                  void *d_ws, size_t ws_bytes, void *hip_stream, shh_result *out);
 
+/* Steps 3-4 for a voxel modulus grid in one of three encodings (e_dtype):
+     SHH_EDTYPE_U8   one byte per voxel, a solid/void code: E_e = E where the
+                     byte is nonzero, E_void where it is zero (the hard
+                     threshold of Eq. (7) in its most compact form; requires
+                     E > 0, 0 <= E_void <= E); out->vol_frac = share of solid
+                     voxels;
+     SHH_EDTYPE_F32  n^3 floats (the moduli rounded to FP32 on entry, e.g. a
+                     mixed-precision caller's own grid);
+     SHH_EDTYPE_F64  n^3 doubles (the same as shh_homogenize_stiffness).
+   For F32/F64, E and E_void are ignored and out->vol_frac is mean(E)/max(E).
+   d_E: device array [n][n][n] (x fastest), caller-owned, read only.  Workspace
+   from shh_workspace_bytes_stiffness.  SHH_INVALID_ARG for an unknown
+   e_dtype, a grid with no positive modulus, or the conditions above. */
+#define SHH_EDTYPE_U8  0
+#define SHH_EDTYPE_F32 1
+#define SHH_EDTYPE_F64 2
+int32_t shh_homogenize_field(int32_t n, const void *d_E, int32_t e_dtype, double E, double E_void, double nu,
+                             const shh_opts *opts, void *d_ws, size_t ws_bytes, void *hip_stream,
+                             shh_result *out);
+
 /* Steps 1-2 only (Eq. (6)-(7)).  Writes the device arrays d_F [n^3],
    d_G [3][n^3] (dF/dx, dF/dy, dF/dz), d_d [n^3] (distance) and d_beta [n^3]
    (occupancy), all doubles; any of them may be NULL.  out->vol_frac and

@@ -7,8 +7,10 @@ Because every u^(k) is at equilibrium, the energy form is stationary in u and
     dC_ij / dE_e = (1/n^3) (chi^i + u^i_e)^T K_0 (chi^j + u^j_e)
 (no adjoint solve).  dbeta_e/dtheta follows from the logistic occupancy of
 Sec. 4.1, the distance d = |F - c| / ||grad F|| of Eq. (7) and the charge field
-of Eq. (6); the thickness t is held fixed.  The hard step has no useful
-derivative and is rejected.
+of Eq. (6); the parameters are the charge positions and values, the
+spectral weights alpha_hkl and the half-thickness t (Sec. 4.3 lists all
+three), the last either free or tied to a target volume by the implicit
+function theorem.  The hard step has no useful derivative and is rejected.
 
 Conventions at kinks: sgn(0) = 0 where F = c; where the gradient norm is
 clamped at its floor the clamped value is treated as a constant.
@@ -94,6 +96,69 @@ def charge_gradients(gF, gG, pos, q, n, K=3, alpha=None):
             dpos[j, 1] -= q[j] * np.sum(gF * py + gG[0] * pxy + gG[1] * pyy + gG[2] * pyz)
             dpos[j, 2] -= q[j] * np.sum(gF * pz + gG[0] * pxz + gG[1] * pyz + gG[2] * pzz)
     return dpos, dq
+
+
+def alpha_gradients(gF, gG, pos, q, n, K=3):
+    """Pull (g_F, g_G) back onto the spectral weights: Eq. (6) is linear in
+    alpha, so dF/dalpha_hkl = w_hkl / (h^2+k^2+l^2) sum_j q_j cos cos cos and
+    d(grad F)/dalpha_hkl is its gradient.  Direct summation over every (charge,
+    mode) term; returns dL/dalpha of shape (K+1, K+1, K+1), entry (0,0,0) zero
+    (B_000 = 0)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    c = fld.voxel_centers(n)
+    tp = 2.0 * np.pi
+    out = np.zeros((K + 1,) * 3)
+
+    def outer(fz, fy, fx):
+        return fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+
+    for (h, k, l) in fld.modes(K):
+        base = fld.mode_weight(h, k, l) / (h * h + k * k + l * l)
+        acc = 0.0
+        for j in range(len(q)):
+            ax, ay, az = tp * h * (c - pos[j, 0]), tp * k * (c - pos[j, 1]), tp * l * (c - pos[j, 2])
+            cx, cy, cz = np.cos(ax), np.cos(ay), np.cos(az)
+            dx, dy, dz = -tp * h * np.sin(ax), -tp * k * np.sin(ay), -tp * l * np.sin(az)
+            acc += q[j] * np.sum(gF * outer(cz, cy, cx) + gG[0] * outer(cz, cy, dx) +
+                                 gG[1] * outer(cz, dy, cx) + gG[2] * outer(dz, cy, cx))
+        out[h, k, l] = base * acc
+    return out
+
+
+def thickness_gradient(s_e, beta, kappa, E, E_void, dL_dV):
+    """dL/dt with t a free parameter: beta = 1 / (1 + exp(-kappa (t - d))) gives
+    dbeta/dt = kappa beta (1 - beta), and dL/dbeta_e = s_e (E - E_void) + dL/dV / n^3."""
+    if kappa <= 0:
+        raise ValueError("the hard step has no gradient; use kappa > 0")
+    n = beta.shape[0]
+    gbeta = s_e * (E - E_void) + dL_dV / n ** 3
+    return float(np.sum(gbeta * kappa * beta * (1.0 - beta)))
+
+
+def design_gradient_full(info, pos, q, n, dL_dC, dL_dV, *, K=3, alpha=None, iso=0.0,
+                         kappa, dist_mode=0, E=1.0, nu=0.3, E_void=1e-3):
+    """Eq. (9) for every design parameter theta in {charge positions, charge
+    values, alpha_hkl, t} (t held as an independent parameter): returns
+    (dL/dpos (N,3), dL/dq (N,), dL/dalpha (K+1,K+1,K+1), dL/dt)."""
+    s_e = element_energy_weights(info["Ee"], info["U"], nu, n, dL_dC)
+    gF, gG = voxel_sensitivities(info["F"], info["G"], info["d"], info["beta"], info["t"],
+                                 kappa, E, E_void, s_e, dL_dV, iso=iso, dist_mode=dist_mode)
+    dpos, dq = charge_gradients(gF, gG, pos, q, n, K=K, alpha=alpha)
+    dalpha = alpha_gradients(gF, gG, pos, q, n, K=K)
+    dt = thickness_gradient(s_e, info["beta"], kappa, E, E_void, dL_dV)
+    return dpos, dq, dalpha, dt
+
+
+def volume_constrained(grad_L, grad_V):
+    """Gradient of L along the volume constraint V(theta, t) = V* with t
+    re-solved for every theta (Sec. 4.3's joint optimization, where t is set
+    by bisection): by the implicit function theorem dt/dtheta = -(dV/dtheta) /
+    (dV/dt), so dL/dtheta|_V = dL/dtheta - (dL/dt / dV/dt) dV/dtheta.  grad_L
+    and grad_V are (dpos, dq, dalpha, dt) tuples of design_gradient_full for
+    (dL/dC, dL/dV) and for (0, 1); returns (dpos, dq, dalpha)."""
+    r = grad_L[3] / grad_V[3]
+    return tuple(gl - r * gv for gl, gv in zip(grad_L[:3], grad_V[:3]))
 
 
 def design_gradient(info, pos, q, n, dL_dC, dL_dV, *, K=3, alpha=None, iso=0.0,

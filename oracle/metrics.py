@@ -74,8 +74,10 @@ def hashin_shtrikman_upper(f1, K1, G1, K2, G2):
     """Two-phase Hashin-Shtrikman upper bounds on the bulk and shear moduli, with
     phase 1 the stiffer phase at volume fraction f1 and phase 2 at 1 - f1."""
     f2 = 1.0 - f1
-    KU = K1 + f2 / (1.0 / (K2 - K1) + 3.0 * f1 / (3.0 * K1 + 4.0 * G1))
-    GU = G1 + f2 / (1.0 / (G2 - G1) + 6.0 * f1 * (K1 + 2.0 * G1) / (5.0 * G1 * (3.0 * K1 + 4.0 * G1)))
+    # equal phase moduli: the correction term vanishes (1 / (K2 - K1) -> infinity)
+    KU = K1 if K2 == K1 else K1 + f2 / (1.0 / (K2 - K1) + 3.0 * f1 / (3.0 * K1 + 4.0 * G1))
+    GU = G1 if G2 == G1 else G1 + f2 / (1.0 / (G2 - G1) + 6.0 * f1 * (K1 + 2.0 * G1) /
+                                       (5.0 * G1 * (3.0 * K1 + 4.0 * G1)))
     return KU, GU
 
 

@@ -132,6 +132,29 @@ def homogenize_stiffness(E, nu, precision="mixed", rtol=None, max_iter=20000, re
     return B.result_dict(res)
 
 
+def homogenize_field(E, nu, E_solid=1.0, E_void=0.0, precision="mixed", rtol=None, max_iter=20000,
+                     recompute_every=0, check_every=0, solver="jacobi"):
+    """Steps 3-4 for a voxel grid E (n, n, n) on the GPU in one of three
+    encodings, chosen by its dtype: uint8 (solid/void code: E_solid where
+    nonzero, E_void where zero), float32 or float64 moduli."""
+    _require_gpu()
+    codes = {torch.uint8: B.EDTYPE_U8, torch.float32: B.EDTYPE_F32, torch.float64: B.EDTYPE_F64}
+    if not (E.is_cuda and E.dtype in codes and E.dim() == 3 and E.is_contiguous()
+            and E.shape[0] == E.shape[1] == E.shape[2]):
+        raise ValueError("E must be a contiguous uint8/float32/float64 CUDA tensor of shape (n, n, n)")
+    n = E.shape[0]
+    opts = B.make_opts(precision, rtol, max_iter, recompute_every, False, check_every, solver)
+    nb = c_size_t(0)
+    B.check(B.lib().shh_workspace_bytes_stiffness(n, byref(opts), byref(nb)), "shh_workspace_bytes_stiffness")
+    ws = Workspace(nb.value)
+    res = B.ShhResult()
+    rc = B.lib().shh_homogenize_field(n, _ptr(E), codes[E.dtype], c_double(E_solid), c_double(E_void),
+                                      c_double(nu), byref(opts), ws.ptr, c_size_t(ws.nbytes), _stream(),
+                                      byref(res))
+    B.check(rc, "shh_homogenize_field")
+    return B.result_dict(res)
+
+
 def field(design):
     """Steps 1-2: F (n,n,n), G (3,n,n,n), d (n,n,n), beta (n,n,n) as float64 CUDA
     tensors, plus V and t."""

@@ -71,6 +71,8 @@ EXPORTS = {
                                   c_size_t, c_void_p]),
     "shh_homogenize_stiffness": (c_int32, [c_int32, c_void_p, c_double, POINTER(ShhOpts), c_void_p, c_size_t,
                                            c_void_p, POINTER(ShhResult)]),
+    "shh_homogenize_field": (c_int32, [c_int32, c_void_p, c_int32, c_double, c_double, c_double,
+                                       POINTER(ShhOpts), c_void_p, c_size_t, c_void_p, POINTER(ShhResult)]),
     "shh_field": (c_int32, [POINTER(ShhDesign), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p, POINTER(ShhResult)]),
     "shh_apply_stiffness": (c_int32, [c_int32, c_int32, c_void_p, c_double, c_int32, c_void_p, c_void_p,
@@ -149,6 +151,7 @@ class DesignArgs:
 
 
 SOLVER_JACOBI, SOLVER_MG = 0, 1
+EDTYPE_U8, EDTYPE_F32, EDTYPE_F64 = 0, 1, 2
 
 
 def make_opts(precision="mixed", rtol=None, max_iter=20000, recompute_every=0, save_for_backward=False,

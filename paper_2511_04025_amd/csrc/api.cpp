@@ -240,15 +240,18 @@ int32_t shh_workspace_bytes_operator(int32_t n, int32_t precision, size_t *bytes
 }
 
 // Slot over a workspace with moduli copied from d_E (scale taken from max E).
-static int moduli_slot(Slot &s, int32_t n, const double *d_E, double nu, const shh_opts *o, void *d_ws,
-                       size_t ws_bytes, hipStream_t st, char **seg_mem, bool vectors) {
+static int moduli_slot(Slot &s, int32_t n, const void *d_E, double nu, const shh_opts *o, void *d_ws,
+                       size_t ws_bytes, hipStream_t st, char **seg_mem, bool vectors,
+                       int e_dtype = SHH_EDTYPE_F64, double Es = 0.0, double Ev = 0.0) {
   if (n < 2 || n > 512 || !d_E || !(nu > -1.0 && nu < 0.5)) return SHH_INVALID_ARG;
+  if (e_dtype != SHH_EDTYPE_U8 && e_dtype != SHH_EDTYPE_F32 && e_dtype != SHH_EDTYPE_F64) return SHH_INVALID_ARG;
+  if (e_dtype == SHH_EDTYPE_U8 && !(Es > 0.0 && std::isfinite(Es) && Ev >= 0.0 && Ev <= Es)) return SHH_INVALID_ARG;
   shh_opts oo = *o;
   oo.save_for_backward = 0;
   const shh_design d = stiffness_design(n, nu);
   SHH_TRY(prepare_slot(s, &d, &oo, d_ws, ws_bytes, seg_mem, vectors));
   SHH_TRY(slot_init(s, s.base, st));
-  SHH_TRY(slot_setup_moduli(s, d_E, st));
+  SHH_TRY(slot_setup_moduli(s, d_E, e_dtype, Es, Ev, st));
   SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
   SHH_HIP(hipStreamSynchronize(st));
   const double emax = s.state.Emax;
@@ -271,6 +274,28 @@ int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const 
   Events ev(&s);
   SHH_HIP(hipEventRecord(s.ev[0], st));
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true));
+  Solver sv(st);
+  sv.set_segment_memory(seg_mem, seg_region());
+  SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
+  fill_result(s, out);
+  return s.status;
+}
+
+int32_t shh_homogenize_field(int32_t n, const void *d_E, int32_t e_dtype, double E, double E_void, double nu,
+                             const shh_opts *opts, void *d_ws, size_t ws_bytes, void *hip_stream,
+                             shh_result *out) {
+  shh_opts o;
+  SHH_TRY(normalize_opts(opts, &o));
+  if (!out || n < 2 || n > 512 || !d_E || !(nu > -1.0 && nu < 0.5)) return SHH_INVALID_ARG;
+  if (e_dtype != SHH_EDTYPE_U8 && e_dtype != SHH_EDTYPE_F32 && e_dtype != SHH_EDTYPE_F64) return SHH_INVALID_ARG;
+  if (e_dtype == SHH_EDTYPE_U8 && !(E > 0.0 && std::isfinite(E) && E_void >= 0.0 && E_void <= E))
+    return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  char *seg_mem = nullptr;
+  Events ev(&s);
+  SHH_HIP(hipEventRecord(s.ev[0], st));
+  SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true, e_dtype, E, E_void));
   Solver sv(st);
   sv.set_segment_memory(seg_mem, seg_region());
   SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
@@ -624,9 +649,21 @@ static void engine_retire(shh_engine *eng, size_t idx) {
 
 int32_t shh_engine_step(shh_engine *eng, int32_t iters, int32_t *n_resident, int32_t *n_queued) {
   if (!eng || iters < 0) return SHH_INVALID_ARG;
-  std::vector<Slot *> fresh;
+  std::vector<Slot *> fresh, failed;
   SHH_TRY(engine_admit(eng, fresh));
-  SHH_TRY(eng->solver->start(fresh));
+  // a request whose own setup fails completes with its status; the others go on
+  SHH_TRY(eng->solver->start(fresh, &failed));
+  for (Slot *f : failed) {
+    shh_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.status = f->status;
+    eng->completed.emplace_back(f->id, r);
+  }
+  if (!failed.empty()) {
+    SHH_HIP(hipStreamSynchronize(eng->st));  // their memory may still be in use
+    for (size_t i = eng->resident.size(); i-- > 0;)
+      if (eng->resident[i]->finished) engine_retire(eng, i);
+  }
   std::vector<Slot *> live;
   for (auto &s : eng->resident) live.push_back(s.get());
   if (!live.empty() && iters > 0) {

@@ -294,9 +294,21 @@ __global__ __launch_bounds__(256) void occupancy_kernel(SlotDev *s, double *beta
   }
 }
 
-// Moduli given directly (solver-only entry): copy, round, and record the
-// volume fraction as mean(E) / max(E) (the bitwise max is taken beforehand).
-__global__ __launch_bounds__(256) void moduli_copy_kernel(SlotDev *s, const double *E, int nblocks) {
+// Moduli given directly (solver-only entries).  The source grid is one of
+//   DT = 0: a 1-byte solid/void code, E_e = E where the code is nonzero, else E_void
+//   DT = 1: float moduli,  DT = 2: double moduli.
+template <int DT>
+__device__ __forceinline__ double decode_modulus(const void *E, long long i, double Es, double Ev) {
+  if constexpr (DT == 0) return ((const unsigned char *)E)[i] ? Es : Ev;
+  else if constexpr (DT == 1) return (double)((const float *)E)[i];
+  else return ((const double *)E)[i];
+}
+
+// Copy, round, and record the volume fraction: the solid share of the code
+// (DT = 0), else mean(E) / max(E) (the bitwise max is taken beforehand).
+template <int DT>
+__global__ __launch_bounds__(256) void moduli_copy_kernel(SlotDev *s, const void *E, double Es, double Ev,
+                                                          int nblocks) {
   __shared__ double red[16];
   __shared__ int lastflag;
   CgState *st = s->st;
@@ -304,10 +316,11 @@ __global__ __launch_bounds__(256) void moduli_copy_kernel(SlotDev *s, const doub
   double v[1] = {0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
        i += (long long)nblocks * blockDim.x) {
-    const double e = E[i];
+    const double e = decode_modulus<DT>(E, i, Es, Ev);
     s->E64[i] = e;
     if (s->E32) s->E32[i] = (float)e;
-    v[0] += e;
+    if constexpr (DT == 0) v[0] += ((const unsigned char *)E)[i] ? 1.0 : 0.0;
+    else v[0] += e;
   }
   block_sum<1>(v, red, 256);
   if (threadIdx.x == 0) s->partials[4 * blockIdx.x] = v[0];
@@ -317,18 +330,20 @@ __global__ __launch_bounds__(256) void moduli_copy_kernel(SlotDev *s, const doub
   if (threadIdx.x == 0) {
     const double emax = __longlong_as_double((long long)st->gmax_bits);
     st->Emax = emax;
-    st->V = emax > 0.0 ? tot[0] / double(nn) / emax : 0.0;
+    if constexpr (DT == 0) st->V = tot[0] / double(nn);
+    else st->V = emax > 0.0 ? tot[0] / double(nn) / emax : 0.0;
     st->t = 0.0;
     st->cnt[6] = 0;
   }
 }
 
-__global__ __launch_bounds__(256) void max_bits_kernel(SlotDev *s, const double *E) {
+template <int DT>
+__global__ __launch_bounds__(256) void max_bits_kernel(SlotDev *s, const void *E, double Es, double Ev) {
   const long long nn = s->nn;
   unsigned long long mx = 0ull;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
        i += (long long)gridDim.x * blockDim.x) {
-    const double e = E[i];
+    const double e = decode_modulus<DT>(E, i, Es, Ev);
     const unsigned long long b = e > 0.0 ? (unsigned long long)__double_as_longlong(e) : 0ull;
     mx = b > mx ? b : mx;
   }
@@ -405,10 +420,19 @@ hipError_t launch_occupancy(SlotDev *d_slot, long long nn, double *beta_out, hip
   return hipGetLastError();
 }
 
-hipError_t launch_moduli_copy(SlotDev *d_slot, long long nn, const double *E, hipStream_t st) {
-  max_bits_kernel<<<grid_for(nn, 1024), 256, 0, st>>>(d_slot, E);
-  const int nbk = reduce_blocks(nn);
-  moduli_copy_kernel<<<nbk, 256, 0, st>>>(d_slot, E, nbk);
+hipError_t launch_moduli_copy(SlotDev *d_slot, long long nn, const void *E, int e_dtype, double Es, double Ev,
+                              hipStream_t st) {
+  const int g = grid_for(nn, 1024), nbk = reduce_blocks(nn);
+  if (e_dtype == 0) {
+    max_bits_kernel<0><<<g, 256, 0, st>>>(d_slot, E, Es, Ev);
+    moduli_copy_kernel<0><<<nbk, 256, 0, st>>>(d_slot, E, Es, Ev, nbk);
+  } else if (e_dtype == 1) {
+    max_bits_kernel<1><<<g, 256, 0, st>>>(d_slot, E, Es, Ev);
+    moduli_copy_kernel<1><<<nbk, 256, 0, st>>>(d_slot, E, Es, Ev, nbk);
+  } else {
+    max_bits_kernel<2><<<g, 256, 0, st>>>(d_slot, E, Es, Ev);
+    moduli_copy_kernel<2><<<nbk, 256, 0, st>>>(d_slot, E, Es, Ev, nbk);
+  }
   return hipGetLastError();
 }
 

@@ -15,7 +15,9 @@ hipError_t launch_select_hard(SlotDev *d_slot, long long nn, long long k, hipStr
 hipError_t launch_minmax_d(SlotDev *d_slot, long long nn, hipStream_t st);
 hipError_t launch_bisect_steps(SlotDev *d_slot, long long nn, int steps, hipStream_t st);
 hipError_t launch_occupancy(SlotDev *d_slot, long long nn, double *beta_out, hipStream_t st);
-hipError_t launch_moduli_copy(SlotDev *d_slot, long long nn, const double *E, hipStream_t st);
+// e_dtype 0: 1-byte solid/void code (E = Es where nonzero, else Ev); 1: float; 2: double
+hipError_t launch_moduli_copy(SlotDev *d_slot, long long nn, const void *E, int e_dtype, double Es, double Ev,
+                              hipStream_t st);
 hipError_t launch_dinv(SlotDev *d_slot, long long nn, int prec, hipStream_t st);
 
 // stencil.hip (segments of (slot, load case, tile)); the PCG launch is one

@@ -413,16 +413,30 @@ int mg_setup_coefficients(Slot &s, const MgDev &est, double bound0, hipStream_t 
 
 }  // namespace
 
-int mg_setup(const std::vector<Slot *> &slots, hipStream_t st) {
-  if (slots.empty()) return SHH_OK;
-  const int prec = slots[0]->host.prec;
-  std::vector<double> bound0(slots.size());
+int mg_setup(const std::vector<Slot *> &all, hipStream_t st, std::vector<int> *rcs) {
+  if (rcs) rcs->assign(all.size(), SHH_OK);
+  if (all.empty()) return SHH_OK;
+  const int prec = all[0]->host.prec;
+  // a slot's own failure is recorded (when asked) and the slot left out;
+  // HIP errors end the setup of all
+  auto fail = [&](size_t i, int rc) { return (!rcs || rc == SHH_HIP_ERROR) ? rc : ((*rcs)[i] = rc, 0); };
+  std::vector<Slot *> slots;
+  std::vector<size_t> idx;
+  std::vector<double> bound0;
   int rc;
   int max_l = 0;
-  for (size_t i = 0; i < slots.size(); ++i) {
-    if ((rc = mg_setup_levels(*slots[i], st, bound0[i]))) return rc;
-    max_l = std::max(max_l, slots[i]->mg.L);
+  for (size_t i = 0; i < all.size(); ++i) {
+    double b0 = 0.0;
+    if ((rc = mg_setup_levels(*all[i], st, b0))) {
+      if ((rc = fail(i, rc))) return rc;
+      continue;
+    }
+    slots.push_back(all[i]);
+    idx.push_back(i);
+    bound0.push_back(b0);
+    max_l = std::max(max_l, all[i]->mg.L);
   }
+  if (slots.empty()) return SHH_OK;
   // lambda_max(D^-1 A) of every coarse smoothing level by power iteration
   // on load case 0, entirely on the device and batched over the slots that
   // have the level (phase 0 start, then per step: apply, phase 1 sweep,
@@ -455,12 +469,12 @@ int mg_setup(const std::vector<Slot *> &slots, hipStream_t st) {
     SHH_HIP(hipMemcpyAsync(&est[i], slots[i]->d_mg, sizeof(MgDev), hipMemcpyDeviceToHost, st));
   SHH_HIP(hipStreamSynchronize(st));
   for (size_t i = 0; i < slots.size(); ++i)
-    if ((rc = mg_setup_coefficients(*slots[i], est[i], bound0[i], st))) return rc;
+    if ((rc = mg_setup_coefficients(*slots[i], est[i], bound0[i], st)) && (rc = fail(idx[i], rc))) return rc;
   SHH_HIP(hipStreamSynchronize(st));
   return SHH_OK;
 }
 
-int mg_setup(Slot &s, hipStream_t st) { return mg_setup({&s}, st); }
+int mg_setup(Slot &s, hipStream_t st) { return mg_setup(std::vector<Slot *>{&s}, st); }
 
 int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
   if (l < 1 || l > s.mg.L) return SHH_INVALID_ARG;

@@ -285,9 +285,9 @@ int slot_setup_field(Slot &s, double *beta_out, hipStream_t st) {
   return SHH_OK;
 }
 
-int slot_setup_moduli(Slot &s, const double *d_E, hipStream_t st) {
+int slot_setup_moduli(Slot &s, const void *d_E, int e_dtype, double Es, double Ev, hipStream_t st) {
   const SlotDev &h = s.host;
-  SHH_HIP(launch_moduli_copy(s.d_slot, h.nn, d_E, st));
+  SHH_HIP(launch_moduli_copy(s.d_slot, h.nn, d_E, e_dtype, Es, Ev, st));
   SHH_HIP(launch_dinv(s.d_slot, h.nn, h.prec, st));
   return SHH_OK;
 }
@@ -381,16 +381,30 @@ int Solver::residual(const std::vector<Slot *> &slots, int mode) {
   return SHH_OK;
 }
 
-int Solver::start(const std::vector<Slot *> &slots) {
-  if (slots.empty()) return SHH_OK;
-  const int prec = slots[0]->host.prec;
+int Solver::start(const std::vector<Slot *> &in, std::vector<Slot *> *failed) {
+  if (in.empty()) return SHH_OK;
+  const int prec = in[0]->host.prec;
   LaunchArgs la;
   int rc;
   // multigrid hierarchies first: their setup borrows the CG vector region
   std::vector<Slot *> mgs;
-  for (Slot *s : slots)
+  for (Slot *s : in)
     if (s->opts.solver == SHH_SOLVER_MG) mgs.push_back(s);
-  if ((rc = mg_setup(mgs, st_))) return rc;
+  std::vector<int> rcs;
+  if ((rc = mg_setup(mgs, st_, failed ? &rcs : nullptr))) return rc;
+  std::vector<Slot *> slots;
+  for (Slot *s : in) {
+    bool ok = true;
+    for (size_t i = 0; i < rcs.size(); ++i)
+      if (mgs[i] == s && rcs[i] != SHH_OK) {
+        s->finished = true;
+        s->status = rcs[i];
+        failed->push_back(s);
+        ok = false;
+      }
+    if (ok) slots.push_back(s);
+  }
+  if (slots.empty()) return SHH_OK;
   if ((rc = build(K_ZERO, slots, 0, true, la))) return rc;
   SHH_HIP(launch_zero_vectors(la, prec, st_));
   for (Slot *s : slots) SHH_HIP(hipEventRecord(s->ev[1], st_));

@@ -64,8 +64,11 @@ size_t mg_region_bytes(int n, int prec);
 // multigrid setup of a slot whose moduli and D^-1 are in place (before the CG
 // vectors are zeroed: the element matrices use the vector region as scratch)
 int mg_setup(Slot &s, hipStream_t st);
-// the same for several slots at once (their power iterations batched)
-int mg_setup(const std::vector<Slot *> &slots, hipStream_t st);
+// the same for several slots at once (their power iterations batched).  With
+// `rcs` null the first failure is returned; otherwise (*rcs)[i] receives slot
+// i's own status (a slot that fails is left out of the remaining steps) and
+// only HIP errors are returned.
+int mg_setup(const std::vector<Slot *> &slots, hipStream_t st, std::vector<int> *rcs = nullptr);
 // Voxel-level operator launches of the multigrid iteration: the CG direction
 // pass (p_j = z + beta p_{j-1} into the other p buffer, q[0] = K p_j, partials
 // p_j . q); r - K d for the stored Chebyshev direction (the residual the
@@ -87,8 +90,9 @@ void copy_design(const shh_design *src, DesignCopy &dst);
 int slot_init(Slot &s, char *base, hipStream_t st);
 // Field, distance, thickness, occupancy, Jacobi diagonal (steps 1-2).
 int slot_setup_field(Slot &s, double *beta_out, hipStream_t st);
-// Moduli given directly instead of steps 1-2.
-int slot_setup_moduli(Slot &s, const double *d_E, hipStream_t st);
+// Moduli given directly instead of steps 1-2 (e_dtype as SHH_EDTYPE_*; Es, Ev
+// the solid and void moduli of the byte code).
+int slot_setup_moduli(Slot &s, const void *d_E, int e_dtype, double Es, double Ev, hipStream_t st);
 
 // Batched solver over a set of slots sharing one stream.
 class Solver {
@@ -97,8 +101,12 @@ class Solver {
   // Device memory for the segment tables (must hold seg_bytes(max_slots)).
   void set_segment_memory(char *d_mem, size_t bytes);
   static size_t seg_bytes(int max_slots);
-  // zero vectors + initial residual for newly set-up slots
-  int start(const std::vector<Slot *> &slots);
+  // zero vectors + initial residual for newly set-up slots.  With `failed`
+  // null the first failure is returned; otherwise a slot whose own setup fails
+  // (e.g. a multigrid hierarchy without a positive spectrum estimate) is marked
+  // finished with that status, appended to *failed and left out, and the
+  // others start; only HIP errors are returned then.
+  int start(const std::vector<Slot *> &slots, std::vector<Slot *> *failed = nullptr);
   // run `iters` CG iterations over the resident slots (recomputes as due)
   int iterate(const std::vector<Slot *> &slots, int iters);
   // read back states; for slots whose load cases are all inactive run the final

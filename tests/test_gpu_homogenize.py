@@ -100,3 +100,34 @@ def test_logistic_void_1e6_vs_golden(seed, precision, tol):
     assert r["status"] == 0
     assert abs(r["V"] - g["V"]) <= 1e-13
     assert_ch_close(r["C"], np.array(g["C"]), tol)
+
+
+@pytest.mark.parametrize("solver,n", [("jacobi", 14), ("mg", 16)])
+def test_field_entry_point_encodings_vs_oracle(solver, n):
+    # shh_homogenize_field in its three encodings of the same hard-threshold
+    # shell: the 1-byte solid/void code (E, E_void rebuilt in the kernel),
+    # FP32 moduli and FP64 moduli, each against the oracle's C^H of exactly
+    # the moduli the encoding carries (FP64 solve to 1e-11, bar 1e-8; mixed
+    # at 1e-7, bar 1e-4)
+    from oracle import field as fld
+    A = api()
+    d = wl.random_design(77 + n, n, N=12, vf=0.2)
+    F, G = fld.field_and_gradient(d.pos, d.q, n)
+    dist = fld.distance(F, G)
+    beta = fld.occupancy(dist, fld.thickness_for_volume(dist, 0.2, 0.0), 0.0)
+    Es, Ev, nu = 1.3, 2e-3, 0.3
+    E64 = fld.stiffness_field(beta, Es, Ev)
+    E32 = E64.astype(np.float32)
+    cases = {"u8": (torch.tensor(beta.astype(np.uint8), device="cuda"), E64, beta.mean()),
+             "f32": (torch.tensor(E32, device="cuda"), E32.astype(np.float64), None),
+             "f64": (torch.tensor(E64, device="cuda"), E64, None)}
+    for name, (grid, ref_E, V) in cases.items():
+        C_ref, _ = hom.homogenize_stiffness(ref_E, nu, solver="direct")
+        for prec, rtol, tol in (("fp64", 1e-11, 1e-8), ("mixed", 1e-7, 1e-4)):
+            r = A.homogenize_field(grid, nu, E_solid=Es, E_void=Ev, precision=prec, rtol=rtol, solver=solver)
+            assert r["status"] == 0, (name, prec)
+            assert_ch_close(r["C"], C_ref, tol)
+            if V is not None:
+                assert r["V"] == V
+            else:
+                assert abs(r["V"] - ref_E.mean() / ref_E.max()) <= 1e-14

@@ -38,7 +38,8 @@ def test_small_shell_vs_oracle(precision, rtol, tol):
     assert r["iters"].max() * 4 < rj["iters"].max()
 
 
-@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-7), ("mixed", 3e-6, 1e-4)])
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-7), ("mixed", 3e-6, 1e-4),
+                                                ("mixed", 1e-5, 1e-4)])
 def test_shell_designs_at_48_vs_oracle(precision, rtol, tol):
     A = api()
     designs = wl.shell_128_designs(n=48, count=8)
@@ -99,9 +100,9 @@ def test_mixed_vs_fp64_at_128_served():
     # the headline designs at 128^3 through the multigrid solver: the served
     # mixed path within 1e-4 of the FP64 path (itself tied to the oracle at 48^3)
     A = api()
-    designs = wl.shell_128_designs(n=128, count=2)
+    designs = wl.shell_128_designs(n=128, count=4)
     print("mg 128^3 served vs fp64", flush=True)
-    mg = A.homogenize_batch(designs, precision="mixed", rtol=3e-6, solver="mg")
+    mg = A.homogenize_batch(designs, precision="mixed", rtol=1e-5, solver="mg")
     ref = A.homogenize_batch(designs, precision="fp64", rtol=1e-10, solver="mg")
     for a, b in zip(mg, ref):
         assert a["status"] == 0 and b["status"] == 0
@@ -252,3 +253,58 @@ def test_wide_coarse_operator_sampled_against_galerkin_product(precision, tol):
     got = q[:, :, sample].transpose(2, 1, 0)
     scale = np.abs(ref).max()
     assert np.max(np.abs(got - ref)) <= tol * scale, np.max(np.abs(got - ref)) / scale
+
+
+def _drain(eng, got, iters):
+    nr, nq = eng.step(iters)
+    for rid, r in eng.poll():
+        got[rid] = r
+    return nr, nq
+
+
+def test_served_engine_vs_oracle_with_staggered_arrivals():
+    # the served configuration -- engine, multigrid, mixed precision, CG
+    # tolerance 1e-5 -- on the eight 48^3 designs the oracle has values for.
+    # Requests arrive in three waves between engine steps of uneven length;
+    # every C^H is within the per-entry bar of the oracle's, and each design's
+    # result is bit-for-bit the one it gets alone (a converged load case stops
+    # changing, and every reduction has a fixed order)
+    from paper_2511_04025_amd import serving
+    designs = wl.shell_128_designs(n=48, count=8)
+    kw = dict(precision="mixed", rtol=1e-5, solver="mg")
+    print("served engine 48^3: alone", flush=True)
+    alone = {}
+    for i, d in enumerate(designs):
+        eng = serving.Engine(1 << 30, max_slots=2, **kw)
+        eng.submit(d, i)
+        got = {}
+        for _ in range(400):
+            nr, nq = _drain(eng, got, 16)
+            if nr == 0 and nq == 0:
+                break
+        eng.close()
+        alone[i] = got[i]
+    print("served engine 48^3: staggered mix", flush=True)
+    eng = serving.Engine(2 << 30, max_slots=8, **kw)
+    got, peak = {}, 0
+    waves = {0: [0, 1, 2], 1: [3, 4], 3: [5, 6, 7]}
+    steps = [5, 3, 7, 4]
+    for k in range(2000):
+        for i in waves.get(k, []):
+            eng.submit(designs[i], i)
+        nr, nq = _drain(eng, got, steps[k % len(steps)])
+        peak = max(peak, nr)
+        if k > 3 and nr == 0 and nq == 0:
+            break
+    eng.close()
+    assert sorted(got) == list(range(8)) and peak >= 5
+    for i, d in enumerate(designs):
+        g = golden(f"shell_n48_seed{d.seed}.json")
+        r = got[i]
+        assert r["status"] == 0 and np.all(r["rel_res"] <= 1e-5), (i, r["status"], r["rel_res"])
+        assert r["V"] == g["V"]
+        rel, small, frob = assert_ch_close(r["C"], np.array(g["C"]), 1e-4)
+        print(f"served 48^3 seed {d.seed}: iters {r['iters'].tolist()} vs oracle rel {rel:.2e} "
+              f"small {small:.2e} frob {frob:.2e}", flush=True)
+        assert np.array_equal(r["C"], alone[i]["C"]), i
+        assert np.array_equal(r["iters"], alone[i]["iters"]), i

@@ -136,3 +136,21 @@ def test_cancel_and_failure_isolation():
     e1.close()
     assert res[0]["status"] == B.SHH_NOT_CONVERGED and res[0]["iters"].max() <= 3
     assert res[1]["status"] == 0 and np.array_equal(res[1]["C"], r_alone[0]["C"])
+
+
+def test_setup_failure_stays_isolated():
+    # a request with no material at all (half-thickness 0 and a zero void
+    # floor) gives its multigrid hierarchy no positive spectrum estimate: it
+    # completes with SHH_BREAKDOWN at admission, and the request admitted in
+    # the same step finishes exactly as it does alone
+    from paper_2511_04025_amd import binding as B
+    good = wl.random_design(340, 24, N=16, vf=0.12, E_void=1e-6)
+    empty = wl.random_design(341, 24, N=16, E_void=0.0).with_(thickness=0.0, target_vf=None)
+    e = engine(1 << 30, slots=4, solver="mg")
+    alone, _ = run_all(e, [good])
+    e.close()
+    e = engine(1 << 30, slots=4, solver="mg")
+    res, _ = run_all(e, [empty, good])
+    e.close()
+    assert res[0]["status"] == B.SHH_BREAKDOWN
+    assert res[1]["status"] == 0 and np.array_equal(res[1]["C"], alone[0]["C"])

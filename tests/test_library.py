@@ -189,3 +189,16 @@ def test_multigrid_solver_option(lib):
     a = B.DesignArgs(wl.small_shell_24())
     nb = c_size_t(0)
     assert lib.shh_workspace_bytes(byref(a.c), byref(o), byref(nb)) == B.SHH_INVALID_ARG
+
+
+def test_field_entry_point_validation(lib):
+    # argument checks of shh_homogenize_field that return before any device work
+    from ctypes import c_double, c_void_p
+    o = B.make_opts("mixed")
+    res = B.ShhResult()
+    fake = c_void_p(256)  # never dereferenced: every call below fails validation first
+    for n, dt, Es, Ev, nu in ((1, 0, 1.0, 0.0, 0.3), (8, 3, 1.0, 0.0, 0.3), (8, 0, 0.0, 0.0, 0.3),
+                              (8, 0, 1.0, 2.0, 0.3), (8, 0, 1.0, -1.0, 0.3), (8, 2, 1.0, 0.0, 0.5)):
+        rc = lib.shh_homogenize_field(n, fake, dt, c_double(Es), c_double(Ev), c_double(nu), byref(o), fake,
+                                      c_size_t(1 << 20), None, byref(res))
+        assert rc == B.SHH_INVALID_ARG, (n, dt, Es, Ev, nu)

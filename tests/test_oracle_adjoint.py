@@ -93,3 +93,89 @@ def test_hard_step_rejected():
     with pytest.raises(ValueError):
         adj.voxel_sensitivities(np.zeros((2, 2, 2)), np.zeros((3, 2, 2, 2)), np.zeros((2, 2, 2)),
                                 np.zeros((2, 2, 2)), 0.1, 0.0, 1.0, 0.0, np.zeros((2, 2, 2)), 0.0)
+
+
+def _loss_full(pos, q, n, t, kappa, E_void, dLdC, dLdV, alpha):
+    C, info = hom.homogenize_design(pos, q, n, thickness=t, kappa=kappa, E_void=E_void, alpha=alpha,
+                                    solver="direct")
+    return np.sum(dLdC * C) + dLdV * info["V"], info
+
+
+def _setup_full(n=8, seed=47):
+    from oracle import field as fld
+    d = wl.random_design(seed, n, N=6, vf=0.2, E_void=1e-3)
+    kappa = 4.0 * n
+    alpha = 1.0 + 0.3 * np.random.default_rng(seed).standard_normal((4, 4, 4))
+    F, G = fld.field_and_gradient(d.pos, d.q, n, alpha=alpha)
+    t = fld.thickness_for_volume(fld.distance(F, G), 0.25, kappa)
+    rng = np.random.default_rng(6)
+    dLdC = rng.standard_normal((6, 6))
+    dLdC = dLdC + dLdC.T
+    return d, kappa, alpha, t, dLdC, 0.7
+
+
+def test_alpha_and_thickness_gradients_match_central_differences():
+    # Eq. (9) for theta = alpha_hkl and theta = t, against central differences
+    # of a linear functional of (C^H, V) (direct solves, h = 1e-6)
+    n = 8
+    d, kappa, alpha, t, dLdC, dLdV = _setup_full(n)
+    _, info = _loss_full(d.pos, d.q, n, t, kappa, d.E_void, dLdC, dLdV, alpha)
+    dpos, dq, dalpha, dt = adj.design_gradient_full(info, d.pos, d.q, n, dLdC, dLdV, alpha=alpha,
+                                                    kappa=kappa, E_void=d.E_void)
+    h = 1e-6
+    scale = np.abs(dalpha).max()
+    for (a, b, c) in ((0, 0, 1), (1, 2, 3), (3, 0, 0), (2, 2, 0)):
+        ap, am = alpha.copy(), alpha.copy()
+        ap[a, b, c] += h
+        am[a, b, c] -= h
+        fd = (_loss_full(d.pos, d.q, n, t, kappa, d.E_void, dLdC, dLdV, ap)[0] -
+              _loss_full(d.pos, d.q, n, t, kappa, d.E_void, dLdC, dLdV, am)[0]) / (2 * h)
+        assert abs(fd - dalpha[a, b, c]) < 1e-7 * scale, ((a, b, c), fd, dalpha[a, b, c])
+    assert dalpha[0, 0, 0] == 0.0
+    fd = (_loss_full(d.pos, d.q, n, t + h, kappa, d.E_void, dLdC, dLdV, alpha)[0] -
+          _loss_full(d.pos, d.q, n, t - h, kappa, d.E_void, dLdC, dLdV, alpha)[0]) / (2 * h)
+    assert abs(fd - dt) < 1e-7 * abs(dt), (fd, dt)
+    # F is linear in alpha and d = |F| / ||grad F|| is invariant to scaling F,
+    # so the loss is flat along alpha itself
+    assert abs(np.sum(alpha * dalpha)) < 1e-10 * np.abs(alpha * dalpha).sum()
+    # the same position and charge gradients as the fixed-thickness routine
+    dpos0, dq0 = adj.design_gradient(info, d.pos, d.q, n, dLdC, dLdV, alpha=alpha, kappa=kappa,
+                                     E_void=d.E_void)
+    assert np.array_equal(dpos0, dpos) and np.array_equal(dq0, dq)
+
+
+def test_volume_constrained_gradient_matches_differences_with_bisection():
+    # t re-solved by bisection for the target volume at every perturbed design
+    # (Sec. 4.3's joint optimization): the implicit-function gradient against
+    # central differences of the constrained loss
+    from oracle import field as fld
+    n = 8
+    d, kappa, alpha, _, dLdC, _ = _setup_full(n, seed=53)
+    V_star = 0.25
+
+    def constrained_loss(pos, al):
+        F, G = fld.field_and_gradient(pos, d.q, n, alpha=al)
+        t = fld.thickness_for_volume(fld.distance(F, G), V_star, kappa)
+        return _loss_full(pos, d.q, n, t, kappa, d.E_void, dLdC, 0.0, al)
+
+    L0, info = constrained_loss(d.pos, alpha)
+    assert abs(info["V"] - V_star) <= 1e-12
+    gL = adj.design_gradient_full(info, d.pos, d.q, n, dLdC, 0.0, alpha=alpha, kappa=kappa, E_void=d.E_void)
+    gV = adj.design_gradient_full(info, d.pos, d.q, n, np.zeros((6, 6)), 1.0, alpha=alpha, kappa=kappa,
+                                  E_void=d.E_void)
+    dpos, dq, dalpha = adj.volume_constrained(gL, gV)
+    h = 1e-5
+    scale = max(np.abs(dpos).max(), np.abs(dalpha).max())
+    for kind, idx in (("pos", (1, 0)), ("pos", (3, 2)), ("alpha", (1, 1, 0)), ("alpha", (0, 2, 3))):
+        pp, pm = d.pos.copy(), d.pos.copy()
+        ap, am = alpha.copy(), alpha.copy()
+        if kind == "pos":
+            pp[idx] += h
+            pm[idx] -= h
+            ref = dpos[idx]
+        else:
+            ap[idx] += h
+            am[idx] -= h
+            ref = dalpha[idx]
+        fd = (constrained_loss(pp, ap)[0] - constrained_loss(pm, am)[0]) / (2 * h)
+        assert abs(fd - ref) < 2e-6 * scale, (kind, idx, fd, ref)

@@ -177,3 +177,32 @@ def test_axis_swap_permutes_tensor_and_voxel_shift_invariance():
     # 1-homogeneity in the moduli
     C4, _ = hom.homogenize_design(d.pos, d.q, n, thickness=t, E=3.0, E_void=3.0 * d.E_void, solver="direct")
     assert np.max(np.abs(C4 - 3.0 * C)) < 1e-10 * np.abs(C).max()
+
+
+def test_design_path_moduli_full_solid():
+    """Through the whole forward path: a half-thickness above every distance
+    makes every voxel solid, so C^H = E D exactly (E_void plays no part)."""
+    d = wl.random_design(11, 6, N=8, pm=True)
+    C, info = hom.homogenize_design(d.pos, d.q, 6, thickness=1e300, E=2.5, E_void=0.1, nu=NU)
+    assert info["V"] == 1.0
+    assert np.max(np.abs(C - fem.isotropic_D(2.5, NU))) < 1e-13 * 2.5
+
+
+def test_design_path_moduli_planar_field_backus():
+    """Through the whole forward path: a field of (0,0,l) modes only gives whole
+    voxel layers, solid ones at E and void ones at the floor E_void, so C^H is
+    the Backus laminate of those two moduli -- which fixes the modulus mapping
+    E_e = E_void + (E - E_void) beta_e voxel by voxel."""
+    d = wl.random_design(5, 8, N=8, pm=True)
+    alpha = np.zeros((4, 4, 4))
+    alpha[0, 0, 1] = 1.0
+    alpha[0, 0, 3] = 0.4
+    n, E, Ev = 8, 1.7, 0.05
+    C, info = hom.homogenize_design(d.pos, d.q, n, alpha=alpha, target_vf=0.5, E=E, E_void=Ev,
+                                    nu=NU, solver="direct")
+    assert info["V"] == 0.5
+    phases = []
+    for e in (E, Ev):
+        lam, mu = fem.lame(e, NU)
+        phases.append((0.5, lam, mu))
+    assert np.max(np.abs(C - backus_z(phases))) < 1e-12
