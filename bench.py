@@ -24,62 +24,75 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the CG pass kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
-# then WRITE_SIZE; one 128^3 design, all six load cases active), each scaled by
-# what the counter reads for a 1 GiB device copy (FETCH x2.0, WRITE x1.0), per
-# (node, active load case); see profiles/stencil_pcg_128_hbm_traffic.md.  It
-# holds only for the kernel sources it was measured on (digest below): after
-# any change to them the bench reports null until the counters are taken again.
-PCG_TRAFFIC = {
-    "sources": ("stencil.hip", "common.hpp", "hexop.hpp"),
-    "sha256": "548616e66795f56036fddfad1b68ca60527e0088c015c9f263ed644fbb9b0ac8",
-    "fetch_bytes_per_node_case": 66.17,
-    "write_bytes_per_node_case": 48.01,
-}
-# What a plain 1 GiB device-to-device copy sustains on this GPU (read + write,
-# kernel trace of `bench.py --copy-only`): the achievable ceiling of a stream
-# that reads and writes, reported beside the 8 TB/s peak.
-COPY_CEILING_GBS = 5020.0
+# Achievable read+write stream on this GPU: the library's plain 16-byte-vector
+# copy kernel (shh_stream_copy) over 4 GiB, far above the 256 MB last-level
+# cache, timed with HIP events by `bench.py --copy-only`
+# (profiles/stream_copy_calibration.md).  Reported beside the 8 TB/s peak.
+COPY_CEILING_GBS = None
+
+# Measured HBM traffic of the dominant kernel relative to its algorithmic
+# bytes (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+# reads for the 4 GiB stream copy), keyed by kernel family; it holds only for
+# the kernel sources it was measured on (digest), null otherwise.
+TRAFFIC = {}
 
 
-def pcg_traffic_per_node_case():
-    """Measured HBM bytes per (node, active load case) of the CG pass, or None
-    when the kernel sources differ from the ones the counters were taken on."""
+def traffic_ratio(kind):
     import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2511_04025_amd", "csrc")
-    for f in PCG_TRAFFIC["sources"]:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != PCG_TRAFFIC["sha256"]:
-        return None
-    return PCG_TRAFFIC["fetch_bytes_per_node_case"] + PCG_TRAFFIC["write_bytes_per_node_case"]
-
-
-# HBM traffic of the first coarse level's operator kernel relative to its
-# algorithmic bytes: FETCH_SIZE x2.0 + WRITE_SIZE x1.0 summed over every launch
-# of the kernel in one step of the default workload, over the algorithmic bytes
-# of the same launches (profiles/mg_apply_128_hbm_traffic.md).  It holds only
-# for the sources it was measured on (digest); null otherwise.
-MG_APPLY_TRAFFIC = {
-    "sources": ("mg.hip", "mg.hpp", "mgsolve.cpp", "common.hpp"),
-    "sha256": "8b7ab882304002413021a7c87535a83f40d0ed1f962a3a4242251ee954c104d2",
-    "traffic_per_algorithmic_byte": 2.0970,
-}
-
-
-def mg_apply_traffic_per_byte():
-    import hashlib
-    if MG_APPLY_TRAFFIC["sha256"] is None:
+    t = TRAFFIC.get(kind)
+    if not t:
         return None
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_04025_amd", "csrc")
-    for f in MG_APPLY_TRAFFIC["sources"]:
+    for f in t["sources"]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != MG_APPLY_TRAFFIC["sha256"]:
-        return None
-    return MG_APPLY_TRAFFIC["traffic_per_algorithmic_byte"]
+    return t["ratio"] if h.hexdigest() == t["sha256"] else None
+
+
+def family_bytes(results, n, R, solver):
+    """Algorithmic HBM bytes per kernel family over the given results (FP32
+    vectors, 12 B per node and load case per vector; a design's per-node data
+    -- moduli, D^-1, coarse stencils -- counts once per iteration in which any
+    of its load cases runs).  Only the work that each design's iteration
+    counts imply is counted: restarted V-cycles after a residual replacement
+    are not, so the figures are lower bounds.
+      multigrid voxel level, per (node, load case):
+        direction pass  48 (z, p read; p, q written) + 4 E per node
+        pre-smoothing   48 (b staged; r, d1, x written) + 8 (E, D^-1) per node
+        r - K d1        36 (d1 staged, r read, r written) + 4
+        post-smoothing  36 (x staged, b read, r written) + 4
+        last sweep      48 (r staged; b, x read; x written) + 8
+        CG update       72 (x, p, b, q read; x, b written)
+        restriction     12 fine read + 12 per coarse node written
+        prolongation    24 fine read and written + 12 per coarse node read
+      first coarse level operator, 4 per iteration: 504 B of stencil per
+        coarse node + 24 B per (coarse node, load case)
+      FP64 residual: 24 (x64) + 12 (r) per (node, load case) + 8 (E) per node,
+        every R iterations and once at the end
+      Jacobi CG pass: 96 per (node, load case) + 8 per node"""
+    nn = n ** 3
+    nn1 = nn // 8
+    out = {k: 0.0 for k in ("cg_pass", "mg_dir", "mg_step1", "mg_res", "mg_post", "mg_last", "mg_update",
+                            "mg_restrict", "mg_prolong", "mg_apply1", "resid64")}
+    for r in results:
+        it = [int(v) for v in r["iters"]]
+        Ik, Im = sum(it), max(it)
+        nres = [v // R + 1 for v in it]  # replacements, then the final check
+        out["resid64"] += 36.0 * nn * sum(nres) + 8.0 * nn * max(nres)
+        if solver == "jacobi":
+            out["cg_pass"] += 96.0 * nn * Ik + 8.0 * nn * Im
+            continue
+        out["mg_dir"] += 48.0 * nn * Ik + 4.0 * nn * Im
+        out["mg_step1"] += 48.0 * nn * Ik + 8.0 * nn * Im
+        out["mg_res"] += 36.0 * nn * Ik + 4.0 * nn * Im
+        out["mg_post"] += 36.0 * nn * Ik + 4.0 * nn * Im
+        out["mg_last"] += 48.0 * nn * Ik + 8.0 * nn * Im
+        out["mg_update"] += 72.0 * nn * Ik
+        out["mg_restrict"] += (12.0 * nn + 12.0 * nn1) * Ik
+        out["mg_prolong"] += (24.0 * nn + 12.0 * nn1) * Ik
+        out["mg_apply1"] += 4 * (504.0 * nn1 * Im + 24.0 * nn1 * Ik)
+    return out
 
 
 def parse():
@@ -102,7 +115,10 @@ def parse():
                     help="with --solver mg: designs also run with the Jacobi-preconditioned CG (mixed)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--iters-per-step", type=int, default=16)
+    ap.add_argument("--iters-per-step", type=int, default=4,
+                    help="engine iterations between polls (admission and retirement happen at polls)")
+    ap.add_argument("--recompute-every", type=int, default=0,
+                    help="FP64 residual replacement period R (0: the library default, 50)")
     ap.add_argument("--max-iter", type=int, default=20000,
                     help="CG iteration cap (lower it only for hardware-counter runs)")
     ap.add_argument("--copy-only", action="store_true",
@@ -204,30 +220,36 @@ def inverse_step(args):
 
 
 def copy_calibration():
-    """A plain copy kernel of known size: 1 GiB read + 1 GiB written, 3 times.
-    Its FETCH_SIZE / WRITE_SIZE readings calibrate the HBM traffic counters."""
+    """The library's plain streaming copy at 4 GiB (far above the 256 MB
+    last-level cache) and at 64 MiB (inside it), 5 times each, timed with HIP
+    events on the stream it runs on.  Under rocprofv3 --pmc its FETCH_SIZE /
+    WRITE_SIZE readings calibrate the HBM traffic counters."""
+    import ctypes
     import torch
-    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": a.numel() * 4, "repeats": 3}))
-
-
-def stencil_bytes(results, n, prec_bytes):
-    """Algorithmic HBM bytes moved by the CG pass kernel (one whole PCG
-    iteration) over the given results: per active load case and node it reads
-    r, q, p of the previous iteration and x and writes the new r, q, p and x
-    (8 x 3 values); per node and launch it reads E_e and D^-1 once."""
-    nn = n ** 3
-    total = 0
-    launches = 0
-    for r in results:
-        it = r["iters"]
-        total += int(it.sum()) * nn * 24 * prec_bytes + int(it.max()) * nn * 2 * prec_bytes
-        launches += int(it.max())
-    return total, launches
+    from paper_2511_04025_amd import binding as B
+    lib = B.lib()
+    st = torch.cuda.current_stream()
+    out = {}
+    for nbytes in (4 << 30, 64 << 20):
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        ms = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            B.check(lib.shh_stream_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                        ctypes.c_size_t(nbytes), ctypes.c_void_p(st.cuda_stream)), "shh_stream_copy")
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        assert torch.equal(a, b)
+        best = min(ms[1:])
+        out[f"copy_{nbytes >> 20}MiB"] = {"bytes_each_way": nbytes, "ms": [round(v, 4) for v in ms],
+                                          "rw_gbs_best": round(2 * nbytes / best / 1e6, 1),
+                                          "rw_gbs_mean": round(2 * nbytes / (sum(ms[1:]) / 4) / 1e6, 1)}
+        del a, b
+        torch.cuda.empty_cache()
+    print(json.dumps(out))
 
 
 def cpu_baseline(design, gpu_iters, budget_s):
@@ -296,7 +318,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     designs = wl.shell_128_designs(n=args.n, count=args.designs)
-    eng_opts = dict(precision="mixed", rtol=args.rtol, max_iter=args.max_iter, solver=args.solver)
+    eng_opts = dict(precision="mixed", rtol=args.rtol, max_iter=args.max_iter, solver=args.solver,
+                    recompute_every=args.recompute_every)
     probe = serving.Engine(1 << 20, max_slots=1, **eng_opts)
     fp = probe.footprint(designs[0])
     probe.close()
@@ -331,46 +354,48 @@ def main():
         all_lat += lat
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launches = ctypes_int64()
-    ms_total = ctypes_double()
-    timed_bytes = ctypes_double()
-    lib.shh_profile_read_bytes(launches, ms_total, timed_bytes)
+    fam = {}
+    for k, name in enumerate(B.PROF_KINDS):
+        launches, ms = ctypes_int64(), ctypes_double()
+        B.check(lib.shh_profile_read(k, launches, ms), "shh_profile_read")
+        fam[name] = (launches.value, ms.value)
     lib.shh_profile_enable(0)
     ndes = args.steps * len(designs)
     value = ndes / wall
     ms_per_step = wall / args.steps * 1e3
     bad = [r["status"] for r in all_res if r["status"] != 0]
 
-    n_launch = launches.value
-    t_kernel = ms_total.value / 1e3
-    if args.solver == "jacobi":
-        # roofline of the CG pass kernel: algorithmic bytes / event-timed duration
-        nbytes, _ = stencil_bytes(all_res, args.n, 4)
-        # measured HBM bytes per launch: per-(node, load case) counter figure times
-        # the (node, load case) pairs an average launch of this run processed
-        node_cases = sum(int(r["iters"].sum()) for r in all_res) * args.n ** 3
-        per_nc = pcg_traffic_per_node_case()
-        traffic = int(per_nc * node_cases / max(n_launch, 1)) if per_nc is not None else None
-        kname = "stencil_kernel<float,float,PCG>"
-    else:
-        # roofline of the first coarse level's operator q = A_1 v (27-point
-        # 3x3-block stencil, all six load cases and two z-adjacent nodes per
-        # thread; the kernel with the largest share of the multigrid
-        # iteration): the library adds each timed launch's algorithmic bytes
-        nbytes = timed_bytes.value
-        per_launch = mg_apply_traffic_per_byte()
-        traffic = int(per_launch * nbytes / max(n_launch, 1)) if per_launch is not None else None
-        kname = "mg_apply_pair_kernel<float>"
-    achieved = nbytes / t_kernel / 1e9 if t_kernel > 0 else 0.0
+    # per-family roofline: algorithmic bytes implied by the iteration counts
+    # over the event-timed milliseconds of that family's launches
+    R = args.recompute_every if args.recompute_every > 0 else 50
+    fbytes = family_bytes(all_res, args.n, R, args.solver)
+    kernels = {}
+    for name, (nl, ms) in fam.items():
+        if nl == 0:
+            continue
+        gbs = fbytes[name] / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        kernels[name] = {"launches": nl, "ms": round(ms, 2), "avg_launch_ms": round(ms / nl, 4),
+                         "algorithmic_bytes": int(fbytes[name]), "gbs": round(gbs, 1),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    kd = kernels[dom]
+    ratio = traffic_ratio(dom)
+    per_launch = kd["algorithmic_bytes"] / kd["launches"]
     roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
-        "measured_gbs": round(traffic / (ms_total.value / max(n_launch, 1)) / 1e6, 1) if traffic else None,
+        "bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["frac"],
+        "traffic": int(ratio * per_launch) if ratio is not None else None, "traffic_unit": "bytes/launch",
+        "kernel": dom, "launches": kd["launches"], "avg_launch_ms": kd["avg_launch_ms"],
+        "algorithmic_bytes_per_launch": int(per_launch),
         "copy_ceiling_gbs": COPY_CEILING_GBS,
-        "kernel": kname, "launches": n_launch,
-        "avg_launch_ms": round(ms_total.value / max(n_launch, 1), 4),
-        "algorithmic_bytes_per_launch": int(nbytes / max(n_launch, 1)),
     }
+    tb = sum(v["algorithmic_bytes"] for v in kernels.values())
+    tms = sum(v["ms"] for v in kernels.values())
+    loop = {"algorithmic_bytes": int(tb), "timed_kernel_ms": round(tms, 1),
+            "timed_kernels_gbs": round(tb / (tms / 1e3) / 1e9, 1) if tms > 0 else None,
+            "timed_kernels_frac": round(tb / (tms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if tms > 0 else None,
+            "wall_gbs": round(tb / wall / 1e9, 1), "wall_frac": round(tb / wall / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "bytes of every timed kernel family (lower bound: restarts not counted) over their "
+                    "summed event time, and over the whole timed region's wall time"}
 
     # FP64 GPU path on a subset, and the C^H error of mixed vs FP64
     fp64 = {}
@@ -431,6 +456,8 @@ def main():
         "cg_iters_mean": float(np.mean(iters)),
         "status_failures": len(bad),
         "roofline": roofline,
+        "loop_roofline": loop,
+        "kernels": kernels,
     }
     out.update(fp64)
     out.update(jac)

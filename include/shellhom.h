@@ -60,6 +60,7 @@ extern "C" {
 
 #define SHH_SOLVER_JACOBI 0  /* CG with the Jacobi preconditioner                        */
 #define SHH_SOLVER_MG     1  /* CG with a geometric multigrid V-cycle preconditioner     */
+#define SHH_SOLVER_AUTO   2  /* per design: MG where the grid coarsens, else Jacobi      */
 
 /* One design (Eq. (6)-(7) parameters and material). */
 typedef struct {
@@ -220,35 +221,65 @@ int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, d
                    void *d_ws, size_t ws_bytes, void *hip_stream);
 
 /* Adjoint of Eq. (9) for the forward run that used d_ws (which must have had
-   save_for_backward = 1 and kappa > 0, t held fixed): given dL/dC^H (36 doubles,
-   row-major) and dL/dV, writes dL/dpos [N][3] and dL/dq [N] (host arrays).
+   save_for_backward = 1 and kappa > 0): given dL/dC^H (36 doubles, row-major)
+   and dL/dV, writes the gradient with respect to every design parameter that
+   Sec. 4.3 lists, theta in {charge positions, charge values, alpha_hkl, t}:
+     dL_dpos   [N][3]        host, required
+     dL_dq     [N]           host, required
+     dL_dalpha [(K+1)^3]     host or NULL; index (h (K+1) + k) (K+1) + l as for
+                             alpha; entry (0,0,0) is 0 (B_000 = 0)
+     dL_dt     [1]           host or NULL; t as an independent parameter (for a
+                             volume constraint combine it with the gradient of
+                             V: call again with dL/dC = 0, dL/dV = 1)
+   The forward's own t (given or chosen from target_vf) is the point of
+   evaluation.  The workspace's vectors are overwritten (scratch); F, grad F,
+   beta and u survive, so several calls may follow one forward.
    Returns SHH_UNSUPPORTED for the hard step. */
 int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
-                 const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq,
-                 void *hip_stream);
+                 const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq, double *dL_dalpha,
+                 double *dL_dt, void *hip_stream);
 
-/* Batched adjoint over the designs of one shh_homogenize_batch call.
-   dL_dCH: [count][36]; dL_dV: [count]; dL_dpos, dL_dq: per-design host arrays
-   laid out back to back ([sum N_i][3] and [sum N_i]). */
+/* Batched adjoint over the designs of one shh_homogenize_batch call, with one
+   synchronization for all of them.  dL_dCH: [count][36]; dL_dV: [count];
+   dL_dpos, dL_dq, dL_dalpha: per-design host arrays laid out back to back
+   ([sum N_i][3], [sum N_i], [sum (K_i+1)^3]); dL_dt: [count].  dL_dalpha and
+   dL_dt may be NULL. */
 int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts *opts,
                        void *const *d_ws, const size_t *ws_bytes, const double *dL_dCH,
-                       const double *dL_dV, double *dL_dpos, double *dL_dq, void *hip_stream);
+                       const double *dL_dV, double *dL_dpos, double *dL_dq, double *dL_dalpha,
+                       double *dL_dt, void *hip_stream);
 
 /* ---- instrumentation ------------------------------------------------------
-   When enabled, every launch of the solver's dominant kernel is bracketed by
-   two HIP events on the stream it runs on: with SHH_SOLVER_JACOBI the CG pass
-   kernel (one whole PCG iteration: q = K p fused with the vector updates),
-   with SHH_SOLVER_MG the coarse-grid operator q = A_1 v of the first coarse
-   level (the 27-point block stencil, all six load cases per launch), whose
-   launches also add their algorithmic bytes (the stored stencil once, v read
-   and q written per load case).  Elapsed times are
-   accumulated process-wide when the solver next synchronizes.
-   shh_profile_read returns the number of timed launches and their total
-   milliseconds, shh_profile_read_bytes also the bytes (0 for CG pass
-   launches); shh_profile_enable(1) also resets. */
+   When enabled, every launch of the solver's main kernel families is
+   bracketed by two HIP events on the stream it runs on, and the elapsed time
+   is accumulated per family, process-wide, when the solver next
+   synchronizes (profiling state is the library's only process-wide mutable
+   state besides a small cache of constants per Poisson ratio; neither holds
+   design data).  Families: */
+#define SHH_PROF_CG_PASS      0  /* Jacobi-PCG: the fused pass, q = K p with the vector updates */
+#define SHH_PROF_MG_DIR       1  /* multigrid CG, voxel level: p = z + beta p, q = K p, p.q     */
+#define SHH_PROF_MG_STEP1     2  /*   operator fused with the first pre-smoothing sweep         */
+#define SHH_PROF_MG_RES       3  /*   r - K d1 (the residual the restriction takes)            */
+#define SHH_PROF_MG_POST      4  /*   operator fused with the first post-smoothing sweep        */
+#define SHH_PROF_MG_LAST      5  /*   operator fused with the last sweep and the r.z partials   */
+#define SHH_PROF_MG_UPDATE    6  /*   CG update x += alpha p, r -= alpha q                     */
+#define SHH_PROF_MG_RESTRICT  7  /*   restriction to the first coarse level                    */
+#define SHH_PROF_MG_PROLONG   8  /*   prolongation from the first coarse level                 */
+#define SHH_PROF_MG_APPLY1    9  /* multigrid, first coarse level: q = A_1 v (27-point blocks)  */
+#define SHH_PROF_RESID64     10  /* FP64 residual f - K u (replacement and final check)         */
+#define SHH_PROF_NKIND       11
+/* shh_profile_enable(1) also resets the counters.  shh_profile_read gives the
+   number of timed launches of one family and their total milliseconds
+   (SHH_INVALID_ARG for an unknown family). */
 int32_t shh_profile_enable(int32_t on);
-int32_t shh_profile_read(int64_t *launches, double *ms_total);
-int32_t shh_profile_read_bytes(int64_t *launches, double *ms_total, double *bytes);
+int32_t shh_profile_read(int32_t kind, int64_t *launches, double *ms_total);
+
+/* Reference stream for the measurements: copies `bytes` (a multiple of 16,
+   both pointers 16-byte aligned) from d_src to d_dst with 16-byte vector
+   loads and stores, enqueued on hip_stream (asynchronous, unlike the calls
+   above).  Its duration is the read+write rate the GPU sustains, and its
+   hardware traffic counters calibrate those of the solver kernels. */
+int32_t shh_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
 
 /* ---- serving engine: continuous batching ------------------------------
    Requests are admitted into slots while a free slot and enough arena memory

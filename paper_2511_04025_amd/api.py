@@ -234,17 +234,57 @@ def energy(E, u, nu):
     return np.array(C[:]).reshape(6, 6)
 
 
-def grad(design, opts, workspace, dL_dC, dL_dV):
-    """Adjoint of a forward run with save_for_backward: (dL/dpos (N,3), dL/dq (N,))."""
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(c_double))
+
+
+def grad(design, opts, workspace, dL_dC, dL_dV, full=False):
+    """Adjoint of a forward run with save_for_backward: (dL/dpos (N,3), dL/dq (N,)),
+    and with full=True also dL/dalpha ((K+1)^3,) and dL/dt (t held free)."""
     _require_gpu()
     a = B.DesignArgs(design)
     N = a.q.size
+    K1 = int(design.K) + 1
     g = np.ascontiguousarray(np.asarray(dL_dC, dtype=np.float64).reshape(36))
     dpos = np.zeros((N, 3))
     dq = np.zeros(N)
-    rc = B.lib().shh_grad(byref(a.c), byref(opts), workspace.ptr, c_size_t(workspace.nbytes),
-                          g.ctypes.data_as(ctypes.POINTER(c_double)), c_double(float(dL_dV)),
-                          dpos.ctypes.data_as(ctypes.POINTER(c_double)), dq.ctypes.data_as(ctypes.POINTER(c_double)),
-                          _stream())
+    dalpha = np.zeros(K1 ** 3)
+    dt = np.zeros(1)
+    rc = B.lib().shh_grad(byref(a.c), byref(opts), workspace.ptr, c_size_t(workspace.nbytes), _dp(g),
+                          c_double(float(dL_dV)), _dp(dpos), _dp(dq), _dp(dalpha), _dp(dt), _stream())
     B.check(rc, "shh_grad")
+    if full:
+        return dpos, dq, dalpha.reshape(K1, K1, K1), float(dt[0])
     return dpos, dq
+
+
+def grad_batch(designs, opts, workspaces, dL_dC, dL_dV):
+    """Adjoint of one homogenize_batch call (one synchronization for all
+    designs): lists of dL/dpos (N_i,3), dL/dq (N_i,), dL/dalpha ((K_i+1)^3 as
+    (K+1,K+1,K+1)) and an array of dL/dt."""
+    _require_gpu()
+    args = [B.DesignArgs(d) for d in designs]
+    count = len(designs)
+    arr = (B.ShhDesign * count)(*[a.c for a in args])
+    ptrs = (c_void_p * count)(*[w.ptr.value for w in workspaces])
+    sizes = (c_size_t * count)(*[w.nbytes for w in workspaces])
+    gC = np.ascontiguousarray(np.asarray(dL_dC, dtype=np.float64).reshape(count, 36))
+    gV = np.ascontiguousarray(np.asarray(dL_dV, dtype=np.float64).reshape(count))
+    Ns = [a.q.size for a in args]
+    K1s = [int(d.K) + 1 for d in designs]
+    dpos = np.zeros((sum(Ns), 3))
+    dq = np.zeros(sum(Ns))
+    dalpha = np.zeros(sum(k ** 3 for k in K1s))
+    dt = np.zeros(count)
+    rc = B.lib().shh_grad_batch(arr, count, byref(opts), ptrs, sizes, _dp(gC), _dp(gV), _dp(dpos), _dp(dq),
+                                _dp(dalpha), _dp(dt), _stream())
+    B.check(rc, "shh_grad_batch")
+    out_p, out_q, out_a = [], [], []
+    o = oa = 0
+    for N, K1 in zip(Ns, K1s):
+        out_p.append(dpos[o:o + N])
+        out_q.append(dq[o:o + N])
+        out_a.append(dalpha[oa:oa + K1 ** 3].reshape(K1, K1, K1))
+        o += N
+        oa += K1 ** 3
+    return out_p, out_q, out_a, dt

@@ -1,13 +1,24 @@
 """Differentiable homogenization: torch.autograd.Function over the HIP forward
 path and its hand-written adjoint (Eq. (9)).
 
-``Homogenize.apply(pos, q, spec)`` maps charge positions (B, N, 3) and values
-(B, N) (float64, any device; they are read on the host) to C^H (B, 6, 6) and
-V (B,) on the CPU.  ``spec`` fixes everything else: resolution, spectral
-weights, the logistic sharpness kappa and the half-thickness t of each design
-(held fixed -- set it once from a target volume with ``initial_thickness``),
-materials and solver options.  The backward pass calls the library's adjoint
-with the workspaces the forward kept: no second solve.
+``Homogenize.apply(pos, q, spec, alpha=None, thickness=None)`` maps charge
+positions (B, N, 3) and values (B, N) -- and optionally the spectral weights
+alpha ((K+1,)*3 shared by the batch, or (B, K+1, K+1, K+1)) and the
+half-thicknesses t (B,) -- to C^H (B, 6, 6) and V (B,) on the CPU (inputs are
+float64 on any device and are read on the host).  ``spec`` fixes everything
+else: resolution, the logistic sharpness kappa, materials, solver options, and
+how t is set:
+
+* ``spec.target_vf`` None: t comes from the ``thickness`` input if given, else
+  from ``spec.thickness`` (fixed numbers, e.g. ``initial_thickness``); t is a
+  free parameter and receives dL/dt.
+* ``spec.target_vf`` set: every forward chooses t by bisection so that V
+  equals the target (Sec. 4.3's volume constraint), and the backward returns
+  the gradient along that constraint (implicit function theorem: dt/dtheta =
+  -(dV/dtheta)/(dV/dt)), from a second adjoint of V on the same workspaces.
+
+The backward pass calls the library's batched adjoint with the workspaces the
+forward kept: no second solve.
 """
 from dataclasses import dataclass, field as dc_field
 from typing import List, Optional
@@ -23,7 +34,7 @@ from .workloads import Design
 @dataclass
 class Spec:
     n: int
-    thickness: List[float]
+    thickness: Optional[List[float]]
     kappa: float
     K: int = 3
     alpha: Optional[np.ndarray] = None
@@ -36,13 +47,23 @@ class Spec:
     rtol: Optional[float] = None
     max_iter: int = 20000
     solver: str = "jacobi"
+    target_vf: Optional[float] = None
     state: dict = dc_field(default_factory=dict)
 
-    def designs(self, pos, q):
+    def designs(self, pos, q, alpha=None, thickness=None):
         out = []
         for b in range(pos.shape[0]):
-            out.append(Design(pos=pos[b], q=q[b], n=self.n, K=self.K, alpha=self.alpha, iso=self.iso,
-                              thickness=float(self.thickness[b]), kappa=self.kappa, dist_mode=self.dist_mode,
+            if alpha is None:
+                al = self.alpha
+            else:
+                al = alpha if alpha.ndim == 3 else alpha[b]
+            if self.target_vf is not None:
+                th, vf = None, float(self.target_vf)
+            else:
+                th = float(thickness[b]) if thickness is not None else float(self.thickness[b])
+                vf = None
+            out.append(Design(pos=pos[b], q=q[b], n=self.n, K=self.K, alpha=al, iso=self.iso,
+                              thickness=th, target_vf=vf, kappa=self.kappa, dist_mode=self.dist_mode,
                               E=self.E, nu=self.nu, E_void=self.E_void))
         return out
 
@@ -52,24 +73,32 @@ def initial_thickness(designs):
     return [api.field(d)["t"] for d in designs]
 
 
+def _host(x):
+    return None if x is None else x.detach().to("cpu", torch.float64).numpy()
+
+
+def _like(arr, ref):
+    return torch.tensor(arr, dtype=ref.dtype, device=ref.device)
+
+
 class Homogenize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, pos, q, spec):
+    def forward(ctx, pos, q, spec, alpha=None, thickness=None):
         if spec.kappa <= 0:
             raise ValueError("gradients need the logistic occupancy (kappa > 0)")
-        P = pos.detach().to("cpu", torch.float64).numpy()
-        Q = q.detach().to("cpu", torch.float64).numpy()
-        designs = spec.designs(P, Q)
+        if thickness is not None and spec.target_vf is not None:
+            raise ValueError("thickness is set by the volume constraint when spec.target_vf is given")
+        designs = spec.designs(_host(pos), _host(q), _host(alpha), _host(thickness))
         outs, ws, opts = api.homogenize_batch(designs, precision=spec.precision, rtol=spec.rtol,
                                               max_iter=spec.max_iter, save_for_backward=True,
                                               return_workspaces=True, solver=spec.solver)
         spec.state["last"] = outs
         ctx.spec = spec
-        ctx.designs = designs
+        # the adjoint evaluates at the forward's own t (given or bisected)
+        ctx.designs = [d.with_(thickness=o["t"], target_vf=None) for d, o in zip(designs, outs)]
         ctx.ws = ws
         ctx.opts = opts
-        ctx.pos_meta = (pos.device, pos.dtype)
-        ctx.q_meta = (q.device, q.dtype)
+        ctx.refs = (pos, q, alpha, thickness)
         C = torch.tensor(np.stack([o["C"] for o in outs]), dtype=torch.float64)
         V = torch.tensor([o["V"] for o in outs], dtype=torch.float64)
         return C, V
@@ -79,14 +108,24 @@ class Homogenize(torch.autograd.Function):
         Bsz = len(ctx.designs)
         gC = torch.zeros((Bsz, 6, 6), dtype=torch.float64) if gC is None else gC.detach().cpu().double()
         gV = torch.zeros(Bsz, dtype=torch.float64) if gV is None else gV.detach().cpu().double()
-        gpos, gq = [], []
-        for b, d in enumerate(ctx.designs):
-            dp, dq = api.grad(d, ctx.opts, ctx.ws[b], gC[b].numpy(), float(gV[b]))
-            gpos.append(dp)
-            gq.append(dq)
-        gpos = torch.tensor(np.stack(gpos), dtype=ctx.pos_meta[1], device=ctx.pos_meta[0])
-        gq = torch.tensor(np.stack(gq), dtype=ctx.q_meta[1], device=ctx.q_meta[0])
-        return gpos, gq, None
+        gp, gq, ga, gt = api.grad_batch(ctx.designs, ctx.opts, ctx.ws, gC.numpy(), gV.numpy())
+        if ctx.spec.target_vf is not None:
+            # along V(theta, t) = V*: subtract (dL/dt / dV/dt) dV/dtheta
+            vp, vq, va, vt = api.grad_batch(ctx.designs, ctx.opts, ctx.ws, np.zeros((Bsz, 6, 6)), np.ones(Bsz))
+            r = gt / vt
+            gp = [a - rb * b for a, b, rb in zip(gp, vp, r)]
+            gq = [a - rb * b for a, b, rb in zip(gq, vq, r)]
+            ga = [a - rb * b for a, b, rb in zip(ga, va, r)]
+            gt = None
+        pos, q, alpha, thickness = ctx.refs
+        g_pos = _like(np.stack(gp), pos)
+        g_q = _like(np.stack(gq), q)
+        g_alpha = None
+        if alpha is not None:
+            A = np.stack(ga)
+            g_alpha = _like(A.sum(axis=0) if alpha.dim() == 3 else A, alpha)
+        g_t = None if (thickness is None or gt is None) else _like(gt, thickness)
+        return g_pos, g_q, None, g_alpha, g_t
 
 
 def voigt_bulk(C):

@@ -81,13 +81,14 @@ EXPORTS = {
     "shh_energy": (c_int32, [c_int32, c_void_p, c_double, c_void_p, POINTER(c_double), c_void_p, c_size_t,
                              c_void_p]),
     "shh_grad": (c_int32, [POINTER(ShhDesign), POINTER(ShhOpts), c_void_p, c_size_t, POINTER(c_double),
-                           c_double, POINTER(c_double), POINTER(c_double), c_void_p]),
+                           c_double, POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                           POINTER(c_double), c_void_p]),
     "shh_grad_batch": (c_int32, [POINTER(ShhDesign), c_int32, POINTER(ShhOpts), POINTER(c_void_p),
                                  POINTER(c_size_t), POINTER(c_double), POINTER(c_double), POINTER(c_double),
-                                 POINTER(c_double), c_void_p]),
+                                 POINTER(c_double), POINTER(c_double), POINTER(c_double), c_void_p]),
     "shh_profile_enable": (c_int32, [c_int32]),
-    "shh_profile_read": (c_int32, [POINTER(ctypes.c_int64), POINTER(c_double)]),
-    "shh_profile_read_bytes": (c_int32, [POINTER(ctypes.c_int64), POINTER(c_double), POINTER(c_double)]),
+    "shh_profile_read": (c_int32, [c_int32, POINTER(ctypes.c_int64), POINTER(c_double)]),
+    "shh_stream_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "shh_engine_create": (c_int32, [c_void_p, c_size_t, c_int32, c_void_p, POINTER(c_void_p)]),
     "shh_engine_footprint": (c_int32, [POINTER(ShhDesign), POINTER(ShhOpts), POINTER(c_size_t)]),
     "shh_engine_submit": (c_int32, [c_void_p, POINTER(ShhDesign), POINTER(ShhOpts), c_uint64]),
@@ -150,7 +151,9 @@ class DesignArgs:
             E=float(design.E), nu=float(design.nu), E_void=float(design.E_void))
 
 
-SOLVER_JACOBI, SOLVER_MG = 0, 1
+SOLVER_JACOBI, SOLVER_MG, SOLVER_AUTO = 0, 1, 2
+PROF_KINDS = ("cg_pass", "mg_dir", "mg_step1", "mg_res", "mg_post", "mg_last", "mg_update", "mg_restrict",
+              "mg_prolong", "mg_apply1", "resid64")
 EDTYPE_U8, EDTYPE_F32, EDTYPE_F64 = 0, 1, 2
 
 
@@ -159,7 +162,9 @@ def make_opts(precision="mixed", rtol=None, max_iter=20000, recompute_every=0, s
     prec = PREC_MIXED if precision in ("mixed", PREC_MIXED) else PREC_FP64
     if rtol is None:
         rtol = 1e-6 if prec == PREC_MIXED else 1e-10
-    sv = SOLVER_MG if solver in ("mg", SOLVER_MG) else SOLVER_JACOBI
+    sv = {"mg": SOLVER_MG, "jacobi": SOLVER_JACOBI, "auto": SOLVER_AUTO}.get(solver, solver)
+    if sv not in (SOLVER_MG, SOLVER_JACOBI, SOLVER_AUTO):
+        raise ValueError(f"unknown solver {solver!r}")
     return ShhOpts(precision=prec, rtol=float(rtol), max_iter=int(max_iter),
                    recompute_every=int(recompute_every), save_for_backward=int(bool(save_for_backward)),
                    check_every=int(check_every), solver=sv)

@@ -31,8 +31,10 @@ constexpr int MAX_BATCH = 64;
 // Segment tables of one solve live in a fixed block of the first workspace.
 size_t seg_region() { return Solver::seg_bytes(MAX_BATCH); }
 
-// The multigrid solver needs n = m 2^k, k >= 1, m <= 8, n >= 6.
-int check_solver(int n, const shh_opts *o) {
+// The multigrid solver needs n = m 2^k, k >= 1, m <= 8, n >= 6;
+// SHH_SOLVER_AUTO resolves here, per grid, to it or to Jacobi.
+int check_solver(int n, shh_opts *o) {
+  if (o->solver == SHH_SOLVER_AUTO) o->solver = mg_num_levels(n) >= 2 ? SHH_SOLVER_MG : SHH_SOLVER_JACOBI;
   if (o->solver == SHH_SOLVER_MG && mg_num_levels(n) < 2) return SHH_UNSUPPORTED;
   return SHH_OK;
 }
@@ -65,7 +67,8 @@ int prepare_slot(Slot &s, const shh_design *d, const shh_opts *o, void *d_ws, si
                  char **seg_mem, bool vectors = true) {
   copy_design(d, s.design);
   s.opts = *o;
-  SHH_TRY(check_solver(d->n, o));
+  SHH_TRY(check_solver(d->n, &s.opts));
+  o = &s.opts;
   s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, vectors,
                       vectors ? o->solver : SHH_SOLVER_JACOBI);
   if (!d_ws) return SHH_INVALID_ARG;
@@ -405,63 +408,108 @@ int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, d
 
 // ---- adjoint -------------------------------------------------------------------
 
-int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
-                 const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq, void *hip_stream) {
+namespace {
+
+// Enqueue the adjoint of one forward run (its workspace kept with
+// save_for_backward); the results land in the slot's partials region:
+// [N][4] charge gradients, then dL/dalpha [(K+1)^3] and dL/dt.
+struct GradJob {
+  Slot s;
+  double *d_out = nullptr;
+  int N = 0, nalpha = 0;
+  std::vector<double> host;
+};
+
+int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
+                 const double dL_dCH[36], double dL_dV, hipStream_t st) {
   SHH_TRY(validate_design(design));
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
-  if (!dL_dCH || !dL_dpos || !dL_dq || !std::isfinite(dL_dV)) return SHH_INVALID_ARG;
+  if (!dL_dCH || !std::isfinite(dL_dV)) return SHH_INVALID_ARG;
   if (!(design->kappa > 0.0)) return SHH_UNSUPPORTED;
   if (!o.save_for_backward) return SHH_INVALID_ARG;
   for (int i = 0; i < 36; ++i)
     if (!std::isfinite(dL_dCH[i])) return SHH_INVALID_ARG;
-  hipStream_t st = (hipStream_t)hip_stream;
-  Slot s;
+  Slot &s = job.s;
   SHH_TRY(prepare_slot(s, design, &o, d_ws, ws_bytes, nullptr));
   // the device descriptor written by the forward call is still in place; read it back
   SHH_HIP(hipMemcpyAsync(&s.host, (SlotDev *)(s.base + s.lay.slotdev), sizeof(SlotDev),
                          hipMemcpyDeviceToHost, st));
   SHH_HIP(hipStreamSynchronize(st));
   s.d_slot = (SlotDev *)(s.base + s.lay.slotdev);
-  if (s.host.n != design->n || s.host.N != design->num_charges || s.host.prec != o.precision)
+  if (s.host.n != design->n || s.host.N != design->num_charges || s.host.prec != o.precision ||
+      s.host.K != design->K)
     return SHH_INVALID_ARG;
   // dL/dE_e weights: symmetric fold of dL/dC over the 21 distinct entries
   double g21[21];
   int t = 0;
   for (int i = 0; i < 6; ++i)
     for (int j = i; j < 6; ++j) g21[t++] = (i == j) ? dL_dCH[i * 6 + i] : dL_dCH[i * 6 + j] + dL_dCH[j * 6 + i];
-  const int N = s.host.N;
+  job.N = s.host.N;
+  const int K1 = s.host.K + 1;
+  job.nalpha = K1 * K1 * K1;
   double *d_g21 = (double *)(s.base + s.lay.segs);
-  double *d_out = s.host.partials;  // N x 4 doubles; free after the forward
-  if (sizeof(double) * 4 * (size_t)N > sizeof(double) * NRHS * (size_t)s.lay.maxparts * PSTRIDE)
+  job.d_out = s.host.partials;  // free after the forward
+  const size_t outd = 4 * (size_t)job.N + job.nalpha + 1;
+  if (sizeof(double) * outd > sizeof(double) * NRHS * (size_t)s.lay.maxparts * PSTRIDE)
     return SHH_WORKSPACE_TOO_SMALL;
   double *d_gE = (double *)s.host.r[0];  // n^3 doubles
-  double *d_scr = (double *)s.host.p[0]; // p[0], p[1], q[0], ...: 4 n^3 + small
-  SHH_HIP(hipMemcpyAsync(d_g21, g21, sizeof(g21), hipMemcpyHostToDevice, st));
+  double *d_scr = (double *)(s.base + s.lay.adj);  // sized for the adjoint by the layout
+  job.host.assign(outd, 0.0);
+  std::memcpy(job.host.data(), g21, sizeof(g21));
+  SHH_HIP(hipMemcpyAsync(d_g21, job.host.data(), sizeof(g21), hipMemcpyHostToDevice, st));
   SHH_HIP(launch_energy_sens(s.d_slot, s.host.nn, d_g21, d_gE, st));
-  SHH_HIP(launch_adjoint(s.d_slot, s.host.n, s.host.nb, N, d_gE, dL_dV, d_scr, d_out, st));
-  std::vector<double> host(4 * (size_t)N);
-  SHH_HIP(hipMemcpyAsync(host.data(), d_out, sizeof(double) * host.size(), hipMemcpyDeviceToHost, st));
-  SHH_HIP(hipStreamSynchronize(st));
-  for (int j = 0; j < N; ++j) {
-    dL_dpos[3 * j] = host[4 * j];
-    dL_dpos[3 * j + 1] = host[4 * j + 1];
-    dL_dpos[3 * j + 2] = host[4 * j + 2];
-    dL_dq[j] = host[4 * j + 3];
+  SHH_HIP(launch_adjoint(s.d_slot, s.host.n, s.host.nb, job.N, s.host.K, d_gE, dL_dV, d_scr, job.d_out,
+                         job.d_out + 4 * job.N, job.d_out + 4 * job.N + job.nalpha, st));
+  SHH_HIP(hipMemcpyAsync(job.host.data(), job.d_out, sizeof(double) * outd, hipMemcpyDeviceToHost, st));
+  return SHH_OK;
+}
+
+void grad_unpack(const GradJob &job, double *dL_dpos, double *dL_dq, double *dL_dalpha, double *dL_dt) {
+  for (int j = 0; j < job.N; ++j) {
+    dL_dpos[3 * j] = job.host[4 * j];
+    dL_dpos[3 * j + 1] = job.host[4 * j + 1];
+    dL_dpos[3 * j + 2] = job.host[4 * j + 2];
+    dL_dq[j] = job.host[4 * j + 3];
   }
+  if (dL_dalpha)
+    for (int m = 0; m < job.nalpha; ++m) dL_dalpha[m] = job.host[4 * job.N + m];
+  if (dL_dt) *dL_dt = job.host[4 * job.N + job.nalpha];
+}
+
+}  // namespace
+
+int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
+                 const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq, double *dL_dalpha,
+                 double *dL_dt, void *hip_stream) {
+  if (!dL_dpos || !dL_dq) return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  GradJob job;
+  SHH_TRY(grad_enqueue(job, design, opts, d_ws, ws_bytes, dL_dCH, dL_dV, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  grad_unpack(job, dL_dpos, dL_dq, dL_dalpha, dL_dt);
   return SHH_OK;
 }
 
 int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts *opts, void *const *d_ws,
                        const size_t *ws_bytes, const double *dL_dCH, const double *dL_dV, double *dL_dpos,
-                       double *dL_dq, void *hip_stream) {
+                       double *dL_dq, double *dL_dalpha, double *dL_dt, void *hip_stream) {
   if (count < 1 || !designs || !d_ws || !ws_bytes || !dL_dCH || !dL_dV || !dL_dpos || !dL_dq)
     return SHH_INVALID_ARG;
-  size_t off = 0;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // every design's adjoint is enqueued before the one synchronization
+  std::vector<std::unique_ptr<GradJob>> jobs;
   for (int i = 0; i < count; ++i) {
-    SHH_TRY(shh_grad(&designs[i], opts, d_ws[i], ws_bytes[i], dL_dCH + 36 * i, dL_dV[i], dL_dpos + 3 * off,
-                     dL_dq + off, hip_stream));
+    jobs.emplace_back(new GradJob());
+    SHH_TRY(grad_enqueue(*jobs.back(), &designs[i], opts, d_ws[i], ws_bytes[i], dL_dCH + 36 * i, dL_dV[i], st));
+  }
+  SHH_HIP(hipStreamSynchronize(st));
+  size_t off = 0, aoff = 0;
+  for (int i = 0; i < count; ++i) {
+    grad_unpack(*jobs[i], dL_dpos + 3 * off, dL_dq + off, dL_dalpha ? dL_dalpha + aoff : nullptr,
+                dL_dt ? dL_dt + i : nullptr);
     off += designs[i].num_charges;
+    aoff += jobs[i]->nalpha;
   }
   return SHH_OK;
 }
@@ -471,17 +519,12 @@ int32_t shh_profile_enable(int32_t on) {
   return SHH_OK;
 }
 
-int32_t shh_profile_read(int64_t *launches, double *ms_total) {
-  return shh_profile_read_bytes(launches, ms_total, nullptr);
-}
-
-int32_t shh_profile_read_bytes(int64_t *launches, double *ms_total, double *bytes) {
+int32_t shh_profile_read(int32_t kind, int64_t *launches, double *ms_total) {
   long long l = 0;
-  double m = 0.0, b = 0.0;
-  profile_read(&l, &m, &b);
+  double m = 0.0;
+  SHH_TRY(profile_read(kind, &l, &m));
   if (launches) *launches = l;
   if (ms_total) *ms_total = m;
-  if (bytes) *bytes = b;
   return SHH_OK;
 }
 
@@ -587,6 +630,7 @@ int32_t shh_engine_submit(shh_engine *eng, const shh_design *design, const shh_o
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   if (eng->prec >= 0 && o.precision != eng->prec) return SHH_INVALID_ARG;
+  SHH_TRY(check_solver(design->n, &o));  // SHH_SOLVER_AUTO: multigrid or Jacobi for this grid
   size_t need = 0;
   SHH_TRY(shh_engine_footprint(design, &o, &need));
   if (need > eng->bytes - eng->header) return SHH_OVER_BUDGET;

@@ -14,6 +14,8 @@
 // respect to each charge position and value closes the chain.
 #include "common.hpp"
 #include "hexop.hpp"
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace shh {
@@ -135,20 +137,24 @@ __device__ __forceinline__ double logistic_d(double kappa, double t, double d) {
   return e / (1.0 + e);
 }
 
-// gF = dL/dF_e, gG = dL/d(grad F)_e  (layout [4][nn])
+// gF = dL/dF_e, gG = dL/d(grad F)_e  (layout [4][nn]); per workgroup the
+// partial sum of dL/dt = sum_e dL/dbeta_e kappa beta_e (1 - beta_e) (t free)
 __global__ __launch_bounds__(256) void voxel_adjoint_kernel(SlotDev *s, const double *gE, double gV,
-                                                            double *gout) {
+                                                            double *gout, double *t_parts) {
+  __shared__ double red[16];
   const long long nn = s->nn;
   const CgState *st = s->st;
   const double t = st->t, kappa = s->kappa, dE = s->E - s->E_void, iso = s->iso;
   const double gmax = __longlong_as_double((long long)st->gmax_bits);
   const double gmin = 1e-12 * gmax;
+  double gt[1] = {0.0};
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
        i += (long long)gridDim.x * blockDim.x) {
     const double d = s->d[i];
     const double b = logistic_d(kappa, t, d);
     const double gbeta = gE[i] * dE + gV / double(nn);
     const double gd = gbeta * (-kappa * b * (1.0 - b));
+    gt[0] -= gd;
     const double diff = s->F[i] - iso;
     const double sgn = diff > 0.0 ? 1.0 : (diff < 0.0 ? -1.0 : 0.0);
     double gF, gx = 0.0, gy = 0.0, gz = 0.0;
@@ -172,6 +178,63 @@ __global__ __launch_bounds__(256) void voxel_adjoint_kernel(SlotDev *s, const do
     gout[2 * nn + i] = gy;
     gout[3 * nn + i] = gz;
   }
+  block_sum<1>(gt, red, 256);
+  if (threadIdx.x == 0) t_parts[blockIdx.x] = gt[0];
+}
+
+// dL/dt: the workgroup partials of voxel_adjoint_kernel in a fixed order
+__global__ __launch_bounds__(256) void adj_thickness_kernel(const double *t_parts, int count, double *out) {
+  __shared__ double red[16];
+  double tot[1];
+  sum_partials<1, 1>(t_parts, count, tot, red, 256);
+  if (threadIdx.x == 0) *out = tot[0];
+}
+
+// dL/dalpha_hkl from dL/dcoef: coef[u][v][w] = sum_hkl alpha_hkl w_hkl / (h^2+k^2+l^2)
+// sum_j q_j T_u(x_j) T_v(y_j) T_w(z_j), the charge-side basis T pairing cos
+// with cos and sin with sin, so dL/dalpha_hkl sums dL/dcoef over the (at most
+// 8) basis triples of mode (h, k, l) against the charges' products.  One
+// thread per mode.
+__global__ __launch_bounds__(256) void adj_alpha_kernel(SlotDev *s, const double *dcoef, double *out) {
+  const int K = s->K, K1 = K + 1, nb = s->nb, N = s->N;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= K1 * K1 * K1) return;
+  const int h = m / (K1 * K1), k = (m / K1) % K1, l = m % K1;
+  if (h + k + l == 0) {
+    out[m] = 0.0;
+    return;
+  }
+  const int zeros = (h == 0) + (k == 0) + (l == 0);
+  const double wgt = (zeros == 0 ? 1.0 : (zeros == 1 ? 0.5 : 0.25)) / double(h * h + k * k + l * l);
+  // basis indices of the mode per axis: u = 0 (h = 0), else 2h - 1 (cos) and 2h (sin)
+  const int hu[3] = {h, k, l};
+  double acc = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const double *ch = s->charges + 4 * j;
+    double T[3][2];
+    int nu_[3], u0[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      if (hu[ax] == 0) {
+        nu_[ax] = 1;
+        u0[ax] = 0;
+        T[ax][0] = 1.0;
+      } else {
+        nu_[ax] = 2;
+        u0[ax] = 2 * hu[ax] - 1;
+        double sn, cs;
+        sincospi(2.0 * hu[ax] * ch[ax], &sn, &cs);
+        T[ax][0] = cs;
+        T[ax][1] = sn;
+      }
+    }
+    double sj = 0.0;
+    for (int a = 0; a < nu_[0]; ++a)
+      for (int b = 0; b < nu_[1]; ++b)
+        for (int c = 0; c < nu_[2]; ++c)
+          sj += dcoef[((u0[0] + a) * nb + (u0[1] + b)) * nb + (u0[2] + c)] * T[0][a] * T[1][b] * T[2][c];
+    acc += ch[3] * sj;
+  }
+  out[m] = wgt * acc;
 }
 
 // 1D basis table at the voxel centers: val[i][u], der[i][u]
@@ -295,8 +358,18 @@ __global__ void adj_charges_kernel(SlotDev *s, const double *dcoef, double *out)
   }
 }
 
-hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, const double *d_gE, double gV,
-                          double *d_scratch, double *d_out, hipStream_t st) {
+size_t adjoint_scratch_bytes(int n, int K) {
+  const long long nn = (long long)n * n * n;
+  const long long nb = 2 * K + 1;
+  const long long parts = std::min((nn + 255) / 256, 8192LL);  // voxel_adjoint_kernel workgroups
+  const long long doubles = 4 * nn + 2 * n * nb + (long long)n * n * 3 * nb + (long long)n * 2 * nb * nb +
+                            nb * nb * nb + parts;
+  return size_t(doubles) * sizeof(double);
+}
+
+hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, int K, const double *d_gE, double gV,
+                          double *d_scratch, double *d_out, double *d_alpha_out, double *d_t_out,
+                          hipStream_t st) {
   const long long nn = (long long)n * n * n;
   double *g = d_scratch;                          // [4][nn]
   double *val = g + 4 * nn;                       // [n][nb]
@@ -304,15 +377,19 @@ hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, const double *d
   double *rows = der + (long long)n * nb;         // [n*n][3 nb]
   double *planes = rows + (long long)n * n * 3 * nb;  // [n][2][nb*nb]
   double *dcoef = planes + (long long)n * 2 * nb * nb;  // [nb^3]
+  double *t_parts = dcoef + (long long)nb * nb * nb;    // [<= 8192]
   long long gg = (nn + 255) / 256;
   if (gg > 8192) gg = 8192;
-  voxel_adjoint_kernel<<<int(gg), 256, 0, st>>>(d_slot, d_gE, gV, g);
+  voxel_adjoint_kernel<<<int(gg), 256, 0, st>>>(d_slot, d_gE, gV, g, t_parts);
+  if (d_t_out) adj_thickness_kernel<<<1, 256, 0, st>>>(t_parts, int(gg), d_t_out);
   basis_table_kernel<<<(n * nb + 255) / 256, 256, 0, st>>>(n, nb, val, der);
   const long long nrows = (long long)n * n;
   adj_rows_kernel<<<int((nrows + 3) / 4), 256, 0, st>>>(n, nb, g, val, der, rows);
   adj_planes_kernel<<<n, 64, 0, st>>>(n, nb, rows, val, der, planes);
   adj_coef_kernel<<<(nb * nb * nb + 127) / 128, 128, 0, st>>>(n, nb, planes, val, der, dcoef);
   adj_charges_kernel<<<N, 256, 0, st>>>(d_slot, dcoef, d_out);
+  const int K1 = K + 1;
+  if (d_alpha_out) adj_alpha_kernel<<<(K1 * K1 * K1 + 255) / 256, 256, 0, st>>>(d_slot, dcoef, d_alpha_out);
   return hipGetLastError();
 }
 

@@ -38,7 +38,12 @@ hipError_t launch_zero_vectors(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_energy(SlotDev *d_slot, long long nn, hipStream_t st);
 hipError_t launch_energy_sens(SlotDev *d_slot, long long nn, const double *d_G36, double *d_out,
                               hipStream_t st);
-hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, const double *d_gE, double gV,
-                          double *d_scratch, double *d_out, hipStream_t st);
+// device scratch (bytes) the adjoint needs for an n^3 grid at truncation order K
+size_t adjoint_scratch_bytes(int n, int K);
+// d_out [N][4] (dL/dx, dL/dy, dL/dz, dL/dq); d_alpha_out [(K+1)^3] and d_t_out
+// [1] (either may be null) receive dL/dalpha and dL/dt
+hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, int K, const double *d_gE, double gV,
+                          double *d_scratch, double *d_out, double *d_alpha_out, double *d_t_out,
+                          hipStream_t st);
 
 }  // namespace shh

@@ -145,13 +145,23 @@ __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l)
 // thread per node and load case: six times the threads, so latency overlaps)
 // on small ones.
 template <typename T, int RHS>
-__global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src) {
+__global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src, int live) {
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const long long nn = L.nn;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nn * (NRHS / RHS)) return;
   const long long v = t % nn;
   const int r0 = int(t / nn) * RHS;
+  // live: load cases that have converged (or broken down) are skipped, as in
+  // the voxel-level passes (Sec. 4.2.2: per-right-hand-side convergence)
+  bool act[RHS];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < RHS; ++r) {
+    act[r] = !live || B.slot[blockIdx.z]->st->active[r0 + r] != 0;
+    any = any || act[r];
+  }
+  if (!any) return;
   const int n = L.n;
   const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
   const T *S = (const T *)L.S;
@@ -181,6 +191,7 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
     }
 #pragma unroll
     for (int r = 0; r < RHS; ++r) {
+      if (!act[r]) continue;
       const T *vr = in + (long long)r * 3 * nn;
       const T u0 = vr[u], u1 = vr[nn + u], u2 = vr[2 * nn + u];
 #pragma unroll
@@ -190,8 +201,9 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
   T *q = (T *)L.q + (long long)r0 * 3 * nn;
 #pragma unroll
   for (int r = 0; r < RHS; ++r)
+    if (act[r])
 #pragma unroll
-    for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = acc[r][c];
+      for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = acc[r][c];
 }
 
 // q = A_l v as above, all six load cases, for two z-adjacent nodes per thread
@@ -199,13 +211,21 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
 // planes between them are loaded once for both (12 % faster per launch than
 // one node per thread).  Occupancy 3 waves per SIMD in FP32.
 template <typename T>
-__global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, int src) {
+__global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, int src, int live) {
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const long long nn = L.nn;
   const int n = L.n;
   const long long plane = (long long)n * n;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nn / 2) return;
+  bool act[NRHS];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) {
+    act[r] = !live || B.slot[blockIdx.z]->st->active[r] != 0;
+    any = any || act[r];
+  }
+  if (!any) return;
   const long long xy = t % plane;
   const int x = int(xy % n), y = int(xy / n), z0 = 2 * int(t / plane);
   const long long v0 = (long long)z0 * plane + xy;
@@ -230,7 +250,7 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
 #pragma unroll
       for (int r = 0; r < NRHS; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) val[r][c] = in[((long long)r * 3 + c) * nn + u];
+        for (int c = 0; c < 3; ++c) val[r][c] = act[r] ? in[((long long)r * 3 + c) * nn + u] : T(0);
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const int dz = pz - 1 - k;
@@ -260,8 +280,9 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
   for (int k = 0; k < 2; ++k)
 #pragma unroll
     for (int r = 0; r < NRHS; ++r)
+      if (act[r])
 #pragma unroll
-      for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v0 + k * plane] = acc[k][r][c];
+        for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v0 + k * plane] = acc[k][r][c];
 }
 
 // b_{l+1} = P^T (r_l - q_l), the residual after the pre-smoother (q = A d of
@@ -277,6 +298,7 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l, int 
   if (t >= C.nn * NRHS) return;
   const long long I = t % C.nn;
   const int k = int(t / C.nn);
+  if (!B.slot[blockIdx.z]->st->active[k]) return;
   const int nc = C.n, nf = F.n;
   const int X = int(I % nc), Y = int((I / nc) % nc), Z = int(I / ((long long)nc * nc));
   const T *r = (const T *)F.r + (long long)k * 3 * F.nn;
@@ -316,6 +338,7 @@ __global__ __launch_bounds__(256) void mg_prolong_kernel(MgBatch B, int l) {
   if (t >= F.nn * NRHS) return;
   const long long i = t % F.nn;
   const int k = int(t / F.nn);
+  if (!B.slot[blockIdx.z]->st->active[k]) return;
   const int nf = F.n, nc = C.n;
   const int x = int(i % nf), y = int((i / nf) % nf), z = int(i / ((long long)nf * nf));
   const int cx0 = x >> 1, cy0 = y >> 1, cz0 = z >> 1;
@@ -344,6 +367,7 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(MgBatch B) {
   const MgDev *mg = B.mg[blockIdx.z];
   const MgLevel &L = mg->lv[mg->L];
   const int k = blockIdx.x;
+  if (!B.slot[blockIdx.z]->st->active[k]) return;
   const int nd = mg->ndof_c;
   const long long nn = L.nn;
   const double *M = mg->Mc;
@@ -379,7 +403,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const int k = blockIdx.y;
   const long long nn = L.nn;
-  if (blockIdx.x >= (unsigned)L.nchunks) return;
+  if (blockIdx.x >= (unsigned)L.nchunks || !s->st->active[k]) return;
   const long long i0 = (long long)blockIdx.x * CHUNK;
   const long long i1 = min(i0 + (long long)CHUNK, nn);
   const T ith = (T)L.inv_theta, c1 = (T)L.c1, c2 = (T)L.c2;
@@ -451,8 +475,8 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
   double tot[2];
   sum_partials<2, PSTRIDE>(parts, s->ntiles[s->prec], tot, red, VEC_THREADS);
   if (threadIdx.x != 0) return;
-  // the direction pass ran for every load case, active or not
-  if (phase == MGS_ALPHA) st->mgpar[k] ^= 1;
+  // the direction pass ran for the active load cases only: their new
+  // direction becomes current
   if (!st->active[k]) {
     st->alpha[k] = 0.0;
     st->beta[k] = 0.0;
@@ -468,6 +492,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
       st->active[k] = 0;
     }
   } else if (phase == MGS_ALPHA) {
+    st->mgpar[k] ^= 1;
     const double sigma = tot[0], rho = st->rho[k];
     const bool ok = isfinite(sigma) && sigma > 0.0 && rho > 0.0;
     st->alpha[k] = ok ? rho / sigma : 0.0;
@@ -684,19 +709,19 @@ hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, h
 bool mg_apply_wide(long long nn_max) { return nn_max > 32768; }
 
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
-                           hipStream_t st) {
+                           hipStream_t st, int live) {
   if (mg_apply_wide(nn_max) && even) {
     const dim3 g(blocks_for(nn_max / 2, 256), 1, B.count);
-    if (prec == 0) mg_apply_pair_kernel<double><<<g, 256, 0, st>>>(B, l, src);
-    else mg_apply_pair_kernel<float><<<g, 256, 0, st>>>(B, l, src);
+    if (prec == 0) mg_apply_pair_kernel<double><<<g, 256, 0, st>>>(B, l, src, live);
+    else mg_apply_pair_kernel<float><<<g, 256, 0, st>>>(B, l, src, live);
   } else if (mg_apply_wide(nn_max)) {
     const dim3 g(blocks_for(nn_max, 256), 1, B.count);
-    if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(B, l, src);
-    else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(B, l, src);
+    if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(B, l, src, live);
+    else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(B, l, src, live);
   } else {
     const dim3 g(blocks_for(nn_max * NRHS, 256), 1, B.count);
-    if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, src);
-    else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, src);
+    if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, src, live);
+    else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, src, live);
   }
   return hipGetLastError();
 }
@@ -704,8 +729,8 @@ hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, b
 // q = A_l v for load case 0 only (the setup's power iteration)
 hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st) {
   const dim3 g(blocks_for(nn_max, 256), 1, B.count);
-  if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, 0);
-  else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, 0);
+  if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, 0, 0);
+  else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, 0, 0);
   return hipGetLastError();
 }
 

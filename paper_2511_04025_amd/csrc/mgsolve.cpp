@@ -26,8 +26,9 @@ hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long n
 hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st);
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
 hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
+// live = 1: skip the load cases whose CG has stopped (state read on the device)
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
-                           hipStream_t st);
+                           hipStream_t st, int live);
 hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st);
 bool mg_apply_wide(long long nn_max);
 hipError_t mg_launch_restrict(const MgBatch &B, int l, bool formed, long long nn_coarse_max, int prec,
@@ -252,14 +253,6 @@ MgBatch batch_of(const std::vector<Slot *> &slots) {
   return B;
 }
 
-// Algorithmic bytes of one coarse-level operator application q = A_l v: the
-// stored half stencil (MG_STENCIL values per node, read once for all load
-// cases) and, per load case, v read and q written (3 components each).
-double apply_bytes(const Slot &s, int l) {
-  const double ts = s.host.prec == SHH_PREC_FP64 ? 8.0 : 4.0;
-  return double(s.mg.lv[l].nn) * (MG_STENCIL + NRHS * 3 * 2) * ts;
-}
-
 // One V-cycle from level l down, for slots that all have at least l + 1
 // levels; slots whose coarsest level is l take the dense solve there.
 int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *timer, const MgApply0 &apply0) {
@@ -279,23 +272,22 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
     all_even = all_even && s->mg.lv[l].n % 2 == 0;
   }
   int rc;
+  // when profiling, the voxel level's launches and the first coarse level's
+  // operator are timed by kernel family (the rest is small)
+  hipEvent_t e0 = nullptr;
+  auto tb = [&](bool on) -> int { return (on && timer) ? timer->timed_begin(&e0) : (e0 = nullptr, 0); };
+  auto te = [&](int kind) -> int { return (e0 && timer) ? timer->timed_end(e0, kind) : 0; };
   auto vec = [&](int op) -> int {
+    const bool t = l == 0 && op == MGV_INIT;
+    if ((rc = tb(t))) return rc;
     SHH_HIP(mg_launch_vec(B, l, op, nch_max, prec, st));
-    return SHH_OK;
+    return te(SHH_PROF_MG_UPDATE);
   };
-  // when profiling, the coarse operator launches that take a node per thread
-  // for all load cases (the largest coarse level) are timed with their
-  // algorithmic bytes
   auto app = [&](int src) -> int {
     if (l == 0) return apply0(smooth, MG_SRC_RES);  // r - K d1 in place of r
-    const bool timed = timer && mg_apply_wide(nn_max);
-    hipEvent_t e0 = nullptr;
-    if (timed && (rc = timer->timed_begin(&e0))) return rc;
-    SHH_HIP(mg_launch_apply(B, l, src, nn_max, all_even, prec, st));
-    if (!timed) return SHH_OK;
-    double bytes = 0.0;
-    for (Slot *s : smooth) bytes += apply_bytes(*s, l);
-    return timer->timed_end(e0, bytes);
+    if ((rc = tb(l == 1))) return rc;
+    SHH_HIP(mg_launch_apply(B, l, src, nn_max, all_even, prec, st, 1));
+    return te(SHH_PROF_MG_APPLY1);
   };
   // pre-smoother (at the voxel level INIT also applies the pending CG
   // update, and the operator runs fused with the sweep after it)
@@ -304,9 +296,13 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   else if (!(rc = app(1))) rc = vec(MGV_STEP1);
   if (rc || (rc = app(1))) return rc;
   // coarse-grid correction of the residual r - A d
+  if ((rc = tb(l == 0))) return rc;
   SHH_HIP(mg_launch_restrict(B, l, l == 0, nn_next_max, prec, st));
+  if ((rc = te(SHH_PROF_MG_RESTRICT))) return rc;
   if ((rc = vcycle(smooth, l + 1, st, timer, apply0))) return rc;
+  if ((rc = tb(l == 0))) return rc;
   SHH_HIP(mg_launch_prolong(B, l, nn_max, prec, st));
+  if ((rc = te(SHH_PROF_MG_PROLONG))) return rc;
   // post-smoother
   if (l == 0) {
     if ((rc = apply0(smooth, MG_SRC_POST)) || (rc = apply0(smooth, MG_SRC_LAST))) return rc;
@@ -481,7 +477,7 @@ int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
   const MgLevel &L = s.mg.lv[l];
   const size_t bytes = (size_t)NRHS * 3 * L.nn * (s.host.prec == SHH_PREC_FP64 ? 8 : 4);
   SHH_HIP(hipMemcpyAsync(L.x, d_v, bytes, hipMemcpyDeviceToDevice, st));
-  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, L.n % 2 == 0, s.host.prec, st));
+  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, L.n % 2 == 0, s.host.prec, st, 0));
   SHH_HIP(hipMemcpyAsync(d_q, L.q, bytes, hipMemcpyDeviceToDevice, st));
   SHH_HIP(hipStreamSynchronize(st));
   return SHH_OK;

@@ -23,32 +23,32 @@ namespace shh {
 namespace {
 std::atomic<bool> g_prof_on{false};
 std::mutex g_prof_mu;
-long long g_prof_launches = 0;
-double g_prof_ms = 0.0;
-double g_prof_bytes = 0.0;
+long long g_prof_launches[SHH_PROF_NKIND] = {};
+double g_prof_ms[SHH_PROF_NKIND] = {};
 }  // namespace
 
 void profile_enable(bool on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on;
   if (on) {
-    g_prof_launches = 0;
-    g_prof_ms = 0.0;
-    g_prof_bytes = 0.0;
+    for (int k = 0; k < SHH_PROF_NKIND; ++k) {
+      g_prof_launches[k] = 0;
+      g_prof_ms[k] = 0.0;
+    }
   }
 }
 bool profile_on() { return g_prof_on.load(); }
-void profile_read(long long *launches, double *ms, double *bytes) {
+int profile_read(int kind, long long *launches, double *ms) {
+  if (kind < 0 || kind >= SHH_PROF_NKIND) return SHH_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (launches) *launches = g_prof_launches;
-  if (ms) *ms = g_prof_ms;
-  if (bytes) *bytes = g_prof_bytes;
+  if (launches) *launches = g_prof_launches[kind];
+  if (ms) *ms = g_prof_ms[kind];
+  return SHH_OK;
 }
-void profile_add(double ms, double bytes) {
+void profile_add(int kind, double ms) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_launches += 1;
-  g_prof_ms += ms;
-  g_prof_bytes += bytes;
+  g_prof_launches[kind] += 1;
+  g_prof_ms[kind] += ms;
 }
 
 double now_ms() {
@@ -90,7 +90,8 @@ int normalize_opts(const shh_opts *in, shh_opts *out) {
   if (out->precision != SHH_PREC_FP64 && out->precision != SHH_PREC_MIXED) return SHH_INVALID_ARG;
   if (!(out->rtol > 0.0 && out->rtol < 1.0)) return SHH_INVALID_ARG;
   if (out->max_iter < 0 || out->recompute_every < 0 || out->check_every < 0) return SHH_INVALID_ARG;
-  if (out->solver != SHH_SOLVER_JACOBI && out->solver != SHH_SOLVER_MG) return SHH_INVALID_ARG;
+  if (out->solver != SHH_SOLVER_JACOBI && out->solver != SHH_SOLVER_MG && out->solver != SHH_SOLVER_AUTO)
+    return SHH_INVALID_ARG;
   if (out->recompute_every == 0 && out->precision == SHH_PREC_MIXED) out->recompute_every = 50;
   if (out->check_every == 0) out->check_every = 16;
   return SHH_OK;
@@ -139,6 +140,13 @@ Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors, int s
   L.x64 = prec == SHH_PREC_MIXED ? take(sizeof(double) * NRHS * 3 * nn) : 0;
   L.vec_bytes = align256(ts * NRHS * 3 * nn);
   L.vec = take(7 * L.vec_bytes);  // r[2], p[2], q[2], x
+  // after a forward with save, the adjoint takes r[0] for dL/dE and p[0], p[1],
+  // q[0], q[1] as scratch -- or a region of its own on grids too small for
+  // that, so that the solution (x, or x64) survives for further calls
+  if (save) {
+    const size_t adj = align256(adjoint_scratch_bytes(n, K));
+    L.adj = adj <= 4 * L.vec_bytes ? L.vec + 2 * L.vec_bytes : take(adj);
+  }
   L.field = save ? take(sizeof(double) * 5 * nn) : L.vec;  // F, G[3], d (aliased unless saved)
   if (solver == SHH_SOLVER_MG) L.mg = take(mg_region_bytes(n, prec));
   L.total = off;
@@ -369,7 +377,10 @@ int Solver::residual(const std::vector<Slot *> &slots, int mode) {
     SHH_HIP(launch_fold(la, prec, st_));
   }
   if ((rc = build(K_RESID, slots, mode, all, la))) return rc;
+  hipEvent_t e0 = nullptr;
+  if (la.total > 0 && (rc = timed_begin(&e0))) return rc;
   SHH_HIP(launch_stencil_resid(la, prec, st_));
+  if ((rc = timed_end(e0, SHH_PROF_RESID64))) return rc;
   LaunchArgs ls;
   if ((rc = build(K_SCAL_RES, slots, mode, all, ls))) return rc;
   SHH_HIP(launch_scalar(ls, PH_MEAN, st_));
@@ -435,20 +446,13 @@ hipEvent_t Solver::get_event() {
 
 // Call only after the stream has been synchronized.
 void Solver::resolve_events() {
-  for (auto &pr : ev_pending_) {
+  for (auto &tk : ev_timed_) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) profile_add(ms, 0.0);
-    ev_pool_.push_back(pr.first);
-    ev_pool_.push_back(pr.second);
+    if (hipEventElapsedTime(&ms, tk.e0, tk.e1) == hipSuccess) profile_add(tk.kind, ms);
+    ev_pool_.push_back(tk.e0);
+    ev_pool_.push_back(tk.e1);
   }
-  ev_pending_.clear();
-  for (auto &tb : ev_bytes_) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, tb.e0, tb.e1) == hipSuccess) profile_add(ms, tb.bytes);
-    ev_pool_.push_back(tb.e0);
-    ev_pool_.push_back(tb.e1);
-  }
-  ev_bytes_.clear();
+  ev_timed_.clear();
 }
 
 int Solver::iterate(const std::vector<Slot *> &all, int iters) {
@@ -461,21 +465,13 @@ int Solver::iterate(const std::vector<Slot *> &all, int iters) {
   const int prec = slots[0]->host.prec;
   LaunchArgs la_s;
   if ((rc = build(K_STENCIL, slots, 0, false, la_s))) return rc;
-  const bool prof = profile_on();
   LaunchArgs la_c;
   if ((rc = build(K_SCAL_IT, slots, 0, false, la_c))) return rc;
   for (int it = 0; it < iters; ++it) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof && la_s.total > 0) {
-      e0 = get_event();
-      e1 = get_event();
-      if (e0) SHH_HIP(hipEventRecord(e0, st_));
-    }
+    hipEvent_t e0 = nullptr;
+    if (la_s.total > 0 && (rc = timed_begin(&e0))) return rc;
     SHH_HIP(launch_stencil_pcg(la_s, prec, st_));
-    if (e0 && e1) {
-      SHH_HIP(hipEventRecord(e1, st_));
-      ev_pending_.emplace_back(e0, e1);
-    }
+    if ((rc = timed_end(e0, SHH_PROF_CG_PASS))) return rc;
     SHH_HIP(launch_scalar(la_c, PH_ITER, st_));
     std::vector<Slot *> due;
     for (Slot *s : slots) {
@@ -496,15 +492,22 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
     static const Kind kinds[5] = {K_MG_DIR, K_MG_RES, K_MG_STEP1, K_MG_POST, K_MG_LAST};
     static const int ops[5] = {SMG_DIR, SMG_RES, SMG_STEP1, SMG_POST, SMG_LAST};
+    static const int prof[5] = {SHH_PROF_MG_DIR, SHH_PROF_MG_RES, SHH_PROF_MG_STEP1, SHH_PROF_MG_POST,
+                                SHH_PROF_MG_LAST};
     if (src < 0 || src > MG_SRC_LAST) return SHH_INVALID_ARG;
     LaunchArgs la;
     int r;
-    if ((r = build(kinds[src], ss, 0, true, la))) return r;
+    // segments of the load cases still running at the last read-back; the
+    // kernels also skip those that stopped since
+    if ((r = build(kinds[src], ss, 0, false, la))) return r;
+    if (la.total == 0) return SHH_OK;
+    hipEvent_t e0 = nullptr;
+    if ((r = timed_begin(&e0))) return r;
     SHH_HIP(launch_stencil_mg(la, ss[0]->host.prec, ops[src], st_));
-    return SHH_OK;
+    return timed_end(e0, prof[src]);
   };
   for (int it = 0; it < iters; ++it) {
-    if ((rc = mg_iterate(slots, st_, profile_on() ? this : nullptr, apply0))) return rc;
+    if ((rc = mg_iterate(slots, st_, this, apply0))) return rc;
     std::vector<Slot *> due;
     for (Slot *s : slots) {
       s->launched += 1;
@@ -516,17 +519,22 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
 }
 
 int Solver::timed_begin(hipEvent_t *e0) {
+  *e0 = nullptr;
+  if (!profile_on()) return SHH_OK;
   *e0 = get_event();
   if (*e0) SHH_HIP(hipEventRecord(*e0, st_));
   return SHH_OK;
 }
 
-int Solver::timed_end(hipEvent_t e0, double bytes) {
+int Solver::timed_end(hipEvent_t e0, int kind) {
   if (!e0) return SHH_OK;
   hipEvent_t e1 = get_event();
-  if (!e1) return SHH_OK;
+  if (!e1) {
+    ev_pool_.push_back(e0);
+    return SHH_OK;
+  }
   SHH_HIP(hipEventRecord(e1, st_));
-  ev_bytes_.push_back({e0, e1, bytes});
+  ev_timed_.push_back({e0, e1, kind});
   return SHH_OK;
 }
 

@@ -20,6 +20,7 @@ namespace shh {
 struct Layout {
   size_t slotdev, state, charges, alpha, coef, partials, segs;
   size_t E64, E32, Dinv, x64, vec, field;
+  size_t adj;         // adjoint scratch (save_for_backward only)
   size_t vec_bytes;   // one [6][3][n^3] vector
   size_t mg;          // multigrid region (0 bytes unless the multigrid solver is used)
   size_t total;
@@ -113,10 +114,10 @@ class Solver {
   // residual check and, if it holds, the C^H reduction. Returns slots finished now.
   int poll(const std::vector<Slot *> &slots, std::vector<Slot *> &done);
   int sync();
-  // bracket one launch on the solver's stream with events; `bytes` is its
-  // algorithmic traffic (profiling only)
+  // bracket one launch on the solver's stream with events when profiling is
+  // on (kind: SHH_PROF_*); resolved at the next synchronization
   int timed_begin(hipEvent_t *e0);
-  int timed_end(hipEvent_t e0, double bytes);
+  int timed_end(hipEvent_t e0, int kind);
 
  private:
   enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_MG_DIR, K_MG_RES,
@@ -131,14 +132,13 @@ class Solver {
   char *seg_mem_ = nullptr;
   size_t seg_cap_ = 0;
   std::vector<Segment> host_segs_[K_NKIND];
-  // events bracketing stencil launches, resolved at the next synchronization
+  // events bracketing timed launches, resolved at the next synchronization
   std::vector<hipEvent_t> ev_pool_;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending_;
-  struct TimedBytes {
+  struct Timed {
     hipEvent_t e0, e1;
-    double bytes;
+    int kind;
   };
-  std::vector<TimedBytes> ev_bytes_;
+  std::vector<Timed> ev_timed_;
   hipEvent_t get_event();
   void resolve_events();
 
@@ -146,11 +146,11 @@ class Solver {
   ~Solver();
 };
 
-// process-wide stencil-launch timing (shh_profile_*)
+// process-wide launch timing by kernel family (shh_profile_*, SHH_PROF_*)
 void profile_enable(bool on);
 bool profile_on();
-void profile_read(long long *launches, double *ms, double *bytes);
-void profile_add(double ms, double bytes);
+int profile_read(int kind, long long *launches, double *ms);
+void profile_add(int kind, double ms);
 
 double now_ms();
 void fill_result(const Slot &s, shh_result *out);

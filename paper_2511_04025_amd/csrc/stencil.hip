@@ -89,7 +89,9 @@ void stencil_kernel(LaunchArgs la) {
   const SHH_CONST SlotDev *s = to_const(w.slot);
   const SHH_CONST CgState *st = to_const(s->st);
   const int rhs = w.rhs;
-  if (MODE == MODE_PCG && !st->active[rhs]) return;
+  // load cases whose CG has stopped are skipped (Sec. 4.2.2: per-right-hand-
+  // side convergence); the multigrid passes likewise
+  if ((MODE == MODE_PCG || MODE >= MODE_MGDIR) && !st->active[rhs]) return;
   if (MODE == MODE_RESID) {
     if (w.flag == RES_RECOMPUTE && !st->active[rhs]) return;
     if (w.flag == RES_FINAL && !(st->ff[rhs] > s->ffloor * s->ffloor)) return;

@@ -107,3 +107,111 @@ def test_autograd_function_against_finite_differences():
     # d is invariant to scaling the charges (iso = 0): the loss is flat along q
     for b in range(2):
         assert abs(np.dot(Q0[b], gq[b])) <= 1e-8 * scale * np.abs(Q0[b]).sum()
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-8), ("mixed", 1e-7, 1e-4)])
+def test_alpha_and_thickness_gradients_match_oracle(precision, rtol, tol):
+    # Eq. (9) for every parameter of Sec. 4.3 (positions, values, alpha_hkl,
+    # t) against the oracle's direct-summation gradients, with non-uniform
+    # spectral weights; and the batched adjoint equals the single one
+    from paper_2511_04025_amd import api
+    n = 12
+    d = wl.random_design(63, n, N=8, vf=0.25, E_void=1e-3, kappa=4.0 * n)
+    alpha = 1.0 + 0.3 * np.random.default_rng(63).standard_normal((4, 4, 4))
+    F, G = fld.field_and_gradient(d.pos, d.q, n, alpha=alpha)
+    t = fld.thickness_for_volume(fld.distance(F, G), 0.25, d.kappa)
+    C, info = hom.homogenize_design(d.pos, d.q, n, alpha=alpha, thickness=t, kappa=d.kappa, E_void=d.E_void,
+                                    solver="direct")
+    rng = np.random.default_rng(9)
+    dLdC = rng.standard_normal((6, 6))
+    ref = adj.design_gradient_full(info, d.pos, d.q, n, dLdC, 0.4, alpha=alpha, kappa=d.kappa, E_void=d.E_void)
+    dd = d.with_(thickness=t, alpha=alpha)
+    r = api.homogenize(dd, precision=precision, rtol=rtol, save_for_backward=True, return_workspace=True)
+    assert r["status"] == 0
+    got = api.grad(dd, r["opts"], r["workspace"], dLdC, 0.4, full=True)
+    for name, a, b in zip(("pos", "q", "alpha"), got[:3], ref[:3]):
+        assert np.max(np.abs(a - b)) <= tol * np.abs(b).max(), (name, rel_err(a, b))
+    assert abs(got[3] - ref[3]) <= tol * abs(ref[3]), (got[3], ref[3])
+    # a second call on the same workspace sees the same solution
+    again = api.grad(dd, r["opts"], r["workspace"], dLdC, 0.4, full=True)
+    assert all(np.array_equal(x, y) for x, y in zip(again[:3], got[:3])) and again[3] == got[3]
+    outs, ws, opts = api.homogenize_batch([dd, dd.with_(seed=None)], precision=precision, rtol=rtol,
+                                          save_for_backward=True, return_workspaces=True)
+    gp, gq, ga, gt = api.grad_batch([dd, dd], opts, ws, np.stack([dLdC, dLdC]), [0.4, 0.4])
+    for b in range(2):
+        assert np.array_equal(gp[b], got[0]) and np.array_equal(gq[b], got[1])
+        assert np.array_equal(ga[b], got[2]) and gt[b] == got[3]
+
+
+def test_autograd_alpha_thickness_and_volume_constraint():
+    # autograd through alpha and t (free), and along the volume constraint
+    # (t bisected on the GPU for every forward), against central differences
+    # of the GPU forward in FP64
+    from paper_2511_04025_amd import autograd as AG
+    n = 16
+    base = [wl.random_design(90 + b, n, N=8, vf=0.2, E_void=1e-3, kappa=4.0 * n) for b in range(2)]
+    t0 = AG.initial_thickness(base)
+    spec = AG.Spec(n=n, thickness=t0, kappa=4.0 * n, E_void=1e-3, precision="fp64", rtol=1e-12)
+    pos = torch.tensor(np.stack([d.pos for d in base]), dtype=torch.float64)
+    q = torch.tensor(np.stack([d.q for d in base]), dtype=torch.float64)
+    alpha0 = 1.0 + 0.2 * np.random.default_rng(90).standard_normal((4, 4, 4))
+    w = torch.tensor(np.random.default_rng(91).standard_normal((6, 6)))
+
+    def loss(C, V):
+        return (w * C).sum() + 0.3 * V.sum()
+
+    # free t, shared alpha
+    a = torch.tensor(alpha0, requires_grad=True)
+    th = torch.tensor(t0, dtype=torch.float64, requires_grad=True)
+    C, V = AG.Homogenize.apply(pos, q, spec, a, th)
+    loss(C, V).backward()
+    ga, gt = a.grad.numpy().copy(), th.grad.numpy().copy()
+
+    def f(al, tt):
+        with torch.no_grad():
+            Cc, Vv = AG.Homogenize.apply(pos, q, spec, torch.tensor(al), torch.tensor(tt))
+            return float(loss(Cc, Vv))
+
+    h = 1e-6
+    for idx in [(0, 0, 1), (2, 1, 3), (3, 3, 0)]:
+        ap, am = alpha0.copy(), alpha0.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fd = (f(ap, t0) - f(am, t0)) / (2 * h)
+        assert abs(fd - ga[idx]) <= 2e-5 * np.abs(ga).max(), (idx, fd, ga[idx])
+    for b in range(2):
+        tp, tm = list(t0), list(t0)
+        tp[b] += h
+        tm[b] -= h
+        fd = (f(alpha0, tp) - f(alpha0, tm)) / (2 * h)
+        assert abs(fd - gt[b]) <= 2e-5 * np.abs(gt).max(), (b, fd, gt[b])
+    # volume-constrained: V stays at the target, the gradient is the one along it
+    cspec = AG.Spec(n=n, thickness=None, kappa=4.0 * n, E_void=1e-3, precision="fp64", rtol=1e-12,
+                    target_vf=0.2)
+    a = torch.tensor(alpha0, requires_grad=True)
+    p = pos.clone().requires_grad_(True)
+    C, V = AG.Homogenize.apply(p, q, cspec, a)
+    assert np.all(np.abs(V.numpy() - 0.2) <= 1e-12)
+    (w * C).sum().backward()
+    ga, gp = a.grad.numpy().copy(), p.grad.numpy().copy()
+
+    def fc(al, P):
+        with torch.no_grad():
+            Cc, _ = AG.Homogenize.apply(torch.tensor(P), q, cspec, torch.tensor(al))
+            return float((w * Cc).sum())
+
+    P0 = pos.numpy()
+    h = 1e-5
+    scale = max(np.abs(ga).max(), np.abs(gp).max())
+    for idx in [(1, 0, 2), (0, 3, 3)]:
+        ap, am = alpha0.copy(), alpha0.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fd = (fc(ap, P0) - fc(am, P0)) / (2 * h)
+        assert abs(fd - ga[idx]) <= 2e-5 * scale, (idx, fd, ga[idx])
+    for idx in [(0, 1, 0), (1, 4, 2)]:
+        Pp, Pm = P0.copy(), P0.copy()
+        Pp[idx] += h
+        Pm[idx] -= h
+        fd = (fc(alpha0, Pp) - fc(alpha0, Pm)) / (2 * h)
+        assert abs(fd - gp[idx]) <= 2e-5 * scale, (idx, fd, gp[idx])

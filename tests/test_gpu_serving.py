@@ -154,3 +154,21 @@ def test_setup_failure_stays_isolated():
     e.close()
     assert res[0]["status"] == B.SHH_BREAKDOWN
     assert res[1]["status"] == 0 and np.array_equal(res[1]["C"], alone[0]["C"])
+
+
+def test_auto_solver_serves_grids_the_multigrid_cannot_coarsen():
+    # SHH_SOLVER_AUTO: a 37^3 request (odd, no hierarchy) takes Jacobi, a 32^3
+    # one the multigrid, in the same engine; each equals its own solver's
+    # single-design result
+    from paper_2511_04025_amd import api
+    odd = wl.random_design(350, 37, N=16, vf=0.15, E_void=1e-6)
+    even = wl.random_design(351, 32, N=16, vf=0.15, E_void=1e-6)
+    e = engine(1 << 30, slots=4, solver="auto", rtol=1e-5)
+    res, peak = run_all(e, [odd, even], iters=4)
+    e.close()
+    assert peak == 2
+    rj = api.homogenize(odd, precision="mixed", rtol=1e-5, solver="jacobi")
+    rm = api.homogenize(even, precision="mixed", rtol=1e-5, solver="mg")
+    assert res[0]["status"] == 0 and res[1]["status"] == 0
+    assert np.array_equal(res[0]["C"], rj["C"]) and np.array_equal(res[1]["C"], rm["C"])
+    assert res[0]["iters"].max() > 4 * res[1]["iters"].max()

@@ -185,7 +185,14 @@ def test_multigrid_solver_option(lib):
             _, nj = ws_bytes(lib, d, "mixed")
             # the hierarchy adds its stencils and vectors (~1/8 of the voxel level's per level)
             assert nj < nb < 2 * nj
-    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=2)
+    # SHH_SOLVER_AUTO takes the multigrid where the grid coarsens and Jacobi elsewhere
+    for n in (24, 37, 50, 4):
+        d = wl.shell_128(2000, n=n)
+        rc_a, na = ws_bytes(lib, d, "mixed", solver="auto")
+        rc_m, nm = ws_bytes(lib, d, "mixed", solver="mg")
+        _, nj = ws_bytes(lib, d, "mixed", solver="jacobi")
+        assert rc_a == B.SHH_OK and na == (nm if rc_m == B.SHH_OK else nj), n
+    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=3)
     a = B.DesignArgs(wl.small_shell_24())
     nb = c_size_t(0)
     assert lib.shh_workspace_bytes(byref(a.c), byref(o), byref(nb)) == B.SHH_INVALID_ARG
