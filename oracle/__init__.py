@@ -19,6 +19,8 @@ NumPy/SciPy double precision:
                     direct cross-check.
 * ``homogenize`` -- the energy form of C^H (Eq. (8)) and the whole forward path.
 * ``adjoint``    -- the self-adjoint sensitivities of Eq. (9).
+* ``selective``  -- the culled cell problems of Sec. 4.2: active voxels
+                    beta > 1e-3, unknowns on the active nodes only, no floor.
 * ``multigrid``  -- the coarse grids of Sec. 4.2's hierarchy: periodic
                     trilinear prolongation and Galerkin coarse operators.
 * ``metrics``    -- the material metrics and bounds of Sec. 5.2 and the
