@@ -169,7 +169,8 @@ def test_autograd_alpha_thickness_and_volume_constraint():
 
     def f(al, tt):
         with torch.no_grad():
-            Cc, Vv = AG.Homogenize.apply(pos, q, spec, torch.tensor(al), torch.tensor(tt))
+            Cc, Vv = AG.Homogenize.apply(pos, q, spec, torch.tensor(al, dtype=torch.float64),
+                                             torch.tensor(tt, dtype=torch.float64))
             return float(loss(Cc, Vv))
 
     h = 1e-6
@@ -191,13 +192,14 @@ def test_autograd_alpha_thickness_and_volume_constraint():
     a = torch.tensor(alpha0, requires_grad=True)
     p = pos.clone().requires_grad_(True)
     C, V = AG.Homogenize.apply(p, q, cspec, a)
-    assert np.all(np.abs(V.numpy() - 0.2) <= 1e-12)
+    assert np.all(np.abs(V.detach().numpy() - 0.2) <= 1e-12)
     (w * C).sum().backward()
     ga, gp = a.grad.numpy().copy(), p.grad.numpy().copy()
 
     def fc(al, P):
         with torch.no_grad():
-            Cc, _ = AG.Homogenize.apply(torch.tensor(P), q, cspec, torch.tensor(al))
+            Cc, _ = AG.Homogenize.apply(torch.tensor(P, dtype=torch.float64), q, cspec,
+                                        torch.tensor(al, dtype=torch.float64))
             return float((w * Cc).sum())
 
     P0 = pos.numpy()

@@ -119,7 +119,7 @@ def fp64_256():
     return d, rd
 
 
-@pytest.mark.parametrize("solver,rtol", [("mg", 1e-5), ("jacobi", 1e-6)])
+@pytest.mark.parametrize("solver,rtol", [("mg", 3e-6), ("jacobi", 1e-6)])
 def test_large_shell_256_mixed_vs_fp64(fp64_256, solver, rtol):
     # 256^3, 64 charges +-1, V = 0.05, void E 1e-6: FP32 stencil and vectors
     # with the FP64 residual replaced every 50 iterations, all six load cases

@@ -38,8 +38,7 @@ def test_small_shell_vs_oracle(precision, rtol, tol):
     assert r["iters"].max() * 4 < rj["iters"].max()
 
 
-@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-7), ("mixed", 3e-6, 1e-4),
-                                                ("mixed", 1e-5, 1e-4)])
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-7), ("mixed", 3e-6, 1e-4)])
 def test_shell_designs_at_48_vs_oracle(precision, rtol, tol):
     A = api()
     designs = wl.shell_128_designs(n=48, count=8)
@@ -102,7 +101,7 @@ def test_mixed_vs_fp64_at_128_served():
     A = api()
     designs = wl.shell_128_designs(n=128, count=4)
     print("mg 128^3 served vs fp64", flush=True)
-    mg = A.homogenize_batch(designs, precision="mixed", rtol=1e-5, solver="mg")
+    mg = A.homogenize_batch(designs, precision="mixed", rtol=3e-6, solver="mg")
     ref = A.homogenize_batch(designs, precision="fp64", rtol=1e-10, solver="mg")
     for a, b in zip(mg, ref):
         assert a["status"] == 0 and b["status"] == 0
@@ -264,14 +263,16 @@ def _drain(eng, got, iters):
 
 def test_served_engine_vs_oracle_with_staggered_arrivals():
     # the served configuration -- engine, multigrid, mixed precision, CG
-    # tolerance 1e-5 -- on the eight 48^3 designs the oracle has values for.
+    # tolerance 3e-6 -- on the eight 48^3 designs the oracle has values for
+    # (at 1e-5 one of them, seed 2004, misses the per-entry bar: 1.27e-4 on
+    # an entry at 2e-3 of the largest).
     # Requests arrive in three waves between engine steps of uneven length;
     # every C^H is within the per-entry bar of the oracle's, and each design's
     # result is bit-for-bit the one it gets alone (a converged load case stops
     # changing, and every reduction has a fixed order)
     from paper_2511_04025_amd import serving
     designs = wl.shell_128_designs(n=48, count=8)
-    kw = dict(precision="mixed", rtol=1e-5, solver="mg")
+    kw = dict(precision="mixed", rtol=3e-6, solver="mg")
     print("served engine 48^3: alone", flush=True)
     alone = {}
     for i, d in enumerate(designs):
@@ -301,7 +302,7 @@ def test_served_engine_vs_oracle_with_staggered_arrivals():
     for i, d in enumerate(designs):
         g = golden(f"shell_n48_seed{d.seed}.json")
         r = got[i]
-        assert r["status"] == 0 and np.all(r["rel_res"] <= 1e-5), (i, r["status"], r["rel_res"])
+        assert r["status"] == 0 and np.all(r["rel_res"] <= 3e-6), (i, r["status"], r["rel_res"])
         assert r["V"] == g["V"]
         rel, small, frob = assert_ch_close(r["C"], np.array(g["C"]), 1e-4)
         print(f"served 48^3 seed {d.seed}: iters {r['iters'].tolist()} vs oracle rel {rel:.2e} "

@@ -163,12 +163,15 @@ def test_auto_solver_serves_grids_the_multigrid_cannot_coarsen():
     from paper_2511_04025_amd import api
     odd = wl.random_design(350, 37, N=16, vf=0.15, E_void=1e-6)
     even = wl.random_design(351, 32, N=16, vf=0.15, E_void=1e-6)
-    e = engine(1 << 30, slots=4, solver="auto", rtol=1e-5)
-    res, peak = run_all(e, [odd, even], iters=4)
+    e = engine(1 << 30, slots=4, solver="auto", rtol=3e-6)
+    res, peak = run_all(e, [odd, even], iters=16)
     e.close()
     assert peak == 2
-    rj = api.homogenize(odd, precision="mixed", rtol=1e-5, solver="jacobi")
-    rm = api.homogenize(even, precision="mixed", rtol=1e-5, solver="mg")
+    rj = api.homogenize(odd, precision="mixed", rtol=3e-6, solver="jacobi")
+    rm = api.homogenize(even, precision="mixed", rtol=3e-6, solver="mg")
     assert res[0]["status"] == 0 and res[1]["status"] == 0
-    assert np.array_equal(res[0]["C"], rj["C"]) and np.array_equal(res[1]["C"], rm["C"])
+    print("auto: jacobi max diff", np.abs(res[0]["C"] - rj["C"]).max(), "mg max diff",
+          np.abs(res[1]["C"] - rm["C"]).max(), flush=True)
+    assert np.array_equal(res[1]["C"], rm["C"])
+    assert np.array_equal(res[0]["C"], rj["C"])
     assert res[0]["iters"].max() > 4 * res[1]["iters"].max()
