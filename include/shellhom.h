@@ -53,6 +53,8 @@ extern "C" {
 #define SHH_UNSUPPORTED         (-5) /* e.g. gradient of the hard step (kappa = 0)       */
 #define SHH_BREAKDOWN           (-6) /* CG breakdown: p^T K p <= 0 or NaN                */
 #define SHH_NOT_FOUND           (-7) /* engine: unknown request id                       */
+#define SHH_SCRATCH_TOO_SMALL   (-8) /* shh_homogenize_noalloc: the design's workspace
+                                        exceeds SHH_NOALLOC_SCRATCH_BYTES                */
 
 #define SHH_PREC_FP64  0  /* FP64 stencil, vectors, dots and reductions                 */
 #define SHH_PREC_MIXED 1  /* FP32 stencil and CG vectors; FP64 dots, residual
@@ -130,6 +132,24 @@ int32_t shh_workspace_bytes(const shh_design *design, const shh_opts *opts, size
    Returns SHH_OK, SHH_NOT_CONVERGED, or an error. */
 int32_t shh_homogenize(const shh_design *design, const shh_opts *opts,
                        void *d_ws, size_t ws_bytes, void *hip_stream, shh_result *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the path of
+   shh_homogenize with the library's own fixed workspace, a device array of
+   SHH_NOALLOC_SCRATCH_BYTES bytes that each GPU the library runs on holds
+   until the process ends (its address is resolved on the first call on a
+   device).  The call allocates nothing and creates no HIP events, so
+   out->ms[] is zero.  Designs whose shh_workspace_bytes exceeds the scratch
+   return SHH_SCRATCH_TOO_SMALL before any work.  Every call on one GPU
+   shares that GPU's array and overwrites what the previous call left there
+   (the call initializes every part it reads): calls that overlap on one GPU
+   -- two host threads, or two streams -- race and must be serialized by the
+   caller.  save_for_backward is accepted, but a later call overwrites the
+   saved state; shh_grad needs a caller-owned workspace.  Results equal
+   shh_homogenize's for the same design and options. */
+#define SHH_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int32_t shh_homogenize_noalloc(const shh_design *design, const shh_opts *opts, void *hip_stream,
+                               shh_result *out);
 
 /* The same path for `count` designs at once: every phase is one batched launch
    over all designs (different n and charge counts allowed).  d_ws[i] and

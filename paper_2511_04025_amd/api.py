@@ -72,6 +72,20 @@ def homogenize(design, precision="mixed", rtol=None, max_iter=20000, recompute_e
     return out
 
 
+def homogenize_noalloc(design, precision="mixed", rtol=None, max_iter=20000, recompute_every=0,
+                       check_every=0, solver="jacobi"):
+    """shh_homogenize_noalloc: the path on the library's fixed device scratch
+    (no workspace, no device allocation by the call); same result dict as
+    homogenize (ms all zero).  Raises for designs larger than the scratch."""
+    _require_gpu()
+    opts = B.make_opts(precision, rtol, max_iter, recompute_every, False, check_every, solver)
+    a = B.DesignArgs(design)
+    res = B.ShhResult()
+    B.check(B.lib().shh_homogenize_noalloc(byref(a.c), byref(opts), _stream(), byref(res)),
+            "shh_homogenize_noalloc")
+    return B.result_dict(res)
+
+
 def homogenize_batch(designs, precision="mixed", rtol=None, max_iter=20000, recompute_every=0,
                      save_for_backward=False, check_every=0, workspaces=None, return_workspaces=False,
                      solver="jacobi"):

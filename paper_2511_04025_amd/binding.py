@@ -26,6 +26,8 @@ SHH_OVER_BUDGET = -4
 SHH_UNSUPPORTED = -5
 SHH_BREAKDOWN = -6
 SHH_NOT_FOUND = -7
+SHH_SCRATCH_TOO_SMALL = -8
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 PREC_FP64 = 0
 PREC_MIXED = 1
@@ -63,6 +65,7 @@ EXPORTS = {
     "shh_workspace_bytes": (c_int32, [POINTER(ShhDesign), POINTER(ShhOpts), POINTER(c_size_t)]),
     "shh_homogenize": (c_int32, [POINTER(ShhDesign), POINTER(ShhOpts), c_void_p, c_size_t, c_void_p,
                                  POINTER(ShhResult)]),
+    "shh_homogenize_noalloc": (c_int32, [POINTER(ShhDesign), POINTER(ShhOpts), c_void_p, POINTER(ShhResult)]),
     "shh_homogenize_batch": (c_int32, [POINTER(ShhDesign), c_int32, POINTER(ShhOpts), POINTER(c_void_p),
                                        POINTER(c_size_t), c_void_p, POINTER(ShhResult)]),
     "shh_workspace_bytes_stiffness": (c_int32, [c_int32, POINTER(ShhOpts), POINTER(c_size_t)]),

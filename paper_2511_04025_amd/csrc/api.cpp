@@ -120,6 +120,8 @@ const char *shh_strerror(int32_t code) {
     case SHH_UNSUPPORTED: return "unsupported (hard-step gradient, or a grid the multigrid solver cannot coarsen)";
     case SHH_BREAKDOWN: return "CG breakdown (p^T K p <= 0 or NaN)";
     case SHH_NOT_FOUND: return "unknown request id";
+    case SHH_SCRATCH_TOO_SMALL:
+      return "design needs more workspace than the fixed device scratch of shh_homogenize_noalloc";
     default: return "unknown status";
   }
 }
@@ -134,9 +136,14 @@ int32_t shh_workspace_bytes(const shh_design *design, const shh_opts *opts, size
   return SHH_OK;
 }
 
-int32_t shh_homogenize_batch(const shh_design *designs, int32_t count, const shh_opts *opts,
-                             void *const *d_ws, const size_t *ws_bytes, void *hip_stream,
-                             shh_result *out) {
+}  // extern "C"
+
+namespace {
+
+// The path for `count` designs; `timed` false creates no HIP events (result
+// timings stay zero), which keeps the no-allocation entry point free of them.
+int homogenize_run(const shh_design *designs, int32_t count, const shh_opts *opts, void *const *d_ws,
+                   const size_t *ws_bytes, void *hip_stream, shh_result *out, bool timed) {
   if (count < 1 || count > MAX_BATCH || !designs || !d_ws || !ws_bytes || !out) return SHH_INVALID_ARG;
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
@@ -148,14 +155,15 @@ int32_t shh_homogenize_batch(const shh_design *designs, int32_t count, const shh
   for (int i = 0; i < count; ++i) {
     slots.emplace_back(new Slot());
     SHH_TRY(prepare_slot(*slots.back(), &designs[i], &o, d_ws[i], ws_bytes[i], i == 0 ? &seg_mem : nullptr));
-    evs.emplace_back(new Events(slots.back().get()));
+    if (timed) evs.emplace_back(new Events(slots.back().get()));
   }
   for (auto &s : slots) {
-    SHH_HIP(hipEventRecord(s->ev[0], st));
+    if (s->ev[0]) SHH_HIP(hipEventRecord(s->ev[0], st));
     SHH_TRY(slot_init(*s, s->base, st));
     SHH_TRY(slot_setup_field(*s, nullptr, st));
   }
   Solver sv(st);
+  sv.set_timing(timed);
   sv.set_segment_memory(seg_mem, seg_region());
   std::vector<Slot *> ptrs;
   for (auto &s : slots) ptrs.push_back(s.get());
@@ -170,9 +178,31 @@ int32_t shh_homogenize_batch(const shh_design *designs, int32_t count, const shh
   return worst;
 }
 
+}  // namespace
+
+extern "C" {
+
+int32_t shh_homogenize_batch(const shh_design *designs, int32_t count, const shh_opts *opts,
+                             void *const *d_ws, const size_t *ws_bytes, void *hip_stream,
+                             shh_result *out) {
+  return homogenize_run(designs, count, opts, d_ws, ws_bytes, hip_stream, out, true);
+}
+
 int32_t shh_homogenize(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
                        void *hip_stream, shh_result *out) {
   return shh_homogenize_batch(design, 1, opts, &d_ws, &ws_bytes, hip_stream, out);
+}
+
+int32_t shh_homogenize_noalloc(const shh_design *design, const shh_opts *opts, void *hip_stream,
+                               shh_result *out) {
+  if (!design || !out) return SHH_INVALID_ARG;
+  size_t need = 0;
+  SHH_TRY(shh_workspace_bytes(design, opts, &need));
+  if (need > SHH_NOALLOC_SCRATCH_BYTES) return SHH_SCRATCH_TOO_SMALL;
+  void *ws = nullptr;
+  SHH_TRY(noalloc_scratch(&ws));
+  const size_t cap = SHH_NOALLOC_SCRATCH_BYTES;
+  return homogenize_run(design, 1, opts, &ws, &cap, hip_stream, out, false);
 }
 
 int32_t shh_field(const shh_design *design, void *d_ws, size_t ws_bytes, double *d_F, double *d_G,

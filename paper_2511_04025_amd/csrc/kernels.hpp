@@ -46,4 +46,7 @@ hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, int K, const do
                           double *d_scratch, double *d_out, double *d_alpha_out, double *d_t_out,
                           hipStream_t st);
 
+// device address of the current device's shh_homogenize_noalloc scratch
+int noalloc_scratch(void **out);
+
 }  // namespace shh

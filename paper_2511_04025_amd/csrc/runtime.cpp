@@ -418,10 +418,10 @@ int Solver::start(const std::vector<Slot *> &in, std::vector<Slot *> *failed) {
   if (slots.empty()) return SHH_OK;
   if ((rc = build(K_ZERO, slots, 0, true, la))) return rc;
   SHH_HIP(launch_zero_vectors(la, prec, st_));
-  for (Slot *s : slots) SHH_HIP(hipEventRecord(s->ev[1], st_));
+  for (Slot *s : slots) if (s->ev[1]) SHH_HIP(hipEventRecord(s->ev[1], st_));
   if ((rc = residual(slots, RES_INIT))) return rc;
   for (Slot *s : slots) {
-    SHH_HIP(hipEventRecord(s->ev[2], st_));
+    if (s->ev[2]) SHH_HIP(hipEventRecord(s->ev[2], st_));
     for (int r = 0; r < NRHS; ++r) s->state.active[r] = 1;  // refreshed at the next read-back
     s->launched = 0;
   }
@@ -520,7 +520,7 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
 
 int Solver::timed_begin(hipEvent_t *e0) {
   *e0 = nullptr;
-  if (!profile_on()) return SHH_OK;
+  if (!timing_ || !profile_on()) return SHH_OK;
   *e0 = get_event();
   if (*e0) SHH_HIP(hipEventRecord(*e0, st_));
   return SHH_OK;
@@ -573,7 +573,7 @@ int Solver::poll(const std::vector<Slot *> &slots, std::vector<Slot *> &done) {
   for (Slot *s : slots)
     if (!s->finished && all_inactive(s->state)) cand.push_back(s);
   if (cand.empty()) return SHH_OK;
-  for (Slot *s : cand) SHH_HIP(hipEventRecord(s->ev[3], st_));
+  for (Slot *s : cand) if (s->ev[3]) SHH_HIP(hipEventRecord(s->ev[3], st_));
   if ((rc = final_check(cand))) return rc;
   std::vector<Slot *> fin;
   for (Slot *s : cand) {
@@ -590,7 +590,7 @@ int Solver::poll(const std::vector<Slot *> &slots, std::vector<Slot *> &done) {
   }
   for (Slot *s : fin) {
     SHH_HIP(launch_energy(s->d_slot, s->host.nn, st_));
-    SHH_HIP(hipEventRecord(s->ev[4], st_));
+    if (s->ev[4]) SHH_HIP(hipEventRecord(s->ev[4], st_));
   }
   if (!fin.empty()) {
     if ((rc = read_states(fin))) return rc;

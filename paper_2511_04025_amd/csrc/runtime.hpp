@@ -118,8 +118,12 @@ class Solver {
   // on (kind: SHH_PROF_*); resolved at the next synchronization
   int timed_begin(hipEvent_t *e0);
   int timed_end(hipEvent_t e0, int kind);
+  // false: no HIP events are created for launch timing (the no-allocation
+  // entry point), whatever shh_profile_enable says
+  void set_timing(bool on) { timing_ = on; }
 
  private:
+  bool timing_ = true;
   enum Kind { K_STENCIL = 0, K_RESID, K_FINISH, K_FOLD, K_ZERO, K_SCAL_IT, K_SCAL_RES, K_MG_DIR, K_MG_RES,
               K_MG_STEP1, K_MG_POST, K_MG_LAST,
               K_NKIND };
