@@ -63,6 +63,13 @@ extern "C" {
 #define SHH_SOLVER_JACOBI 0  /* CG with the Jacobi preconditioner                        */
 #define SHH_SOLVER_MG     1  /* CG with a geometric multigrid V-cycle preconditioner     */
 #define SHH_SOLVER_AUTO   2  /* per design: MG where the grid coarsens, else Jacobi      */
+#define SHH_SOLVER_SELECTIVE 3 /* the selective solve of Sec. 4.2: voxels with beta <=
+                                 1e-3 are culled (no stiffness floor: an active voxel
+                                 carries E beta, E_void is ignored), unknowns only on
+                                 the active nodes, held as compact lists in ascending
+                                 packed-coordinate order; Jacobi-preconditioned CG on
+                                 them.  Any n.  Not served by the engine, no adjoint
+                                 (SHH_UNSUPPORTED)                                       */
 
 /* One design (Eq. (6)-(7) parameters and material). */
 typedef struct {
@@ -114,6 +121,8 @@ typedef struct {
   double rel_res[6];    /* final true relative residual per load case (FP64)             */
   double ms[5];         /* wall time: field+threshold, rhs, solve, C^H, total            */
   int32_t status;       /* SHH_OK, SHH_NOT_CONVERGED or a negative code                  */
+  int32_t active_nodes; /* nodes carrying unknowns: n^3, or the active nodes of the
+                           selective solve                                               */
 } shh_result;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -177,6 +186,8 @@ int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const 
                      mixed-precision caller's own grid);
      SHH_EDTYPE_F64  n^3 doubles (the same as shh_homogenize_stiffness).
    For F32/F64, E and E_void are ignored and out->vol_frac is mean(E)/max(E).
+   With SHH_SOLVER_SELECTIVE a zero modulus culls the voxel (the U8 code's
+   zeros are culled, E_void ignored) and an all-zero grid gives C^H = 0.
    d_E: device array [n][n][n] (x fastest), caller-owned, read only.  Workspace
    from shh_workspace_bytes_stiffness.  SHH_INVALID_ARG for an unknown
    e_dtype, a grid with no positive modulus, or the conditions above. */

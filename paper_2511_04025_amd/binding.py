@@ -56,6 +56,7 @@ class ShhResult(ctypes.Structure):
     _fields_ = [
         ("CH", c_double * 36), ("vol_frac", c_double), ("t_used", c_double),
         ("iters", c_int32 * 6), ("rel_res", c_double * 6), ("ms", c_double * 5), ("status", c_int32),
+        ("active_nodes", c_int32),
     ]
 
 
@@ -154,7 +155,7 @@ class DesignArgs:
             E=float(design.E), nu=float(design.nu), E_void=float(design.E_void))
 
 
-SOLVER_JACOBI, SOLVER_MG, SOLVER_AUTO = 0, 1, 2
+SOLVER_JACOBI, SOLVER_MG, SOLVER_AUTO, SOLVER_SELECTIVE = 0, 1, 2, 3
 PROF_KINDS = ("cg_pass", "mg_dir", "mg_step1", "mg_res", "mg_post", "mg_last", "mg_update", "mg_restrict",
               "mg_prolong", "mg_apply1", "resid64")
 EDTYPE_U8, EDTYPE_F32, EDTYPE_F64 = 0, 1, 2
@@ -165,8 +166,9 @@ def make_opts(precision="mixed", rtol=None, max_iter=20000, recompute_every=0, s
     prec = PREC_MIXED if precision in ("mixed", PREC_MIXED) else PREC_FP64
     if rtol is None:
         rtol = 1e-6 if prec == PREC_MIXED else 1e-10
-    sv = {"mg": SOLVER_MG, "jacobi": SOLVER_JACOBI, "auto": SOLVER_AUTO}.get(solver, solver)
-    if sv not in (SOLVER_MG, SOLVER_JACOBI, SOLVER_AUTO):
+    sv = {"mg": SOLVER_MG, "jacobi": SOLVER_JACOBI, "auto": SOLVER_AUTO,
+          "selective": SOLVER_SELECTIVE}.get(solver, solver)
+    if sv not in (SOLVER_MG, SOLVER_JACOBI, SOLVER_AUTO, SOLVER_SELECTIVE):
         raise ValueError(f"unknown solver {solver!r}")
     return ShhOpts(precision=prec, rtol=float(rtol), max_iter=int(max_iter),
                    recompute_every=int(recompute_every), save_for_backward=int(bool(save_for_backward)),
@@ -182,4 +184,5 @@ def result_dict(r):
         "rel_res": np.array(r.rel_res[:], dtype=np.float64),
         "ms": {k: float(v) for k, v in zip(("field", "rhs", "solve", "C", "all"), r.ms[:])},
         "status": int(r.status),
+        "active_nodes": int(r.active_nodes),
     }

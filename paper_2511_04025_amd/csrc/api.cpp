@@ -161,6 +161,17 @@ int homogenize_run(const shh_design *designs, int32_t count, const shh_opts *opt
     if (s->ev[0]) SHH_HIP(hipEventRecord(s->ev[0], st));
     SHH_TRY(slot_init(*s, s->base, st));
     SHH_TRY(slot_setup_field(*s, nullptr, st));
+    if (o.solver == SHH_SOLVER_SELECTIVE) SHH_TRY(sel_solve(*s, st));  // one design at a time
+  }
+  if (o.solver == SHH_SOLVER_SELECTIVE) {
+    int worst = SHH_OK;
+    for (int i = 0; i < count; ++i) {
+      fill_result(*slots[i], &out[i]);
+      const int s = slots[i]->status;
+      if (s < 0 && (worst >= 0 || s < worst)) worst = s;
+      else if (s > 0 && worst == SHH_OK) worst = s;
+    }
+    return worst;
   }
   Solver sv(st);
   sv.set_timing(timed);
@@ -284,11 +295,14 @@ static int moduli_slot(Slot &s, int32_t n, const void *d_E, double nu, const shh
   const shh_design d = stiffness_design(n, nu);
   SHH_TRY(prepare_slot(s, &d, &oo, d_ws, ws_bytes, seg_mem, vectors));
   SHH_TRY(slot_init(s, s.base, st));
-  SHH_TRY(slot_setup_moduli(s, d_E, e_dtype, Es, Ev, st));
+  // a culled voxel of the selective solve carries nothing, whatever E_void says
+  SHH_TRY(slot_setup_moduli(s, d_E, e_dtype, Es, oo.solver == SHH_SOLVER_SELECTIVE ? 0.0 : Ev, st));
   SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
   SHH_HIP(hipStreamSynchronize(st));
   const double emax = s.state.Emax;
-  if (!(emax > 0.0) || !std::isfinite(emax)) return SHH_INVALID_ARG;
+  // the selective solve culls zero moduli; an all-zero grid is an empty cell
+  const bool sel = oo.solver == SHH_SOLVER_SELECTIVE;
+  if (!std::isfinite(emax) || !(emax > 0.0 || (sel && emax == 0.0))) return SHH_INVALID_ARG;
   s.host.E = emax;
   s.host.ffloor = 1e-12 * emax * std::sqrt(3.0 * double(s.host.nn));
   SHH_HIP(hipMemcpyAsync(s.d_slot, &s.host, sizeof(SlotDev), hipMemcpyHostToDevice, st));
@@ -307,9 +321,13 @@ int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const 
   Events ev(&s);
   SHH_HIP(hipEventRecord(s.ev[0], st));
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true));
-  Solver sv(st);
-  sv.set_segment_memory(seg_mem, seg_region());
-  SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
+  if (o.solver == SHH_SOLVER_SELECTIVE) {
+    SHH_TRY(sel_solve(s, st));
+  } else {
+    Solver sv(st);
+    sv.set_segment_memory(seg_mem, seg_region());
+    SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
+  }
   fill_result(s, out);
   return s.status;
 }
@@ -329,9 +347,13 @@ int32_t shh_homogenize_field(int32_t n, const void *d_E, int32_t e_dtype, double
   Events ev(&s);
   SHH_HIP(hipEventRecord(s.ev[0], st));
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true, e_dtype, E, E_void));
-  Solver sv(st);
-  sv.set_segment_memory(seg_mem, seg_region());
-  SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
+  if (o.solver == SHH_SOLVER_SELECTIVE) {
+    SHH_TRY(sel_solve(s, st));
+  } else {
+    Solver sv(st);
+    sv.set_segment_memory(seg_mem, seg_region());
+    SHH_TRY(solve_all(sv, {&s}, o.check_every, o.max_iter));
+  }
   fill_result(s, out);
   return s.status;
 }
@@ -456,7 +478,7 @@ int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, v
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   if (!dL_dCH || !std::isfinite(dL_dV)) return SHH_INVALID_ARG;
-  if (!(design->kappa > 0.0)) return SHH_UNSUPPORTED;
+  if (!(design->kappa > 0.0) || o.solver == SHH_SOLVER_SELECTIVE) return SHH_UNSUPPORTED;
   if (!o.save_for_backward) return SHH_INVALID_ARG;
   for (int i = 0; i < 36; ++i)
     if (!std::isfinite(dL_dCH[i])) return SHH_INVALID_ARG;
@@ -661,6 +683,7 @@ int32_t shh_engine_submit(shh_engine *eng, const shh_design *design, const shh_o
   SHH_TRY(normalize_opts(opts, &o));
   if (eng->prec >= 0 && o.precision != eng->prec) return SHH_INVALID_ARG;
   SHH_TRY(check_solver(design->n, &o));  // SHH_SOLVER_AUTO: multigrid or Jacobi for this grid
+  if (o.solver == SHH_SOLVER_SELECTIVE) return SHH_UNSUPPORTED;  // solved one design at a time
   size_t need = 0;
   SHH_TRY(shh_engine_footprint(design, &o, &need));
   if (need > eng->bytes - eng->header) return SHH_OVER_BUDGET;

@@ -111,6 +111,9 @@ struct SlotDev {
   double E, E_void, iso, kappa, t_given, target_vf;
   double rtol;
   double ffloor;        // ||f|| at or below this counts as a zero load
+  double cull;          // > 0: selective solve, voxels with beta <= cull carry no
+                        // stiffness and the others E beta (Sec. 4.2); 0: the
+                        // stiffness floor E_void + (E - E_void) beta
   int max_iter;
   int pad_;
   // element operator in the per-axis Walsh-Hadamard basis, already scaled by

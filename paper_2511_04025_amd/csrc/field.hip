@@ -272,12 +272,12 @@ __global__ __launch_bounds__(256) void occupancy_kernel(SlotDev *s, double *beta
   CgState *st = s->st;
   const double t = st->t, kappa = s->kappa, E = s->E, Ev = s->E_void;
   const long long nn = s->nn;
-  double v[1] = {0.0};
+  double v[1] = {0.0};  // V = mean beta over every voxel, culled or not
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
        i += (long long)nblocks * blockDim.x) {
     const double d = s->d[i];
     const double b = kappa == 0.0 ? (d < t ? 1.0 : 0.0) : logistic(kappa, t, d);
-    const double e = Ev + (E - Ev) * b;
+    const double e = s->cull > 0.0 ? (b > s->cull ? E * b : 0.0) : Ev + (E - Ev) * b;
     s->E64[i] = e;
     if (s->E32) s->E32[i] = (float)e;
     if (beta_out) beta_out[i] = b;

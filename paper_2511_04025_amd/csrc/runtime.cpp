@@ -2,6 +2,7 @@
 // batched PCG driver shared by the single-design entry points, the batch
 // entry points and the serving engine.
 #include "runtime.hpp"
+#include "sel.hpp"
 
 #include <algorithm>
 #include <atomic>
@@ -90,7 +91,8 @@ int normalize_opts(const shh_opts *in, shh_opts *out) {
   if (out->precision != SHH_PREC_FP64 && out->precision != SHH_PREC_MIXED) return SHH_INVALID_ARG;
   if (!(out->rtol > 0.0 && out->rtol < 1.0)) return SHH_INVALID_ARG;
   if (out->max_iter < 0 || out->recompute_every < 0 || out->check_every < 0) return SHH_INVALID_ARG;
-  if (out->solver != SHH_SOLVER_JACOBI && out->solver != SHH_SOLVER_MG && out->solver != SHH_SOLVER_AUTO)
+  if (out->solver != SHH_SOLVER_JACOBI && out->solver != SHH_SOLVER_MG && out->solver != SHH_SOLVER_AUTO &&
+      out->solver != SHH_SOLVER_SELECTIVE)
     return SHH_INVALID_ARG;
   if (out->recompute_every == 0 && out->precision == SHH_PREC_MIXED) out->recompute_every = 50;
   if (out->check_every == 0) out->check_every = 16;
@@ -223,6 +225,7 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.rtol = s.opts.rtol;
   h.max_iter = s.opts.max_iter;
   h.ffloor = 1e-12 * d.E * std::sqrt(3.0 * double(h.nn));
+  h.cull = s.opts.solver == SHH_SOLVER_SELECTIVE ? SEL_EPS : 0.0;
   element_operator(d.nu, h.kop64);
   for (int i = 0; i < KOP_N; ++i) h.kop32[i] = (float)h.kop64[i];
   h.charges = (double *)(base + L.charges);
@@ -625,6 +628,7 @@ void fill_result(const Slot &s, shh_result *out) {
   }
   for (int i = 0; i < 5; ++i) out->ms[i] = s.ms[i];
   out->status = s.status;
+  out->active_nodes = s.opts.solver == SHH_SOLVER_SELECTIVE ? s.sel_active_nodes : int32_t(s.host.nn);
 }
 
 }  // namespace shh

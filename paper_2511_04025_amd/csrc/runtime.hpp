@@ -55,6 +55,7 @@ struct Slot {
   MgDev mg;                     // host image of the level descriptors
   MgDev *d_mg = nullptr;
   bool mg_restart = false;      // next iteration starts from z = V r, p = z
+  int sel_active_nodes = 0;     // selective solve: active nodes
 };
 
 int validate_design(const shh_design *d);
@@ -157,6 +158,9 @@ int profile_read(int kind, long long *launches, double *ms);
 void profile_add(int kind, double ms);
 
 double now_ms();
+// the selective solve of one slot whose culled moduli are in place (field
+// setup or given moduli): compaction, CG on the active nodes, C^H
+int sel_solve(Slot &s, hipStream_t st);
 void fill_result(const Slot &s, shh_result *out);
 
 }  // namespace shh

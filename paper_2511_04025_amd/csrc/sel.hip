@@ -1,0 +1,772 @@
+// Kernels of the selective (active-set) solve: compaction of the active nodes,
+// the node-centric operator on the compact lists, and the CG vector and scalar
+// phases.  See sel.hpp for the layout and the operator's construction.
+#include "sel.hpp"
+
+namespace shh {
+
+namespace {
+
+__device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ int wrap_inc(int v, int n) { return v + 1 == n ? 0 : v + 1; }
+
+// node (x, y, z) is active if one of the eight voxels it is a corner of --
+// lower corners (x - ax, y - ay, z - az) -- carries stiffness
+__device__ __forceinline__ bool node_active(const double *E, int n, int x, int y, int z) {
+  const int xm = wrap_dec(x, n), ym = wrap_dec(y, n), zm = wrap_dec(z, n);
+  const long long n2 = (long long)n * n;
+  const long long z0 = (long long)z * n2, z1 = (long long)zm * n2;
+  const long long y0 = (long long)y * n, y1 = (long long)ym * n;
+  return E[z0 + y0 + x] > 0.0 || E[z0 + y0 + xm] > 0.0 || E[z0 + y1 + x] > 0.0 || E[z0 + y1 + xm] > 0.0 ||
+         E[z1 + y0 + x] > 0.0 || E[z1 + y0 + xm] > 0.0 || E[z1 + y1 + x] > 0.0 || E[z1 + y1 + xm] > 0.0;
+}
+
+// exclusive prefix sum over the 256 threads of a workgroup
+__device__ __forceinline__ int block_exclusive_scan(int v, int *s, int *total) {
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < SEL_THREADS; off <<= 1) {
+    const int add = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  const int incl = s[t];
+  if (total) *total = s[SEL_THREADS - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+}  // namespace
+
+// ---- compaction ---------------------------------------------------------------
+// Chunk b covers grid nodes [b * 1024, (b + 1) * 1024), four consecutive nodes
+// per thread; nodes keep their linear (z, y, x) order.
+__global__ __launch_bounds__(SEL_THREADS) void sel_count_kernel(SelDev *S) {
+  __shared__ int s[SEL_THREADS];
+  const int n = S->n;
+  const long long nn = S->nn;
+  int cnt = 0;
+  const long long base = (long long)blockIdx.x * SEL_CHUNK + 4 * threadIdx.x;
+  for (int j = 0; j < 4; ++j) {
+    const long long i = base + j;
+    if (i < nn) {
+      const int x = int(i % n), y = int((i / n) % n), z = int(i / ((long long)n * n));
+      cnt += node_active(S->E64, n, x, y, z) ? 1 : 0;
+    }
+  }
+  int total;
+  block_exclusive_scan(cnt, s, &total);
+  if (threadIdx.x == 0) S->counts[blockIdx.x] = total;
+}
+
+// exclusive offsets of the chunk counts (one workgroup of 1024 threads, each
+// summing a contiguous run); counts[nchunks] receives the total
+__global__ __launch_bounds__(1024) void sel_scan_kernel(SelDev *S) {
+  __shared__ long long s[1024];
+  const int nc = S->nchunks;
+  const int per = (nc + 1023) / 1024;
+  const int lo = threadIdx.x * per, hi = min(lo + per, nc);
+  long long sum = 0;
+  for (int b = lo; b < hi; ++b) sum += S->counts[b];
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const long long add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  long long run = s[threadIdx.x] - sum;
+  for (int b = lo; b < hi; ++b) {
+    const int c = S->counts[b];
+    S->counts[b] = int(run);
+    run += c;
+  }
+  if (threadIdx.x == 1023) S->counts[nc] = int(s[1023]);
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void sel_write_kernel(SelDev *S) {
+  __shared__ int s[SEL_THREADS];
+  const int n = S->n;
+  const long long nn = S->nn;
+  const long long base = (long long)blockIdx.x * SEL_CHUNK + 4 * threadIdx.x;
+  bool act[4];
+  int cnt = 0;
+  for (int j = 0; j < 4; ++j) {
+    const long long i = base + j;
+    act[j] = false;
+    if (i < nn) {
+      const int x = int(i % n), y = int((i / n) % n), z = int(i / ((long long)n * n));
+      act[j] = node_active(S->E64, n, x, y, z);
+    }
+    cnt += act[j] ? 1 : 0;
+  }
+  int idx = S->counts[blockIdx.x] + block_exclusive_scan(cnt, s, nullptr);
+  for (int j = 0; j < 4; ++j) {
+    const long long i = base + j;
+    if (i >= nn) break;
+    if (act[j]) {
+      const int x = int(i % n), y = int((i / n) % n), z = int(i / ((long long)n * n));
+      S->map[i] = idx;
+      S->coord[idx] = ((unsigned)z << 20) | ((unsigned)y << 10) | (unsigned)x;
+      ++idx;
+    } else {
+      S->map[i] = -1;
+    }
+  }
+}
+
+// moduli and Jacobi diagonal on the compact list
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_gather_kernel(SelDev *S) {
+  const int n = S->n, na = S->na;
+  const double c = (S->lam + 4.0 * S->mu) / 9.0;
+  const double *E = S->E64;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    const unsigned cd = S->coord[i];
+    const int x = int(cd & 1023u), y = int((cd >> 10) & 1023u), z = int(cd >> 20);
+    const int xm = wrap_dec(x, n), ym = wrap_dec(y, n), zm = wrap_dec(z, n);
+    auto at = [&](int a, int b, int cc) { return E[((long long)cc * n + b) * n + a]; };
+    const double e = at(x, y, z);
+    const double sum = ((e + at(xm, y, z)) + (at(x, ym, z) + at(xm, ym, z))) +
+                       ((at(x, y, zm) + at(xm, y, zm)) + (at(x, ym, zm) + at(xm, ym, zm)));
+    ((T *)S->Ec)[i] = (T)e;
+    S->Ec64[i] = e;
+    ((T *)S->Dinv)[i] = (T)(1.0 / (c * sum));
+  }
+}
+
+// ---- the node-centric operator ------------------------------------------------
+// Block A(r) of the row of node i for the neighbour at offset r, from the
+// moduli E[a] of the eight elements around i (element with lower corner i - a,
+// a = ax + 2 ay + 4 az).  Element a contains both nodes when a_d = 0 for
+// r_d = +1, a_d = 1 for r_d = -1 (either for r_d = 0).  The integrals of the
+// trilinear shape functions give, per axis, 1/3 (same corner) or 1/6 (other
+// corner) for the mass factor, +1 / -1 for the stiffness factor, and +-1/2
+// for the mixed factor, whose sign is -1 at corner 0 and +1 at corner 1.
+// Hence:
+//   A_cc  = [(lam + mu) T_c + mu (T_x + T_y + T_z)] * sum_shared E
+//   A_cc' = (1/4) M_d * { -(lam + mu) r_c r_c' sumE       both axes move
+//                         (lam - mu) r_c' D_c              c free, c' moves
+//                         (mu - lam) r_c D_c'              c moves, c' free
+//                         (lam + mu) D_cc' }               both free
+// with T_c = S_c prod_{d != c} M_d, d the third axis, D_c the sum over the
+// shared elements of E times sigma_c (+1 where a_c = 1, -1 where a_c = 0).
+template <int RX, int RY, int RZ, typename TE>
+__device__ __forceinline__ TE shared_sum(const TE (&E)[8], int sx, int sy, int sz) {
+  // sx: weight mode on x for free axes: 0 sum, 1 sigma
+  TE acc = TE(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    if (RX == 1 && ax != 0) continue;
+    if (RX == -1 && ax != 1) continue;
+    if (RY == 1 && ay != 0) continue;
+    if (RY == -1 && ay != 1) continue;
+    if (RZ == 1 && az != 0) continue;
+    if (RZ == -1 && az != 1) continue;
+    int sg = 1;
+    if (RX == 0 && sx) sg *= ax ? 1 : -1;
+    if (RY == 0 && sy) sg *= ay ? 1 : -1;
+    if (RZ == 0 && sz) sg *= az ? 1 : -1;
+    acc = sg > 0 ? acc + E[a] : acc - E[a];
+  }
+  return acc;
+}
+
+template <int R>
+__device__ constexpr double mass1(void) { return R == 0 ? 1.0 / 3.0 : 1.0 / 6.0; }
+template <int R>
+__device__ constexpr double stiff1(void) { return R == 0 ? 1.0 : -1.0; }
+
+template <int RX, int RY, int RZ, typename TE>
+__device__ __forceinline__ void block_of(const TE (&E)[8], TE lam, TE mu, TE (&A)[3][3]) {
+  constexpr int r[3] = {RX, RY, RZ};
+  constexpr double M[3] = {mass1<RX>(), mass1<RY>(), mass1<RZ>()};
+  constexpr double Sd[3] = {stiff1<RX>(), stiff1<RY>(), stiff1<RZ>()};
+  constexpr double Tc[3] = {Sd[0] * M[1] * M[2], Sd[1] * M[0] * M[2], Sd[2] * M[0] * M[1]};
+  const TE sE = shared_sum<RX, RY, RZ>(E, 0, 0, 0);
+  const TE lpm = lam + mu, lmm = lam - mu;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    A[c][c] = (lpm * TE(Tc[c]) + mu * TE(Tc[0] + Tc[1] + Tc[2])) * sE;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int cp = 0; cp < 3; ++cp) {
+      if (c == cp) continue;
+      const int d = 3 - c - cp;
+      const TE q = TE(0.25 * M[d]);
+      TE v;
+      if (r[c] != 0 && r[cp] != 0) {
+        v = -q * TE(r[c] * r[cp]) * lpm * sE;
+      } else if (r[c] == 0 && r[cp] != 0) {
+        v = q * TE(r[cp]) * lmm * shared_sum<RX, RY, RZ>(E, c == 0, c == 1, c == 2);
+      } else if (r[c] != 0 && r[cp] == 0) {
+        v = -q * TE(r[c]) * lmm * shared_sum<RX, RY, RZ>(E, cp == 0, cp == 1, cp == 2);
+      } else {
+        v = q * lpm * shared_sum<RX, RY, RZ>(E, c == 0 || cp == 0, c == 1 || cp == 1, c == 2 || cp == 2);
+      }
+      A[c][cp] = v;
+    }
+  }
+}
+
+// q[k] += A(r) u_j[k] for the active load cases
+template <int RX, int RY, int RZ, typename TE, typename TV>
+__device__ __forceinline__ void accumulate(const TE (&E)[8], TE lam, TE mu, int j, const TV *u, int na,
+                                           const unsigned act, TE (&q)[NRHS][3]) {
+  if (j < 0) return;  // a culled neighbour shares no stiffness with the node
+  TE A[3][3];
+  block_of<RX, RY, RZ>(E, lam, mu, A);
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) {
+    if (!((act >> k) & 1u)) continue;
+    const TE u0 = (TE)u[(long long)(3 * k + 0) * na + j];
+    const TE u1 = (TE)u[(long long)(3 * k + 1) * na + j];
+    const TE u2 = (TE)u[(long long)(3 * k + 2) * na + j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[k][c] += A[c][0] * u0 + A[c][1] * u1 + A[c][2] * u2;
+  }
+}
+
+// K u at node i: the 27 offsets, unrolled at compile time
+template <typename TE, typename TV>
+__device__ __forceinline__ void apply_row(const TE (&E)[8], TE lam, TE mu, const int (&nb)[27], const TV *u,
+                                          int na, unsigned act, TE (&q)[NRHS][3]) {
+#define SEL_ACC(dx, dy, dz) accumulate<dx, dy, dz>(E, lam, mu, nb[((dz) + 1) * 9 + ((dy) + 1) * 3 + (dx) + 1], u, na, act, q)
+#define SEL_ROW(dy, dz) SEL_ACC(-1, dy, dz); SEL_ACC(0, dy, dz); SEL_ACC(1, dy, dz)
+#define SEL_PLANE(dz) SEL_ROW(-1, dz); SEL_ROW(0, dz); SEL_ROW(1, dz)
+  SEL_PLANE(-1);
+  SEL_PLANE(0);
+  SEL_PLANE(1);
+#undef SEL_PLANE
+#undef SEL_ROW
+#undef SEL_ACC
+}
+
+// neighbour indices (offset index (dz + 1) 9 + (dy + 1) 3 + dx + 1) and the
+// eight element moduli of node i
+template <typename TE>
+__device__ __forceinline__ void node_frame(const SelDev *S, int i, const TE *Ec, int (&nb)[27], TE (&E)[8]) {
+  const int n = S->n;
+  const unsigned cd = S->coord[i];
+  const int x = int(cd & 1023u), y = int((cd >> 10) & 1023u), z = int(cd >> 20);
+  const int xs[3] = {wrap_dec(x, n), x, wrap_inc(x, n)};
+  const int ys[3] = {wrap_dec(y, n), y, wrap_inc(y, n)};
+  const int zs[3] = {wrap_dec(z, n), z, wrap_inc(z, n)};
+  const int *map = S->map;
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const long long row = ((long long)zs[dz] * n + ys[dy]) * n;
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) nb[dz * 9 + dy * 3 + dx] = map[row + xs[dx]];
+    }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = a >> 2;
+    const int j = nb[(1 - az) * 9 + (1 - ay) * 3 + (1 - ax)];
+    E[a] = j >= 0 ? Ec[j] : TE(0);
+  }
+}
+
+// load cases a residual pass covers: replacement passes only the running ones,
+// the initial and final passes every load case with a nonzero load
+__device__ __forceinline__ unsigned resid_cases(const CgState *st, int rmode, double ffloor) {
+  unsigned m = 0;
+  for (int k = 0; k < NRHS; ++k) {
+    bool on;
+    if (rmode == 0) on = true;                                   // initial
+    else if (rmode == 1) on = st->active[k] != 0;                // replacement
+    else on = st->ff[k] > ffloor * ffloor;                       // final
+    if (on) m |= 1u << k;
+  }
+  return m;
+}
+
+// PCG: q = K p for the running load cases and the per-workgroup sums
+//   p.q, r.D^-1 r, q.D^-1 r, q.D^-1 q, r.r, q.r, q.q
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_pcg_kernel(SelDev *S) {
+  __shared__ double red[7 * 16];
+  const int na = S->na;
+  const CgState *st = S->st;
+  unsigned act = 0;
+  for (int k = 0; k < NRHS; ++k)
+    if (st->active[k]) act |= 1u << k;
+  if (!act) return;
+  const T lam = (T)S->lam, mu = (T)S->mu;
+  const T *P = (const T *)S->p, *Rv = (const T *)S->r, *Dv = (const T *)S->Dinv;
+  T *Q = (T *)S->q;
+  // one node per thread (the grid covers the list), so the sums below need
+  // no accumulators across nodes
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  T q[NRHS][3];
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) q[k][0] = q[k][1] = q[k][2] = T(0);
+  double dv = 0.0;
+  if (i < na) {
+    int nb[27];
+    T E[8];
+    node_frame<T>(S, i, (const T *)S->Ec, nb, E);
+    apply_row<T, T>(E, lam, mu, nb, P, na, act, q);
+    dv = (double)Dv[i];
+  }
+  double *parts = S->partials;
+  const int np = S->nparts;
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) {
+    if (!((act >> k) & 1u)) continue;
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < na) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long o = (long long)(3 * k + c) * na + i;
+        Q[o] = q[k][c];
+        const double qv = (double)q[k][c], pv = (double)P[o], rv = (double)Rv[o];
+        v[0] += pv * qv;
+        v[1] += rv * dv * rv;
+        v[2] += qv * dv * rv;
+        v[3] += qv * dv * qv;
+        v[4] += rv * rv;
+        v[5] += qv * rv;
+        v[6] += qv * qv;
+      }
+    }
+    block_sum<7>(v, red, SEL_THREADS);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int s = 0; s < 7; ++s) parts[((long long)k * np + blockIdx.x) * SEL_PS + s] = v[s];
+    }
+  }
+}
+
+// r = f - K u in FP64 (u = the FP64 solution), stored in the working
+// precision; per-workgroup component sums of r (for the mean removal).
+// f at node i is -sum_a E_a (K_0 chi^k)_a.
+template <typename TV>
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_resid_kernel(SelDev *S, int rmode) {
+  __shared__ double red[3 * 16];
+  const int na = S->na;
+  const unsigned act = resid_cases(S->st, rmode, S->ffloor);
+  if (!act) return;
+  const double lam = S->lam, mu = S->mu;
+  const double *U = S->x64;
+  TV *Rv = (TV *)S->r;
+  double acc[NRHS][3];
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    int nb[27];
+    double E[8];
+    node_frame<double>(S, i, S->Ec64, nb, E);
+    double q[NRHS][3];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) q[k][0] = q[k][1] = q[k][2] = 0.0;
+    apply_row<double, double>(E, lam, mu, nb, U, na, act, q);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+      if (!((act >> k) & 1u)) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double f = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) f -= E[a] * S->f0[k][a][c];
+        const double rv = f - q[k][c];
+        Rv[(long long)(3 * k + c) * na + i] = (TV)rv;
+        acc[k][c] += rv;
+      }
+    }
+  }
+  double *parts = S->partials;
+  const int np = S->nparts;
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) {
+    if (!((act >> k) & 1u)) continue;
+    double v[3] = {acc[k][0], acc[k][1], acc[k][2]};
+    block_sum<3>(v, red, SEL_THREADS);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) parts[((long long)k * np + blockIdx.x) * SEL_PS + c] = v[c];
+    }
+  }
+}
+
+// the energy form of Eq. (8) on the compact lists: with u^k at equilibrium,
+//   sum_e E_e (chi^i + u^i_e)^T K_0 (chi^j + u^j_e)
+//     = (sum_e E_e) D_ij - f^i . u^j - f^j . u^i + u^i . K u^j,
+// since chi^i^T K_0 chi^j = D_ij and f^i = -sum_e P_e^T E_e K_0 chi^i.
+// Per workgroup: the 21 sums S_ij (i <= j) and sum_e E_e.
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_energy_kernel(SelDev *S) {
+  __shared__ double red[22 * 16];
+  const int na = S->na;
+  const double lam = S->lam, mu = S->mu;
+  const double *U = S->x64;
+  double acc[22];
+#pragma unroll
+  for (int s = 0; s < 22; ++s) acc[s] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    int nb[27];
+    double E[8];
+    node_frame<double>(S, i, S->Ec64, nb, E);
+    double q[NRHS][3];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) q[k][0] = q[k][1] = q[k][2] = 0.0;
+    apply_row<double, double>(E, lam, mu, nb, U, na, 0x3Fu, q);
+    double u[NRHS][3], f[NRHS][3];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        u[k][c] = U[(long long)(3 * k + c) * na + i];
+        double fv = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) fv -= E[a] * S->f0[k][a][c];
+        f[k][c] = fv;
+      }
+    int s = 0;
+#pragma unroll
+    for (int a = 0; a < NRHS; ++a)
+#pragma unroll
+      for (int b = a; b < NRHS; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v += u[a][c] * q[b][c] - f[a][c] * u[b][c] - f[b][c] * u[a][c];
+        acc[s++] += v;
+      }
+    acc[21] += E[0];  // the element whose lower corner is node i
+  }
+  block_sum<22>(acc, red, SEL_THREADS);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < 22; ++s) S->partials[(long long)s * S->nparts + blockIdx.x] = acc[s];
+  }
+}
+
+// plain q = K p for every load case (operator parity tests)
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_apply_kernel(SelDev *S) {
+  const int na = S->na;
+  const T lam = (T)S->lam, mu = (T)S->mu;
+  const T *P = (const T *)S->p;
+  T *Q = (T *)S->q;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    int nb[27];
+    T E[8];
+    node_frame<T>(S, i, (const T *)S->Ec, nb, E);
+    T q[NRHS][3];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) q[k][0] = q[k][1] = q[k][2] = T(0);
+    apply_row<T, T>(E, lam, mu, nb, P, na, 0x3Fu, q);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Q[(long long)(3 * k + c) * na + i] = q[k][c];
+  }
+}
+
+// ---- vector phases ------------------------------------------------------------
+// x += alpha p, r -= alpha q, p = D^-1 r + beta p for the load cases the
+// scalar phase gave a step (alpha != 0)
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_update_kernel(SelDev *S) {
+  const int na = S->na;
+  const CgState *st = S->st;
+  T *X = (T *)S->x, *Rv = (T *)S->r, *P = (T *)S->p;
+  const T *Q = (const T *)S->q, *Dv = (const T *)S->Dinv;
+  for (int k = 0; k < NRHS; ++k) {
+    const double al = st->alpha[k];
+    if (al == 0.0) continue;
+    const T a = (T)al, b = (T)st->beta[k];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+      const T d = Dv[i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long o = (long long)(3 * k + c) * na + i;
+        const T pv = P[o];
+        const T rv = Rv[o] - a * Q[o];
+        X[o] += a * pv;
+        Rv[o] = rv;
+        P[o] = d * rv + b * pv;
+      }
+    }
+  }
+}
+
+// p = D^-1 r (start of the iteration) for every load case still running
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_dir0_kernel(SelDev *S) {
+  const int na = S->na;
+  const CgState *st = S->st;
+  T *P = (T *)S->p;
+  const T *Rv = (const T *)S->r, *Dv = (const T *)S->Dinv;
+  for (int k = 0; k < NRHS; ++k) {
+    if (!st->active[k]) continue;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long o = (long long)(3 * k + c) * na + i;
+        P[o] = Dv[i] * Rv[o];
+      }
+  }
+}
+
+// mixed: x64 += x32, x32 = 0 (every load case, or the running ones)
+__global__ __launch_bounds__(SEL_THREADS) void sel_fold_kernel(SelDev *S, int all) {
+  const int na = S->na;
+  const CgState *st = S->st;
+  float *X = (float *)S->x;
+  double *X64 = S->x64;
+  for (int k = 0; k < NRHS; ++k) {
+    if (!all && !st->active[k]) continue;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long o = (long long)(3 * k + c) * na + i;
+        X64[o] += (double)X[o];
+        X[o] = 0.0f;
+      }
+  }
+}
+
+// the recomputed residual: remove its component means (rigid translations of
+// the whole active set), then the sums r.D^-1 r and r.r
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_finish_kernel(SelDev *S, int rmode) {
+  __shared__ double red[2 * 16];
+  const int na = S->na;
+  const CgState *st = S->st;
+  const unsigned act = resid_cases(st, rmode, S->ffloor);
+  T *Rv = (T *)S->r;
+  const T *Dv = (const T *)S->Dinv;
+  for (int k = 0; k < NRHS; ++k) {
+    if (!((act >> k) & 1u)) continue;
+    const T m[3] = {(T)st->mean[k][0], (T)st->mean[k][1], (T)st->mean[k][2]};
+    double v[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+      const double d = (double)Dv[i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long o = (long long)(3 * k + c) * na + i;
+        const T rv = Rv[o] - m[c];
+        Rv[o] = rv;
+        const double r64 = (double)rv;
+        v[0] += r64 * d * r64;
+        v[1] += r64 * r64;
+      }
+    }
+    block_sum<2>(v, red, SEL_THREADS);
+    if (threadIdx.x == 0) {
+      S->partials[((long long)k * S->nparts + blockIdx.x) * SEL_PS + 0] = v[0];
+      S->partials[((long long)k * S->nparts + blockIdx.x) * SEL_PS + 1] = v[1];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_zero_kernel(SelDev *S) {
+  const long long m = (long long)NRHS * 3 * S->na;
+  T *X = (T *)S->x, *P = (T *)S->p;
+  double *X64 = S->x64;
+  const bool mixed = S->prec == SHH_PREC_MIXED;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (long long)gridDim.x * blockDim.x) {
+    X[i] = T(0);
+    P[i] = T(0);
+    if (mixed) X64[i] = 0.0;
+  }
+}
+
+// ---- scalar phases (one workgroup per load case; one in total for C^H) --------
+__global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(SelDev *S, int phase) {
+  __shared__ double red[22 * 16];
+  CgState *st = S->st;
+  const int np = S->nparts;
+  if (phase == SSC_ENERGY) {
+    double tot[22];
+    for (int s = 0; s < 22; ++s) tot[s] = 0.0;
+    for (int b = threadIdx.x; b < np; b += SEL_THREADS)
+      for (int s = 0; s < 22; ++s) tot[s] += S->partials[(long long)s * np + b];
+    block_sum<22>(tot, red, SEL_THREADS);
+    if (threadIdx.x != 0) return;
+    const double lam = S->lam, mu = S->mu, sumE = tot[21], inv = 1.0 / double(S->nn);
+    int s = 0;
+    for (int a = 0; a < NRHS; ++a)
+      for (int b = a; b < NRHS; ++b) {
+        double D = 0.0;
+        if (a < 3 && b < 3) D = a == b ? lam + 2.0 * mu : lam;
+        else if (a == b) D = mu;
+        const double c = (sumE * D + tot[s++]) * inv;
+        st->C[a * 6 + b] = c;
+        st->C[b * 6 + a] = c;
+      }
+    return;
+  }
+  const int k = blockIdx.x;
+  const double *parts = S->partials + (long long)k * np * SEL_PS;
+  if (phase == SSC_ITER) {
+    if (!st->active[k]) {
+      if (threadIdx.x == 0) st->alpha[k] = 0.0;
+      return;
+    }
+    double tot[7];
+    sum_partials<7, SEL_PS>(parts, np, tot, red, SEL_THREADS);
+    if (threadIdx.x != 0) return;
+    const double pq = tot[0], rho = tot[1], qzr = tot[2], qzq = tot[3], rr = tot[4], qr = tot[5], qq = tot[6];
+    if (!(pq > 0.0) || !(rho >= 0.0)) {  // breakdown (or NaN)
+      st->alpha[k] = 0.0;
+      st->active[k] = 0;
+      st->status[k] = ST_BREAKDOWN;
+      return;
+    }
+    const double a = rho / pq;
+    const double rho1 = rho - 2.0 * a * qzr + a * a * qzq;
+    const double rr1 = fmax(rr - 2.0 * a * qr + a * a * qq, 0.0);
+    st->alpha[k] = a;
+    st->beta[k] = rho > 0.0 ? rho1 / rho : 0.0;
+    st->rho[k] = rho1;
+    st->rr[k] = rr1;
+    st->iters[k] += 1;
+    const double rel = sqrt(rr1 / st->ff[k]);
+    st->rel[k] = rel;
+    if (rel <= S->rtol) {
+      st->active[k] = 0;
+      st->status[k] = ST_CONVERGED;
+    } else if (st->iters[k] >= S->max_iter) {
+      st->active[k] = 0;
+      st->status[k] = ST_MAXIT;
+    }
+    return;
+  }
+  // residual phases: rmode 0 initial, 1 replacement, 2 final
+  const int rmode = phase == SSC_RESID_INIT ? 0 : (phase == SSC_RESID_REPLACE ? 1 : 2);
+  if (phase == SSC_MEAN) return;  // launched through sel_launch_scalar_mean
+  const unsigned act = resid_cases(st, rmode, S->ffloor);
+  if (!((act >> k) & 1u)) return;
+  double tot[2];
+  sum_partials<2, SEL_PS>(parts, np, tot, red, SEL_THREADS);
+  if (threadIdx.x != 0) return;
+  const double rho = tot[0], rr = tot[1];
+  if (rmode == 0) {
+    st->ff[k] = rr;
+    st->rr[k] = rr;
+    st->rho[k] = rho;
+    st->alpha[k] = 0.0;
+    st->beta[k] = 0.0;
+    st->iters[k] = 0;
+    if (sqrt(rr) <= S->ffloor) {  // zero load: u = 0
+      st->active[k] = 0;
+      st->status[k] = ST_CONVERGED;
+      st->rel[k] = st->rel_true[k] = 0.0;
+    } else {
+      st->active[k] = S->max_iter > 0 ? 1 : 0;
+      st->status[k] = S->max_iter > 0 ? ST_RUNNING : ST_MAXIT;
+      st->rel[k] = st->rel_true[k] = 1.0;
+    }
+  } else if (rmode == 1) {
+    st->rr[k] = rr;
+    st->rel_true[k] = sqrt(rr / st->ff[k]);
+  } else {
+    st->rr[k] = rr;
+    const double rel = sqrt(rr / st->ff[k]);
+    st->rel_true[k] = rel;
+    if (rel <= S->rtol) {
+      st->active[k] = 0;
+      st->status[k] = ST_CONVERGED;
+    } else if (st->status[k] != ST_BREAKDOWN && st->iters[k] < S->max_iter) {
+      st->active[k] = 1;  // the recursive residual was optimistic: resume
+      st->status[k] = ST_RUNNING;
+    } else if (st->status[k] != ST_BREAKDOWN) {
+      st->active[k] = 0;
+      st->status[k] = ST_MAXIT;
+    }
+  }
+}
+
+// component means of the recomputed residual
+__global__ __launch_bounds__(SEL_THREADS) void sel_mean_kernel(SelDev *S, int rmode) {
+  __shared__ double red[3 * 16];
+  CgState *st = S->st;
+  const int k = blockIdx.x;
+  const unsigned act = resid_cases(st, rmode, S->ffloor);
+  if (!((act >> k) & 1u)) return;
+  double tot[3];
+  sum_partials<3, SEL_PS>(S->partials + (long long)k * S->nparts * SEL_PS, S->nparts, tot, red, SEL_THREADS);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) st->mean[k][c] = tot[c] / double(S->na);
+}
+
+// ---- launchers ----------------------------------------------------------------
+hipError_t sel_launch_compact(SelDev *d, const SelDev &h, hipStream_t st) {
+  sel_count_kernel<<<h.nchunks, SEL_THREADS, 0, st>>>(d);
+  sel_scan_kernel<<<1, 1024, 0, st>>>(d);
+  sel_write_kernel<<<h.nchunks, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_gather(SelDev *d, const SelDev &h, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_gather_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  else sel_gather_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_op(SelDev *d, const SelDev &h, int mode, hipStream_t st) {
+  const bool f64 = h.prec == SHH_PREC_FP64;
+  if (mode == SOP_PCG) {
+    if (f64) sel_op_pcg_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+    else sel_op_pcg_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  } else if (mode == SOP_ENERGY) {
+    sel_op_energy_kernel<<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  } else if (mode == SOP_APPLY) {
+    if (f64) sel_op_apply_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+    else sel_op_apply_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  } else {
+    // SOP_RESID + rmode: 10 + rmode
+    const int rmode = mode - 10;
+    if (f64) sel_op_resid_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
+    else sel_op_resid_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
+  }
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_scalar(SelDev *d, int phase, hipStream_t st) {
+  if (phase == SSC_ENERGY) sel_scalar_kernel<<<1, SEL_THREADS, 0, st>>>(d, phase);
+  else if (phase >= 100) sel_mean_kernel<<<NRHS, SEL_THREADS, 0, st>>>(d, phase - 100);
+  else sel_scalar_kernel<<<NRHS, SEL_THREADS, 0, st>>>(d, phase);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_update(SelDev *d, const SelDev &h, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_update_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  else sel_update_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_dir0(SelDev *d, const SelDev &h, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_dir0_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  else sel_dir0_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_fold(SelDev *d, const SelDev &h, int all, hipStream_t st) {
+  if (h.prec == SHH_PREC_MIXED) sel_fold_kernel<<<h.nparts, SEL_THREADS, 0, st>>>(d, all);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_finish(SelDev *d, const SelDev &h, int rmode, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_finish_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
+  else sel_finish_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_zero(SelDev *d, const SelDev &h, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_zero_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  else sel_zero_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+}  // namespace shh

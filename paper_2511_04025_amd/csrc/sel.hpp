@@ -1,0 +1,77 @@
+// Selective (active-set) solve of Sec. 4.2 on compact node lists.
+//
+// Active voxels are those with beta_e > eps (eps = 1e-3, Sec. 4.2.3); an
+// active voxel carries K_e = E beta_e K_0, a culled one nothing.  The unknowns
+// live on the active nodes (vertices of at least one active voxel), numbered
+// in ascending (z, y, x) order -- the order of their packed 32-bit
+// coordinates (z << 20) | (y << 10) | x -- so that consecutive threads touch
+// consecutive nodes of one x-run.  A dense int32 map gives the compact index
+// of every grid node (-1 when culled); the element whose lower corner is a
+// node stores its modulus at that node's index (every active element's lower
+// corner is an active node).
+//
+// The operator is node-centric: row i of K is the 27-point stencil
+// sum_r A_i(r) u_{i+r}, whose 3 x 3 blocks are assembled in registers from the
+// eight moduli around the node.  With the trilinear element's 1D integrals,
+// every entry of A_i(r) is a constant (a function of r, lambda, mu) times a
+// signed sum of those moduli: per axis, a fixed element slice where r moves
+// along it, and either the sum or the difference of the two slices where it
+// does not.  The 64 such sums come from a three-stage transform.
+#pragma once
+
+#include "shellhom.h"
+#include "common.hpp"
+
+namespace shh {
+
+constexpr double SEL_EPS = 1e-3;   // active set: beta > eps (Sec. 4.2.3)
+constexpr int SEL_PS = 8;          // doubles per workgroup partial
+constexpr int SEL_THREADS = 256;
+constexpr int SEL_CHUNK = 1024;    // grid nodes per workgroup of the compaction scan
+
+// device descriptor of one selective solve
+struct SelDev {
+  int n;
+  int na;                 // active nodes
+  int nparts;             // workgroups of the compact kernels
+  int prec;               // SHH_PREC_FP64 / SHH_PREC_MIXED
+  int nchunks;            // compaction chunks
+  int pad_;
+  long long nn;           // n^3
+  double lam, mu;         // Lame parameters at E = 1
+  double rtol, ffloor;
+  int max_iter;
+  int pad2_;
+  // f0[k][a][c]: component c at corner a of K_0 chi^k (E = 1), the element
+  // force of unit strain k; a node's load is -sum_a E_a f0[k][a]
+  double f0[NRHS][8][3];
+  const double *E64;      // dense culled moduli [n^3] (input of the compaction)
+  int *map;               // [n^3] compact index or -1
+  unsigned *coord;        // [na] packed coordinates, ascending
+  int *counts;            // [nchunks + 1] active nodes per chunk, then exclusive offsets; [nchunks] = na
+  void *Ec;               // [na] moduli in the working precision
+  double *Ec64;           // [na] FP64 moduli (== Ec for the FP64 path)
+  void *Dinv;             // [na] inverse Jacobi diagonal (same for the 3 components)
+  void *r, *p, *q, *x;    // [6][3][na] working precision
+  double *x64;            // [6][3][na] FP64 solution accumulator (mixed); == x for FP64
+  double *partials;       // [6][nparts][SEL_PS]
+  CgState *st;
+};
+
+// operator pass flavours
+enum { SOP_PCG = 0, SOP_RESID = 1, SOP_ENERGY = 2, SOP_APPLY = 3 };
+// scalar phases
+enum { SSC_ITER = 0, SSC_MEAN = 1, SSC_RESID_INIT = 2, SSC_RESID_REPLACE = 3, SSC_RESID_FINAL = 4,
+       SSC_ENERGY = 5 };
+
+hipError_t sel_launch_compact(SelDev *d, const SelDev &h, hipStream_t st);   // map, coord, counts (na)
+hipError_t sel_launch_gather(SelDev *d, const SelDev &h, hipStream_t st);    // Ec, Ec64, Dinv
+hipError_t sel_launch_op(SelDev *d, const SelDev &h, int mode, hipStream_t st);
+hipError_t sel_launch_scalar(SelDev *d, int phase, hipStream_t st);
+hipError_t sel_launch_update(SelDev *d, const SelDev &h, hipStream_t st);     // x, r, p after alpha, beta
+hipError_t sel_launch_dir0(SelDev *d, const SelDev &h, hipStream_t st);       // p = D^-1 r
+hipError_t sel_launch_fold(SelDev *d, const SelDev &h, int all, hipStream_t st);  // x64 += x32, x32 = 0
+hipError_t sel_launch_finish(SelDev *d, const SelDev &h, int rmode, hipStream_t st);  // r -= mean; rho, rr partials
+hipError_t sel_launch_zero(SelDev *d, const SelDev &h, hipStream_t st);       // x, x64, p = 0
+
+}  // namespace shh

@@ -1,7 +1,7 @@
 """Write the stored expected values under tests/golden/ by running the FP64
 oracle (and nothing else) on the seeded workloads.
 
-    python tests/golden/make_golden.py [small] [shell48] [smooth] [--procs 8]
+    python tests/golden/make_golden.py [small] [shell48] [smooth] [sel] [--procs 8]
 
 small: 24^3, 16 charges of +-1, V = 0.12, void E 1e-3              -> small_shell_n24_seed1.json
 shell48: 48^3 versions of the 128^3 designs (seeds 2000-2007), void 1e-6 -> shell_n48_seed<s>.json
@@ -9,7 +9,11 @@ smooth: 24^3 logistic designs (seeds 5000, 5001), kappa = 4n, t from V = 0.10,
     void 1e-6, with the oracle's design gradients of two functionals of
     (C^H, V): the bulk/Poisson loss, and a fixed random linear functional
     -> smooth_shell_n24_seed<s>.json
-All solves: Jacobi-PCG to ||r|| <= 1e-12 ||f|| (node 0 pinned).
+sel: the selective (culled, Sec. 4.2) oracle on the 48^3 designs (seeds
+    2000-2003), on the 24^3 design of `small`, and on the 24^3 logistic design
+    5000 (voxels with beta <= 1e-3 culled) -> selective_n<n>_seed<s>.json
+All dense solves: Jacobi-PCG to ||r|| <= 1e-12 ||f|| (node 0 pinned); the
+selective ones: Jacobi-PCG on the active nodes to the same tolerance.
 """
 import json
 import os
@@ -24,6 +28,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 from oracle import adjoint as adj, fem, field as fld, homogenize as hom, metrics  # noqa: E402
+from oracle import selective as sel  # noqa: E402
 from paper_2511_04025_amd import workloads as wl  # noqa: E402
 
 
@@ -91,12 +96,33 @@ def run_smooth(seed):
     return f"smooth {seed}"
 
 
+def run_sel(key):
+    if key == "small":
+        d = wl.small_shell_24()
+        kw = dict(target_vf=d.target_vf)
+    elif key == "smooth":
+        d = wl.smooth_shell_96(5000, n=24)
+        F, G = fld.field_and_gradient(d.pos, d.q, 24)
+        kw = dict(thickness=fld.thickness_for_volume(fld.distance(F, G), 0.10, d.kappa), kappa=d.kappa)
+    else:
+        d = wl.shell_128(int(key), n=48)
+        kw = dict(target_vf=d.target_vf)
+    t0 = time.time()
+    C, info = sel.homogenize_design_selective(d.pos, d.q, d.n, rtol=1e-12, maxiter=400000, **kw)
+    _dump(os.path.join(HERE, f"selective_n{d.n}_seed{d.seed}.json"), {
+        "source": "oracle.selective, make_golden.py sel", "seed": d.seed, "n": d.n, "C": C.tolist(),
+        "V": info["V"], "t": info["t"], "kappa": d.kappa, "iters": info["iters"].tolist(),
+        "rel_res": info["rel_res"].tolist(), "active_voxels": info["n_active_voxels"],
+        "active_nodes": info["n_active_nodes"], "seconds": time.time() - t0})
+    return f"sel {key}"
+
+
 def main():
     args = sys.argv[1:]
     procs = 8
     if "--procs" in args:
         procs = int(args[args.index("--procs") + 1])
-    which = [a for a in args if a in ("small", "shell48", "smooth")] or ["small", "shell48", "smooth"]
+    which = [a for a in args if a in ("small", "shell48", "smooth", "sel")] or ["small", "shell48", "smooth", "sel"]
     jobs = []
     if "small" in which:
         jobs.append((run_small, 0))
@@ -104,6 +130,8 @@ def main():
         jobs += [(run_smooth, s) for s in (5000, 5001)]
     if "shell48" in which:
         jobs += [(run_shell48, 2000 + i) for i in range(8)]
+    if "sel" in which:
+        jobs += [(run_sel, k) for k in ("small", "smooth", "2000", "2001", "2002", "2003")]
     with Pool(procs) as pool:
         rs = [pool.apply_async(f, (a,)) for f, a in jobs]
         for r in rs:

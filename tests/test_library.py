@@ -192,10 +192,14 @@ def test_multigrid_solver_option(lib):
         rc_m, nm = ws_bytes(lib, d, "mixed", solver="mg")
         _, nj = ws_bytes(lib, d, "mixed", solver="jacobi")
         assert rc_a == B.SHH_OK and na == (nm if rc_m == B.SHH_OK else nj), n
-    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=3)
     a = B.DesignArgs(wl.small_shell_24())
     nb = c_size_t(0)
+    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=4)
     assert lib.shh_workspace_bytes(byref(a.c), byref(o), byref(nb)) == B.SHH_INVALID_ARG
+    # the selective solve works in the Jacobi path's workspace, at any n
+    for n in (24, 37):
+        d = wl.shell_128(2000, n=n)
+        assert ws_bytes(lib, d, "mixed", solver="selective") == ws_bytes(lib, d, "mixed", solver="jacobi")
 
 
 def test_field_entry_point_validation(lib):
