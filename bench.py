@@ -28,13 +28,18 @@ HBM_PEAK_GBS = 8000.0
 # copy kernel (shh_stream_copy) over 4 GiB, far above the 256 MB last-level
 # cache, timed with HIP events by `bench.py --copy-only`
 # (profiles/stream_copy_calibration.md).  Reported beside the 8 TB/s peak.
-COPY_CEILING_GBS = None
+COPY_CEILING_GBS = 4912.5  # best of five 4 GiB copies (mean 4891.5)
 
-# Measured HBM traffic of the dominant kernel relative to its algorithmic
-# bytes (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
-# reads for the 4 GiB stream copy), keyed by kernel family; it holds only for
+# Measured memory traffic of the dominant kernel relative to its algorithmic
+# bytes (rocprofv3 FETCH_SIZE x 2 and WRITE_SIZE x 1, the factors the 4 GiB
+# stream copy gives; profiles/mg_apply_128_hbm_traffic.md), keyed by kernel
+# family.  The counters count L2-to-fabric bytes, last-level-cache hits
+# included, so the figure bounds HBM traffic from above.  It holds only for
 # the kernel sources it was measured on (digest), null otherwise.
-TRAFFIC = {}
+TRAFFIC = {
+    "mg_apply1": {"ratio": 2.17, "sources": ["mg.hip", "mg.hpp", "common.hpp"],
+                  "sha256": "1597494ebd0f92ee8a14848bacbf99f707a88c964fcd55ad3d6ec7be32ee46cf"},
+}
 
 
 def traffic_ratio(kind):
@@ -70,15 +75,41 @@ def family_bytes(results, n, R, solver):
         coarse node + 24 B per (coarse node, load case)
       FP64 residual: 24 (x64) + 12 (r) per (node, load case) + 8 (E) per node,
         every R iterations and once at the end
-      Jacobi CG pass: 96 per (node, load case) + 8 per node"""
+      Jacobi CG pass: 96 per (node, load case) + 8 per node
+      selective solve, per (active node, running load case) and per active node:
+        Jacobi-preconditioned:
+        operator pass   36 (p, r read; q written) + 16 (coordinate, map entry,
+                        modulus, D^-1)
+        update          84 (x, p, r, q read; x, r, p written) + 4 (D^-1)
+        multigrid-preconditioned, per iteration:
+        q = K p         24 (p read, q written) + 12 (coordinate, map entry, modulus)
+        smoothing       216 over the four fused operator passes (60 + 36 + 60 + 60)
+                        + 64 (16 per pass)
+        vectors         120 (CG update with D^-1 r: 84; p = z + beta p: 36) + 4
+        transfers       36 per (active node, case) + 24 per (level-1 node, case)
+                        + 4 per voxel (map) + 4 per active node (coordinate)
+        FP64 residual   36 (x64 read, r written) + 20"""
     nn = n ** 3
     nn1 = nn // 8
     out = {k: 0.0 for k in ("cg_pass", "mg_dir", "mg_step1", "mg_res", "mg_post", "mg_last", "mg_update",
-                            "mg_restrict", "mg_prolong", "mg_apply1", "resid64")}
+                            "mg_restrict", "mg_prolong", "mg_apply1", "resid64", "sel_op", "sel_update",
+                            "sel_resid", "sel_mg_pq", "sel_mg_smooth", "sel_mg_vec", "sel_mg_transfer")}
     for r in results:
         it = [int(v) for v in r["iters"]]
         Ik, Im = sum(it), max(it)
         nres = [v // R + 1 for v in it]  # replacements, then the final check
+        if solver in ("selective", "selective-jacobi"):
+            na = float(r["active_nodes"])
+            out["sel_resid"] += 36.0 * na * (sum(nres) + 6) + 20.0 * na * (max(nres) + 1)
+            if solver == "selective-jacobi":
+                out["sel_op"] += 36.0 * na * Ik + 16.0 * na * Im
+                out["sel_update"] += 84.0 * na * Ik + 4.0 * na * Im
+            else:
+                out["sel_mg_pq"] += 24.0 * na * Ik + 12.0 * na * Im
+                out["sel_mg_smooth"] += 216.0 * na * Ik + 64.0 * na * Im
+                out["sel_mg_vec"] += 120.0 * na * Ik + 4.0 * na * Im
+                out["sel_mg_transfer"] += (36.0 * na + 24.0 * nn1) * Ik + (4.0 * nn + 4.0 * na) * Im
+            continue
         out["resid64"] += 36.0 * nn * sum(nres) + 8.0 * nn * max(nres)
         if solver == "jacobi":
             out["cg_pass"] += 96.0 * nn * Ik + 8.0 * nn * Im
@@ -108,8 +139,10 @@ def parse():
     # The run checks it on the FP64 subset.
     ap.add_argument("--rtol", type=float, default=None,
                     help="CG tolerance (default 3e-6)")
-    ap.add_argument("--solver", default="mg", choices=["mg", "jacobi"],
-                    help="CG preconditioner: geometric multigrid V-cycle or Jacobi")
+    ap.add_argument("--solver", default="mg", choices=["mg", "jacobi", "selective", "selective-jacobi"],
+                    help="CG preconditioner: geometric multigrid V-cycle or Jacobi; selective: the culled "
+                         "solve on the active nodes, one design at a time (multigrid-preconditioned, or "
+                         "Jacobi-preconditioned with selective-jacobi)")
     ap.add_argument("--fp64-designs", type=int, default=8, help="designs also run on the FP64 GPU path")
     ap.add_argument("--jacobi-designs", type=int, default=8,
                     help="with --solver mg: designs also run with the Jacobi-preconditioned CG (mixed)")
@@ -320,13 +353,32 @@ def main():
     designs = wl.shell_128_designs(n=args.n, count=args.designs)
     eng_opts = dict(precision="mixed", rtol=args.rtol, max_iter=args.max_iter, solver=args.solver,
                     recompute_every=args.recompute_every)
-    probe = serving.Engine(1 << 20, max_slots=1, **eng_opts)
-    fp = probe.footprint(designs[0])
-    probe.close()
-    del probe
-    engine = serving.Engine(fp * args.designs + (64 << 20), max_slots=args.designs, **eng_opts)
+    selective = args.solver in ("selective", "selective-jacobi")
+    engine = None
+    if not selective:
+        probe = serving.Engine(1 << 20, max_slots=1, **eng_opts)
+        fp = probe.footprint(designs[0])
+        probe.close()
+        del probe
+        engine = serving.Engine(fp * args.designs + (64 << 20), max_slots=args.designs, **eng_opts)
+
+    def one_step_selective():
+        # the selective solve runs one design after another inside one call;
+        # a design's latency is the time until its own result is complete
+        t0 = time.perf_counter()
+        res = api.homogenize_batch(designs, **eng_opts)
+        done, lat = 0.0, []
+        for r in res:
+            done += r["ms"]["all"] / 1e3
+            lat.append(done)
+        wall = time.perf_counter() - t0
+        print(f"bench: selective step {wall:.2f} s, iters {[int(r['iters'].max()) for r in res]}", file=sys.stderr,
+              flush=True)
+        return res, lat
 
     def one_step():
+        if selective:
+            return one_step_selective()
         t0 = time.perf_counter()
         for i, d in enumerate(designs):
             engine.submit(d, i)
@@ -367,7 +419,7 @@ def main():
 
     # per-family roofline: algorithmic bytes implied by the iteration counts
     # over the event-timed milliseconds of that family's launches
-    R = args.recompute_every if args.recompute_every > 0 else 50
+    R = args.recompute_every if args.recompute_every > 0 else (10 if args.solver == "selective" else 50)
     fbytes = family_bytes(all_res, args.n, R, args.solver)
     kernels = {}
     for name, (nl, ms) in fam.items():
@@ -403,7 +455,8 @@ def main():
         sub = designs[: args.fp64_designs]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r64 = api.homogenize_batch(sub, precision="fp64", rtol=1e-10, solver=args.solver)
+        r64 = api.homogenize_batch(sub, precision="fp64", rtol=1e-10 if not selective else 1e-9,
+                                   solver=args.solver)
         torch.cuda.synchronize()
         w64 = time.perf_counter() - t1
         errs, small = [], []
@@ -448,12 +501,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"shell_128: {len(designs)} designs/step at {args.n}^3, 48 charges, "
                                f"vf U[0.05,0.15], void E 1e-6, mixed precision, rtol {args.rtol}, "
-                               f"{'multigrid' if args.solver == 'mg' else 'Jacobi'}-preconditioned CG, "
-                               f"continuous-batching engine",
+                               + {"mg": "multigrid-preconditioned CG, continuous-batching engine",
+                                  "jacobi": "Jacobi-preconditioned CG, continuous-batching engine",
+                                  "selective": "selective (culled, beta > 1e-3) CG on the active nodes with "
+                                               "the culled multigrid V-cycle, one design at a time",
+                                  "selective-jacobi": "selective (culled, beta > 1e-3) Jacobi-PCG on the active "
+                                                      "nodes, one design at a time"}[args.solver],
                    "n": args.n, "designs_per_step": len(designs)},
         "latency_p50_s": round(float(np.percentile(all_lat, 50)), 4),
         "latency_p99_s": round(float(np.percentile(all_lat, 99)), 4),
         "cg_iters_mean": float(np.mean(iters)),
+        "active_node_fraction_mean": float(np.mean([r["active_nodes"] for r in all_res])) / args.n ** 3,
         "status_failures": len(bad),
         "roofline": roofline,
         "loop_roofline": loop,
@@ -464,7 +522,8 @@ def main():
     if not args.no_cpu:
         oracle_iters = int(jac.get("jacobi_iters_mean", np.mean(iters))) if args.solver == "mg" else int(np.mean(iters))
         out["cpu_baseline"] = cpu_baseline(designs[0], oracle_iters, args.cpu_seconds)
-    engine.close()
+    if engine is not None:
+        engine.close()
     print(json.dumps(out))
 
 

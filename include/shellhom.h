@@ -67,9 +67,12 @@ extern "C" {
                                  1e-3 are culled (no stiffness floor: an active voxel
                                  carries E beta, E_void is ignored), unknowns only on
                                  the active nodes, held as compact lists in ascending
-                                 packed-coordinate order; Jacobi-preconditioned CG on
-                                 them.  Any n.  Not served by the engine, no adjoint
-                                 (SHH_UNSUPPORTED)                                       */
+                                 packed-coordinate order; CG on them preconditioned by a
+                                 multigrid V-cycle whose coarse levels are the Galerkin
+                                 grids of the culled voxel operator where the grid
+                                 coarsens (as for SHH_SOLVER_MG), else by Jacobi.  Any n.
+                                 Not served by the engine, no adjoint (SHH_UNSUPPORTED)  */
+#define SHH_SOLVER_SELECTIVE_JACOBI 4 /* the same culled system, always Jacobi-preconditioned */
 
 /* One design (Eq. (6)-(7) parameters and material). */
 typedef struct {
@@ -93,7 +96,20 @@ typedef struct {
   double nu;            /* Poisson ratio, -1 < nu < 0.5                                  */
   double E_void;        /* void stiffness floor, 0 <= E_void <= E (0 makes K singular
                            beyond the rigid modes if the solid is not connected)         */
+  int32_t symmetry;     /* fundamental bounding volume (Sec. 3.2): the N charges are
+                           given in it and mirrored over the cell before anything else:
+                           SHH_SYM_NONE as given; SHH_SYM_MIRROR the eight reflections
+                           x_d -> 1 - x_d (a one-eighth-cell volume: orthotropic
+                           structures); SHH_SYM_CUBIC those with the six axis
+                           permutations, 48 images (a tetrahedral volume: cubic
+                           structures).  Images keep the charge value; coincident
+                           images are not merged.  Gradients are with respect to the
+                           N given charges.  N times the image count <= 4096.         */
 } shh_design;
+
+#define SHH_SYM_NONE   0
+#define SHH_SYM_MIRROR 1
+#define SHH_SYM_CUBIC  2
 
 /* Solver options. */
 typedef struct {
@@ -101,8 +117,9 @@ typedef struct {
   double rtol;              /* stop a load case when ||f - K u||_2 <= rtol ||f||_2        */
   int32_t max_iter;         /* CG iteration cap per load case                            */
   int32_t recompute_every;  /* R: replace the recursive residual by f - K u, computed in
-                               FP64, every R iterations (0: default 50 mixed / 0 FP64;
-                               the true residual is always recomputed at the end)        */
+                               FP64, every R iterations (0: default 50 mixed -- 10 for
+                               SHH_SOLVER_SELECTIVE -- / 0 FP64; the true residual is
+                               always recomputed at the end)                             */
   int32_t save_for_backward;/* keep F, grad F and the solution for shh_grad               */
   int32_t check_every;      /* host polls convergence every this many iterations (0: 16) */
   int32_t solver;           /* SHH_SOLVER_JACOBI (0): Jacobi-preconditioned CG, one fused
@@ -205,6 +222,23 @@ int32_t shh_homogenize_field(int32_t n, const void *d_E, int32_t e_dtype, double
 int32_t shh_field(const shh_design *design, void *d_ws, size_t ws_bytes, double *d_F,
                   double *d_G, double *d_d, double *d_beta, void *hip_stream, shh_result *out);
 
+/* The field F of Eq. (6) (iso-level not subtracted) and its gradient at
+   npts arbitrary points, for fitting the charge field to a given surface
+   (the objective of Eq. (10)): d_pts device [npts][3] (cell units, any real:
+   F is 1-periodic), d_F device [npts], d_G device [3][npts] or NULL.  Only the
+   design's charges, alpha, K and symmetry are used.  d_ws: device workspace of
+   shh_workspace_bytes_points bytes.  FP64; synchronizes the stream. */
+int32_t shh_workspace_bytes_points(const shh_design *design, int32_t npts, size_t *bytes);
+int32_t shh_field_points(const shh_design *design, int32_t npts, const double *d_pts, double *d_F, double *d_G,
+                         void *d_ws, size_t ws_bytes, void *hip_stream);
+/* Adjoint of a functional of those values: given dL/dF at the points
+   (device [npts]), writes dL/dpos [N][3], dL/dq [N] (host) and, if not NULL,
+   dL/dalpha [(K+1)^3] (host), with respect to the design's own charges (the
+   fundamental volume's, under a symmetry mode). */
+int32_t shh_field_points_grad(const shh_design *design, int32_t npts, const double *d_pts, const double *d_dL_dF,
+                              double *dL_dpos, double *dL_dq, double *dL_dalpha, void *d_ws, size_t ws_bytes,
+                              void *hip_stream);
+
 /* Workspace of the operator calls below (shh_apply_stiffness,
    shh_load_vectors, shh_energy): the moduli in the working precision, the
    Jacobi diagonal, reduction partials and descriptors, about 16 B per node
@@ -298,7 +332,14 @@ int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts 
 #define SHH_PROF_MG_PROLONG   8  /*   prolongation from the first coarse level                 */
 #define SHH_PROF_MG_APPLY1    9  /* multigrid, first coarse level: q = A_1 v (27-point blocks)  */
 #define SHH_PROF_RESID64     10  /* FP64 residual f - K u (replacement and final check)         */
-#define SHH_PROF_NKIND       11
+#define SHH_PROF_SEL_OP      11  /* selective solve: q = K p on the active nodes, with the sums  */
+#define SHH_PROF_SEL_UPDATE  12  /*   x += alpha p, r -= alpha q, p = D^-1 r + beta p            */
+#define SHH_PROF_SEL_RESID   13  /*   FP64 residual f - K u on the active nodes                  */
+#define SHH_PROF_SEL_MG_PQ   14  /* selective multigrid CG: q = K p on the active nodes, p.q     */
+#define SHH_PROF_SEL_MG_SMOOTH 15 /*  the four operator passes fused with the Chebyshev sweeps  */
+#define SHH_PROF_SEL_MG_VEC  16  /*   x += alpha p, r -= alpha q with D^-1 r; p = z + beta p     */
+#define SHH_PROF_SEL_MG_TRANSFER 17 /* restriction to and prolongation from the first coarse level */
+#define SHH_PROF_NKIND       18
 /* shh_profile_enable(1) also resets the counters.  shh_profile_read gives the
    number of timed launches of one family and their total milliseconds
    (SHH_INVALID_ARG for an unknown family). */

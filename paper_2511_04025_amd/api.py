@@ -302,3 +302,48 @@ def grad_batch(designs, opts, workspaces, dL_dC, dL_dV):
         o += N
         oa += K1 ** 3
     return out_p, out_q, out_a, dt
+
+
+def _points(pts):
+    pts = torch.as_tensor(pts, dtype=torch.float64)
+    if pts.dim() != 2 or pts.shape[1] != 3:
+        raise ValueError("points must be (M, 3)")
+    return pts.to("cuda").contiguous()
+
+
+def _points_workspace(a, npts):
+    nb = c_size_t(0)
+    B.check(B.lib().shh_workspace_bytes_points(byref(a.c), int(npts), byref(nb)), "shh_workspace_bytes_points")
+    return Workspace(nb.value)
+
+
+def field_points(design, pts, gradient=False):
+    """F of Eq. (6) at arbitrary points (M, 3) -> (M,) float64 CUDA tensor (and
+    its gradient (3, M) if asked); only the design's charges, alpha, K and
+    symmetry are used."""
+    _require_gpu()
+    a = B.DesignArgs(design)
+    P = _points(pts)
+    M = P.shape[0]
+    ws = _points_workspace(a, M)
+    F = torch.empty(M, dtype=torch.float64, device="cuda")
+    G = torch.empty((3, M), dtype=torch.float64, device="cuda") if gradient else None
+    B.check(B.lib().shh_field_points(byref(a.c), M, _ptr(P), _ptr(F), _ptr(G) if G is not None else None, ws.ptr,
+                                     c_size_t(ws.nbytes), _stream()), "shh_field_points")
+    return (F, G) if gradient else F
+
+
+def field_points_grad(design, pts, dL_dF):
+    """Adjoint of field_points: dL/dpos (N, 3), dL/dq (N,), dL/dalpha (K+1,)*3."""
+    _require_gpu()
+    a = B.DesignArgs(design)
+    P = _points(pts)
+    M = P.shape[0]
+    g = torch.as_tensor(dL_dF, dtype=torch.float64).to("cuda").contiguous()
+    ws = _points_workspace(a, M)
+    N = a.q.size
+    K1 = int(design.K) + 1
+    dpos, dq, dal = np.zeros((N, 3)), np.zeros(N), np.zeros(K1 ** 3)
+    B.check(B.lib().shh_field_points_grad(byref(a.c), M, _ptr(P), _ptr(g), _dp(dpos), _dp(dq), _dp(dal), ws.ptr,
+                                          c_size_t(ws.nbytes), _stream()), "shh_field_points_grad")
+    return dpos, dq, dal.reshape(K1, K1, K1)

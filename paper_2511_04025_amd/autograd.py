@@ -48,6 +48,7 @@ class Spec:
     max_iter: int = 20000
     solver: str = "jacobi"
     target_vf: Optional[float] = None
+    symmetry: object = 0  # fundamental bounding volume of the charges (workloads.Design.symmetry)
     state: dict = dc_field(default_factory=dict)
 
     def designs(self, pos, q, alpha=None, thickness=None):
@@ -64,7 +65,7 @@ class Spec:
                 vf = None
             out.append(Design(pos=pos[b], q=q[b], n=self.n, K=self.K, alpha=al, iso=self.iso,
                               thickness=th, target_vf=vf, kappa=self.kappa, dist_mode=self.dist_mode,
-                              E=self.E, nu=self.nu, E_void=self.E_void))
+                              E=self.E, nu=self.nu, E_void=self.E_void, symmetry=self.symmetry))
         return out
 
 

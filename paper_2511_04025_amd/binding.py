@@ -41,6 +41,7 @@ class ShhDesign(ctypes.Structure):
         ("iso", c_double), ("thickness", c_double), ("target_vf", c_double), ("kappa", c_double),
         ("dist_mode", c_int32),
         ("E", c_double), ("nu", c_double), ("E_void", c_double),
+        ("symmetry", c_int32),
     ]
 
 
@@ -79,6 +80,11 @@ EXPORTS = {
                                        POINTER(ShhOpts), c_void_p, c_size_t, c_void_p, POINTER(ShhResult)]),
     "shh_field": (c_int32, [POINTER(ShhDesign), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p, POINTER(ShhResult)]),
+    "shh_workspace_bytes_points": (c_int32, [POINTER(ShhDesign), c_int32, POINTER(c_size_t)]),
+    "shh_field_points": (c_int32, [POINTER(ShhDesign), c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                   c_void_p]),
+    "shh_field_points_grad": (c_int32, [POINTER(ShhDesign), c_int32, c_void_p, c_void_p, POINTER(c_double),
+                                        POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p]),
     "shh_apply_stiffness": (c_int32, [c_int32, c_int32, c_void_p, c_double, c_int32, c_void_p, c_void_p,
                                       c_void_p, c_size_t, c_void_p]),
     "shh_load_vectors": (c_int32, [c_int32, c_void_p, c_double, c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -152,12 +158,16 @@ class DesignArgs:
             iso=float(design.iso), thickness=-1.0 if th is None else float(th),
             target_vf=0.0 if design.target_vf is None else float(design.target_vf),
             kappa=float(design.kappa), dist_mode=int(design.dist_mode),
-            E=float(design.E), nu=float(design.nu), E_void=float(design.E_void))
+            E=float(design.E), nu=float(design.nu), E_void=float(design.E_void),
+            symmetry=SYMMETRY[getattr(design, "symmetry", 0)])
 
 
-SOLVER_JACOBI, SOLVER_MG, SOLVER_AUTO, SOLVER_SELECTIVE = 0, 1, 2, 3
+SOLVER_JACOBI, SOLVER_MG, SOLVER_AUTO, SOLVER_SELECTIVE, SOLVER_SELECTIVE_JACOBI = 0, 1, 2, 3, 4
+# fundamental bounding volumes (Sec. 3.2): by name or by the C constant
+SYMMETRY = {0: 0, 1: 1, 2: 2, None: 0, "none": 0, "mirror": 1, "cubic": 2}
 PROF_KINDS = ("cg_pass", "mg_dir", "mg_step1", "mg_res", "mg_post", "mg_last", "mg_update", "mg_restrict",
-              "mg_prolong", "mg_apply1", "resid64")
+              "mg_prolong", "mg_apply1", "resid64", "sel_op", "sel_update", "sel_resid", "sel_mg_pq",
+              "sel_mg_smooth", "sel_mg_vec", "sel_mg_transfer")
 EDTYPE_U8, EDTYPE_F32, EDTYPE_F64 = 0, 1, 2
 
 
@@ -167,8 +177,8 @@ def make_opts(precision="mixed", rtol=None, max_iter=20000, recompute_every=0, s
     if rtol is None:
         rtol = 1e-6 if prec == PREC_MIXED else 1e-10
     sv = {"mg": SOLVER_MG, "jacobi": SOLVER_JACOBI, "auto": SOLVER_AUTO,
-          "selective": SOLVER_SELECTIVE}.get(solver, solver)
-    if sv not in (SOLVER_MG, SOLVER_JACOBI, SOLVER_AUTO, SOLVER_SELECTIVE):
+          "selective": SOLVER_SELECTIVE, "selective-jacobi": SOLVER_SELECTIVE_JACOBI}.get(solver, solver)
+    if sv not in (SOLVER_MG, SOLVER_JACOBI, SOLVER_AUTO, SOLVER_SELECTIVE, SOLVER_SELECTIVE_JACOBI):
         raise ValueError(f"unknown solver {solver!r}")
     return ShhOpts(precision=prec, rtol=float(rtol), max_iter=int(max_iter),
                    recompute_every=int(recompute_every), save_for_backward=int(bool(save_for_backward)),

@@ -40,7 +40,7 @@ int check_solver(int n, shh_opts *o) {
 }
 
 size_t ws_bytes_for(const shh_design *d, const shh_opts *o) {
-  const Layout L = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, true,
+  const Layout L = make_layout(d->n, charge_count(d), d->K, o->precision, o->save_for_backward != 0, true,
                                o->solver);
   return L.total + seg_region() + 256;
 }
@@ -69,7 +69,7 @@ int prepare_slot(Slot &s, const shh_design *d, const shh_opts *o, void *d_ws, si
   s.opts = *o;
   SHH_TRY(check_solver(d->n, &s.opts));
   o = &s.opts;
-  s.lay = make_layout(d->n, d->num_charges, d->K, o->precision, o->save_for_backward != 0, vectors,
+  s.lay = make_layout(d->n, charge_count(d), d->K, o->precision, o->save_for_backward != 0, vectors,
                       vectors ? o->solver : SHH_SOLVER_JACOBI);
   if (!d_ws) return SHH_INVALID_ARG;
   char *base = aligned(d_ws);
@@ -161,9 +161,10 @@ int homogenize_run(const shh_design *designs, int32_t count, const shh_opts *opt
     if (s->ev[0]) SHH_HIP(hipEventRecord(s->ev[0], st));
     SHH_TRY(slot_init(*s, s->base, st));
     SHH_TRY(slot_setup_field(*s, nullptr, st));
-    if (o.solver == SHH_SOLVER_SELECTIVE) SHH_TRY(sel_solve(*s, st));  // one design at a time
+    s->timing = timed;
+    if (is_selective(o.solver)) SHH_TRY(sel_solve(*s, st));  // one design at a time
   }
-  if (o.solver == SHH_SOLVER_SELECTIVE) {
+  if (is_selective(o.solver)) {
     int worst = SHH_OK;
     for (int i = 0; i < count; ++i) {
       fill_result(*slots[i], &out[i]);
@@ -296,12 +297,12 @@ static int moduli_slot(Slot &s, int32_t n, const void *d_E, double nu, const shh
   SHH_TRY(prepare_slot(s, &d, &oo, d_ws, ws_bytes, seg_mem, vectors));
   SHH_TRY(slot_init(s, s.base, st));
   // a culled voxel of the selective solve carries nothing, whatever E_void says
-  SHH_TRY(slot_setup_moduli(s, d_E, e_dtype, Es, oo.solver == SHH_SOLVER_SELECTIVE ? 0.0 : Ev, st));
+  SHH_TRY(slot_setup_moduli(s, d_E, e_dtype, Es, is_selective(oo.solver) ? 0.0 : Ev, st));
   SHH_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
   SHH_HIP(hipStreamSynchronize(st));
   const double emax = s.state.Emax;
   // the selective solve culls zero moduli; an all-zero grid is an empty cell
-  const bool sel = oo.solver == SHH_SOLVER_SELECTIVE;
+  const bool sel = is_selective(oo.solver);
   if (!std::isfinite(emax) || !(emax > 0.0 || (sel && emax == 0.0))) return SHH_INVALID_ARG;
   s.host.E = emax;
   s.host.ffloor = 1e-12 * emax * std::sqrt(3.0 * double(s.host.nn));
@@ -321,7 +322,7 @@ int32_t shh_homogenize_stiffness(int32_t n, const double *d_E, double nu, const 
   Events ev(&s);
   SHH_HIP(hipEventRecord(s.ev[0], st));
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true));
-  if (o.solver == SHH_SOLVER_SELECTIVE) {
+  if (is_selective(o.solver)) {
     SHH_TRY(sel_solve(s, st));
   } else {
     Solver sv(st);
@@ -347,7 +348,7 @@ int32_t shh_homogenize_field(int32_t n, const void *d_E, int32_t e_dtype, double
   Events ev(&s);
   SHH_HIP(hipEventRecord(s.ev[0], st));
   SHH_TRY(moduli_slot(s, n, d_E, nu, &o, d_ws, ws_bytes, st, &seg_mem, true, e_dtype, E, E_void));
-  if (o.solver == SHH_SOLVER_SELECTIVE) {
+  if (is_selective(o.solver)) {
     SHH_TRY(sel_solve(s, st));
   } else {
     Solver sv(st);
@@ -468,7 +469,8 @@ namespace {
 struct GradJob {
   Slot s;
   double *d_out = nullptr;
-  int N = 0, nalpha = 0;
+  int N = 0, nalpha = 0;        // N: charges after the fundamental volume's expansion
+  int sym = 0, nfbv = 0;        // the caller's symmetry mode and charge count
   std::vector<double> host;
 };
 
@@ -478,7 +480,7 @@ int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, v
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   if (!dL_dCH || !std::isfinite(dL_dV)) return SHH_INVALID_ARG;
-  if (!(design->kappa > 0.0) || o.solver == SHH_SOLVER_SELECTIVE) return SHH_UNSUPPORTED;
+  if (!(design->kappa > 0.0) || is_selective(o.solver)) return SHH_UNSUPPORTED;
   if (!o.save_for_backward) return SHH_INVALID_ARG;
   for (int i = 0; i < 36; ++i)
     if (!std::isfinite(dL_dCH[i])) return SHH_INVALID_ARG;
@@ -489,9 +491,11 @@ int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, v
                          hipMemcpyDeviceToHost, st));
   SHH_HIP(hipStreamSynchronize(st));
   s.d_slot = (SlotDev *)(s.base + s.lay.slotdev);
-  if (s.host.n != design->n || s.host.N != design->num_charges || s.host.prec != o.precision ||
+  if (s.host.n != design->n || s.host.N != charge_count(design) || s.host.prec != o.precision ||
       s.host.K != design->K)
     return SHH_INVALID_ARG;
+  job.sym = design->symmetry;
+  job.nfbv = design->num_charges;
   // dL/dE_e weights: symmetric fold of dL/dC over the 21 distinct entries
   double g21[21];
   int t = 0;
@@ -518,11 +522,19 @@ int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, v
 }
 
 void grad_unpack(const GradJob &job, double *dL_dpos, double *dL_dq, double *dL_dalpha, double *dL_dt) {
-  for (int j = 0; j < job.N; ++j) {
-    dL_dpos[3 * j] = job.host[4 * j];
-    dL_dpos[3 * j + 1] = job.host[4 * j + 1];
-    dL_dpos[3 * j + 2] = job.host[4 * j + 2];
-    dL_dq[j] = job.host[4 * j + 3];
+  // expanded charge j * G + g is image g of given charge j: fold its gradient back
+  const int G = sym_images(job.sym);
+  for (int j = 0; j < job.nfbv; ++j) {
+    double gp[3] = {0.0, 0.0, 0.0}, gq = 0.0;
+    for (int g = 0; g < G; ++g) {
+      const double *h = &job.host[4 * ((size_t)j * G + g)];
+      sym_fold(g, h, gp);
+      gq += h[3];
+    }
+    dL_dpos[3 * j] = gp[0];
+    dL_dpos[3 * j + 1] = gp[1];
+    dL_dpos[3 * j + 2] = gp[2];
+    dL_dq[j] = gq;
   }
   if (dL_dalpha)
     for (int m = 0; m < job.nalpha; ++m) dL_dalpha[m] = job.host[4 * job.N + m];
@@ -563,6 +575,120 @@ int32_t shh_grad_batch(const shh_design *designs, int32_t count, const shh_opts 
     off += designs[i].num_charges;
     aoff += jobs[i]->nalpha;
   }
+  return SHH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Byte sizes of the point-field workspace: a field-only slot (no grid), then
+// the per-point basis table, dL/dcoef and the charge/alpha gradients.
+struct PointsLayout {
+  size_t slot, basis, dcoef, out, total;
+};
+
+PointsLayout points_layout(const shh_design *d, int npts) {
+  const Layout L = make_layout(2, charge_count(d), d->K, SHH_PREC_FP64, false, false);
+  const size_t nb = 2 * (size_t)d->K + 1, K1 = (size_t)d->K + 1;
+  PointsLayout P;
+  P.slot = al256(L.total + seg_region() + 256);
+  P.basis = al256(sizeof(double) * (size_t)npts * 3 * nb);
+  P.dcoef = al256(sizeof(double) * nb * nb * nb);
+  P.out = al256(sizeof(double) * (4 * (size_t)charge_count(d) + K1 * K1 * K1));
+  P.total = P.slot + P.basis + P.dcoef + P.out;
+  return P;
+}
+
+// The point field reads only the charges, alpha, K and the symmetry mode:
+// the rest of the design is replaced by valid placeholders before validation.
+shh_design points_design(const shh_design *in) {
+  shh_design d = *in;
+  d.n = 2;
+  d.iso = 0.0;
+  d.thickness = 0.0;
+  d.target_vf = 0.0;
+  d.kappa = 0.0;
+  d.dist_mode = 0;
+  d.E = 1.0;
+  d.nu = 0.3;
+  d.E_void = 0.0;
+  return d;
+}
+
+int points_slot(Slot &s, const shh_design *design, int npts, void *d_ws, size_t ws_bytes, PointsLayout &P,
+                hipStream_t st) {
+  if (!design) return SHH_INVALID_ARG;
+  shh_design d = points_design(design);
+  SHH_TRY(validate_design(&d));
+  if (npts < 1 || npts > (1 << 26) || !d_ws) return SHH_INVALID_ARG;
+  P = points_layout(&d, npts);
+  if (ws_bytes < P.total) return SHH_WORKSPACE_TOO_SMALL;
+  shh_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.precision = SHH_PREC_FP64;
+  o.rtol = 1e-10;
+  o.max_iter = 1;
+  SHH_TRY(normalize_opts(&o, &o));
+  SHH_TRY(prepare_slot(s, &d, &o, d_ws, ws_bytes, nullptr, false));
+  SHH_TRY(slot_init(s, s.base, st));
+  return SHH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t shh_workspace_bytes_points(const shh_design *design, int32_t npts, size_t *bytes) {
+  if (!design) return SHH_INVALID_ARG;
+  const shh_design d = points_design(design);
+  SHH_TRY(validate_design(&d));
+  if (npts < 1 || npts > (1 << 26) || !bytes) return SHH_INVALID_ARG;
+  *bytes = points_layout(&d, npts).total;
+  return SHH_OK;
+}
+
+int32_t shh_field_points(const shh_design *design, int32_t npts, const double *d_pts, double *d_F, double *d_G,
+                         void *d_ws, size_t ws_bytes, void *hip_stream) {
+  if (!d_pts || !d_F) return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  PointsLayout P;
+  SHH_TRY(points_slot(s, design, npts, d_ws, ws_bytes, P, st));
+  SHH_HIP(launch_coef(s.d_slot, s.host.nb, st));
+  SHH_HIP(launch_points_field(s.d_slot, s.host.nb, npts, d_pts, d_F, d_G, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
+
+int32_t shh_field_points_grad(const shh_design *design, int32_t npts, const double *d_pts, const double *d_dL_dF,
+                              double *dL_dpos, double *dL_dq, double *dL_dalpha, void *d_ws, size_t ws_bytes,
+                              void *hip_stream) {
+  if (!d_pts || !d_dL_dF || !dL_dpos || !dL_dq) return SHH_INVALID_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Slot s;
+  PointsLayout P;
+  SHH_TRY(points_slot(s, design, npts, d_ws, ws_bytes, P, st));
+  char *base = (char *)d_ws;
+  base = (char *)(((uintptr_t)base + 255) & ~uintptr_t(255));
+  double *d_basis = (double *)(base + P.slot);
+  double *d_dcoef = (double *)(base + P.slot + P.basis);
+  double *d_out = (double *)(base + P.slot + P.basis + P.dcoef);
+  const int Nx = s.host.N, K1 = s.host.K + 1;
+  SHH_HIP(launch_points_dcoef(s.host.nb, npts, d_pts, d_dL_dF, d_basis, d_dcoef, st));
+  SHH_HIP(launch_coef_adjoint(s.d_slot, Nx, s.host.K, d_dcoef, d_out, d_out + 4 * Nx, st));
+  GradJob job;
+  job.N = Nx;
+  job.nalpha = K1 * K1 * K1;
+  job.sym = design->symmetry;
+  job.nfbv = design->num_charges;
+  job.host.assign(4 * (size_t)Nx + job.nalpha + 1, 0.0);
+  SHH_HIP(hipMemcpyAsync(job.host.data(), d_out, sizeof(double) * (4 * (size_t)Nx + job.nalpha),
+                         hipMemcpyDeviceToHost, st));
+  SHH_HIP(hipStreamSynchronize(st));
+  grad_unpack(job, dL_dpos, dL_dq, dL_dalpha, nullptr);
   return SHH_OK;
 }
 
@@ -644,7 +770,7 @@ int32_t shh_engine_footprint(const shh_design *design, const shh_opts *opts, siz
   SHH_TRY(normalize_opts(opts, &o));
   if (!bytes) return SHH_INVALID_ARG;
   SHH_TRY(check_solver(design->n, &o));
-  const Layout L = make_layout(design->n, design->num_charges, design->K, o.precision, o.save_for_backward != 0,
+  const Layout L = make_layout(design->n, charge_count(design), design->K, o.precision, o.save_for_backward != 0,
                                true, o.solver);
   *bytes = (L.total + 255) & ~size_t(255);
   return SHH_OK;
@@ -683,7 +809,7 @@ int32_t shh_engine_submit(shh_engine *eng, const shh_design *design, const shh_o
   SHH_TRY(normalize_opts(opts, &o));
   if (eng->prec >= 0 && o.precision != eng->prec) return SHH_INVALID_ARG;
   SHH_TRY(check_solver(design->n, &o));  // SHH_SOLVER_AUTO: multigrid or Jacobi for this grid
-  if (o.solver == SHH_SOLVER_SELECTIVE) return SHH_UNSUPPORTED;  // solved one design at a time
+  if (is_selective(o.solver)) return SHH_UNSUPPORTED;  // solved one design at a time
   size_t need = 0;
   SHH_TRY(shh_engine_footprint(design, &o, &need));
   if (need > eng->bytes - eng->header) return SHH_OVER_BUDGET;

@@ -393,4 +393,13 @@ hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, int K, const do
   return hipGetLastError();
 }
 
+// dL/d(charges, alpha) from dL/dcoef alone (the point-field adjoint)
+hipError_t launch_coef_adjoint(SlotDev *d_slot, int N, int K, const double *d_dcoef, double *d_out,
+                               double *d_alpha_out, hipStream_t st) {
+  adj_charges_kernel<<<N, 256, 0, st>>>(d_slot, d_dcoef, d_out);
+  const int K1 = K + 1;
+  if (d_alpha_out) adj_alpha_kernel<<<(K1 * K1 * K1 + 255) / 256, 256, 0, st>>>(d_slot, d_dcoef, d_alpha_out);
+  return hipGetLastError();
+}
+
 }  // namespace shh

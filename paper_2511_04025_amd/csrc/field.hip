@@ -442,4 +442,9 @@ hipError_t launch_dinv(SlotDev *d_slot, long long nn, int prec, hipStream_t st) 
   return hipGetLastError();
 }
 
+hipError_t launch_coef(SlotDev *d_slot, int nb, hipStream_t st) {
+  coef_kernel<<<(nb * nb * nb + 255) / 256, 256, 0, st>>>(d_slot);
+  return hipGetLastError();
+}
+
 }  // namespace shh

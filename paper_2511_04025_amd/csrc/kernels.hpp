@@ -46,6 +46,16 @@ hipError_t launch_adjoint(SlotDev *d_slot, int n, int nb, int N, int K, const do
                           double *d_scratch, double *d_out, double *d_alpha_out, double *d_t_out,
                           hipStream_t st);
 
+// the field's trig coefficient tensor alone; dL/d(charges, alpha) from dL/dcoef
+hipError_t launch_coef(SlotDev *d_slot, int nb, hipStream_t st);
+hipError_t launch_coef_adjoint(SlotDev *d_slot, int N, int K, const double *d_dcoef, double *d_out,
+                               double *d_alpha_out, hipStream_t st);
+// the field and its gradient at arbitrary points, and dL/dcoef from dL/dF there
+hipError_t launch_points_field(SlotDev *d_slot, int nb, int npts, const double *d_pts, double *d_F,
+                               double *d_G, hipStream_t st);
+hipError_t launch_points_dcoef(int nb, int npts, const double *d_pts, const double *d_gF, double *d_basis,
+                               double *d_dcoef, hipStream_t st);
+
 // device address of the current device's shh_homogenize_noalloc scratch
 int noalloc_scratch(void **out);
 

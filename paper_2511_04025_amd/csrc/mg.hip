@@ -639,6 +639,7 @@ __global__ __launch_bounds__(1024) void mg_coarse_inverse_kernel(MgDev *mg) {
   if (threadIdx.x == 0) red[0] = acc[0];
   __syncthreads();
   const double add = red[0] / m / double(nn);
+  const double mean_diag = red[0] / m;
   for (long long k = threadIdx.x; k < (long long)m * m; k += blockDim.x) {
     const int i = int(k / m), j = int(k % m);
     if (i % 3 == j % 3) A[k] += add;
@@ -652,6 +653,20 @@ __global__ __launch_bounds__(1024) void mg_coarse_inverse_kernel(MgDev *mg) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   for (int k = 0; k < m; ++k) {
     const double piv = A[(long long)k * m + k];
+    if (!(piv > 1e-12 * mean_diag)) {
+      // a vanishing pivot of the (positive semidefinite) Schur complement: the
+      // dof is a null direction beyond the rigid translations (nodes whose
+      // elements are all culled, pieces that float at this level).  It is
+      // taken out -- row and column k zero -- so the result stays a symmetric
+      // generalized inverse.  Never taken on the floored operator.
+      __syncthreads();
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        A[(long long)i * m + k] = 0.0;
+        A[(long long)k * m + i] = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
     for (int i = threadIdx.x; i < m; i += blockDim.x) colk[i] = A[(long long)i * m + k];
     __syncthreads();
     for (int j = threadIdx.x; j < m; j += blockDim.x) {

@@ -472,6 +472,13 @@ int mg_setup(const std::vector<Slot *> &all, hipStream_t st, std::vector<int> *r
 
 int mg_setup(Slot &s, hipStream_t st) { return mg_setup(std::vector<Slot *>{&s}, st); }
 
+int mg_vcycle_coarse(Slot &s, hipStream_t st) {
+  if (s.mg.L < 1) return SHH_UNSUPPORTED;
+  // levels >= 1 never call the voxel-level operator
+  const MgApply0 none = [](const std::vector<Slot *> &, int) { return SHH_UNSUPPORTED; };
+  return vcycle(std::vector<Slot *>{&s}, 1, st, nullptr, none);
+}
+
 int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
   if (l < 1 || l > s.mg.L) return SHH_INVALID_ARG;
   const MgLevel &L = s.mg.lv[l];

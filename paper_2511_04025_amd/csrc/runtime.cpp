@@ -59,10 +59,36 @@ double now_ms() {
 
 static bool finite(double v) { return std::isfinite(v); }
 
+int sym_images(int sym) { return sym == SHH_SYM_MIRROR ? 8 : (sym == SHH_SYM_CUBIC ? 48 : 1); }
+
+// Image g of a point under the fundamental volume's group: the axes permuted
+// (permutation g / 8 of six, cubic only), then reflected x_d -> 1 - x_d for
+// the bits of g % 8.
+static const int kPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+void sym_image(int g, const double *p, double *v) {
+  const int *pm = kPerm[g / 8];
+  for (int d = 0; d < 3; ++d) {
+    v[d] = p[pm[d]];
+    if ((g >> d) & 1) v[d] = 1.0 - v[d];
+  }
+}
+
+// dL/dp of a given charge accumulates dL/dv of its image g (the transpose of
+// the image map's linear part)
+void sym_fold(int g, const double *gv, double *gp) {
+  const int *pm = kPerm[g / 8];
+  for (int d = 0; d < 3; ++d) gp[pm[d]] += ((g >> d) & 1) ? -gv[d] : gv[d];
+}
+
+int charge_count(const shh_design *d) { return d->num_charges * sym_images(d->symmetry); }
+
 int validate_design(const shh_design *d) {
   if (!d) return SHH_INVALID_ARG;
   if (d->n < 2 || d->n > 512) return SHH_INVALID_ARG;  // 32-bit byte offsets per vector
   if (d->num_charges < 1 || !d->pos || !d->q) return SHH_INVALID_ARG;
+  if (d->symmetry < SHH_SYM_NONE || d->symmetry > SHH_SYM_CUBIC) return SHH_INVALID_ARG;
+  if ((long long)d->num_charges * sym_images(d->symmetry) > 4096) return SHH_INVALID_ARG;
   if (d->K < 1 || d->K > MAXK) return SHH_INVALID_ARG;
   for (int j = 0; j < d->num_charges; ++j) {
     if (!finite(d->pos[3 * j]) || !finite(d->pos[3 * j + 1]) || !finite(d->pos[3 * j + 2]) ||
@@ -92,9 +118,13 @@ int normalize_opts(const shh_opts *in, shh_opts *out) {
   if (!(out->rtol > 0.0 && out->rtol < 1.0)) return SHH_INVALID_ARG;
   if (out->max_iter < 0 || out->recompute_every < 0 || out->check_every < 0) return SHH_INVALID_ARG;
   if (out->solver != SHH_SOLVER_JACOBI && out->solver != SHH_SOLVER_MG && out->solver != SHH_SOLVER_AUTO &&
-      out->solver != SHH_SOLVER_SELECTIVE)
+      !is_selective(out->solver))
     return SHH_INVALID_ARG;
-  if (out->recompute_every == 0 && out->precision == SHH_PREC_MIXED) out->recompute_every = 50;
+  // the selective multigrid solve replaces its FP32 residual five times as
+  // often: its V-cycle puts large components along the culled operator's
+  // (near-)null modes, which the FP32 recursion turns into residual drift
+  if (out->recompute_every == 0 && out->precision == SHH_PREC_MIXED)
+    out->recompute_every = out->solver == SHH_SOLVER_SELECTIVE ? 10 : 50;
   if (out->check_every == 0) out->check_every = 16;
   return SHH_OK;
 }
@@ -150,16 +180,27 @@ Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors, int s
     L.adj = adj <= 4 * L.vec_bytes ? L.vec + 2 * L.vec_bytes : take(adj);
   }
   L.field = save ? take(sizeof(double) * 5 * nn) : L.vec;  // F, G[3], d (aliased unless saved)
-  if (solver == SHH_SOLVER_MG) L.mg = take(mg_region_bytes(n, prec));
+  // the selective solve takes the same multigrid region for its coarse levels
+  if (solver == SHH_SOLVER_MG || solver == SHH_SOLVER_SELECTIVE) L.mg = take(mg_region_bytes(n, prec));
   L.total = off;
   return L;
 }
 
 void copy_design(const shh_design *src, DesignCopy &dst) {
   dst.d = *src;
-  const int N = src->num_charges;
-  dst.pos.assign(src->pos, src->pos + 3 * N);
-  dst.q.assign(src->q, src->q + N);
+  const int N = src->num_charges, G = sym_images(src->symmetry);
+  dst.sym = src->symmetry;
+  dst.nfbv = N;
+  // the fundamental volume's charges and their images, charge by charge
+  dst.pos.resize(3 * (size_t)N * G);
+  dst.q.resize((size_t)N * G);
+  for (int j = 0; j < N; ++j)
+    for (int g = 0; g < G; ++g) {
+      sym_image(g, src->pos + 3 * j, &dst.pos[3 * ((size_t)j * G + g)]);
+      dst.q[(size_t)j * G + g] = src->q[j];
+    }
+  dst.d.num_charges = N * G;
+  dst.d.symmetry = SHH_SYM_NONE;
   if (src->alpha) {
     const int K1 = src->K + 1;
     dst.alpha.assign(src->alpha, src->alpha + K1 * K1 * K1);
@@ -225,7 +266,7 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.rtol = s.opts.rtol;
   h.max_iter = s.opts.max_iter;
   h.ffloor = 1e-12 * d.E * std::sqrt(3.0 * double(h.nn));
-  h.cull = s.opts.solver == SHH_SOLVER_SELECTIVE ? SEL_EPS : 0.0;
+  h.cull = is_selective(s.opts.solver) ? SEL_EPS : 0.0;
   element_operator(d.nu, h.kop64);
   for (int i = 0; i < KOP_N; ++i) h.kop32[i] = (float)h.kop64[i];
   h.charges = (double *)(base + L.charges);
@@ -628,7 +669,7 @@ void fill_result(const Slot &s, shh_result *out) {
   }
   for (int i = 0; i < 5; ++i) out->ms[i] = s.ms[i];
   out->status = s.status;
-  out->active_nodes = s.opts.solver == SHH_SOLVER_SELECTIVE ? s.sel_active_nodes : int32_t(s.host.nn);
+  out->active_nodes = is_selective(s.opts.solver) ? s.sel_active_nodes : int32_t(s.host.nn);
 }
 
 }  // namespace shh

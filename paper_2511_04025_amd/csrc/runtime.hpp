@@ -29,8 +29,11 @@ struct Layout {
 };
 
 struct DesignCopy {
-  shh_design d;                 // pointers below point into the vectors
+  shh_design d;                 // pointers below point into the vectors; charges expanded
+                                // over the fundamental volume's images (d.symmetry = 0)
   std::vector<double> pos, q, alpha;
+  int sym = 0;                  // the caller's symmetry mode
+  int nfbv = 0;                 // the caller's charge count
 };
 
 struct Slot {
@@ -56,9 +59,20 @@ struct Slot {
   MgDev *d_mg = nullptr;
   bool mg_restart = false;      // next iteration starts from z = V r, p = z
   int sel_active_nodes = 0;     // selective solve: active nodes
+  bool timing = true;           // launch timing allowed (false: the no-allocation entry point)
 };
 
+// the culled solve of Sec. 4.2 (either preconditioner)
+inline bool is_selective(int solver) {
+  return solver == SHH_SOLVER_SELECTIVE || solver == SHH_SOLVER_SELECTIVE_JACOBI;
+}
 int validate_design(const shh_design *d);
+// fundamental bounding volumes (shh_design.symmetry): image count, image g of a
+// point, gradient fold of image g, charges after expansion
+int sym_images(int sym);
+void sym_image(int g, const double *p, double *v);
+void sym_fold(int g, const double *gv, double *gp);
+int charge_count(const shh_design *d);
 int normalize_opts(const shh_opts *in, shh_opts *out);
 Layout make_layout(int n, int N, int K, int prec, bool save, bool vectors = true, int solver = 0);
 // bytes of the multigrid region of an n^3 slot (levels >= 1, coarsest inverse, descriptors)
@@ -83,6 +97,9 @@ using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // (timer: when profiling, the largest coarse level's operator launches are
 // timed with their algorithmic bytes)
 int mg_iterate(const std::vector<Slot *> &slots, hipStream_t st, Solver *timer, const MgApply0 &apply0);
+// the V-cycle of a set-up slot from level 1 down: lv[1].b in, lv[1].x out
+// (the selective solve runs the voxel level itself)
+int mg_vcycle_coarse(Slot &s, hipStream_t st);
 // q = A_l v for the Galerkin operator of level l >= 1 of a set-up slot (all six
 // load cases, [6][3][n_l^3] in the slot's precision)
 int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st);

@@ -10,6 +10,38 @@ namespace {
 __device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int wrap_inc(int v, int n) { return v + 1 == n ? 0 : v + 1; }
 
+// Vectors are node-major: the 18 values (load case k, component c at 3 k + c)
+// of one node are contiguous, so a neighbour's values come in nine 8- or
+// 16-byte loads (the row of node j starts at 72 j or 144 j bytes).
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
+template <typename TV, typename TE>
+__device__ __forceinline__ void load_row(const TV *u, long long j, TE (&v)[3 * NRHS]) {
+  using P2 = typename Pair<TV>::type;
+  const P2 *p = reinterpret_cast<const P2 *>(u + j * (3 * NRHS));
+#pragma unroll
+  for (int t = 0; t < 3 * NRHS / 2; ++t) {
+    const P2 w = p[t];
+    v[2 * t] = (TE)w.x;
+    v[2 * t + 1] = (TE)w.y;
+  }
+}
+
+template <typename TV, typename TE>
+__device__ __forceinline__ void store_row(TV *u, long long j, const TE (&v)[3 * NRHS]) {
+  using P2 = typename Pair<TV>::type;
+  P2 *p = reinterpret_cast<P2 *>(u + j * (3 * NRHS));
+#pragma unroll
+  for (int t = 0; t < 3 * NRHS / 2; ++t) {
+    P2 w;
+    w.x = (TV)v[2 * t];
+    w.y = (TV)v[2 * t + 1];
+    p[t] = w;
+  }
+}
+
 // node (x, y, z) is active if one of the eight voxels it is a corner of --
 // lower corners (x - ax, y - ay, z - az) -- carries stiffness
 __device__ __forceinline__ bool node_active(const double *E, int n, int x, int y, int z) {
@@ -221,14 +253,13 @@ __device__ __forceinline__ void accumulate(const TE (&E)[8], TE lam, TE mu, int 
   if (j < 0) return;  // a culled neighbour shares no stiffness with the node
   TE A[3][3];
   block_of<RX, RY, RZ>(E, lam, mu, A);
+  TE v[3 * NRHS];
+  load_row(u, j, v);
 #pragma unroll
   for (int k = 0; k < NRHS; ++k) {
     if (!((act >> k) & 1u)) continue;
-    const TE u0 = (TE)u[(long long)(3 * k + 0) * na + j];
-    const TE u1 = (TE)u[(long long)(3 * k + 1) * na + j];
-    const TE u2 = (TE)u[(long long)(3 * k + 2) * na + j];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) q[k][c] += A[c][0] * u0 + A[c][1] * u1 + A[c][2] * u2;
+    for (int c = 0; c < 3; ++c) q[k][c] += A[c][0] * v[3 * k] + A[c][1] * v[3 * k + 1] + A[c][2] * v[3 * k + 2];
   }
 }
 
@@ -309,12 +340,21 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_pcg_kernel(SelDev *S) {
 #pragma unroll
   for (int k = 0; k < NRHS; ++k) q[k][0] = q[k][1] = q[k][2] = T(0);
   double dv = 0.0;
+  T pr[3 * NRHS], rr[3 * NRHS];
   if (i < na) {
     int nb[27];
     T E[8];
     node_frame<T>(S, i, (const T *)S->Ec, nb, E);
     apply_row<T, T>(E, lam, mu, nb, P, na, act, q);
     dv = (double)Dv[i];
+    T qr[3 * NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) qr[3 * k + c] = q[k][c];
+    store_row(Q, i, qr);
+    load_row(P, i, pr);
+    load_row(Rv, i, rr);
   }
   double *parts = S->partials;
   const int np = S->nparts;
@@ -325,9 +365,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_pcg_kernel(SelDev *S) {
     if (i < na) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const long long o = (long long)(3 * k + c) * na + i;
-        Q[o] = q[k][c];
-        const double qv = (double)q[k][c], pv = (double)P[o], rv = (double)Rv[o];
+        const double qv = (double)q[k][c], pv = (double)pr[3 * k + c], rv = (double)rr[3 * k + c];
         v[0] += pv * qv;
         v[1] += rv * dv * rv;
         v[2] += qv * dv * rv;
@@ -377,7 +415,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_resid_kernel(SelDev *S, in
 #pragma unroll
         for (int a = 0; a < 8; ++a) f -= E[a] * S->f0[k][a][c];
         const double rv = f - q[k][c];
-        Rv[(long long)(3 * k + c) * na + i] = (TV)rv;
+        Rv[(long long)i * (3 * NRHS) + 3 * k + c] = (TV)rv;
         acc[k][c] += rv;
       }
     }
@@ -422,7 +460,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_energy_kernel(SelDev *S) {
     for (int k = 0; k < NRHS; ++k)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        u[k][c] = U[(long long)(3 * k + c) * na + i];
+        u[k][c] = U[(long long)i * (3 * NRHS) + 3 * k + c];
         double fv = 0.0;
 #pragma unroll
         for (int a = 0; a < 8; ++a) fv -= E[a] * S->f0[k][a][c];
@@ -465,7 +503,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_apply_kernel(SelDev *S) {
 #pragma unroll
     for (int k = 0; k < NRHS; ++k)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Q[(long long)(3 * k + c) * na + i] = q[k][c];
+      for (int c = 0; c < 3; ++c) Q[(long long)i * (3 * NRHS) + 3 * k + c] = q[k][c];
   }
 }
 
@@ -478,22 +516,37 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_update_kernel(SelDev *S) {
   const CgState *st = S->st;
   T *X = (T *)S->x, *Rv = (T *)S->r, *P = (T *)S->p;
   const T *Q = (const T *)S->q, *Dv = (const T *)S->Dinv;
+  T a[NRHS], b[NRHS];
+  unsigned step = 0;
   for (int k = 0; k < NRHS; ++k) {
-    const double al = st->alpha[k];
-    if (al == 0.0) continue;
-    const T a = (T)al, b = (T)st->beta[k];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
-      const T d = Dv[i];
+    a[k] = (T)st->alpha[k];
+    b[k] = (T)st->beta[k];
+    if (st->alpha[k] != 0.0) step |= 1u << k;
+  }
+  if (!step) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    const T d = Dv[i];
+    T x[3 * NRHS], r[3 * NRHS], p[3 * NRHS], q[3 * NRHS];
+    load_row(X, i, x);
+    load_row(Rv, i, r);
+    load_row(P, i, p);
+    load_row(Q, i, q);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+      if (!((step >> k) & 1u)) continue;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const long long o = (long long)(3 * k + c) * na + i;
-        const T pv = P[o];
-        const T rv = Rv[o] - a * Q[o];
-        X[o] += a * pv;
-        Rv[o] = rv;
-        P[o] = d * rv + b * pv;
+        const int o = 3 * k + c;
+        const T pv = p[o];
+        const T rv = r[o] - a[k] * q[o];
+        x[o] += a[k] * pv;
+        r[o] = rv;
+        p[o] = d * rv + b[k] * pv;
       }
     }
+    store_row(X, i, x);
+    store_row(Rv, i, r);
+    store_row(P, i, p);
   }
 }
 
@@ -509,7 +562,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_dir0_kernel(SelDev *S) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const long long o = (long long)(3 * k + c) * na + i;
+        const long long o = (long long)i * (3 * NRHS) + 3 * k + c;
         P[o] = Dv[i] * Rv[o];
       }
   }
@@ -526,7 +579,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_fold_kernel(SelDev *S, int al
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const long long o = (long long)(3 * k + c) * na + i;
+        const long long o = (long long)i * (3 * NRHS) + 3 * k + c;
         X64[o] += (double)X[o];
         X[o] = 0.0f;
       }
@@ -551,7 +604,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_finish_kernel(SelDev *S, int 
       const double d = (double)Dv[i];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const long long o = (long long)(3 * k + c) * na + i;
+        const long long o = (long long)i * (3 * NRHS) + 3 * k + c;
         const T rv = Rv[o] - m[c];
         Rv[o] = rv;
         const double r64 = (double)rv;
@@ -608,6 +661,48 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(SelDev *S, int 
   }
   const int k = blockIdx.x;
   const double *parts = S->partials + (long long)k * np * SEL_PS;
+  if (phase == SSC_MG_ALPHA) {  // alpha = rho / p . K p
+    if (!st->active[k]) {
+      if (threadIdx.x == 0) st->alpha[k] = 0.0;
+      return;
+    }
+    double tot[1];
+    sum_partials<1, SEL_PS>(parts, np, tot, red, SEL_THREADS);
+    if (threadIdx.x != 0) return;
+    const double pq = tot[0];
+    if (!(pq > 0.0) || !(st->rho[k] > 0.0)) {
+      st->alpha[k] = 0.0;
+      st->active[k] = 0;
+      st->status[k] = ST_BREAKDOWN;
+      return;
+    }
+    st->alpha[k] = st->rho[k] / pq;
+    return;
+  }
+  if (phase == SSC_MG_BETA || phase == SSC_MG_RESTART) {  // rho' = r . z, ||r||, beta
+    if (!st->active[k]) return;
+    double tot[2];
+    sum_partials<2, SEL_PS>(parts, np, tot, red, SEL_THREADS);
+    if (threadIdx.x != 0) return;
+    const double rho1 = tot[0], rr = tot[1];
+    st->rr[k] = rr;
+    const double rel = sqrt(rr / st->ff[k]);
+    st->rel[k] = rel;
+    if (phase == SSC_MG_BETA) st->iters[k] += 1;
+    if (rel <= S->rtol) {
+      st->active[k] = 0;
+      st->status[k] = ST_CONVERGED;
+    } else if (!(rho1 > 0.0)) {  // r . V r > 0 unless the cycle lost definiteness
+      st->active[k] = 0;
+      st->status[k] = ST_BREAKDOWN;
+    } else if (st->iters[k] >= S->max_iter) {
+      st->active[k] = 0;
+      st->status[k] = ST_MAXIT;
+    }
+    st->beta[k] = phase == SSC_MG_RESTART ? 0.0 : rho1 / st->rho[k];
+    st->rho[k] = rho1;
+    return;
+  }
   if (phase == SSC_ITER) {
     if (!st->active[k]) {
       if (threadIdx.x == 0) st->alpha[k] = 0.0;
@@ -700,6 +795,261 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mean_kernel(SelDev *S, int rm
     for (int c = 0; c < 3; ++c) st->mean[k][c] = tot[c] / double(S->na);
 }
 
+// ---- the multigrid-preconditioned solve: voxel-level V-cycle steps ------------
+// The same degree-2 Chebyshev smoothing on D^-1 A as the dense path (interval
+// [h/33, h], h the element bound of lambda_max): with b the CG residual,
+//   pre:  d0 = D^-1 b / theta;  r1 = b - A d0;  d1 = c1 d0 + c2 D^-1 r1;
+//         x = d0 + d1;  r2 = r1 - A d1            (restricted to level 1)
+//   post: x += P x1;  r = b - A x;  d0 = D^-1 r / theta;  x += d0;
+//         r' = r - A d0;  d1 = c1 d0 + c2 D^-1 r';  z = x + d1.
+// Each operator pass fuses the element-wise step after it, and none writes
+// the vector its operator reads (a neighbour's input).
+__device__ __forceinline__ unsigned active_mask(const CgState *st) {
+  unsigned act = 0;
+  for (int k = 0; k < NRHS; ++k)
+    if (st->active[k]) act |= 1u << k;
+  return act;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(SelDev *S) {
+  __shared__ double red[2 * 16];
+  const int na = S->na;
+  const unsigned act = active_mask(S->st);
+  if (!act) return;
+  const T lam = (T)S->lam, mu = (T)S->mu;
+  const T *in = (const T *)(MODE == SMO_PQ ? S->p : MODE == SMO_STEP1 ? S->d0 : MODE == SMO_RES ? S->d1
+                           : MODE == SMO_POST ? S->xv : S->d0);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  T q[NRHS][3];
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) q[k][0] = q[k][1] = q[k][2] = T(0);
+  double acc[NRHS][2];
+#pragma unroll
+  for (int k = 0; k < NRHS; ++k) acc[k][0] = acc[k][1] = 0.0;
+  if (i < na) {
+    int nb[27];
+    T E[8];
+    node_frame<T>(S, i, (const T *)S->Ec, nb, E);
+    apply_row<T, T>(E, lam, mu, nb, in, na, act, q);
+    const T dv = ((const T *)S->Dinv)[i];
+    const T it = (T)S->inv_theta, c1 = (T)S->c1, c2 = (T)S->c2;
+    if constexpr (MODE == SMO_PQ) {
+      T pr[3 * NRHS], qr[3 * NRHS];
+      load_row((const T *)S->p, i, pr);
+#pragma unroll
+      for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          qr[3 * k + c] = q[k][c];
+          acc[k][0] += (double)pr[3 * k + c] * (double)q[k][c];
+        }
+      store_row((T *)S->q, i, qr);
+    } else if constexpr (MODE == SMO_STEP1) {
+      T b[3 * NRHS], d0[3 * NRHS], r1[3 * NRHS], d1[3 * NRHS], x[3 * NRHS];
+      load_row((const T *)S->r, i, b);
+      load_row((const T *)S->d0, i, d0);
+#pragma unroll
+      for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int o = 3 * k + c;
+          r1[o] = b[o] - q[k][c];
+          d1[o] = c1 * d0[o] + c2 * dv * r1[o];
+          x[o] = d0[o] + d1[o];
+        }
+      store_row((T *)S->rv, i, r1);
+      store_row((T *)S->d1, i, d1);
+      store_row((T *)S->xv, i, x);
+    } else if constexpr (MODE == SMO_RES) {
+      T r[3 * NRHS];
+      load_row((const T *)S->rv, i, r);
+#pragma unroll
+      for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[3 * k + c] -= q[k][c];
+      store_row((T *)S->rv, i, r);
+    } else if constexpr (MODE == SMO_POST) {
+      // x is this pass's operand: the updated x goes to d1 (free after the
+      // restriction), not over the neighbours' input
+      T b[3 * NRHS], x[3 * NRHS], r[3 * NRHS], d0[3 * NRHS];
+      load_row((const T *)S->r, i, b);
+      load_row((const T *)S->xv, i, x);
+#pragma unroll
+      for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int o = 3 * k + c;
+          r[o] = b[o] - q[k][c];
+          d0[o] = it * dv * r[o];
+          x[o] += d0[o];
+        }
+      store_row((T *)S->rv, i, r);
+      store_row((T *)S->d0, i, d0);
+      store_row((T *)S->d1, i, x);
+    } else {  // SMO_LAST: z = x + d1 into xv, and the sums b . z, b . b
+      T b[3 * NRHS], x[3 * NRHS], r[3 * NRHS], d0[3 * NRHS];
+      load_row((const T *)S->r, i, b);
+      load_row((const T *)S->d1, i, x);
+      load_row((const T *)S->rv, i, r);
+      load_row((const T *)S->d0, i, d0);
+#pragma unroll
+      for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int o = 3 * k + c;
+          const T r2 = r[o] - q[k][c];
+          x[o] += c1 * d0[o] + c2 * dv * r2;
+          acc[k][0] += (double)b[o] * (double)x[o];
+          acc[k][1] += (double)b[o] * (double)b[o];
+        }
+      store_row((T *)S->xv, i, x);
+    }
+  }
+  if constexpr (MODE == SMO_PQ || MODE == SMO_LAST) {
+    double *parts = S->partials;
+    const int np = S->nparts;
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+      if (!((act >> k) & 1u)) continue;
+      double v[2] = {acc[k][0], acc[k][1]};
+      block_sum<2>(v, red, SEL_THREADS);
+      if (threadIdx.x == 0) {
+        parts[((long long)k * np + blockIdx.x) * SEL_PS + 0] = v[0];
+        parts[((long long)k * np + blockIdx.x) * SEL_PS + 1] = v[1];
+      }
+    }
+  }
+}
+
+// the CG update x += alpha p, r -= alpha q (not on a restart), then the first
+// Chebyshev direction d0 = D^-1 r / theta
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_s1_kernel(SelDev *S, int restart) {
+  const int na = S->na;
+  const CgState *st = S->st;
+  T a[NRHS];
+  for (int k = 0; k < NRHS; ++k) a[k] = restart ? T(0) : (T)st->alpha[k];
+  const T it = (T)S->inv_theta;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    const T dv = ((const T *)S->Dinv)[i];
+    T x[3 * NRHS], r[3 * NRHS], p[3 * NRHS], q[3 * NRHS], d0[3 * NRHS];
+    load_row((const T *)S->r, i, r);
+    if (!restart) {
+      load_row((const T *)S->x, i, x);
+      load_row((const T *)S->p, i, p);
+      load_row((const T *)S->q, i, q);
+    }
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int o = 3 * k + c;
+        if (!restart && a[k] != T(0)) {
+          x[o] += a[k] * p[o];
+          r[o] -= a[k] * q[o];
+        }
+        d0[o] = it * dv * r[o];
+      }
+    if (!restart) {
+      store_row((T *)S->x, i, x);
+      store_row((T *)S->r, i, r);
+    }
+    store_row((T *)S->d0, i, d0);
+  }
+}
+
+// p = z + beta p for the running load cases (beta = 0 after a restart)
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_dir_kernel(SelDev *S) {
+  const int na = S->na;
+  const unsigned act = active_mask(S->st);
+  if (!act) return;
+  T b[NRHS];
+  for (int k = 0; k < NRHS; ++k) b[k] = (T)S->st->beta[k];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    T z[3 * NRHS], p[3 * NRHS];
+    load_row((const T *)S->xv, i, z);
+    load_row((const T *)S->p, i, p);
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+      if (!((act >> k) & 1u)) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p[3 * k + c] = z[3 * k + c] + b[k] * p[3 * k + c];
+    }
+    store_row((T *)S->p, i, p);
+  }
+}
+
+// b1 = P^T r2: coarse node I collects the fine nodes 2 I + o, o in {-1, 0, 1}^3,
+// with weight prod (o == 0 ? 1 : 1/2); culled fine nodes hold zero
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_restrict_kernel(SelDev *S) {
+  const int n = S->n, n1 = S->n1;
+  const long long nn1 = S->nn1;
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nn1) return;
+  const int X = int(I % n1), Y = int((I / n1) % n1), Z = int(I / ((long long)n1 * n1));
+  T acc[3 * NRHS];
+#pragma unroll
+  for (int o = 0; o < 3 * NRHS; ++o) acc[o] = T(0);
+  const T *rv = (const T *)S->rv;
+  for (int oz = -1; oz <= 1; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int fx = wrap1(2 * X + ox, n), fy = wrap1(2 * Y + oy, n), fz = wrap1(2 * Z + oz, n);
+        const int j = S->map[((long long)fz * n + fy) * n + fx];
+        if (j < 0) continue;
+        const T w = T((ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0));
+        T v[3 * NRHS];
+        load_row(rv, j, v);
+#pragma unroll
+        for (int o = 0; o < 3 * NRHS; ++o) acc[o] += w * v[o];
+      }
+  T *b1 = (T *)S->b1;
+#pragma unroll
+  for (int o = 0; o < 3 * NRHS; ++o) b1[(long long)o * nn1 + I] = acc[o];
+}
+
+// z += P x1 at the active nodes: per axis, an even fine index has one coarse
+// parent (weight 1), an odd one two (weight 1/2 each)
+template <typename T>
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_prolong_kernel(SelDev *S) {
+  const int na = S->na, n1 = S->n1;
+  const long long nn1 = S->nn1;
+  const T *x1 = (const T *)S->x1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    const unsigned cd = S->coord[i];
+    const int c3[3] = {int(cd & 1023u), int((cd >> 10) & 1023u), int(cd >> 20)};
+    int par[3][2];
+    T wt[3][2];
+    int cnt[3];
+    for (int a = 0; a < 3; ++a) {
+      if ((c3[a] & 1) == 0) {
+        par[a][0] = c3[a] >> 1;
+        wt[a][0] = T(1);
+        cnt[a] = 1;
+      } else {
+        par[a][0] = c3[a] >> 1;
+        par[a][1] = (c3[a] >> 1) + 1 == n1 ? 0 : (c3[a] >> 1) + 1;
+        wt[a][0] = wt[a][1] = T(0.5);
+        cnt[a] = 2;
+      }
+    }
+    T z[3 * NRHS];
+    load_row((const T *)S->xv, i, z);
+    for (int kz = 0; kz < cnt[2]; ++kz)
+      for (int ky = 0; ky < cnt[1]; ++ky)
+        for (int kx = 0; kx < cnt[0]; ++kx) {
+          const long long I = ((long long)par[2][kz] * n1 + par[1][ky]) * n1 + par[0][kx];
+          const T w = wt[0][kx] * wt[1][ky] * wt[2][kz];
+#pragma unroll
+          for (int o = 0; o < 3 * NRHS; ++o) z[o] += w * x1[(long long)o * nn1 + I];
+        }
+    store_row((T *)S->xv, i, z);
+  }
+}
+
 // ---- launchers ----------------------------------------------------------------
 hipError_t sel_launch_compact(SelDev *d, const SelDev &h, hipStream_t st) {
   sel_count_kernel<<<h.nchunks, SEL_THREADS, 0, st>>>(d);
@@ -766,6 +1116,47 @@ hipError_t sel_launch_finish(SelDev *d, const SelDev &h, int rmode, hipStream_t 
 hipError_t sel_launch_zero(SelDev *d, const SelDev &h, hipStream_t st) {
   if (h.prec == SHH_PREC_FP64) sel_zero_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
   else sel_zero_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_mg_op(SelDev *d, const SelDev &h, int mode, hipStream_t st) {
+  const bool f64 = h.prec == SHH_PREC_FP64;
+#define SEL_MG_OP(M)                                                                     \
+  if (f64) sel_mg_op_kernel<double, M><<<h.nparts, SEL_THREADS, 0, st>>>(d);            \
+  else sel_mg_op_kernel<float, M><<<h.nparts, SEL_THREADS, 0, st>>>(d)
+  switch (mode) {
+    case SMO_PQ: SEL_MG_OP(SMO_PQ); break;
+    case SMO_STEP1: SEL_MG_OP(SMO_STEP1); break;
+    case SMO_RES: SEL_MG_OP(SMO_RES); break;
+    case SMO_POST: SEL_MG_OP(SMO_POST); break;
+    default: SEL_MG_OP(SMO_LAST); break;
+  }
+#undef SEL_MG_OP
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_mg_s1(SelDev *d, const SelDev &h, int restart, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_mg_s1_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d, restart);
+  else sel_mg_s1_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d, restart);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_mg_dir(SelDev *d, const SelDev &h, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_mg_dir_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  else sel_mg_dir_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_mg_restrict(SelDev *d, const SelDev &h, hipStream_t st) {
+  const int g = int((h.nn1 + SEL_THREADS - 1) / SEL_THREADS);
+  if (h.prec == SHH_PREC_FP64) sel_mg_restrict_kernel<double><<<g, SEL_THREADS, 0, st>>>(d);
+  else sel_mg_restrict_kernel<float><<<g, SEL_THREADS, 0, st>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_mg_prolong(SelDev *d, const SelDev &h, hipStream_t st) {
+  if (h.prec == SHH_PREC_FP64) sel_mg_prolong_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+  else sel_mg_prolong_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
   return hipGetLastError();
 }
 

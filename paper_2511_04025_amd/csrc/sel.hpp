@@ -56,13 +56,26 @@ struct SelDev {
   double *x64;            // [6][3][na] FP64 solution accumulator (mixed); == x for FP64
   double *partials;       // [6][nparts][SEL_PS]
   CgState *st;
+  // multigrid preconditioner (mg != 0): the voxel level's V-cycle steps run on
+  // the compact lists, the coarse levels on the dense hierarchy built from the
+  // culled moduli.  Chebyshev coefficients of the voxel level, the V-cycle's
+  // vectors (node-major, working precision) and the first coarse level's
+  // right-hand side and iterate ([6][3][n1^3], dense)
+  int mg;
+  int n1;
+  long long nn1;
+  double inv_theta, c1, c2;
+  void *d0, *d1, *xv, *rv;
+  void *b1, *x1;
 };
 
 // operator pass flavours
 enum { SOP_PCG = 0, SOP_RESID = 1, SOP_ENERGY = 2, SOP_APPLY = 3 };
 // scalar phases
 enum { SSC_ITER = 0, SSC_MEAN = 1, SSC_RESID_INIT = 2, SSC_RESID_REPLACE = 3, SSC_RESID_FINAL = 4,
-       SSC_ENERGY = 5 };
+       SSC_ENERGY = 5, SSC_MG_ALPHA = 6, SSC_MG_BETA = 7, SSC_MG_RESTART = 8 };
+// voxel-level passes of the multigrid-preconditioned solve (input vector -> epilogue)
+enum { SMO_PQ = 0, SMO_STEP1 = 1, SMO_RES = 2, SMO_POST = 3, SMO_LAST = 4 };
 
 hipError_t sel_launch_compact(SelDev *d, const SelDev &h, hipStream_t st);   // map, coord, counts (na)
 hipError_t sel_launch_gather(SelDev *d, const SelDev &h, hipStream_t st);    // Ec, Ec64, Dinv
@@ -73,5 +86,13 @@ hipError_t sel_launch_dir0(SelDev *d, const SelDev &h, hipStream_t st);       //
 hipError_t sel_launch_fold(SelDev *d, const SelDev &h, int all, hipStream_t st);  // x64 += x32, x32 = 0
 hipError_t sel_launch_finish(SelDev *d, const SelDev &h, int rmode, hipStream_t st);  // r -= mean; rho, rr partials
 hipError_t sel_launch_zero(SelDev *d, const SelDev &h, hipStream_t st);       // x, x64, p = 0
+// multigrid: operator pass with a V-cycle epilogue; the CG update fused with
+// the first Chebyshev direction (restart: no update); the CG direction;
+// restriction to and prolongation from the first coarse level
+hipError_t sel_launch_mg_op(SelDev *d, const SelDev &h, int mode, hipStream_t st);
+hipError_t sel_launch_mg_s1(SelDev *d, const SelDev &h, int restart, hipStream_t st);
+hipError_t sel_launch_mg_dir(SelDev *d, const SelDev &h, hipStream_t st);
+hipError_t sel_launch_mg_restrict(SelDev *d, const SelDev &h, hipStream_t st);
+hipError_t sel_launch_mg_prolong(SelDev *d, const SelDev &h, hipStream_t st);
 
 }  // namespace shh

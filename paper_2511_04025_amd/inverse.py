@@ -192,10 +192,10 @@ class InverseResult:
     history: History
 
 
-def _spec(n, kappa, target_vf, E_void, precision, rtol, solver, K):
+def _spec(n, kappa, target_vf, E_void, precision, rtol, solver, K, symmetry=0):
     from . import autograd as AG
     return AG.Spec(n=n, thickness=None, kappa=kappa, K=K, E_void=E_void, precision=precision, rtol=rtol,
-                   solver=solver, target_vf=target_vf)
+                   solver=solver, target_vf=target_vf, symmetry=symmetry)
 
 
 def evaluate_population(pos_list, q, alpha, spec, obj):
@@ -204,7 +204,8 @@ def evaluate_population(pos_list, q, alpha, spec, obj):
     from . import api
     from .workloads import Design
     designs = [Design(pos=np.mod(p, 1.0), q=q, n=spec.n, K=spec.K, alpha=alpha, thickness=None,
-                      target_vf=spec.target_vf, kappa=spec.kappa, E_void=spec.E_void) for p in pos_list]
+                      target_vf=spec.target_vf, kappa=spec.kappa, E_void=spec.E_void, symmetry=spec.symmetry)
+               for p in pos_list]
     out = []
     chunk = 64  # the library's largest batch
     for s in range(0, len(designs), chunk):
@@ -219,15 +220,17 @@ def evaluate_population(pos_list, q, alpha, spec, obj):
 
 def alternating_optimize(pos0, q, n, obj, *, alpha0=None, K=3, target_vf=0.1, kappa=None, E_void=1e-6,
                          rounds=2, alpha_steps=4, alpha_lr=0.05, cma_generations=3, popsize=None,
-                         sigma0=0.03, precision="mixed", rtol=3e-6, solver="auto", seed=0,
+                         sigma0=0.03, precision="mixed", rtol=3e-6, solver="auto", seed=0, symmetry=0,
                          callback: Optional[Callable] = None) -> InverseResult:
     """Sec. 4.3's alternating scheme: per round, (i) the volume constraint sets
     t (bisection inside every forward), (ii) `alpha_steps` Adam steps on
     alpha along the constraint, (iii) `cma_generations` CMA-ES generations on
-    the positions.  kappa defaults to 4 n (a one-voxel transition)."""
+    the positions.  kappa defaults to 4 n (a one-voxel transition).  With a
+    symmetry mode the positions are those of the fundamental bounding volume
+    (Sec. 3.2): every evaluation mirrors them over the cell."""
     from . import autograd as AG
     kappa = 4.0 * n if kappa is None else float(kappa)
-    spec = _spec(n, kappa, target_vf, E_void, precision, rtol, solver, K)
+    spec = _spec(n, kappa, target_vf, E_void, precision, rtol, solver, K, symmetry)
     pos = np.mod(np.asarray(pos0, dtype=np.float64).reshape(-1, 3), 1.0)
     q = np.asarray(q, dtype=np.float64).ravel()
     alpha = np.ones((K + 1,) * 3) if alpha0 is None else np.asarray(alpha0, dtype=np.float64).copy()

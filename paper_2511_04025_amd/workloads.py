@@ -41,6 +41,7 @@ class Design:
     E_void: float = 1e-3
     seed: Optional[int] = None
     tag: str = ""
+    symmetry: object = 0  # 0/'none', 1/'mirror' (8 images), 2/'cubic' (48 images): pos, q lie in the FBV
 
     def with_(self, **kw):
         return replace(self, **kw)

@@ -42,12 +42,36 @@ def test_every_declared_function_is_exported(lib):
     assert sorted(B.EXPORTS) == names
 
 
-def test_struct_layouts_match_the_header():
-    # shh_design: 2 int32, 2 pointers, int32 (+pad), pointer, 4 doubles, int32 (+pad), 3 doubles
-    assert ctypes.sizeof(B.ShhDesign) == 104
+def test_struct_layouts_match_the_header(tmp_path):
+    # shh_design: 2 int32, 2 pointers, int32 (+pad), pointer, 4 doubles, int32 (+pad), 3 doubles, int32 (+pad)
+    assert ctypes.sizeof(B.ShhDesign) == 112
     assert ctypes.sizeof(B.ShhOpts) == 40
     assert ctypes.sizeof(B.ShhResult) == 36 * 8 + 2 * 8 + 6 * 4 + 6 * 8 + 5 * 8 + 8
     assert B.ShhResult.status.offset == ctypes.sizeof(B.ShhResult) - 8
+    assert B.ShhResult.active_nodes.offset == ctypes.sizeof(B.ShhResult) - 4
+    # and the C compiler agrees, field by field
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    inc = os.path.join(os.path.dirname(B.HERE), "include")
+    checks = []
+    for struct, cls in (("shh_design", B.ShhDesign), ("shh_opts", B.ShhOpts), ("shh_result", B.ShhResult)):
+        checks.append(f'printf("{struct} %zu\\n", sizeof({struct}));')
+        for name, _ in cls._fields_:
+            checks.append(f'printf("{struct}.{name} %zu\\n", offsetof({struct}, {name}));')
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"shellhom.h\"\nint main(void) {\n"
+                   + "\n".join(checks) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    for struct, cls in (("shh_design", B.ShhDesign), ("shh_opts", B.ShhOpts), ("shh_result", B.ShhResult)):
+        assert int(out[struct]) == ctypes.sizeof(cls), struct
+        for name, _ in cls._fields_:
+            assert int(out[f"{struct}.{name}"]) == getattr(cls, name).offset, (struct, name)
 
 
 def test_version_and_status_strings(lib):
@@ -194,12 +218,17 @@ def test_multigrid_solver_option(lib):
         assert rc_a == B.SHH_OK and na == (nm if rc_m == B.SHH_OK else nj), n
     a = B.DesignArgs(wl.small_shell_24())
     nb = c_size_t(0)
-    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=4)
+    o = B.ShhOpts(precision=1, rtol=1e-6, max_iter=10, solver=5)
     assert lib.shh_workspace_bytes(byref(a.c), byref(o), byref(nb)) == B.SHH_INVALID_ARG
-    # the selective solve works in the Jacobi path's workspace, at any n
+    # the selective solve works in the multigrid solver's workspace where the
+    # grid coarsens, else (and with Jacobi only) in the Jacobi path's, at any n
     for n in (24, 37):
         d = wl.shell_128(2000, n=n)
-        assert ws_bytes(lib, d, "mixed", solver="selective") == ws_bytes(lib, d, "mixed", solver="jacobi")
+        _, nsel = ws_bytes(lib, d, "mixed", solver="selective")
+        _, nsj = ws_bytes(lib, d, "mixed", solver="selective-jacobi")
+        _, nj = ws_bytes(lib, d, "mixed", solver="jacobi")
+        rc_m, nm = ws_bytes(lib, d, "mixed", solver="mg")
+        assert nsj == nj and nsel == (nm if rc_m == B.SHH_OK else nj), n
 
 
 def test_field_entry_point_validation(lib):
@@ -213,3 +242,20 @@ def test_field_entry_point_validation(lib):
         rc = lib.shh_homogenize_field(n, fake, dt, c_double(Es), c_double(Ev), c_double(nu), byref(o), fake,
                                       c_size_t(1 << 20), None, byref(res))
         assert rc == B.SHH_INVALID_ARG, (n, dt, Es, Ev, nu)
+
+
+def test_point_field_workspace_needs_only_charges(lib):
+    # the point-field entries read the charges, alpha, K and symmetry mode only:
+    # a design without a thickness rule is accepted, and the size grows with
+    # the points and with the symmetry images
+    d = wl.Design(pos=np.zeros((2, 3)), q=np.array([1.0, -1.0]), n=8, K=3)
+    sizes = []
+    for npts, sym in ((100, 0), (10000, 0), (100, 2)):
+        a = B.DesignArgs(d.with_(symmetry=sym))
+        nb = c_size_t(0)
+        assert lib.shh_workspace_bytes_points(byref(a.c), npts, byref(nb)) == B.SHH_OK
+        sizes.append(nb.value)
+    assert sizes[1] > sizes[0] and sizes[2] > sizes[0]
+    a = B.DesignArgs(d)
+    nb = c_size_t(0)
+    assert lib.shh_workspace_bytes_points(byref(a.c), 0, byref(nb)) == B.SHH_INVALID_ARG
