@@ -162,9 +162,11 @@ int homogenize_run(const shh_design *designs, int32_t count, const shh_opts *opt
     SHH_TRY(slot_init(*s, s->base, st));
     SHH_TRY(slot_setup_field(*s, nullptr, st));
     s->timing = timed;
-    if (is_selective(o.solver)) SHH_TRY(sel_solve(*s, st));  // one design at a time
   }
   if (is_selective(o.solver)) {
+    std::vector<Slot *> ptrs;
+    for (auto &s : slots) ptrs.push_back(s.get());
+    SHH_TRY(sel_solve(ptrs, st));  // the batch shares every launch
     int worst = SHH_OK;
     for (int i = 0; i < count; ++i) {
       fill_result(*slots[i], &out[i]);

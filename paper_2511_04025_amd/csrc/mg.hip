@@ -162,6 +162,15 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
     any = any || act[r];
   }
   if (!any) return;
+  if (((const T *)L.Dinv)[v] == T(0)) {  // a zero row (all elements around the node culled)
+    T *q = (T *)L.q + (long long)r0 * 3 * nn;
+#pragma unroll
+    for (int r = 0; r < RHS; ++r)
+      if (act[r])
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = T(0);
+    return;
+  }
   const int n = L.n;
   const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
   const T *S = (const T *)L.S;
@@ -231,6 +240,22 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
   const long long v0 = (long long)z0 * plane + xy;
   const T *S = (const T *)L.S;
   const T *in = (const T *)(src == 0 ? L.x : L.d);
+  T *q = (T *)L.q;
+  {
+    // nodes with a zero diagonal have a zero row (every element around them
+    // culled): their output is zero without reading their stencil
+    const T *Dv = (const T *)L.Dinv;
+    if (Dv[v0] == T(0) && Dv[v0 + plane] == T(0)) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+          if (act[r])
+#pragma unroll
+            for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v0 + k * plane] = T(0);
+      return;
+    }
+  }
   T acc[2][NRHS][3];
 #pragma unroll
   for (int k = 0; k < 2; ++k)
@@ -275,7 +300,6 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
       }
     }
   }
-  T *q = (T *)L.q;
 #pragma unroll
   for (int k = 0; k < 2; ++k)
 #pragma unroll

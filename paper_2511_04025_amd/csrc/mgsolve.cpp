@@ -472,11 +472,17 @@ int mg_setup(const std::vector<Slot *> &all, hipStream_t st, std::vector<int> *r
 
 int mg_setup(Slot &s, hipStream_t st) { return mg_setup(std::vector<Slot *>{&s}, st); }
 
-int mg_vcycle_coarse(Slot &s, hipStream_t st) {
-  if (s.mg.L < 1) return SHH_UNSUPPORTED;
+int mg_vcycle_coarse(const std::vector<Slot *> &slots, hipStream_t st) {
+  for (Slot *s : slots)
+    if (s->mg.L < 1) return SHH_UNSUPPORTED;
   // levels >= 1 never call the voxel-level operator
   const MgApply0 none = [](const std::vector<Slot *> &, int) { return SHH_UNSUPPORTED; };
-  return vcycle(std::vector<Slot *>{&s}, 1, st, nullptr, none);
+  int rc;
+  for (size_t b0 = 0; b0 < slots.size(); b0 += MG_MAXB) {
+    const std::vector<Slot *> part(slots.begin() + b0, slots.begin() + std::min(slots.size(), b0 + MG_MAXB));
+    if ((rc = vcycle(part, 1, st, nullptr, none))) return rc;
+  }
+  return SHH_OK;
 }
 
 int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {

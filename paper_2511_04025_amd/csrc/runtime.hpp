@@ -97,9 +97,9 @@ using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // (timer: when profiling, the largest coarse level's operator launches are
 // timed with their algorithmic bytes)
 int mg_iterate(const std::vector<Slot *> &slots, hipStream_t st, Solver *timer, const MgApply0 &apply0);
-// the V-cycle of a set-up slot from level 1 down: lv[1].b in, lv[1].x out
-// (the selective solve runs the voxel level itself)
-int mg_vcycle_coarse(Slot &s, hipStream_t st);
+// the V-cycle of set-up slots from level 1 down: lv[1].b in, lv[1].x out
+// (the selective solve runs the voxel level itself); batched launches
+int mg_vcycle_coarse(const std::vector<Slot *> &slots, hipStream_t st);
 // q = A_l v for the Galerkin operator of level l >= 1 of a set-up slot (all six
 // load cases, [6][3][n_l^3] in the slot's precision)
 int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st);
@@ -175,9 +175,11 @@ int profile_read(int kind, long long *launches, double *ms);
 void profile_add(int kind, double ms);
 
 double now_ms();
-// the selective solve of one slot whose culled moduli are in place (field
-// setup or given moduli): compaction, CG on the active nodes, C^H
-int sel_solve(Slot &s, hipStream_t st);
+// the selective solve of slots whose culled moduli are in place (field setup
+// or given moduli): compaction, CG on the active nodes, C^H; the slots share
+// every launch (same precision and solver option)
+int sel_solve(const std::vector<Slot *> &slots, hipStream_t st);
+inline int sel_solve(Slot &s, hipStream_t st) { return sel_solve(std::vector<Slot *>{&s}, st); }
 void fill_result(const Slot &s, shh_result *out);
 
 }  // namespace shh

@@ -75,7 +75,9 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *s, int *total) {
 // ---- compaction ---------------------------------------------------------------
 // Chunk b covers grid nodes [b * 1024, (b + 1) * 1024), four consecutive nodes
 // per thread; nodes keep their linear (z, y, x) order.
-__global__ __launch_bounds__(SEL_THREADS) void sel_count_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_count_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nchunks) return;
   __shared__ int s[SEL_THREADS];
   const int n = S->n;
   const long long nn = S->nn;
@@ -95,7 +97,8 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_count_kernel(SelDev *S) {
 
 // exclusive offsets of the chunk counts (one workgroup of 1024 threads, each
 // summing a contiguous run); counts[nchunks] receives the total
-__global__ __launch_bounds__(1024) void sel_scan_kernel(SelDev *S) {
+__global__ __launch_bounds__(1024) void sel_scan_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
   __shared__ long long s[1024];
   const int nc = S->nchunks;
   const int per = (nc + 1023) / 1024;
@@ -119,7 +122,9 @@ __global__ __launch_bounds__(1024) void sel_scan_kernel(SelDev *S) {
   if (threadIdx.x == 1023) S->counts[nc] = int(s[1023]);
 }
 
-__global__ __launch_bounds__(SEL_THREADS) void sel_write_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_write_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nchunks) return;
   __shared__ int s[SEL_THREADS];
   const int n = S->n;
   const long long nn = S->nn;
@@ -152,11 +157,13 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_write_kernel(SelDev *S) {
 
 // moduli and Jacobi diagonal on the compact list
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_gather_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_gather_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int n = S->n, na = S->na;
   const double c = (S->lam + 4.0 * S->mu) / 9.0;
   const double *E = S->E64;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     const unsigned cd = S->coord[i];
     const int x = int(cd & 1023u), y = int((cd >> 10) & 1023u), z = int(cd >> 20);
     const int xm = wrap_dec(x, n), ym = wrap_dec(y, n), zm = wrap_dec(z, n);
@@ -322,7 +329,9 @@ __device__ __forceinline__ unsigned resid_cases(const CgState *st, int rmode, do
 // PCG: q = K p for the running load cases and the per-workgroup sums
 //   p.q, r.D^-1 r, q.D^-1 r, q.D^-1 q, r.r, q.r, q.q
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_op_pcg_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_pcg_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   __shared__ double red[7 * 16];
   const int na = S->na;
   const CgState *st = S->st;
@@ -387,7 +396,9 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_pcg_kernel(SelDev *S) {
 // precision; per-workgroup component sums of r (for the mean removal).
 // f at node i is -sum_a E_a (K_0 chi^k)_a.
 template <typename TV>
-__global__ __launch_bounds__(SEL_THREADS) void sel_op_resid_kernel(SelDev *S, int rmode) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_resid_kernel(const SelBatch B, int rmode) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   __shared__ double red[3 * 16];
   const int na = S->na;
   const unsigned act = resid_cases(S->st, rmode, S->ffloor);
@@ -398,7 +409,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_resid_kernel(SelDev *S, in
   double acc[NRHS][3];
 #pragma unroll
   for (int k = 0; k < NRHS; ++k) acc[k][0] = acc[k][1] = acc[k][2] = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     int nb[27];
     double E[8];
     node_frame<double>(S, i, S->Ec64, nb, E);
@@ -439,7 +450,9 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_resid_kernel(SelDev *S, in
 //     = (sum_e E_e) D_ij - f^i . u^j - f^j . u^i + u^i . K u^j,
 // since chi^i^T K_0 chi^j = D_ij and f^i = -sum_e P_e^T E_e K_0 chi^i.
 // Per workgroup: the 21 sums S_ij (i <= j) and sum_e E_e.
-__global__ __launch_bounds__(SEL_THREADS) void sel_op_energy_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_energy_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   __shared__ double red[22 * 16];
   const int na = S->na;
   const double lam = S->lam, mu = S->mu;
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_energy_kernel(SelDev *S) {
   double acc[22];
 #pragma unroll
   for (int s = 0; s < 22; ++s) acc[s] = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     int nb[27];
     double E[8];
     node_frame<double>(S, i, S->Ec64, nb, E);
@@ -487,12 +500,14 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_energy_kernel(SelDev *S) {
 
 // plain q = K p for every load case (operator parity tests)
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_op_apply_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_op_apply_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na;
   const T lam = (T)S->lam, mu = (T)S->mu;
   const T *P = (const T *)S->p;
   T *Q = (T *)S->q;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     int nb[27];
     T E[8];
     node_frame<T>(S, i, (const T *)S->Ec, nb, E);
@@ -511,7 +526,9 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_op_apply_kernel(SelDev *S) {
 // x += alpha p, r -= alpha q, p = D^-1 r + beta p for the load cases the
 // scalar phase gave a step (alpha != 0)
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_update_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_update_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na;
   const CgState *st = S->st;
   T *X = (T *)S->x, *Rv = (T *)S->r, *P = (T *)S->p;
@@ -524,7 +541,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_update_kernel(SelDev *S) {
     if (st->alpha[k] != 0.0) step |= 1u << k;
   }
   if (!step) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     const T d = Dv[i];
     T x[3 * NRHS], r[3 * NRHS], p[3 * NRHS], q[3 * NRHS];
     load_row(X, i, x);
@@ -552,14 +569,16 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_update_kernel(SelDev *S) {
 
 // p = D^-1 r (start of the iteration) for every load case still running
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_dir0_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_dir0_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na;
   const CgState *st = S->st;
   T *P = (T *)S->p;
   const T *Rv = (const T *)S->r, *Dv = (const T *)S->Dinv;
   for (int k = 0; k < NRHS; ++k) {
     if (!st->active[k]) continue;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const long long o = (long long)i * (3 * NRHS) + 3 * k + c;
@@ -569,14 +588,16 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_dir0_kernel(SelDev *S) {
 }
 
 // mixed: x64 += x32, x32 = 0 (every load case, or the running ones)
-__global__ __launch_bounds__(SEL_THREADS) void sel_fold_kernel(SelDev *S, int all) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_fold_kernel(const SelBatch B, int all) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na;
   const CgState *st = S->st;
   float *X = (float *)S->x;
   double *X64 = S->x64;
   for (int k = 0; k < NRHS; ++k) {
     if (!all && !st->active[k]) continue;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const long long o = (long long)i * (3 * NRHS) + 3 * k + c;
@@ -589,7 +610,9 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_fold_kernel(SelDev *S, int al
 // the recomputed residual: remove its component means (rigid translations of
 // the whole active set), then the sums r.D^-1 r and r.r
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_finish_kernel(SelDev *S, int rmode) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_finish_kernel(const SelBatch B, int rmode) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   __shared__ double red[2 * 16];
   const int na = S->na;
   const CgState *st = S->st;
@@ -600,7 +623,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_finish_kernel(SelDev *S, int 
     if (!((act >> k) & 1u)) continue;
     const T m[3] = {(T)st->mean[k][0], (T)st->mean[k][1], (T)st->mean[k][2]};
     double v[2] = {0.0, 0.0};
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
       const double d = (double)Dv[i];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -621,13 +644,15 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_finish_kernel(SelDev *S, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_zero_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_zero_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const long long m = (long long)NRHS * 3 * S->na;
   T *X = (T *)S->x, *P = (T *)S->p;
   double *X64 = S->x64;
   const bool mixed = S->prec == SHH_PREC_MIXED;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-       i += (long long)gridDim.x * blockDim.x) {
+       i += (long long)S->nparts * blockDim.x) {
     X[i] = T(0);
     P[i] = T(0);
     if (mixed) X64[i] = 0.0;
@@ -635,7 +660,8 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_zero_kernel(SelDev *S) {
 }
 
 // ---- scalar phases (one workgroup per load case; one in total for C^H) --------
-__global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(SelDev *S, int phase) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch B, int phase) {
+  SelDev *S = B.d[blockIdx.y];
   __shared__ double red[22 * 16];
   CgState *st = S->st;
   const int np = S->nparts;
@@ -783,7 +809,8 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(SelDev *S, int 
 }
 
 // component means of the recomputed residual
-__global__ __launch_bounds__(SEL_THREADS) void sel_mean_kernel(SelDev *S, int rmode) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_mean_kernel(const SelBatch B, int rmode) {
+  SelDev *S = B.d[blockIdx.y];
   __shared__ double red[3 * 16];
   CgState *st = S->st;
   const int k = blockIdx.x;
@@ -812,7 +839,9 @@ __device__ __forceinline__ unsigned active_mask(const CgState *st) {
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   __shared__ double red[2 * 16];
   const int na = S->na;
   const unsigned act = active_mask(S->st);
@@ -925,13 +954,15 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(SelDev *S) {
 // the CG update x += alpha p, r -= alpha q (not on a restart), then the first
 // Chebyshev direction d0 = D^-1 r / theta
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_mg_s1_kernel(SelDev *S, int restart) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_s1_kernel(const SelBatch B, int restart) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na;
   const CgState *st = S->st;
   T a[NRHS];
   for (int k = 0; k < NRHS; ++k) a[k] = restart ? T(0) : (T)st->alpha[k];
   const T it = (T)S->inv_theta;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     const T dv = ((const T *)S->Dinv)[i];
     T x[3 * NRHS], r[3 * NRHS], p[3 * NRHS], q[3 * NRHS], d0[3 * NRHS];
     load_row((const T *)S->r, i, r);
@@ -961,13 +992,15 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_s1_kernel(SelDev *S, int r
 
 // p = z + beta p for the running load cases (beta = 0 after a restart)
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_mg_dir_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_dir_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na;
   const unsigned act = active_mask(S->st);
   if (!act) return;
   T b[NRHS];
   for (int k = 0; k < NRHS; ++k) b[k] = (T)S->st->beta[k];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     T z[3 * NRHS], p[3 * NRHS];
     load_row((const T *)S->xv, i, z);
     load_row((const T *)S->p, i, p);
@@ -984,7 +1017,8 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_dir_kernel(SelDev *S) {
 // b1 = P^T r2: coarse node I collects the fine nodes 2 I + o, o in {-1, 0, 1}^3,
 // with weight prod (o == 0 ? 1 : 1/2); culled fine nodes hold zero
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_mg_restrict_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_restrict_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
   const int n = S->n, n1 = S->n1;
   const long long nn1 = S->nn1;
   const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1014,11 +1048,13 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_restrict_kernel(SelDev *S)
 // z += P x1 at the active nodes: per axis, an even fine index has one coarse
 // parent (weight 1), an odd one two (weight 1/2 each)
 template <typename T>
-__global__ __launch_bounds__(SEL_THREADS) void sel_mg_prolong_kernel(SelDev *S) {
+__global__ __launch_bounds__(SEL_THREADS) void sel_mg_prolong_kernel(const SelBatch B) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
   const int na = S->na, n1 = S->n1;
   const long long nn1 = S->nn1;
   const T *x1 = (const T *)S->x1;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     const unsigned cd = S->coord[i];
     const int c3[3] = {int(cd & 1023u), int((cd >> 10) & 1023u), int(cd >> 20)};
     int par[3][2];
@@ -1051,79 +1087,84 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_prolong_kernel(SelDev *S) 
 }
 
 // ---- launchers ----------------------------------------------------------------
-hipError_t sel_launch_compact(SelDev *d, const SelDev &h, hipStream_t st) {
-  sel_count_kernel<<<h.nchunks, SEL_THREADS, 0, st>>>(d);
-  sel_scan_kernel<<<1, 1024, 0, st>>>(d);
-  sel_write_kernel<<<h.nchunks, SEL_THREADS, 0, st>>>(d);
+// Every launch covers the batch's slots (grid y = slot); workgroups past a
+// slot's own count return at once.
+namespace {
+dim3 parts_grid(const SelBatch &B) { return dim3((unsigned)std::max(B.parts_max, 1), (unsigned)B.count); }
+}  // namespace
+
+#define SEL_PREC_LAUNCH(kern, grid, ...)                                                  \
+  do {                                                                                  \
+    if (B.prec == SHH_PREC_FP64) kern<double><<<grid, SEL_THREADS, 0, st>>>(__VA_ARGS__); \
+    else kern<float><<<grid, SEL_THREADS, 0, st>>>(__VA_ARGS__);                        \
+  } while (0)
+
+hipError_t sel_launch_compact(const SelBatch &B, hipStream_t st) {
+  const dim3 g((unsigned)std::max(B.chunks_max, 1), (unsigned)B.count);
+  sel_count_kernel<<<g, SEL_THREADS, 0, st>>>(B);
+  sel_scan_kernel<<<dim3(1, B.count), 1024, 0, st>>>(B);
+  sel_write_kernel<<<g, SEL_THREADS, 0, st>>>(B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_gather(SelDev *d, const SelDev &h, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_gather_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-  else sel_gather_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_gather(const SelBatch &B, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_gather_kernel, parts_grid(B), B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_op(SelDev *d, const SelDev &h, int mode, hipStream_t st) {
-  const bool f64 = h.prec == SHH_PREC_FP64;
+hipError_t sel_launch_op(const SelBatch &B, int mode, hipStream_t st) {
+  const dim3 g = parts_grid(B);
   if (mode == SOP_PCG) {
-    if (f64) sel_op_pcg_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-    else sel_op_pcg_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+    SEL_PREC_LAUNCH(sel_op_pcg_kernel, g, B);
   } else if (mode == SOP_ENERGY) {
-    sel_op_energy_kernel<<<h.nparts, SEL_THREADS, 0, st>>>(d);
+    sel_op_energy_kernel<<<g, SEL_THREADS, 0, st>>>(B);
   } else if (mode == SOP_APPLY) {
-    if (f64) sel_op_apply_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-    else sel_op_apply_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+    SEL_PREC_LAUNCH(sel_op_apply_kernel, g, B);
   } else {
-    // SOP_RESID + rmode: 10 + rmode
-    const int rmode = mode - 10;
-    if (f64) sel_op_resid_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
-    else sel_op_resid_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
+    const int rmode = mode - 10;  // SOP_RESID + rmode: 10 initial, 11 replacement, 12 final
+    SEL_PREC_LAUNCH(sel_op_resid_kernel, g, B, rmode);
   }
   return hipGetLastError();
 }
 
-hipError_t sel_launch_scalar(SelDev *d, int phase, hipStream_t st) {
-  if (phase == SSC_ENERGY) sel_scalar_kernel<<<1, SEL_THREADS, 0, st>>>(d, phase);
-  else if (phase >= 100) sel_mean_kernel<<<NRHS, SEL_THREADS, 0, st>>>(d, phase - 100);
-  else sel_scalar_kernel<<<NRHS, SEL_THREADS, 0, st>>>(d, phase);
+hipError_t sel_launch_scalar(const SelBatch &B, int phase, hipStream_t st) {
+  if (phase == SSC_ENERGY) sel_scalar_kernel<<<dim3(1, B.count), SEL_THREADS, 0, st>>>(B, phase);
+  else if (phase >= 100) sel_mean_kernel<<<dim3(NRHS, B.count), SEL_THREADS, 0, st>>>(B, phase - 100);
+  else sel_scalar_kernel<<<dim3(NRHS, B.count), SEL_THREADS, 0, st>>>(B, phase);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_update(SelDev *d, const SelDev &h, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_update_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-  else sel_update_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_update(const SelBatch &B, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_update_kernel, parts_grid(B), B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_dir0(SelDev *d, const SelDev &h, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_dir0_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-  else sel_dir0_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_dir0(const SelBatch &B, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_dir0_kernel, parts_grid(B), B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_fold(SelDev *d, const SelDev &h, int all, hipStream_t st) {
-  if (h.prec == SHH_PREC_MIXED) sel_fold_kernel<<<h.nparts, SEL_THREADS, 0, st>>>(d, all);
+hipError_t sel_launch_fold(const SelBatch &B, int all, hipStream_t st) {
+  if (B.prec == SHH_PREC_MIXED) sel_fold_kernel<<<parts_grid(B), SEL_THREADS, 0, st>>>(B, all);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_finish(SelDev *d, const SelDev &h, int rmode, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_finish_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
-  else sel_finish_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d, rmode);
+hipError_t sel_launch_finish(const SelBatch &B, int rmode, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_finish_kernel, parts_grid(B), B, rmode);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_zero(SelDev *d, const SelDev &h, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_zero_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-  else sel_zero_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_zero(const SelBatch &B, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_zero_kernel, parts_grid(B), B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_mg_op(SelDev *d, const SelDev &h, int mode, hipStream_t st) {
-  const bool f64 = h.prec == SHH_PREC_FP64;
-#define SEL_MG_OP(M)                                                                     \
-  if (f64) sel_mg_op_kernel<double, M><<<h.nparts, SEL_THREADS, 0, st>>>(d);            \
-  else sel_mg_op_kernel<float, M><<<h.nparts, SEL_THREADS, 0, st>>>(d)
+hipError_t sel_launch_mg_op(const SelBatch &B, int mode, hipStream_t st) {
+  const bool f64 = B.prec == SHH_PREC_FP64;
+  const dim3 g = parts_grid(B);
+#define SEL_MG_OP(M)                                                                 \
+  if (f64) sel_mg_op_kernel<double, M><<<g, SEL_THREADS, 0, st>>>(B);                \
+  else sel_mg_op_kernel<float, M><<<g, SEL_THREADS, 0, st>>>(B)
   switch (mode) {
     case SMO_PQ: SEL_MG_OP(SMO_PQ); break;
     case SMO_STEP1: SEL_MG_OP(SMO_STEP1); break;
@@ -1135,29 +1176,27 @@ hipError_t sel_launch_mg_op(SelDev *d, const SelDev &h, int mode, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t sel_launch_mg_s1(SelDev *d, const SelDev &h, int restart, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_mg_s1_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d, restart);
-  else sel_mg_s1_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d, restart);
+hipError_t sel_launch_mg_s1(const SelBatch &B, int restart, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_mg_s1_kernel, parts_grid(B), B, restart);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_mg_dir(SelDev *d, const SelDev &h, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_mg_dir_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-  else sel_mg_dir_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_mg_dir(const SelBatch &B, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_mg_dir_kernel, parts_grid(B), B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_mg_restrict(SelDev *d, const SelDev &h, hipStream_t st) {
-  const int g = int((h.nn1 + SEL_THREADS - 1) / SEL_THREADS);
-  if (h.prec == SHH_PREC_FP64) sel_mg_restrict_kernel<double><<<g, SEL_THREADS, 0, st>>>(d);
-  else sel_mg_restrict_kernel<float><<<g, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_mg_restrict(const SelBatch &B, hipStream_t st) {
+  const dim3 g((unsigned)((B.nn1_max + SEL_THREADS - 1) / SEL_THREADS), (unsigned)B.count);
+  SEL_PREC_LAUNCH(sel_mg_restrict_kernel, g, B);
   return hipGetLastError();
 }
 
-hipError_t sel_launch_mg_prolong(SelDev *d, const SelDev &h, hipStream_t st) {
-  if (h.prec == SHH_PREC_FP64) sel_mg_prolong_kernel<double><<<h.nparts, SEL_THREADS, 0, st>>>(d);
-  else sel_mg_prolong_kernel<float><<<h.nparts, SEL_THREADS, 0, st>>>(d);
+hipError_t sel_launch_mg_prolong(const SelBatch &B, hipStream_t st) {
+  SEL_PREC_LAUNCH(sel_mg_prolong_kernel, parts_grid(B), B);
   return hipGetLastError();
 }
+
+#undef SEL_PREC_LAUNCH
 
 }  // namespace shh

@@ -77,22 +77,33 @@ enum { SSC_ITER = 0, SSC_MEAN = 1, SSC_RESID_INIT = 2, SSC_RESID_REPLACE = 3, SS
 // voxel-level passes of the multigrid-preconditioned solve (input vector -> epilogue)
 enum { SMO_PQ = 0, SMO_STEP1 = 1, SMO_RES = 2, SMO_POST = 3, SMO_LAST = 4 };
 
-hipError_t sel_launch_compact(SelDev *d, const SelDev &h, hipStream_t st);   // map, coord, counts (na)
-hipError_t sel_launch_gather(SelDev *d, const SelDev &h, hipStream_t st);    // Ec, Ec64, Dinv
-hipError_t sel_launch_op(SelDev *d, const SelDev &h, int mode, hipStream_t st);
-hipError_t sel_launch_scalar(SelDev *d, int phase, hipStream_t st);
-hipError_t sel_launch_update(SelDev *d, const SelDev &h, hipStream_t st);     // x, r, p after alpha, beta
-hipError_t sel_launch_dir0(SelDev *d, const SelDev &h, hipStream_t st);       // p = D^-1 r
-hipError_t sel_launch_fold(SelDev *d, const SelDev &h, int all, hipStream_t st);  // x64 += x32, x32 = 0
-hipError_t sel_launch_finish(SelDev *d, const SelDev &h, int rmode, hipStream_t st);  // r -= mean; rho, rr partials
-hipError_t sel_launch_zero(SelDev *d, const SelDev &h, hipStream_t st);       // x, x64, p = 0
+// One launch covers up to SEL_MAXB slots (grid y = slot) of one precision.
+constexpr int SEL_MAXB = 16;
+struct SelBatch {
+  SelDev *d[SEL_MAXB];    // device descriptors
+  int count;
+  int prec;
+  int parts_max;          // largest nparts of the batch
+  int chunks_max;         // largest nchunks
+  long long nn1_max;      // largest first-coarse-level node count (multigrid)
+};
+
+hipError_t sel_launch_compact(const SelBatch &B, hipStream_t st);   // map, coord, counts (na)
+hipError_t sel_launch_gather(const SelBatch &B, hipStream_t st);    // Ec, Ec64, Dinv
+hipError_t sel_launch_op(const SelBatch &B, int mode, hipStream_t st);
+hipError_t sel_launch_scalar(const SelBatch &B, int phase, hipStream_t st);
+hipError_t sel_launch_update(const SelBatch &B, hipStream_t st);     // x, r, p after alpha, beta
+hipError_t sel_launch_dir0(const SelBatch &B, hipStream_t st);       // p = D^-1 r
+hipError_t sel_launch_fold(const SelBatch &B, int all, hipStream_t st);  // x64 += x32, x32 = 0
+hipError_t sel_launch_finish(const SelBatch &B, int rmode, hipStream_t st);  // r -= mean; rho, rr partials
+hipError_t sel_launch_zero(const SelBatch &B, hipStream_t st);       // x, x64, p = 0
 // multigrid: operator pass with a V-cycle epilogue; the CG update fused with
 // the first Chebyshev direction (restart: no update); the CG direction;
 // restriction to and prolongation from the first coarse level
-hipError_t sel_launch_mg_op(SelDev *d, const SelDev &h, int mode, hipStream_t st);
-hipError_t sel_launch_mg_s1(SelDev *d, const SelDev &h, int restart, hipStream_t st);
-hipError_t sel_launch_mg_dir(SelDev *d, const SelDev &h, hipStream_t st);
-hipError_t sel_launch_mg_restrict(SelDev *d, const SelDev &h, hipStream_t st);
-hipError_t sel_launch_mg_prolong(SelDev *d, const SelDev &h, hipStream_t st);
+hipError_t sel_launch_mg_op(const SelBatch &B, int mode, hipStream_t st);
+hipError_t sel_launch_mg_s1(const SelBatch &B, int restart, hipStream_t st);
+hipError_t sel_launch_mg_dir(const SelBatch &B, hipStream_t st);
+hipError_t sel_launch_mg_restrict(const SelBatch &B, hipStream_t st);
+hipError_t sel_launch_mg_prolong(const SelBatch &B, hipStream_t st);
 
 }  // namespace shh

@@ -70,9 +70,43 @@ void element_forces(double lam, double mu, double (&f0)[NRHS][8][3]) {
       }
 }
 
-struct SelRun {
+// One design of a batch: its host copy of the descriptor, the device copy,
+// and where it stands.
+struct SelSlot {
+  Slot *s = nullptr;
   SelDev h;
   SelDev *d = nullptr;
+  bool done = false;  // converged (true residual checked), or given up
+  int finals = 0;     // final residual checks so far
+};
+
+SelBatch batch_of(const std::vector<SelSlot *> &v) {
+  SelBatch B;
+  std::memset(&B, 0, sizeof(B));
+  B.count = int(v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    B.d[i] = v[i]->d;
+    B.prec = v[i]->h.prec;
+    B.parts_max = std::max(B.parts_max, v[i]->h.nparts);
+    B.chunks_max = std::max(B.chunks_max, v[i]->h.nchunks);
+    B.nn1_max = std::max(B.nn1_max, v[i]->h.nn1);
+  }
+  return B;
+}
+
+std::vector<Slot *> slots_of(const std::vector<SelSlot *> &v) {
+  std::vector<Slot *> out;
+  for (SelSlot *x : v) out.push_back(x->s);
+  return out;
+}
+
+bool all_stopped(const CgState &c) {
+  for (int k = 0; k < NRHS; ++k)
+    if (c.active[k]) return false;
+  return true;
+}
+
+struct SelRun {
   hipStream_t st;
   bool timing = false;  // shh_profile_enable: HIP events around the timed launches
   std::vector<hipEvent_t> pool;
@@ -119,54 +153,90 @@ struct SelRun {
     }
     timed.clear();
   }
-  int read_state(Slot &s) {
-    SEL_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+  int read_state(const std::vector<SelSlot *> &v) {
+    for (SelSlot *x : v)
+      SEL_HIP(hipMemcpyAsync(&x->s->state, x->s->d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
     SEL_HIP(hipStreamSynchronize(st));
     resolve();
     return SHH_OK;
   }
+  void record(const std::vector<SelSlot *> &v, int k) {
+    for (SelSlot *x : v)
+      if (x->s->ev[k]) (void)hipEventRecord(x->s->ev[k], st);
+  }
   // recompute r = f - K x64 for the cases of rmode (0 initial, 1 replacement, 2 final)
-  int residual(int rmode) {
-    if (rmode != 0) SEL_HIP(sel_launch_fold(d, h, rmode == 2 ? 1 : 0, st));
+  int residual(const SelBatch &B, int rmode) {
+    if (rmode != 0) SEL_HIP(sel_launch_fold(B, rmode == 2 ? 1 : 0, st));
     int rc;
-    if ((rc = run_timed(SHH_PROF_SEL_RESID, [&] { return sel_launch_op(d, h, 10 + rmode, st); }))) return rc;
-    SEL_HIP(sel_launch_scalar(d, 100 + rmode, st));
-    SEL_HIP(sel_launch_finish(d, h, rmode, st));
-    SEL_HIP(sel_launch_scalar(d, rmode == 0 ? SSC_RESID_INIT : (rmode == 1 ? SSC_RESID_REPLACE : SSC_RESID_FINAL),
+    if ((rc = run_timed(SHH_PROF_SEL_RESID, [&] { return sel_launch_op(B, 10 + rmode, st); }))) return rc;
+    SEL_HIP(sel_launch_scalar(B, 100 + rmode, st));
+    SEL_HIP(sel_launch_finish(B, rmode, st));
+    SEL_HIP(sel_launch_scalar(B, rmode == 0 ? SSC_RESID_INIT : (rmode == 1 ? SSC_RESID_REPLACE : SSC_RESID_FINAL),
                               st));
+    return SHH_OK;
+  }
+  // multigrid-preconditioned CG (the V-cycle: a Chebyshev pre-smoothing of
+  // the CG residual at the voxel level, restriction to level 1, the coarse
+  // levels' V-cycle, prolongation, post-smoothing):
+  //   restart:   z = V r, rho = r . z, beta = 0
+  //   iteration: p = z + beta p; q = K p; alpha = rho / p . q;
+  //              x += alpha p, r -= alpha q; z = V r; rho' = r . z; beta
+  int vcycle(const SelBatch &B, const std::vector<Slot *> &ss, int restart) {
+    int rc;
+    if ((rc = run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_s1(B, restart, st); }))) return rc;
+    for (int m : {SMO_STEP1, SMO_RES})
+      if ((rc = run_timed(SHH_PROF_SEL_MG_SMOOTH, [&] { return sel_launch_mg_op(B, m, st); }))) return rc;
+    if ((rc = run_timed(SHH_PROF_SEL_MG_TRANSFER, [&] { return sel_launch_mg_restrict(B, st); }))) return rc;
+    if ((rc = mg_vcycle_coarse(ss, st))) return rc;
+    if ((rc = run_timed(SHH_PROF_SEL_MG_TRANSFER, [&] { return sel_launch_mg_prolong(B, st); }))) return rc;
+    for (int m : {SMO_POST, SMO_LAST})
+      if ((rc = run_timed(SHH_PROF_SEL_MG_SMOOTH, [&] { return sel_launch_mg_op(B, m, st); }))) return rc;
+    return SHH_OK;
+  }
+  int restart(const std::vector<SelSlot *> &v) {
+    const SelBatch B = batch_of(v);
+    int rc;
+    if ((rc = vcycle(B, slots_of(v), 1))) return rc;
+    SEL_HIP(sel_launch_scalar(B, SSC_MG_RESTART, st));
+    return SHH_OK;
+  }
+  int iteration(const std::vector<SelSlot *> &v, bool mg) {
+    const SelBatch B = batch_of(v);
+    int rc;
+    if (mg) {
+      if ((rc = run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_dir(B, st); }))) return rc;
+      if ((rc = run_timed(SHH_PROF_SEL_MG_PQ, [&] { return sel_launch_mg_op(B, SMO_PQ, st); }))) return rc;
+      SEL_HIP(sel_launch_scalar(B, SSC_MG_ALPHA, st));
+      if ((rc = vcycle(B, slots_of(v), 0))) return rc;
+      SEL_HIP(sel_launch_scalar(B, SSC_MG_BETA, st));
+    } else {
+      if ((rc = run_timed(SHH_PROF_SEL_OP, [&] { return sel_launch_op(B, SOP_PCG, st); }))) return rc;
+      SEL_HIP(sel_launch_scalar(B, SSC_ITER, st));
+      if ((rc = run_timed(SHH_PROF_SEL_UPDATE, [&] { return sel_launch_update(B, st); }))) return rc;
+    }
     return SHH_OK;
   }
 };
 
-bool all_stopped(const CgState &c) {
-  for (int k = 0; k < NRHS; ++k)
-    if (c.active[k]) return false;
-  return true;
-}
-
-}  // namespace
-
-size_t sel_descriptor_bytes() { return sizeof(SelDev); }
-
-int sel_solve(Slot &s, hipStream_t st) {
+// Descriptor of one slot before the compaction: the compact arrays in the
+// dense CG vector region (seven [6][3][n^3] vectors): the map, coordinates,
+// counts, moduli and diagonal in vectors 0-1, r, p, q, x in vectors 2, 3, 4,
+// 6, the partials in vector 5; the descriptor in the slot's small parameter
+// block.  Returns the bytes used in vectors 0-1.
+int describe(SelSlot &x, size_t &aux_used) {
+  Slot &s = *x.s;
   const Layout &L = s.lay;
   const SlotDev &sd = s.host;
-  const int n = sd.n;
-  const long long nn = sd.nn;
-  const int prec = sd.prec;
-  const size_t ts = prec == SHH_PREC_FP64 ? 8 : 4;
+  SelDev &h = x.h;
+  const size_t ts = sd.prec == SHH_PREC_FP64 ? 8 : 4;
   char *base = s.base;
   char *vec = base + L.vec;
   const size_t vb = L.vec_bytes;
-  SelRun run;
-  run.st = st;
-  run.timing = s.timing && profile_on();
-  SelDev &h = run.h;
   std::memset(&h, 0, sizeof(h));
-  h.n = n;
-  h.nn = nn;
-  h.prec = prec;
-  h.nchunks = int((nn + SEL_CHUNK - 1) / SEL_CHUNK);
+  h.n = sd.n;
+  h.nn = sd.nn;
+  h.prec = sd.prec;
+  h.nchunks = int((sd.nn + SEL_CHUNK - 1) / SEL_CHUNK);
   h.lam = sd.lam;
   h.mu = sd.mu;
   h.rtol = sd.rtol;
@@ -175,73 +245,53 @@ int sel_solve(Slot &s, hipStream_t st) {
   element_forces(sd.lam, sd.mu, h.f0);
   h.E64 = sd.E64;
   h.st = sd.st;
-  // compact arrays in the dense CG vector region (seven [6][3][n^3] vectors):
-  // the map, coordinates, counts, moduli and diagonal in vectors 0-1, r, p,
-  // q, x in vectors 2, 3, 4, 6, the partials in vector 5; the descriptor in
-  // the slot's small parameter block
   h.r = vec + 2 * vb;
   h.p = vec + 3 * vb;
   h.q = vec + 4 * vb;
   h.x = vec + 6 * vb;
-  h.x64 = prec == SHH_PREC_MIXED ? (double *)(base + L.x64) : (double *)h.x;
-  char *aux = vec;
+  h.x64 = sd.prec == SHH_PREC_MIXED ? (double *)(base + L.x64) : (double *)h.x;
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    char *p = aux + off;
+    char *p = vec + off;
     off = al256(off + bytes);
     return p;
   };
-  h.map = (int *)take(sizeof(int) * nn);
-  h.coord = (unsigned *)take(sizeof(unsigned) * nn);
+  h.map = (int *)take(sizeof(int) * sd.nn);
+  h.coord = (unsigned *)take(sizeof(unsigned) * sd.nn);
   h.counts = (int *)take(sizeof(int) * (h.nchunks + 1));
-  h.Ec = take(ts * nn);
-  h.Ec64 = prec == SHH_PREC_FP64 ? (double *)h.Ec : (double *)take(sizeof(double) * nn);
-  h.Dinv = take(ts * nn);
+  h.Ec = take(ts * sd.nn);
+  h.Ec64 = sd.prec == SHH_PREC_FP64 ? (double *)h.Ec : (double *)take(sizeof(double) * sd.nn);
+  h.Dinv = take(ts * sd.nn);
   if (off > 2 * vb) return SHH_WORKSPACE_TOO_SMALL;
   h.partials = (double *)(vec + 5 * vb);
   static_assert(sizeof(SelDev) <= 4096, "descriptor fits the parameter block");
-  run.d = (SelDev *)(base + L.segs);
-  int rc;
-  // multigrid hierarchy of the culled operator (Galerkin levels from the
-  // culled moduli; its element matrices use the vector region as scratch, so
-  // it is built before the compaction writes there)
-  if (s.opts.solver == SHH_SOLVER_SELECTIVE && L.mg && mg_num_levels(n) >= 2) {
-    rc = mg_setup(s, st);
-    if (rc == SHH_HIP_ERROR) return rc;
-    h.mg = rc == SHH_OK ? 1 : 0;  // otherwise (a failed estimate) Jacobi
-  }
-  if (h.mg) {
-    const MgDev &M = s.mg;
-    h.inv_theta = M.lv[0].inv_theta;
-    h.c1 = M.lv[0].c1;
-    h.c2 = M.lv[0].c2;
-    h.n1 = M.lv[1].n;
-    h.nn1 = M.lv[1].nn;
-    h.b1 = M.lv[1].b;
-    h.x1 = M.lv[1].x;
-    h.d0 = M.lv[0].d;  // the dense level-0 direction buffer: [6][3][n^3] >= [n_a][18]
-  }
-  if (s.ev[1]) SEL_HIP(hipEventRecord(s.ev[1], st));
-  SEL_HIP(hipMemcpyAsync(run.d, &h, sizeof(SelDev), hipMemcpyHostToDevice, st));
-  SEL_HIP(sel_launch_compact(run.d, h, st));
-  int na = 0;
-  SEL_HIP(hipMemcpyAsync(&na, h.counts + h.nchunks, sizeof(int), hipMemcpyDeviceToHost, st));
-  SEL_HIP(hipStreamSynchronize(st));
-  h.na = na;
-  h.nparts = std::max(1, (na + SEL_THREADS - 1) / SEL_THREADS);
+  x.d = (SelDev *)(base + L.segs);
+  aux_used = off;
+  return SHH_OK;
+}
+
+// After the compaction (n_a known): workgroup count, partial room, and the
+// multigrid's three extra [n_a][18] vectors after the compact arrays in
+// vectors 0-1, then after the partials in vector 5 (Jacobi when a nearly full
+// design leaves no room for them).
+int place(SelSlot &x, size_t aux_used) {
+  Slot &s = *x.s;
+  SelDev &h = x.h;
+  const size_t ts = h.prec == SHH_PREC_FP64 ? 8 : 4;
+  char *vec = s.base + s.lay.vec;
+  const size_t vb = s.lay.vec_bytes;
+  h.nparts = std::max(1, (h.na + SEL_THREADS - 1) / SEL_THREADS);
   const size_t pbytes = al256((size_t)NRHS * h.nparts * SEL_PS * sizeof(double));
   if (pbytes > vb || 22ull * h.nparts * sizeof(double) > vb) return SHH_WORKSPACE_TOO_SMALL;
   if (h.mg) {
-    // three more [n_a][18] vectors of the V-cycle's voxel level: after the
-    // compact arrays in vectors 0-1, then after the partials in vector 5
-    const size_t vbytes = al256((size_t)na * 3 * NRHS * ts);
-    char *arena[2] = {aux + off, vec + 5 * vb + pbytes};
-    size_t room[2] = {2 * vb - off, vb - pbytes};
+    const size_t vbytes = al256((size_t)h.na * 3 * NRHS * ts);
+    char *arena[2] = {vec + aux_used, vec + 5 * vb + pbytes};
+    size_t room[2] = {2 * vb - aux_used, vb - pbytes};
     void **dst[3] = {&h.d1, &h.xv, &h.rv};
     for (void **v : dst) {
       const int a = room[0] >= vbytes ? 0 : (room[1] >= vbytes ? 1 : -1);
       if (a < 0) {
-        h.mg = 0;  // a nearly full design: no room, Jacobi
+        h.mg = 0;
         break;
       }
       *v = arena[a];
@@ -249,117 +299,178 @@ int sel_solve(Slot &s, hipStream_t st) {
       room[a] -= vbytes;
     }
   }
-  SEL_HIP(hipMemcpyAsync(run.d, &h, sizeof(SelDev), hipMemcpyHostToDevice, st));
-  s.sel_active_nodes = na;
-  if (na == 0) {  // everything culled: no stiffness, C^H = 0
-    SEL_HIP(hipMemcpyAsync(&s.state, s.d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
-    SEL_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < 36; ++i) s.state.C[i] = 0.0;
-    for (int k = 0; k < NRHS; ++k) {
-      s.state.iters[k] = 0;
-      s.state.rel_true[k] = 0.0;
-      s.state.status[k] = ST_CONVERGED;
+  return SHH_OK;
+}
+
+// the CG loop of one group of slots (one preconditioner), batched
+int run_group(SelRun &run, const std::vector<SelSlot *> &group, bool mg, const shh_opts &o) {
+  hipStream_t st = run.st;
+  int rc;
+  {
+    const SelBatch B = batch_of(group);
+    SEL_HIP(sel_launch_gather(B, st));
+    SEL_HIP(sel_launch_zero(B, st));
+    if ((rc = run.residual(B, 0))) return rc;
+    if (mg) {
+      if ((rc = run.restart(group))) return rc;
+    } else {
+      SEL_HIP(sel_launch_dir0(B, st));
     }
-    s.status = SHH_OK;
-    s.finished = true;
-    return SHH_OK;
   }
-  SEL_HIP(sel_launch_gather(run.d, h, st));
-  SEL_HIP(sel_launch_zero(run.d, h, st));
-  if ((rc = run.residual(0))) return rc;
-  // multigrid-preconditioned CG (the V-cycle: a Chebyshev pre-smoothing of
-  // the CG residual at the voxel level, restriction to level 1, the coarse
-  // levels' V-cycle, prolongation, post-smoothing):
-  //   restart:   z = V r, rho = r . z, beta = 0
-  //   iteration: p = z + beta p; q = K p; alpha = rho / p . q;
-  //              x += alpha p, r -= alpha q; z = V r; rho' = r . z; beta
-  auto vcycle = [&](int restart) -> int {
-    if ((rc = run.run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_s1(run.d, h, restart, st); })))
-      return rc;
-    for (int m : {SMO_STEP1, SMO_RES}) {
-      if ((rc = run.run_timed(SHH_PROF_SEL_MG_SMOOTH, [&] { return sel_launch_mg_op(run.d, h, m, st); })))
-        return rc;
-    }
-    if ((rc = run.run_timed(SHH_PROF_SEL_MG_TRANSFER, [&] { return sel_launch_mg_restrict(run.d, h, st); })))
-      return rc;
-    if ((rc = mg_vcycle_coarse(s, st))) return rc;
-    if ((rc = run.run_timed(SHH_PROF_SEL_MG_TRANSFER, [&] { return sel_launch_mg_prolong(run.d, h, st); })))
-      return rc;
-    for (int m : {SMO_POST, SMO_LAST}) {
-      if ((rc = run.run_timed(SHH_PROF_SEL_MG_SMOOTH, [&] { return sel_launch_mg_op(run.d, h, m, st); })))
-        return rc;
-    }
-    return SHH_OK;
-  };
-  auto restart = [&]() -> int {
-    if ((rc = vcycle(1))) return rc;
-    SEL_HIP(sel_launch_scalar(run.d, SSC_MG_RESTART, st));
-    return SHH_OK;
-  };
-  if (h.mg) {
-    if ((rc = restart())) return rc;
-  } else {
-    SEL_HIP(sel_launch_dir0(run.d, h, st));
-  }
-  if (s.ev[2]) SEL_HIP(hipEventRecord(s.ev[2], st));
-  const int R = prec == SHH_PREC_MIXED ? s.opts.recompute_every : 0;
-  const int check = std::max(1, s.opts.check_every);
+  run.record(group, 2);
+  const int R = group[0]->h.prec == SHH_PREC_MIXED ? o.recompute_every : 0;
+  const int check = std::max(1, o.check_every);
   long long launched = 0;
-  const long long guard = 4LL * s.opts.max_iter + 64LL * check + 1024;
-  int finals = 0;
-  if ((rc = run.read_state(s))) return rc;
-  while (!all_stopped(s.state)) {
-    for (int j = 0; j < check; ++j) {
-      if (h.mg) {
-        if ((rc = run.run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_dir(run.d, h, st); }))) return rc;
-        if ((rc = run.run_timed(SHH_PROF_SEL_MG_PQ, [&] { return sel_launch_mg_op(run.d, h, SMO_PQ, st); })))
-          return rc;
-        SEL_HIP(sel_launch_scalar(run.d, SSC_MG_ALPHA, st));
-        if ((rc = vcycle(0))) return rc;
-        SEL_HIP(sel_launch_scalar(run.d, SSC_MG_BETA, st));
-      } else {
-        if ((rc = run.run_timed(SHH_PROF_SEL_OP, [&] { return sel_launch_op(run.d, h, SOP_PCG, st); }))) return rc;
-        SEL_HIP(sel_launch_scalar(run.d, SSC_ITER, st));
-        if ((rc = run.run_timed(SHH_PROF_SEL_UPDATE, [&] { return sel_launch_update(run.d, h, st); }))) return rc;
+  const long long guard = 4LL * o.max_iter + 64LL * check + 1024;
+  if ((rc = run.read_state(group))) return rc;
+  for (SelSlot *x : group) x->done = false;
+  auto live_of = [&]() {
+    std::vector<SelSlot *> v;
+    for (SelSlot *x : group)
+      if (!x->done) v.push_back(x);
+    return v;
+  };
+  for (std::vector<SelSlot *> live = live_of(); !live.empty(); live = live_of()) {
+    // slots whose every load case has stopped: the true residual decides (a
+    // case whose recursive residual was optimistic resumes, at most 8 times)
+    std::vector<SelSlot *> stopped, running;
+    for (SelSlot *x : live) (all_stopped(x->s->state) ? stopped : running).push_back(x);
+    if (!stopped.empty()) {
+      if ((rc = run.residual(batch_of(stopped), 2))) return rc;
+      if ((rc = run.read_state(stopped))) return rc;
+      std::vector<SelSlot *> resumed;
+      for (SelSlot *x : stopped) {
+        ++x->finals;
+        if (all_stopped(x->s->state) || x->finals >= 8) x->done = true;
+        else resumed.push_back(x);
       }
+      if (mg && !resumed.empty() && (rc = run.restart(resumed))) return rc;
+      for (SelSlot *x : resumed) running.push_back(x);
+    }
+    if (running.empty()) continue;
+    if (launched > guard) {
+      // given up: the true residual of what is left, as the status reports it
+      if ((rc = run.residual(batch_of(running), 2))) return rc;
+      for (SelSlot *x : running) x->done = true;
+      break;
+    }
+    for (int j = 0; j < check; ++j) {
+      if ((rc = run.iteration(running, mg))) return rc;
       ++launched;
       if (R > 0 && launched % R == 0) {
-        if ((rc = run.residual(1))) return rc;
-        if (h.mg && (rc = restart())) return rc;  // the V-cycle of the replaced residual
+        if ((rc = run.residual(batch_of(running), 1))) return rc;
+        if (mg && (rc = run.restart(running))) return rc;  // the V-cycle of the replaced residual
       }
     }
-    if ((rc = run.read_state(s))) return rc;
-    if (all_stopped(s.state)) {
-      // the true residual decides: a case whose recursive residual was
-      // optimistic resumes (at most 8 times)
-      if ((rc = run.residual(2))) return rc;
-      ++finals;
-      if ((rc = run.read_state(s))) return rc;
-      if (finals >= 8) break;
-      if (h.mg && !all_stopped(s.state) && (rc = restart())) return rc;
+    if ((rc = run.read_state(running))) return rc;
+  }
+  return SHH_OK;
+}
+
+}  // namespace
+
+size_t sel_descriptor_bytes() { return sizeof(SelDev); }
+
+int sel_solve(const std::vector<Slot *> &all, hipStream_t st) {
+  if (all.empty()) return SHH_OK;
+  int rc;
+  for (size_t b0 = 0; b0 < all.size(); b0 += SEL_MAXB) {
+    const std::vector<Slot *> part(all.begin() + b0, all.begin() + std::min(all.size(), b0 + SEL_MAXB));
+    SelRun run;
+    run.st = st;
+    run.timing = part[0]->timing && profile_on();
+    std::vector<SelSlot> xs(part.size());
+    std::vector<size_t> aux(part.size());
+    std::vector<Slot *> mgc;
+    for (size_t i = 0; i < part.size(); ++i) {
+      xs[i].s = part[i];
+      if ((rc = describe(xs[i], aux[i]))) return rc;
+      const Slot &s = *part[i];
+      if (s.opts.solver == SHH_SOLVER_SELECTIVE && s.lay.mg && mg_num_levels(s.host.n) >= 2) mgc.push_back(part[i]);
     }
-    if (launched > guard) break;
+    // multigrid hierarchies of the culled operators (Galerkin levels from the
+    // culled moduli; their element matrices use the vector region as scratch,
+    // so they are built before the compaction writes there), batched
+    if (!mgc.empty()) {
+      std::vector<int> rcs;
+      if ((rc = mg_setup(mgc, st, &rcs))) return rc;
+      for (size_t j = 0; j < mgc.size(); ++j) {
+        if (rcs[j] != SHH_OK) continue;  // a failed estimate: Jacobi
+        for (SelSlot &x : xs)
+          if (x.s == mgc[j]) {
+            const MgDev &M = x.s->mg;
+            SelDev &h = x.h;
+            h.mg = 1;
+            h.inv_theta = M.lv[0].inv_theta;
+            h.c1 = M.lv[0].c1;
+            h.c2 = M.lv[0].c2;
+            h.n1 = M.lv[1].n;
+            h.nn1 = M.lv[1].nn;
+            h.b1 = M.lv[1].b;
+            h.x1 = M.lv[1].x;
+            h.d0 = M.lv[0].d;  // the dense level-0 direction buffer: [6][3][n^3] >= [n_a][18]
+          }
+      }
+    }
+    std::vector<SelSlot *> ptrs;
+    for (SelSlot &x : xs) ptrs.push_back(&x);
+    run.record(ptrs, 1);
+    for (SelSlot &x : xs) SEL_HIP(hipMemcpyAsync(x.d, &x.h, sizeof(SelDev), hipMemcpyHostToDevice, st));
+    SEL_HIP(sel_launch_compact(batch_of(ptrs), st));
+    std::vector<int> na(xs.size(), 0);
+    for (size_t i = 0; i < xs.size(); ++i)
+      SEL_HIP(hipMemcpyAsync(&na[i], xs[i].h.counts + xs[i].h.nchunks, sizeof(int), hipMemcpyDeviceToHost, st));
+    SEL_HIP(hipStreamSynchronize(st));
+    std::vector<SelSlot *> gm, gj, empty;
+    for (size_t i = 0; i < xs.size(); ++i) {
+      SelSlot &x = xs[i];
+      x.h.na = na[i];
+      x.s->sel_active_nodes = na[i];
+      if ((rc = place(x, aux[i]))) return rc;
+      SEL_HIP(hipMemcpyAsync(x.d, &x.h, sizeof(SelDev), hipMemcpyHostToDevice, st));
+      (na[i] == 0 ? empty : (x.h.mg ? gm : gj)).push_back(&x);
+    }
+    // everything culled: no stiffness, C^H = 0
+    if (!empty.empty() && (rc = run.read_state(empty))) return rc;
+    for (SelSlot *x : empty) {
+      Slot &s = *x->s;
+      for (int i = 0; i < 36; ++i) s.state.C[i] = 0.0;
+      for (int k = 0; k < NRHS; ++k) {
+        s.state.iters[k] = 0;
+        s.state.rel_true[k] = 0.0;
+        s.state.status[k] = ST_CONVERGED;
+      }
+      s.status = SHH_OK;
+      s.finished = true;
+    }
+    const shh_opts &o = part[0]->opts;
+    if (!gm.empty() && (rc = run_group(run, gm, true, o))) return rc;
+    if (!gj.empty() && (rc = run_group(run, gj, false, o))) return rc;
+    std::vector<SelSlot *> solved(gm);
+    solved.insert(solved.end(), gj.begin(), gj.end());
+    if (solved.empty()) continue;
+    run.record(solved, 3);
+    const SelBatch B = batch_of(solved);
+    SEL_HIP(sel_launch_fold(B, 1, st));
+    SEL_HIP(sel_launch_op(B, SOP_ENERGY, st));
+    SEL_HIP(sel_launch_scalar(B, SSC_ENERGY, st));
+    run.record(solved, 4);
+    if ((rc = run.read_state(solved))) return rc;
+    for (SelSlot *x : solved) {
+      Slot &s = *x->s;
+      float a = 0.f;
+      for (int k = 0; k < 4; ++k)
+        if (s.ev[k] && s.ev[k + 1] && hipEventElapsedTime(&a, s.ev[k], s.ev[k + 1]) == hipSuccess) s.ms[k] = a;
+      if (s.ev[0] && s.ev[4] && hipEventElapsedTime(&a, s.ev[0], s.ev[4]) == hipSuccess) s.ms[4] = a;
+      int status = SHH_OK;
+      for (int k = 0; k < NRHS; ++k) {
+        if (s.state.status[k] == ST_BREAKDOWN) status = SHH_BREAKDOWN;
+        else if (status == SHH_OK && s.state.status[k] != ST_CONVERGED) status = SHH_NOT_CONVERGED;
+      }
+      s.status = status;
+      s.finished = true;
+    }
   }
-  if (!all_stopped(s.state) || finals == 0) {
-    if ((rc = run.residual(2))) return rc;
-  }
-  if (s.ev[3]) SEL_HIP(hipEventRecord(s.ev[3], st));
-  SEL_HIP(sel_launch_fold(run.d, h, 1, st));
-  SEL_HIP(sel_launch_op(run.d, h, SOP_ENERGY, st));
-  SEL_HIP(sel_launch_scalar(run.d, SSC_ENERGY, st));
-  if (s.ev[4]) SEL_HIP(hipEventRecord(s.ev[4], st));
-  if ((rc = run.read_state(s))) return rc;
-  float a = 0.f;
-  for (int k = 0; k < 4; ++k)
-    if (s.ev[k] && s.ev[k + 1] && hipEventElapsedTime(&a, s.ev[k], s.ev[k + 1]) == hipSuccess) s.ms[k] = a;
-  if (s.ev[0] && s.ev[4] && hipEventElapsedTime(&a, s.ev[0], s.ev[4]) == hipSuccess) s.ms[4] = a;
-  int status = SHH_OK;
-  for (int k = 0; k < NRHS; ++k) {
-    if (s.state.status[k] == ST_BREAKDOWN) status = SHH_BREAKDOWN;
-    else if (status == SHH_OK && s.state.status[k] != ST_CONVERGED) status = SHH_NOT_CONVERGED;
-  }
-  s.status = status;
-  s.finished = true;
   return SHH_OK;
 }
 

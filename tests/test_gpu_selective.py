@@ -126,3 +126,19 @@ def test_multigrid_and_jacobi_preconditioners_agree_at_64():
     assert rm["active_nodes"] == rj["active_nodes"] and rm["V"] == rj["V"]
     assert_ch_close(rm["C"], rj["C"], 1e-4)
     assert 4 * max(rm["iters"]) < max(rj["iters"])
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_batched_selective_solve_equals_single_designs(solver):
+    # a batch shares every launch (grid y = design), each design keeps its own
+    # reductions and schedule: results bit-identical to the designs alone
+    A = api()
+    designs = [wl.shell_128(2020, n=32), wl.shell_128(2021, n=40), wl.shell_128(2022, n=48)]
+    print(f"{solver}: batch of {len(designs)} vs single", flush=True)
+    rb = A.homogenize_batch(designs, precision="mixed", rtol=3e-6, solver=solver)
+    for d, r in zip(designs, rb):
+        r1 = A.homogenize(d, precision="mixed", rtol=3e-6, solver=solver)
+        print("  n", d.n, "iters", r["iters"].tolist(), "active", r["active_nodes"], flush=True)
+        assert r["status"] == 0 and r1["status"] == 0
+        assert np.array_equal(r["C"], r1["C"]) and np.array_equal(r["iters"], r1["iters"])
+        assert r["active_nodes"] == r1["active_nodes"]
