@@ -71,8 +71,11 @@ def family_bytes(results, n, R, solver):
         CG update       72 (x, p, b, q read; x, b written)
         restriction     12 fine read + 12 per coarse node written
         prolongation    24 fine read and written + 12 per coarse node read
-      first coarse level operator, 4 per iteration: 504 B of stencil per
-        coarse node + 24 B per (coarse node, load case)
+      first coarse level operator, 4 per iteration, each with the Chebyshev
+        sweep after it in its output stage: 504 B of stencil per coarse node
+        per pass + 36 B of D^-1 per coarse node, and per (coarse node, load
+        case) 60 (d, b read; r, x, d1 written) + 36 (d1, r read; r written)
+        + 60 (x, b read; r, d, x + d written) + 48 (d, x + d, r read; x written)
       FP64 residual: 24 (x64) + 12 (r) per (node, load case) + 8 (E) per node,
         every R iterations and once at the end
       Jacobi CG pass: 96 per (node, load case) + 8 per node
@@ -122,7 +125,7 @@ def family_bytes(results, n, R, solver):
         out["mg_update"] += 72.0 * nn * Ik
         out["mg_restrict"] += (12.0 * nn + 12.0 * nn1) * Ik
         out["mg_prolong"] += (24.0 * nn + 12.0 * nn1) * Ik
-        out["mg_apply1"] += 4 * (504.0 * nn1 * Im + 24.0 * nn1 * Ik)
+        out["mg_apply1"] += (4 * 504.0 + 36.0) * nn1 * Im + 204.0 * nn1 * Ik
     return out
 
 

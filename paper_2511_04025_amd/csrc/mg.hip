@@ -144,7 +144,53 @@ __global__ __launch_bounds__(256) void mg_stencil_kernel(const MgDev *mg, int l)
 // large levels of odd size (even ones take the pair form below), RHS = 1 (one
 // thread per node and load case: six times the threads, so latency overlaps)
 // on small ones.
-template <typename T, int RHS>
+// The coarse-level Chebyshev sweep that follows an operator pass, applied
+// to q = A_l v at node v, load case k (entry j = (3 k + c) nn + v):
+//   MGE_NONE:  q = A v
+//   MGE_STEP1: (v = d0) r = b - q;  d1 = c1 d0 + c2 D^-1 r;  x = d0 + d1;  d1 into q
+//   MGE_RES:   (v = d1, in q) r -= q: the residual the restriction takes
+//   MGE_POST:  (v = x) r = b - q;  d = D^-1 r / theta;  x + d into q
+//   MGE_LAST:  (v = d) x = (x + d, in q) + c1 d + c2 D^-1 (r - q)
+// No pass writes the vector its operator reads.
+template <typename T, int EP>
+__device__ __forceinline__ void mg_epilogue(const MgLevel &L, long long j, T dinv, T a) {
+  T *q = (T *)L.q;
+  if constexpr (EP == MGE_NONE) {
+    q[j] = a;
+  } else if constexpr (EP == MGE_STEP1) {
+    T *r = (T *)L.r, *x = (T *)L.x;
+    const T d0 = ((const T *)L.d)[j];
+    const T rv = ((const T *)L.b)[j] - a;
+    const T d1 = (T)L.c1 * d0 + (T)L.c2 * dinv * rv;
+    r[j] = rv;
+    x[j] = d0 + d1;
+    q[j] = d1;
+  } else if constexpr (EP == MGE_RES) {
+    T *r = (T *)L.r;
+    r[j] = r[j] - a;
+  } else if constexpr (EP == MGE_POST) {
+    T *r = (T *)L.r, *d = (T *)L.d;
+    const T rv = ((const T *)L.b)[j] - a;
+    const T dv = dinv * rv * (T)L.inv_theta;
+    r[j] = rv;
+    d[j] = dv;
+    q[j] = ((const T *)L.x)[j] + dv;
+  } else {  // MGE_LAST
+    T *x = (T *)L.x;
+    x[j] = q[j] + (T)L.c1 * ((const T *)L.d)[j] + (T)L.c2 * dinv * (((const T *)L.r)[j] - a);
+  }
+}
+
+// the operator's input vector of an epilogue (MGE_NONE: src 0 x, 1 d)
+template <typename T, int EP>
+__device__ __forceinline__ const T *mg_operand(const MgLevel &L, int src) {
+  if constexpr (EP == MGE_STEP1 || EP == MGE_LAST) return (const T *)L.d;
+  else if constexpr (EP == MGE_RES) return (const T *)L.q;
+  else if constexpr (EP == MGE_POST) return (const T *)L.x;
+  else return (const T *)(src == 0 ? L.x : L.d);
+}
+
+template <typename T, int RHS, int EP>
 __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src, int live) {
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const long long nn = L.nn;
@@ -162,64 +208,61 @@ __global__ __launch_bounds__(256) void mg_apply_kernel(MgBatch B, int l, int src
     any = any || act[r];
   }
   if (!any) return;
-  if (((const T *)L.Dinv)[v] == T(0)) {  // a zero row (all elements around the node culled)
-    T *q = (T *)L.q + (long long)r0 * 3 * nn;
-#pragma unroll
-    for (int r = 0; r < RHS; ++r)
-      if (act[r])
-#pragma unroll
-        for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = T(0);
-    return;
-  }
   const int n = L.n;
   const int x = int(v % n), y = int((v / n) % n), z = int(v / ((long long)n * n));
   const T *S = (const T *)L.S;
-  const T *in = (const T *)(src == 0 ? L.x : L.d) + (long long)r0 * 3 * nn;
+  const T *Dv = (const T *)L.Dinv;
+  const T *in = mg_operand<T, EP>(L, src) + (long long)r0 * 3 * nn;
   T acc[RHS][3];
 #pragma unroll
   for (int r = 0; r < RHS; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[r][c] = T(0);
+  // a node with a zero diagonal has a zero row (every element around it
+  // culled): A v = 0 there without reading its stencil
+  const bool zero_row = Dv[v] == T(0);
   // three offsets per trip: their loads are in flight together (measured
   // faster than one; more waves per SIMD or fewer load cases per thread are
   // slower, the stencil reads then miss the caches more)
+  if (!zero_row) {
 #pragma unroll 3
-  for (int w = 0; w < 27; ++w) {
-    const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
-    const long long u = ((long long)wrap1(z + dz, n) * n + wrap1(y + dy, n)) * n + wrap1(x + dx, n);
-    T blk[9];
-    if (w >= 13) {
+    for (int w = 0; w < 27; ++w) {
+      const int dx = w % 3 - 1, dy = (w / 3) % 3 - 1, dz = w / 9 - 1;
+      const long long u = ((long long)wrap1(z + dz, n) * n + wrap1(y + dy, n)) * n + wrap1(x + dx, n);
+      T blk[9];
+      if (w >= 13) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) blk[k] = S[((w - 13) * 9 + k) * nn + v];
-    } else {
-      // A[v][u] = A[u][v]^T, stored at u for offset 26 - w
+        for (int k = 0; k < 9; ++k) blk[k] = S[((w - 13) * 9 + k) * nn + v];
+      } else {
+        // A[v][u] = A[u][v]^T, stored at u for offset 26 - w
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int cp = 0; cp < 3; ++cp) blk[3 * c + cp] = S[((13 - w) * 9 + 3 * cp + c) * nn + u];
-    }
+          for (int cp = 0; cp < 3; ++cp) blk[3 * c + cp] = S[((13 - w) * 9 + 3 * cp + c) * nn + u];
+      }
 #pragma unroll
-    for (int r = 0; r < RHS; ++r) {
-      if (!act[r]) continue;
-      const T *vr = in + (long long)r * 3 * nn;
-      const T u0 = vr[u], u1 = vr[nn + u], u2 = vr[2 * nn + u];
+      for (int r = 0; r < RHS; ++r) {
+        if (!act[r]) continue;
+        const T *vr = in + (long long)r * 3 * nn;
+        const T u0 = vr[u], u1 = vr[nn + u], u2 = vr[2 * nn + u];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[r][c] += blk[3 * c] * u0 + blk[3 * c + 1] * u1 + blk[3 * c + 2] * u2;
+        for (int c = 0; c < 3; ++c) acc[r][c] += blk[3 * c] * u0 + blk[3 * c + 1] * u1 + blk[3 * c + 2] * u2;
+      }
     }
   }
-  T *q = (T *)L.q + (long long)r0 * 3 * nn;
 #pragma unroll
   for (int r = 0; r < RHS; ++r)
     if (act[r])
 #pragma unroll
-      for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v] = acc[r][c];
+      for (int c = 0; c < 3; ++c)
+        mg_epilogue<T, EP>(L, ((long long)(r0 + r) * 3 + c) * nn + v, Dv[(long long)c * nn + v], acc[r][c]);
 }
 
 // q = A_l v as above, all six load cases, for two z-adjacent nodes per thread
 // (even n; the form the large levels take): the vector values of the two
 // planes between them are loaded once for both (12 % faster per launch than
 // one node per thread).  Occupancy 3 waves per SIMD in FP32.
-template <typename T>
+template <typename T, int EP>
 __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, int src, int live) {
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const long long nn = L.nn;
@@ -239,23 +282,11 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
   const int x = int(xy % n), y = int(xy / n), z0 = 2 * int(t / plane);
   const long long v0 = (long long)z0 * plane + xy;
   const T *S = (const T *)L.S;
-  const T *in = (const T *)(src == 0 ? L.x : L.d);
-  T *q = (T *)L.q;
-  {
-    // nodes with a zero diagonal have a zero row (every element around them
-    // culled): their output is zero without reading their stencil
-    const T *Dv = (const T *)L.Dinv;
-    if (Dv[v0] == T(0) && Dv[v0 + plane] == T(0)) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r)
-          if (act[r])
-#pragma unroll
-            for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v0 + k * plane] = T(0);
-      return;
-    }
-  }
+  const T *Dv = (const T *)L.Dinv;
+  const T *in = mg_operand<T, EP>(L, src);
+  // nodes with a zero diagonal have a zero row (every element around them
+  // culled): A v = 0 there without reading their stencil
+  const bool zero_rows = Dv[v0] == T(0) && Dv[v0 + plane] == T(0);
   T acc[2][NRHS][3];
 #pragma unroll
   for (int k = 0; k < 2; ++k)
@@ -263,40 +294,42 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
     for (int r = 0; r < NRHS; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[k][r][c] = T(0);
+  if (!zero_rows) {
 #pragma unroll
-  for (int pz = 0; pz < 4; ++pz) {  // planes z0 - 1 .. z0 + 2
-    const long long pzo = (long long)wrap1(z0 - 1 + pz, n) * plane;
-    // three offsets per trip (one and nine measured slower)
+    for (int pz = 0; pz < 4; ++pz) {  // planes z0 - 1 .. z0 + 2
+      const long long pzo = (long long)wrap1(z0 - 1 + pz, n) * plane;
+      // three offsets per trip (one and nine measured slower)
 #pragma unroll 3
-    for (int o = 0; o < 9; ++o) {
-      const int dx = o % 3 - 1, dy = o / 3 - 1;
-      const long long u = pzo + (long long)wrap1(y + dy, n) * n + wrap1(x + dx, n);
-      T val[NRHS][3];
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) val[r][c] = act[r] ? in[((long long)r * 3 + c) * nn + u] : T(0);
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int dz = pz - 1 - k;
-        if (dz < -1 || dz > 1) continue;
-        const int w = (dz + 1) * 9 + o;
-        const long long v = v0 + k * plane;
-        T blk[9];
-        if (w >= 13) {
-#pragma unroll
-          for (int e = 0; e < 9; ++e) blk[e] = S[((w - 13) * 9 + e) * nn + v];
-        } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int cp = 0; cp < 3; ++cp) blk[3 * c + cp] = S[((13 - w) * 9 + 3 * cp + c) * nn + u];
-        }
+      for (int o = 0; o < 9; ++o) {
+        const int dx = o % 3 - 1, dy = o / 3 - 1;
+        const long long u = pzo + (long long)wrap1(y + dy, n) * n + wrap1(x + dx, n);
+        T val[NRHS][3];
 #pragma unroll
         for (int r = 0; r < NRHS; ++r)
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-            acc[k][r][c] += blk[3 * c] * val[r][0] + blk[3 * c + 1] * val[r][1] + blk[3 * c + 2] * val[r][2];
+          for (int c = 0; c < 3; ++c) val[r][c] = act[r] ? in[((long long)r * 3 + c) * nn + u] : T(0);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int dz = pz - 1 - k;
+          if (dz < -1 || dz > 1) continue;
+          const int w = (dz + 1) * 9 + o;
+          const long long v = v0 + k * plane;
+          T blk[9];
+          if (w >= 13) {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) blk[e] = S[((w - 13) * 9 + e) * nn + v];
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+              for (int cp = 0; cp < 3; ++cp) blk[3 * c + cp] = S[((13 - w) * 9 + 3 * cp + c) * nn + u];
+          }
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              acc[k][r][c] += blk[3 * c] * val[r][0] + blk[3 * c + 1] * val[r][1] + blk[3 * c + 2] * val[r][2];
+        }
       }
     }
   }
@@ -306,15 +339,17 @@ __global__ __launch_bounds__(256) void mg_apply_pair_kernel(MgBatch B, int l, in
     for (int r = 0; r < NRHS; ++r)
       if (act[r])
 #pragma unroll
-        for (int c = 0; c < 3; ++c) q[((long long)r * 3 + c) * nn + v0 + k * plane] = acc[k][r][c];
+        for (int c = 0; c < 3; ++c)
+          mg_epilogue<T, EP>(L, ((long long)r * 3 + c) * nn + v0 + k * plane, Dv[(long long)c * nn + v0 + k * plane],
+                             acc[k][r][c]);
 }
 
-// b_{l+1} = P^T (r_l - q_l), the residual after the pre-smoother (q = A d of
-// its last step; at the voxel level r already holds r - q): coarse node I
-// collects fine nodes 2I + o, o in {-1, 0, 1}^3, with weight
-// prod (o == 0 ? 1 : 1/2).  One thread per (coarse node, load case).
+// b_{l+1} = P^T r_l, the residual after the pre-smoother (its last operator
+// pass leaves it in r): coarse node I collects fine nodes 2I + o,
+// o in {-1, 0, 1}^3, with weight prod (o == 0 ? 1 : 1/2).  One thread per
+// (coarse node, load case).
 template <typename T>
-__global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l, int formed) {
+__global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l) {
   const MgDev *mg = B.mg[blockIdx.z];
   const MgLevel &F = mg->lv[l];
   const MgLevel &C = mg->lv[l + 1];
@@ -326,7 +361,6 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l, int 
   const int nc = C.n, nf = F.n;
   const int X = int(I % nc), Y = int((I / nc) % nc), Z = int(I / ((long long)nc * nc));
   const T *r = (const T *)F.r + (long long)k * 3 * F.nn;
-  const T *qf = (const T *)F.q + (long long)k * 3 * F.nn;
   T acc[3] = {T(0), T(0), T(0)};
   for (int oz = -1; oz <= 1; ++oz) {
     const long long pz = (long long)wrap1(2 * Z + oz, nf) * nf;
@@ -340,7 +374,7 @@ __global__ __launch_bounds__(256) void mg_restrict_kernel(MgBatch B, int l, int 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const long long j = (long long)c * F.nn + i;
-          acc[c] += w * (formed ? r[j] : r[j] - qf[j]);
+          acc[c] += w * r[j];
         }
       }
     }
@@ -409,20 +443,19 @@ __global__ __launch_bounds__(256) void mg_coarsest_kernel(MgBatch B) {
   }
 }
 
-// Degree-2 Chebyshev smoothing of A x = b at level l, in four sweeps around
-// the operator applications (q = A d or A x from the launch before):
-//   INIT:  d = D^-1 b / theta                    (x = d is implied)
-//          at the voxel level instead the CG update x_cg += alpha p,
-//          b = r -= alpha q (q = K p), so that b is the new CG residual
-//   STEP1: r = b - q, d' = c1 d + c2 D^-1 r, x = d + d', d = d'
-//   POST:  r = b - q (q = A x), d = D^-1 r / theta, x += d
-//   LAST:  x += c1 d + c2 D^-1 (r - q)
-// (the pre-smoother is INIT, STEP1; the restriction takes r - q after it;
-// the post-smoother is POST, LAST).  At the voxel level only INIT runs here:
-// STEP1, POST and LAST run inside the stencil kernel's operator pass, which
-// also leaves the partial sums b . x and b . b for the CG scalars.
+// Degree-2 Chebyshev smoothing of A x = b at level l:
+//   d = D^-1 b / theta;  r = b - A d;  d' = c1 d + c2 D^-1 r;  x = d + d'
+//   (pre-smoother; the restriction takes r - A d');  after the coarse
+//   correction r = b - A x;  d = D^-1 r / theta;  x += d;
+//   x += c1 d + c2 D^-1 (r - A d)  (post-smoother).
+// Every step after an operator application runs in that pass's output stage
+// (the stencil kernel's multigrid modes at the voxel level, mg_epilogue on
+// the coarse levels); this sweep is the first step, d = D^-1 b / theta, on
+// the coarse levels, and at the voxel level the pending CG update
+// x_cg += alpha p, b = r -= alpha q (q = K p), so that b is the new CG
+// residual (the stencil pass after it forms d itself).
 template <typename T>
-__global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, int op) {
+__global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l) {
   const SlotDev *s = B.slot[blockIdx.z];
   const MgLevel &L = B.mg[blockIdx.z]->lv[l];
   const int k = blockIdx.y;
@@ -430,58 +463,32 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l, i
   if (blockIdx.x >= (unsigned)L.nchunks || !s->st->active[k]) return;
   const long long i0 = (long long)blockIdx.x * CHUNK;
   const long long i1 = min(i0 + (long long)CHUNK, nn);
-  const T ith = (T)L.inv_theta, c1 = (T)L.c1, c2 = (T)L.c2;
   const long long vb = (long long)k * 3 * nn;
   T *b = (T *)L.b + vb;
-  T *x = (T *)L.x + vb;
-  T *r = (T *)L.r + vb;
-  T *d = (T *)L.d + vb;
-  const T *q = (const T *)L.q + vb;
-  const T *Dv = (const T *)L.Dinv;
-  // voxel-level CG update folded into INIT
-  T a = T(0);
-  T *xcg = nullptr;
-  const T *pcg = nullptr;
-  if (l == 0 && op == MGV_INIT) {
-    a = (T)s->st->alpha[k];
-    xcg = (T *)s->x + vb;
-    pcg = (const T *)s->p[s->st->mgpar[k]] + vb;
+  if (l == 0) {
+    const T a = (T)s->st->alpha[k];
+    if (a == T(0)) return;
+    T *xcg = (T *)s->x + vb;
+    const T *pcg = (const T *)s->p[s->st->mgpar[k]] + vb;
+    const T *q = (const T *)L.q + vb;
+    for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long j = c * nn + i;
+        xcg[j] = xcg[j] + a * pcg[j];
+        b[j] = b[j] - a * q[j];
+      }
+    return;
   }
-  for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+  const T ith = (T)L.inv_theta;
+  T *d = (T *)L.d + vb;
+  const T *Dv = (const T *)L.Dinv;
+  for (long long i = i0 + threadIdx.x; i < i1; i += VEC_THREADS)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const long long j = c * nn + i;
-      if (op == MGV_INIT) {
-        if (l == 0) {
-          // the Chebyshev direction d = D^-1 b / theta is formed by the operator pass after this
-          if (a != T(0)) {
-            xcg[j] = xcg[j] + a * pcg[j];
-            b[j] = b[j] - a * q[j];
-          }
-        } else {
-          d[j] = Dv[j] * b[j] * ith;
-        }
-        continue;
-      }
-      const T di = l == 0 ? Dv[i] : Dv[j];
-      if (op == MGV_STEP1) {
-        const T rv = b[j] - q[j];
-        const T d0 = d[j];
-        const T d1 = c1 * d0 + c2 * di * rv;
-        r[j] = rv;
-        d[j] = d1;
-        x[j] = d0 + d1;
-      } else if (op == MGV_POST) {
-        const T rv = b[j] - q[j];
-        const T dv = di * rv * ith;
-        r[j] = rv;
-        d[j] = dv;
-        x[j] = x[j] + dv;
-      } else {  // MGV_LAST
-        x[j] = x[j] + c1 * d[j] + c2 * di * (r[j] - q[j]);
-      }
+      d[j] = Dv[j] * b[j] * ith;
     }
-  }
 }
 
 // CG scalars of the multigrid-preconditioned solve (one workgroup per load
@@ -747,20 +754,34 @@ hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, h
 // whether mg_launch_apply takes the all-load-cases-per-thread variant
 bool mg_apply_wide(long long nn_max) { return nn_max > 32768; }
 
-hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
-                           hipStream_t st, int live) {
+namespace {
+template <int EP>
+void launch_apply_ep(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec, hipStream_t st,
+                     int live) {
   if (mg_apply_wide(nn_max) && even) {
     const dim3 g(blocks_for(nn_max / 2, 256), 1, B.count);
-    if (prec == 0) mg_apply_pair_kernel<double><<<g, 256, 0, st>>>(B, l, src, live);
-    else mg_apply_pair_kernel<float><<<g, 256, 0, st>>>(B, l, src, live);
+    if (prec == 0) mg_apply_pair_kernel<double, EP><<<g, 256, 0, st>>>(B, l, src, live);
+    else mg_apply_pair_kernel<float, EP><<<g, 256, 0, st>>>(B, l, src, live);
   } else if (mg_apply_wide(nn_max)) {
     const dim3 g(blocks_for(nn_max, 256), 1, B.count);
-    if (prec == 0) mg_apply_kernel<double, NRHS><<<g, 256, 0, st>>>(B, l, src, live);
-    else mg_apply_kernel<float, NRHS><<<g, 256, 0, st>>>(B, l, src, live);
+    if (prec == 0) mg_apply_kernel<double, NRHS, EP><<<g, 256, 0, st>>>(B, l, src, live);
+    else mg_apply_kernel<float, NRHS, EP><<<g, 256, 0, st>>>(B, l, src, live);
   } else {
     const dim3 g(blocks_for(nn_max * NRHS, 256), 1, B.count);
-    if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, src, live);
-    else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, src, live);
+    if (prec == 0) mg_apply_kernel<double, 1, EP><<<g, 256, 0, st>>>(B, l, src, live);
+    else mg_apply_kernel<float, 1, EP><<<g, 256, 0, st>>>(B, l, src, live);
+  }
+}
+}  // namespace
+
+hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
+                           hipStream_t st, int live, int ep) {
+  switch (ep) {
+    case MGE_STEP1: launch_apply_ep<MGE_STEP1>(B, l, src, nn_max, even, prec, st, live); break;
+    case MGE_RES: launch_apply_ep<MGE_RES>(B, l, src, nn_max, even, prec, st, live); break;
+    case MGE_POST: launch_apply_ep<MGE_POST>(B, l, src, nn_max, even, prec, st, live); break;
+    case MGE_LAST: launch_apply_ep<MGE_LAST>(B, l, src, nn_max, even, prec, st, live); break;
+    default: launch_apply_ep<MGE_NONE>(B, l, src, nn_max, even, prec, st, live); break;
   }
   return hipGetLastError();
 }
@@ -768,17 +789,16 @@ hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, b
 // q = A_l v for load case 0 only (the setup's power iteration)
 hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st) {
   const dim3 g(blocks_for(nn_max, 256), 1, B.count);
-  if (prec == 0) mg_apply_kernel<double, 1><<<g, 256, 0, st>>>(B, l, 0, 0);
-  else mg_apply_kernel<float, 1><<<g, 256, 0, st>>>(B, l, 0, 0);
+  if (prec == 0) mg_apply_kernel<double, 1, MGE_NONE><<<g, 256, 0, st>>>(B, l, 0, 0);
+  else mg_apply_kernel<float, 1, MGE_NONE><<<g, 256, 0, st>>>(B, l, 0, 0);
   return hipGetLastError();
 }
 
-// formed: r already holds r - q (the voxel level's operator pass wrote it)
-hipError_t mg_launch_restrict(const MgBatch &B, int l, bool formed, long long nn_coarse_max, int prec,
+hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec,
                               hipStream_t st) {
   const dim3 g(blocks_for(nn_coarse_max * NRHS, 256), 1, B.count);
-  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(B, l, formed ? 1 : 0);
-  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(B, l, formed ? 1 : 0);
+  if (prec == 0) mg_restrict_kernel<double><<<g, 256, 0, st>>>(B, l);
+  else mg_restrict_kernel<float><<<g, 256, 0, st>>>(B, l);
   return hipGetLastError();
 }
 
@@ -796,10 +816,10 @@ hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st) {
+hipError_t mg_launch_vec(const MgBatch &B, int l, int nchunks_max, int prec, hipStream_t st) {
   const dim3 g((unsigned)nchunks_max, NRHS, B.count);
-  if (prec == 0) mg_vec_kernel<double><<<g, VEC_THREADS, 0, st>>>(B, l, op);
-  else mg_vec_kernel<float><<<g, VEC_THREADS, 0, st>>>(B, l, op);
+  if (prec == 0) mg_vec_kernel<double><<<g, VEC_THREADS, 0, st>>>(B, l);
+  else mg_vec_kernel<float><<<g, VEC_THREADS, 0, st>>>(B, l);
   return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ struct MgLevel {
   // inverse diagonal [3][nn]; level 0 uses the slot's matrix-free operator and D^-1 [nn]
   void *S, *Dinv;
   // V-cycle vectors [NRHS][3][nn]: right-hand side, iterate, residual,
-  // Chebyshev direction, operator output.  Level 0 aliases the slot's CG
+  // Chebyshev direction, operator output (on levels >= 1 the fused sweeps
+  // keep the next direction and the post-smoothing iterate there).  Level 0 aliases the slot's CG
   // vectors (b = r[0], x = r[1] (z), r = q[1], q = q[0]) except d, which
   // has a buffer of its own (the CG direction alternates between p[0] and p[1]).
   void *b, *x, *r, *d, *q;
@@ -66,10 +67,11 @@ struct MgBatch {
   int count;
 };
 
-// V-cycle vector sweeps at one level (grid: chunks x NRHS); see mg_vec_kernel
-enum { MGV_INIT = 0, MGV_STEP1 = 1, MGV_POST = 2, MGV_LAST = 3 };
 // CG scalar phases
 enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2 };
+// coarse-level operator passes with the Chebyshev sweep that follows them
+// fused into their output stage (see mg_epilogue)
+enum { MGE_NONE = 0, MGE_STEP1 = 1, MGE_RES = 2, MGE_POST = 3, MGE_LAST = 4 };
 
 // Number of levels for an n^3 grid (coarsening while even and above 4^3, so
 // the dense coarsest solve stays at most 8^3 and usually 3^3 or 4^3), or 0

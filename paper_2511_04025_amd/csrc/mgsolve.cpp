@@ -27,15 +27,16 @@ hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
 hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
 // live = 1: skip the load cases whose CG has stopped (state read on the device)
+// ep: the Chebyshev sweep fused into the output stage (MGE_*)
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
-                           hipStream_t st, int live);
+                           hipStream_t st, int live, int ep);
 hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int prec, hipStream_t st);
 bool mg_apply_wide(long long nn_max);
-hipError_t mg_launch_restrict(const MgBatch &B, int l, bool formed, long long nn_coarse_max, int prec,
+hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec,
                               hipStream_t st);
 hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
 hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
-hipError_t mg_launch_vec(const MgBatch &B, int l, int op, int nchunks_max, int prec, hipStream_t st);
+hipError_t mg_launch_vec(const MgBatch &B, int l, int nchunks_max, int prec, hipStream_t st);
 hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st);
 hipError_t mg_launch_power(const MgBatch &B, int l, int phase, int nchunks_max, int prec, hipStream_t st);
 
@@ -277,38 +278,32 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   hipEvent_t e0 = nullptr;
   auto tb = [&](bool on) -> int { return (on && timer) ? timer->timed_begin(&e0) : (e0 = nullptr, 0); };
   auto te = [&](int kind) -> int { return (e0 && timer) ? timer->timed_end(e0, kind) : 0; };
-  auto vec = [&](int op) -> int {
-    const bool t = l == 0 && op == MGV_INIT;
-    if ((rc = tb(t))) return rc;
-    SHH_HIP(mg_launch_vec(B, l, op, nch_max, prec, st));
+  auto vec = [&]() -> int {
+    if ((rc = tb(l == 0))) return rc;
+    SHH_HIP(mg_launch_vec(B, l, nch_max, prec, st));
     return te(SHH_PROF_MG_UPDATE);
   };
-  auto app = [&](int src) -> int {
-    if (l == 0) return apply0(smooth, MG_SRC_RES);  // r - K d1 in place of r
+  // an operator pass with the Chebyshev sweep after it fused in: the voxel
+  // level's stencil passes, the coarse levels' stored-stencil passes
+  auto app = [&](int src0, int ep) -> int {
+    if (l == 0) return apply0(smooth, src0);
     if ((rc = tb(l == 1))) return rc;
-    SHH_HIP(mg_launch_apply(B, l, src, nn_max, all_even, prec, st, 1));
+    SHH_HIP(mg_launch_apply(B, l, 0, nn_max, all_even, prec, st, 1, ep));
     return te(SHH_PROF_MG_APPLY1);
   };
   // pre-smoother (at the voxel level INIT also applies the pending CG
-  // update, and the operator runs fused with the sweep after it)
-  if ((rc = vec(MGV_INIT))) return rc;
-  if (l == 0) rc = apply0(smooth, MG_SRC_STEP1);
-  else if (!(rc = app(1))) rc = vec(MGV_STEP1);
-  if (rc || (rc = app(1))) return rc;
-  // coarse-grid correction of the residual r - A d
+  // update); the second pass leaves r - A d1, the residual to restrict, in r
+  if ((rc = vec()) || (rc = app(MG_SRC_STEP1, MGE_STEP1)) || (rc = app(MG_SRC_RES, MGE_RES))) return rc;
+  // coarse-grid correction
   if ((rc = tb(l == 0))) return rc;
-  SHH_HIP(mg_launch_restrict(B, l, l == 0, nn_next_max, prec, st));
+  SHH_HIP(mg_launch_restrict(B, l, nn_next_max, prec, st));
   if ((rc = te(SHH_PROF_MG_RESTRICT))) return rc;
   if ((rc = vcycle(smooth, l + 1, st, timer, apply0))) return rc;
   if ((rc = tb(l == 0))) return rc;
   SHH_HIP(mg_launch_prolong(B, l, nn_max, prec, st));
   if ((rc = te(SHH_PROF_MG_PROLONG))) return rc;
   // post-smoother
-  if (l == 0) {
-    if ((rc = apply0(smooth, MG_SRC_POST)) || (rc = apply0(smooth, MG_SRC_LAST))) return rc;
-  } else if ((rc = app(0)) || (rc = vec(MGV_POST)) || (rc = app(1)) || (rc = vec(MGV_LAST))) {
-    return rc;
-  }
+  if ((rc = app(MG_SRC_POST, MGE_POST)) || (rc = app(MG_SRC_LAST, MGE_LAST))) return rc;
   return SHH_OK;
 }
 
@@ -490,7 +485,7 @@ int mg_apply_level(Slot &s, int l, const void *d_v, void *d_q, hipStream_t st) {
   const MgLevel &L = s.mg.lv[l];
   const size_t bytes = (size_t)NRHS * 3 * L.nn * (s.host.prec == SHH_PREC_FP64 ? 8 : 4);
   SHH_HIP(hipMemcpyAsync(L.x, d_v, bytes, hipMemcpyDeviceToDevice, st));
-  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, L.n % 2 == 0, s.host.prec, st, 0));
+  SHH_HIP(mg_launch_apply(batch_of({&s}), l, 0, L.nn, L.n % 2 == 0, s.host.prec, st, 0, MGE_NONE));
   SHH_HIP(hipMemcpyAsync(d_q, L.q, bytes, hipMemcpyDeviceToDevice, st));
   SHH_HIP(hipStreamSynchronize(st));
   return SHH_OK;
