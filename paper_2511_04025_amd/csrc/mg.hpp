@@ -13,7 +13,7 @@
 // for the smoother and residual sweeps.  Smoothing is Chebyshev (degree 2)
 // on D^-1 A over [h / 33, h], h an upper bound of lambda_max: on the voxel
 // level the element bound lambda_max(diag(K_0)^-1 K_0), on coarse levels
-// 1.5 x a power-iteration estimate; the coarsest level (at most 8^3 nodes) is
+// 1.2 x a power-iteration estimate; the coarsest level (at most 8^3 nodes) is
 // solved with a dense inverse of its operator made nonsingular on the three
 // rigid translations, assembled and inverted on the device.
 #pragma once
