@@ -65,11 +65,16 @@ constexpr int VEC_THREADS = 256;
 constexpr int PSTRIDE = 8;          // doubles per workgroup partial of the CG kernels
 
 // ---- per-slot device state ----
-enum SolveStatus : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_BREAKDOWN = -6 };
+// ST_STALLED: the selective multigrid CG lost definiteness after keeping its
+// direction across a residual replacement; the case waits for the design's
+// final residual check, which resumes it from a restart, and restarts after
+// every later replacement
+enum SolveStatus : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_STALLED = 3, ST_BREAKDOWN = -6 };
 
 struct CgState {
   double rho[NRHS];       // r^T D^-1 r of the current residual
   double rho_prev[NRHS];  // the previous one (for a replaced residual's beta)
+  double rho_mg[NRHS];    // multigrid CG: r . z at the start of the last iteration
   double alpha[NRHS];     // step length of the update still to be applied to x, r
   double beta[NRHS];      // coefficient of the next direction update
   double rr[NRHS];        // ||r||^2 (recursive, or true after a recompute)
@@ -82,6 +87,7 @@ struct CgState {
   int iters[NRHS];
   int pcur[NRHS];         // which of the two r, p, q buffer sets is current
   int mgpar[NRHS];        // multigrid CG: which p buffer holds the current direction
+  int no_keep[NRHS];      // selective multigrid CG: restart after every replacement (set by a stall)
   unsigned cnt[8];        // last-workgroup counters (0..5 per load case, 6, 7 misc)
   double V;               // volume fraction
   double t;               // half-thickness used

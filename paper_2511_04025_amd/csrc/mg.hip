@@ -495,6 +495,8 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_vec_kernel(MgBatch B, int l) {
 // case; per-tile partials of the voxel-level stencil passes: the direction
 // pass for ALPHA, the last post-smoothing sweep for RESTART and BETA).
 //   RESTART: rho = r . z after a (re)started V-cycle, beta = 0
+//   REPLACE: the same after a residual replacement, the direction kept:
+//            beta = rho' / (rho the last iteration started from)
 //   ALPHA:   alpha = rho / p . K p; the new direction becomes current
 //   BETA:    rho' = r . z, ||r||^2 -> convergence; beta = rho' / rho
 __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int phase) {
@@ -513,10 +515,17 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
     st->beta[k] = 0.0;
     return;
   }
-  if (phase == MGS_RESTART) {
-    const double rho = tot[0];
+  if (phase == MGS_RESTART || phase == MGS_REPLACE) {
+    // (the replacement's residual phase has since overwritten rho and beta
+    // with the Jacobi recurrences; rho_mg kept the iteration's own rho)
+    // The direction is kept only while the replaced residual agrees with the
+    // recursive one (r . z within a factor 2 of it: rho_prev holds the
+    // recursive value); a larger drift restarts.
+    const double rho = tot[0], rho0 = st->rho_mg[k], rho_rec = st->rho_prev[k];
+    const bool keep = phase == MGS_REPLACE && rho0 > 0.0 && rho_rec > 0.0 && rho <= 2.0 * rho_rec &&
+                      rho >= 0.5 * rho_rec;
+    st->beta[k] = keep ? rho / rho0 : 0.0;
     st->rho[k] = rho;
-    st->beta[k] = 0.0;
     st->alpha[k] = 0.0;
     if (!(rho > 0.0) || !isfinite(rho)) {
       st->status[k] = ST_BREAKDOWN;
@@ -541,6 +550,7 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_scalar_kernel(MgBatch B, int p
     const double rho = st->rho[k];
     const bool ok = isfinite(rho_n) && rho_n >= 0.0;
     st->beta[k] = ok && rho > 0.0 ? rho_n / rho : 0.0;
+    st->rho_mg[k] = rho;
     st->rho[k] = rho_n;
     if (rel <= s->rtol) {
       st->status[k] = ST_CONVERGED;

@@ -68,7 +68,7 @@ struct MgBatch {
 };
 
 // CG scalar phases
-enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2 };
+enum { MGS_RESTART = 0, MGS_ALPHA = 1, MGS_BETA = 2, MGS_REPLACE = 3 };
 // coarse-level operator passes with the Chebyshev sweep that follows them
 // fused into their output stage (see mg_epilogue)
 enum { MGE_NONE = 0, MGE_STEP1 = 1, MGE_RES = 2, MGE_POST = 3, MGE_LAST = 4 };

@@ -510,15 +510,20 @@ int mg_iterate(const std::vector<Slot *> &all, hipStream_t st, Solver *timer, co
   int rc;
   for (size_t b0 = 0; b0 < all.size(); b0 += MG_MAXB) {
     const std::vector<Slot *> slots(all.begin() + b0, all.begin() + std::min(all.size(), b0 + MG_MAXB));
-    // (re)started slots: z = V r, rho = r . z, beta = 0 (the direction pass
-    // then starts from p = z)
-    std::vector<Slot *> rs;
+    // slots with a new residual: z = V r, rho = r . z, and beta = 0 (a
+    // restart: the direction pass then starts from p = z) or, after a
+    // residual replacement, beta rho' / rho (the direction is kept)
+    std::vector<Slot *> rs, restart, keep;
     for (Slot *s : slots)
-      if (s->mg_restart) rs.push_back(s);
+      if (s->mg_restart) {
+        rs.push_back(s);
+        (s->mg_keep_dir ? keep : restart).push_back(s);
+      }
     if (!rs.empty()) {
       if ((rc = vcycle(rs, 0, st, timer, apply0))) return rc;
-      SHH_HIP(mg_launch_scalar(batch_of(rs), MGS_RESTART, st));
-      for (Slot *s : rs) s->mg_restart = false;
+      if (!restart.empty()) SHH_HIP(mg_launch_scalar(batch_of(restart), MGS_RESTART, st));
+      if (!keep.empty()) SHH_HIP(mg_launch_scalar(batch_of(keep), MGS_REPLACE, st));
+      for (Slot *s : rs) s->mg_restart = s->mg_keep_dir = false;
     }
     const MgBatch B = batch_of(slots);
     // p = z + beta p, q = K p, partials p . q in one pass; alpha

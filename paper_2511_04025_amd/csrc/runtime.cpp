@@ -431,8 +431,13 @@ int Solver::residual(const std::vector<Slot *> &slots, int mode) {
   if ((rc = build(K_FINISH, slots, mode, all, la))) return rc;
   SHH_HIP(launch_finish_resid(la, prec, st_));
   SHH_HIP(launch_scalar(ls, PH_RESID, st_));
-  // a multigrid-preconditioned CG restarts from the new residual
-  for (Slot *s : slots) s->mg_restart = true;
+  // a multigrid-preconditioned CG takes z = V r of the new residual: a
+  // restart after the first and the final residual, the direction kept after
+  // a replacement (reliable updates)
+  for (Slot *s : slots) {
+    s->mg_restart = true;
+    s->mg_keep_dir = mode == RES_RECOMPUTE;
+  }
   return SHH_OK;
 }
 

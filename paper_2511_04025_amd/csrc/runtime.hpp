@@ -58,6 +58,7 @@ struct Slot {
   MgDev mg;                     // host image of the level descriptors
   MgDev *d_mg = nullptr;
   bool mg_restart = false;      // next iteration starts from z = V r, p = z
+  bool mg_keep_dir = false;     // ... or, after a residual replacement, p = z + beta p
   int sel_active_nodes = 0;     // selective solve: active nodes
   bool timing = true;           // launch timing allowed (false: the no-allocation entry point)
 };

@@ -660,6 +660,11 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_zero_kernel(const SelBatch B)
 }
 
 // ---- scalar phases (one workgroup per load case; one in total for C^H) --------
+// a residual replacement keeps the CG direction while the new r . z is within
+// this factor of the recursive one (and until the case has stalled once)
+#ifndef SHH_KEEP_DIR_RATIO
+#define SHH_KEEP_DIR_RATIO 2.0
+#endif
 __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch B, int phase) {
   SelDev *S = B.d[blockIdx.y];
   __shared__ double red[22 * 16];
@@ -699,13 +704,19 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch 
     if (!(pq > 0.0) || !(st->rho[k] > 0.0)) {
       st->alpha[k] = 0.0;
       st->active[k] = 0;
-      st->status[k] = ST_BREAKDOWN;
+      st->status[k] = ST_STALLED;
+      st->no_keep[k] = 1;
       return;
     }
     st->alpha[k] = st->rho[k] / pq;
     return;
   }
-  if (phase == SSC_MG_BETA || phase == SSC_MG_RESTART) {  // rho' = r . z, ||r||, beta
+  // rho' = r . z, ||r||, and beta: after an iteration rho' / rho; after a
+  // restart 0; after a residual replacement (r replaced by f - K u, z = V r
+  // recomputed) the direction is kept, beta' = beta rho' / rho = rho' over
+  // the rho the last iteration started from, while rho' is within a factor 2
+  // of the recursive rho (a larger drift restarts)
+  if (phase == SSC_MG_BETA || phase == SSC_MG_RESTART || phase == SSC_MG_REPLACE) {
     if (!st->active[k]) return;
     double tot[2];
     sum_partials<2, SEL_PS>(parts, np, tot, red, SEL_THREADS);
@@ -720,12 +731,19 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch 
       st->status[k] = ST_CONVERGED;
     } else if (!(rho1 > 0.0)) {  // r . V r > 0 unless the cycle lost definiteness
       st->active[k] = 0;
-      st->status[k] = ST_BREAKDOWN;
+      st->status[k] = phase == SSC_MG_RESTART ? ST_BREAKDOWN : ST_STALLED;
+      st->no_keep[k] = 1;
     } else if (st->iters[k] >= S->max_iter) {
       st->active[k] = 0;
       st->status[k] = ST_MAXIT;
     }
-    st->beta[k] = phase == SSC_MG_RESTART ? 0.0 : rho1 / st->rho[k];
+    if (phase == SSC_MG_RESTART) st->beta[k] = 0.0;
+    else if (phase == SSC_MG_REPLACE)
+      st->beta[k] = !st->no_keep[k] && rho1 <= SHH_KEEP_DIR_RATIO * st->rho[k] &&
+                            rho1 * SHH_KEEP_DIR_RATIO >= st->rho[k]
+                        ? st->beta[k] * rho1 / st->rho[k]
+                        : 0.0;
+    else st->beta[k] = rho1 / st->rho[k];
     st->rho[k] = rho1;
     return;
   }

@@ -193,11 +193,13 @@ struct SelRun {
       if ((rc = run_timed(SHH_PROF_SEL_MG_SMOOTH, [&] { return sel_launch_mg_op(B, m, st); }))) return rc;
     return SHH_OK;
   }
-  int restart(const std::vector<SelSlot *> &v) {
+  // z = V r of a new residual: a restart (beta = 0), or after a residual
+  // replacement with the direction kept (SSC_MG_REPLACE)
+  int restart(const std::vector<SelSlot *> &v, int phase = SSC_MG_RESTART) {
     const SelBatch B = batch_of(v);
     int rc;
     if ((rc = vcycle(B, slots_of(v), 1))) return rc;
-    SEL_HIP(sel_launch_scalar(B, SSC_MG_RESTART, st));
+    SEL_HIP(sel_launch_scalar(B, phase, st));
     return SHH_OK;
   }
   int iteration(const std::vector<SelSlot *> &v, bool mg) {
@@ -359,7 +361,7 @@ int run_group(SelRun &run, const std::vector<SelSlot *> &group, bool mg, const s
       ++launched;
       if (R > 0 && launched % R == 0) {
         if ((rc = run.residual(batch_of(running), 1))) return rc;
-        if (mg && (rc = run.restart(running))) return rc;  // the V-cycle of the replaced residual
+        if (mg && (rc = run.restart(running, SSC_MG_REPLACE))) return rc;  // z of the replaced residual
       }
     }
     if ((rc = run.read_state(running))) return rc;
@@ -464,7 +466,8 @@ int sel_solve(const std::vector<Slot *> &all, hipStream_t st) {
       if (s.ev[0] && s.ev[4] && hipEventElapsedTime(&a, s.ev[0], s.ev[4]) == hipSuccess) s.ms[4] = a;
       int status = SHH_OK;
       for (int k = 0; k < NRHS; ++k) {
-        if (s.state.status[k] == ST_BREAKDOWN) status = SHH_BREAKDOWN;
+        // a case still stalled after its restarts counts as broken down
+        if (s.state.status[k] == ST_BREAKDOWN || s.state.status[k] == ST_STALLED) status = SHH_BREAKDOWN;
         else if (status == SHH_OK && s.state.status[k] != ST_CONVERGED) status = SHH_NOT_CONVERGED;
       }
       s.status = status;
