@@ -71,7 +71,8 @@ extern "C" {
                                  multigrid V-cycle whose coarse levels are the Galerkin
                                  grids of the culled voxel operator where the grid
                                  coarsens (as for SHH_SOLVER_MG), else by Jacobi.  Any n.
-                                 Not served by the engine, no adjoint (SHH_UNSUPPORTED)  */
+                                 Not served by the engine (SHH_UNSUPPORTED); shh_grad
+                                 differentiates the culled model                         */
 #define SHH_SOLVER_SELECTIVE_JACOBI 4 /* the same culled system, always Jacobi-preconditioned */
 
 /* One design (Eq. (6)-(7) parameters and material). */
@@ -298,7 +299,10 @@ int32_t shh_energy(int32_t n, const double *d_E, double nu, const double *d_u, d
                              V: call again with dL/dC = 0, dL/dV = 1)
    The forward's own t (given or chosen from target_vf) is the point of
    evaluation.  The workspace's vectors are overwritten (scratch); F, grad F,
-   beta and u survive, so several calls may follow one forward.
+   beta and u survive, so several calls may follow one forward.  After a
+   selective solve the gradient is that of the culled model: E_e = E beta_e
+   on an active voxel (dE_e/dbeta_e = E), nothing on a culled one (a voxel
+   crossing beta = 1e-3 is not differentiated).
    Returns SHH_UNSUPPORTED for the hard step. */
 int32_t shh_grad(const shh_design *design, const shh_opts *opts, void *d_ws, size_t ws_bytes,
                  const double dL_dCH[36], double dL_dV, double *dL_dpos, double *dL_dq, double *dL_dalpha,

@@ -14,7 +14,10 @@ vertices of at least one active voxel.  Here:
 * C^H is the energy form of Eq. (8) summed over the active voxels, with |Y|
   the whole cell (n^3 voxels);
 * a right-hand side whose norm is at rounding level (at most 1e-12 E sqrt(3 n^3))
-  is a zero load with u = 0, as in the dense path.
+  is a zero load with u = 0, as in the dense path;
+* the gradient (Eq. (9)) follows the culled model: E_e = E beta_e on an
+  active voxel has dE_e/dbeta_e = E, a culled voxel contributes nothing, and
+  the jump of a voxel crossing eps is not differentiated.
 
 The restricted K is singular beyond the three rigid translations whenever the
 active voxels fall apart into several pieces (every piece floats freely), but
@@ -27,6 +30,7 @@ with the plain Jacobi-PCG of ``solve.py``, without pinning a node.
 import numpy as np
 import scipy.sparse as sp
 
+from . import adjoint as adj
 from . import fem
 from . import field as fld
 from . import homogenize as hom
@@ -139,3 +143,22 @@ def components(node_mask, Ec):
     cols = loc[:, 1:].ravel()
     g = sp.coo_matrix((np.ones(rows.size), (rows, cols)), shape=(nodes.size, nodes.size))
     return connected_components(g, directed=False)
+
+
+def design_gradient_selective(pos, q, n, dL_dC, dL_dV, *, thickness, kappa, K=3, alpha=None, iso=0.0,
+                              dist_mode=0, E=1.0, nu=0.3, eps=EPS_ACTIVE, rtol=1e-13):
+    """Eq. (9) through the culled system for a logistic shell (kappa > 0)
+    with t given: returns (C^H, V, dL/dpos (N, 3), dL/dq (N,)) for the
+    upstream gradients dL/dC (6x6) and dL/dV.  The element weights
+    s_e = dL/dC : dC/dE_e come from the culled solution (zero on culled
+    voxels), then the chain of the dense path with dE_e/dbeta_e = E."""
+    F, G = fld.field_and_gradient(pos, q, n, K=K, alpha=alpha)
+    d = fld.distance(F, G, iso=iso, dist_mode=dist_mode)
+    beta = fld.occupancy(d, thickness, kappa)
+    Ec = culled_moduli(beta, E, eps)
+    C, info = homogenize_selective_stiffness(Ec, nu, rtol=rtol)
+    s_e = adj.element_energy_weights(Ec, info["U"], nu, n, dL_dC) * (Ec > 0.0)
+    gF, gG = adj.voxel_sensitivities(F, G, d, beta, thickness, kappa, E, 0.0, s_e, dL_dV, iso=iso,
+                                     dist_mode=dist_mode)
+    dpos, dq = adj.charge_gradients(gF, gG, pos, q, n, K=K, alpha=alpha)
+    return C, float(beta.mean()), dpos, dq

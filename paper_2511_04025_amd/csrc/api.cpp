@@ -482,7 +482,7 @@ int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, v
   shh_opts o;
   SHH_TRY(normalize_opts(opts, &o));
   if (!dL_dCH || !std::isfinite(dL_dV)) return SHH_INVALID_ARG;
-  if (!(design->kappa > 0.0) || is_selective(o.solver)) return SHH_UNSUPPORTED;
+  if (!(design->kappa > 0.0)) return SHH_UNSUPPORTED;
   if (!o.save_for_backward) return SHH_INVALID_ARG;
   for (int i = 0; i < 36; ++i)
     if (!std::isfinite(dL_dCH[i])) return SHH_INVALID_ARG;
@@ -515,8 +515,13 @@ int grad_enqueue(GradJob &job, const shh_design *design, const shh_opts *opts, v
   double *d_scr = (double *)(s.base + s.lay.adj);  // sized for the adjoint by the layout
   job.host.assign(outd, 0.0);
   std::memcpy(job.host.data(), g21, sizeof(g21));
-  SHH_HIP(hipMemcpyAsync(d_g21, job.host.data(), sizeof(g21), hipMemcpyHostToDevice, st));
-  SHH_HIP(launch_energy_sens(s.d_slot, s.host.nn, d_g21, d_gE, st));
+  if (is_selective(o.solver)) {
+    // the culled system: dL/dE_e from the compact solution (culled voxels 0)
+    SHH_TRY(sel_energy_gradient(s, g21, &d_gE, st));
+  } else {
+    SHH_HIP(hipMemcpyAsync(d_g21, job.host.data(), sizeof(g21), hipMemcpyHostToDevice, st));
+    SHH_HIP(launch_energy_sens(s.d_slot, s.host.nn, d_g21, d_gE, st));
+  }
   SHH_HIP(launch_adjoint(s.d_slot, s.host.n, s.host.nb, job.N, s.host.K, d_gE, dL_dV, d_scr, job.d_out,
                          job.d_out + 4 * job.N, job.d_out + 4 * job.N + job.nalpha, st));
   SHH_HIP(hipMemcpyAsync(job.host.data(), job.d_out, sizeof(double) * outd, hipMemcpyDeviceToHost, st));

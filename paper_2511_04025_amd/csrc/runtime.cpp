@@ -258,7 +258,7 @@ int slot_init(Slot &s, char *base, hipStream_t st) {
   h.lam = d.nu / ((1.0 + d.nu) * (1.0 - 2.0 * d.nu));
   h.mu = 1.0 / (2.0 * (1.0 + d.nu));
   h.E = d.E;
-  h.E_void = d.E_void;
+  h.E_void = is_selective(s.opts.solver) ? 0.0 : d.E_void;  // the culled system has no floor: E_e = E beta
   h.iso = d.iso;
   h.kappa = d.kappa;
   h.t_given = d.thickness;

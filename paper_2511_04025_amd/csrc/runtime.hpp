@@ -181,6 +181,10 @@ double now_ms();
 // every launch (same precision and solver option)
 int sel_solve(const std::vector<Slot *> &slots, hipStream_t st);
 inline int sel_solve(Slot &s, hipStream_t st) { return sel_solve(std::vector<Slot *>{&s}, st); }
+// the selective solve's dL/dE_e (dense [n^3], zero on culled voxels) for the
+// folded weights g21 of dL/dC^H, from a slot solved with save_for_backward;
+// *d_gE points into the slot's workspace
+int sel_energy_gradient(Slot &s, const double g21[21], double **d_gE, hipStream_t st);
 void fill_result(const Slot &s, shh_result *out);
 
 }  // namespace shh

@@ -1,6 +1,7 @@
 // Kernels of the selective (active-set) solve: compaction of the active nodes,
 // the node-centric operator on the compact lists, and the CG vector and scalar
 // phases.  See sel.hpp for the layout and the operator's construction.
+#include "hexop.hpp"
 #include "sel.hpp"
 
 namespace shh {
@@ -1104,6 +1105,69 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_prolong_kernel(const SelBa
   }
 }
 
+// ---- energy sensitivity (the adjoint of Eq. (9) on the culled system) --------
+// With u^k at equilibrium, dC_ij / dE_e = (chi^i + u^i_e)^T K_0 (chi^j + u^j_e) / n^3
+// (the solve's own dependence drops out by self-adjointness), so
+// dL/dE_e = sum_{i<=j} g_ij e_ij / n^3 with g the symmetric fold of dL/dC.
+// One thread per active node: the element whose lower corner it is, when that
+// element carries stiffness (its eight corners are then active nodes); culled
+// elements keep the zero of the fill.
+__global__ __launch_bounds__(SEL_THREADS) void sel_fill_kernel(double *out, long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = 0.0;
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void sel_energy_sens_kernel(const SelBatch B, const double *g21,
+                                                                      double *out) {
+  SelDev *S = B.d[blockIdx.y];
+  if (blockIdx.x >= (unsigned)S->nparts) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S->na) return;
+  if (!(S->Ec64[i] > 0.0)) return;
+  const int n = S->n;
+  const unsigned cd = S->coord[i];
+  const int x = int(cd & 1023u), y = int((cd >> 10) & 1023u), z = int(cd >> 20);
+  const int xs[2] = {x, wrap_inc(x, n)}, ys[2] = {y, wrap_inc(y, n)}, zs[2] = {z, wrap_inc(z, n)};
+  int node[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    node[a] = S->map[((long long)zs[a >> 2] * n + ys[(a >> 1) & 1]) * n + xs[a & 1]];
+  const double *U = S->x64;
+  double g[21];
+#pragma unroll
+  for (int t = 0; t < 21; ++t) g[t] = g21[t];
+  // element Hadamard coefficients of chi^k + u^k for every load case
+  auto coeffs = [&](int k, double (&h)[3][8]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double v[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) v[a] = U[(long long)node[a] * (3 * NRHS) + 3 * k + c];
+      hadamard8<double>(v, h[c]);
+    }
+    add_chi<double>(k, h);
+  };
+  double sens = 0.0;
+  int t = 0;
+  for (int a = 0; a < NRHS; ++a) {
+    double ha[3][8];
+    coeffs(a, ha);
+    for (int b = a; b < NRHS; ++b) {
+      double hb[3][8], wb[3][8];
+      coeffs(b, hb);
+      hex_apply<double>(S->kop, hb, wb, 1.0);
+      double e = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) e += ha[c][m] * wb[c][m];
+      sens += g[t++] * e;
+    }
+  }
+  out[((long long)z * n + y) * n + x] = sens / double(S->nn);
+}
+
 // ---- launchers ----------------------------------------------------------------
 // Every launch covers the batch's slots (grid y = slot); workgroups past a
 // slot's own count return at once.
@@ -1212,6 +1276,14 @@ hipError_t sel_launch_mg_restrict(const SelBatch &B, hipStream_t st) {
 
 hipError_t sel_launch_mg_prolong(const SelBatch &B, hipStream_t st) {
   SEL_PREC_LAUNCH(sel_mg_prolong_kernel, parts_grid(B), B);
+  return hipGetLastError();
+}
+
+hipError_t sel_launch_energy_sens(const SelBatch &B, long long nn, const double *d_g21, double *d_gE,
+                                  hipStream_t st) {
+  sel_fill_kernel<<<(unsigned)std::min<long long>((nn + SEL_THREADS - 1) / SEL_THREADS, 4096), SEL_THREADS, 0, st>>>(
+      d_gE, nn);
+  sel_energy_sens_kernel<<<parts_grid(B), SEL_THREADS, 0, st>>>(B, d_g21, d_gE);
   return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct SelDev {
   // f0[k][a][c]: component c at corner a of K_0 chi^k (E = 1), the element
   // force of unit strain k; a node's load is -sum_a E_a f0[k][a]
   double f0[NRHS][8][3];
+  double kop[KOP_N];      // the element operator's constants (E = 1), for the energy sensitivity
   const double *E64;      // dense culled moduli [n^3] (input of the compaction)
   int *map;               // [n^3] compact index or -1
   unsigned *coord;        // [na] packed coordinates, ascending
@@ -105,5 +106,8 @@ hipError_t sel_launch_mg_s1(const SelBatch &B, int restart, hipStream_t st);
 hipError_t sel_launch_mg_dir(const SelBatch &B, hipStream_t st);
 hipError_t sel_launch_mg_restrict(const SelBatch &B, hipStream_t st);
 hipError_t sel_launch_mg_prolong(const SelBatch &B, hipStream_t st);
+// dL/dE_e over the dense voxel grid (zero on culled voxels) from the solution
+// of one solved design and the folded weights g21 of dL/dC^H
+hipError_t sel_launch_energy_sens(const SelBatch &B, long long nn, const double *d_g21, double *d_gE, hipStream_t st);
 
 }  // namespace shh

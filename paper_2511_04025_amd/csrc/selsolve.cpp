@@ -245,6 +245,7 @@ int describe(SelSlot &x, size_t &aux_used) {
   h.ffloor = sd.ffloor;
   h.max_iter = sd.max_iter;
   element_forces(sd.lam, sd.mu, h.f0);
+  for (int c = 0; c < KOP_N; ++c) h.kop[c] = sd.kop64[c];
   h.E64 = sd.E64;
   h.st = sd.st;
   h.r = vec + 2 * vb;
@@ -372,6 +373,33 @@ int run_group(SelRun &run, const std::vector<SelSlot *> &group, bool mg, const s
 }  // namespace
 
 size_t sel_descriptor_bytes() { return sizeof(SelDev); }
+
+int sel_energy_gradient(Slot &s, const double g21[21], double **d_gE, hipStream_t st) {
+  // the compact lists and the FP64 solution of the forward call are still in
+  // the workspace (save_for_backward); the descriptor is rebuilt from the
+  // layout, n_a read back from the compaction counts
+  SelSlot x;
+  x.s = &s;
+  size_t aux = 0;
+  int rc;
+  if ((rc = describe(x, aux))) return rc;
+  SelDev &h = x.h;
+  SEL_HIP(hipMemcpyAsync(&h.na, h.counts + h.nchunks, sizeof(int), hipMemcpyDeviceToHost, st));
+  SEL_HIP(hipStreamSynchronize(st));
+  h.nparts = std::max(1, (h.na + SEL_THREADS - 1) / SEL_THREADS);
+  // dL/dE_e (n^3 doubles) and the weights after the compact arrays in vectors 0-1
+  char *vec = s.base + s.lay.vec;
+  if (aux + al256(sizeof(double) * (size_t)h.nn) + 256 > 2 * s.lay.vec_bytes) return SHH_WORKSPACE_TOO_SMALL;
+  *d_gE = (double *)(vec + aux);
+  double *d_g21 = (double *)(vec + aux + al256(sizeof(double) * (size_t)h.nn));
+  SEL_HIP(hipMemcpyAsync(x.d, &h, sizeof(SelDev), hipMemcpyHostToDevice, st));
+  SEL_HIP(hipMemcpyAsync(d_g21, g21, 21 * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<SelSlot *> one{&x};
+  SEL_HIP(sel_launch_energy_sens(batch_of(one), h.nn, d_g21, *d_gE, st));
+  // the weights' host copy must outlive the asynchronous upload
+  SEL_HIP(hipStreamSynchronize(st));
+  return SHH_OK;
+}
 
 int sel_solve(const std::vector<Slot *> &all, hipStream_t st) {
   if (all.empty()) return SHH_OK;

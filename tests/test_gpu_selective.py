@@ -142,3 +142,88 @@ def test_batched_selective_solve_equals_single_designs(solver):
         assert r["status"] == 0 and r1["status"] == 0
         assert np.array_equal(r["C"], r1["C"]) and np.array_equal(r["iters"], r1["iters"])
         assert r["active_nodes"] == r1["active_nodes"]
+
+
+def _sweep_design(index):
+    # design `index` of a seeded random sweep (16 ... 128^3, 8-64 charges,
+    # 3-30 % volume, nu from -0.3 to 0.45)
+    rng = np.random.default_rng(777)
+    for i in range(index + 1):
+        n = int(rng.choice([32, 48, 64, 80, 96, 128]))
+        d = wl.random_design(50000 + i, n, N=int(rng.integers(8, 64)), vf=float(rng.uniform(0.03, 0.3)),
+                             E_void=float(rng.choice([1e-6, 1e-4, 1e-3])), pm=bool(rng.random() < 0.5))
+        d = d.with_(nu=float(rng.choice([0.0, 0.2, 0.3, 0.45, -0.3])))
+    return d
+
+
+@pytest.mark.parametrize("index", [18, 34])
+def test_designs_whose_kept_direction_lost_definiteness_converge(index):
+    # on these two designs a CG direction kept across a residual replacement
+    # once made p.Kp or r.z non-positive (a breakdown); the stalled load case
+    # now resumes from a restart and the solve converges to the FP64 result
+    A = api()
+    d = _sweep_design(index)
+    print(f"sweep design {index}: n {d.n}", flush=True)
+    r = A.homogenize(d, precision="mixed", rtol=3e-6, solver="selective")
+    print("  iters", r["iters"].tolist(), "status", r["status"], flush=True)
+    assert r["status"] == 0 and np.all(r["rel_res"] <= 3e-6)
+    r64 = A.homogenize(d, precision="fp64", rtol=1e-10, solver="selective")
+    assert r64["status"] == 0
+    assert_ch_close(r["C"], r64["C"], 1e-4)
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-8), ("mixed", 1e-7, 1e-4)])
+def test_culled_gradient_matches_the_oracle(precision, rtol, tol):
+    # the adjoint of Eq. (9) through the culled system (dE_e/dbeta_e = E on
+    # active voxels, nothing on culled ones) against the oracle's
+    A = api()
+    from oracle import field as fld, selective as osel
+    n = 12
+    d = wl.random_design(63, n, N=6, vf=0.25, E_void=1e-3, kappa=4.0 * n)
+    F, G = fld.field_and_gradient(d.pos, d.q, n)
+    t = fld.thickness_for_volume(fld.distance(F, G), 0.25, d.kappa)
+    rng = np.random.default_rng(9)
+    dLdC = rng.standard_normal((6, 6))
+    C_o, V_o, dpos_o, dq_o = osel.design_gradient_selective(d.pos, d.q, n, dLdC, 0.2, thickness=t, kappa=d.kappa)
+    dt = d.with_(thickness=t)
+    r = A.homogenize(dt, precision=precision, rtol=rtol, save_for_backward=True, return_workspace=True,
+                     solver="selective")
+    assert r["status"] == 0 and abs(r["V"] - V_o) <= 1e-13
+    dpos, dq = A.grad(dt, r["opts"], r["workspace"], dLdC, 0.2)
+    scale = max(np.abs(dpos_o).max(), np.abs(dq_o).max())
+    print(f"culled gradient {precision}: pos {np.abs(dpos - dpos_o).max() / scale:.2e} "
+          f"q {np.abs(dq - dq_o).max() / scale:.2e}", flush=True)
+    assert np.max(np.abs(dpos - dpos_o)) <= tol * scale
+    assert np.max(np.abs(dq - dq_o)) <= tol * scale
+
+
+def test_culled_gradient_in_alpha_and_t_matches_differences():
+    # alpha_hkl and t through the culled system, against central differences
+    # of the GPU forward in FP64 (h small enough that no voxel crosses eps)
+    A = api()
+    n = 16
+    d = wl.random_design(64, n, N=8, vf=0.2, E_void=1e-3, kappa=4.0 * n)
+    alpha = 1.0 + 0.2 * np.random.default_rng(64).standard_normal((4, 4, 4))
+    r0 = A.homogenize(d.with_(alpha=alpha), precision="fp64", rtol=1e-13, solver="selective")
+    dd = d.with_(alpha=alpha, thickness=r0["t"], target_vf=None)
+    w = np.random.default_rng(65).standard_normal((6, 6))
+    r = A.homogenize(dd, precision="fp64", rtol=1e-13, save_for_backward=True, return_workspace=True,
+                     solver="selective")
+    gp, gq, ga, gt = A.grad(dd, r["opts"], r["workspace"], w, 0.3, full=True)
+    ga = np.asarray(ga).reshape(alpha.shape)
+
+    def loss(design):
+        rr = A.homogenize(design, precision="fp64", rtol=1e-13, solver="selective")
+        return float(np.sum(w * rr["C"]) + 0.3 * rr["V"])
+
+    h = 1e-6
+    for idx in ((0, 0, 0), (1, 2, 3)):
+        ap, am = alpha.copy(), alpha.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fd = (loss(dd.with_(alpha=ap)) - loss(dd.with_(alpha=am))) / (2 * h)
+        print("alpha", idx, fd, ga[idx], flush=True)
+        assert abs(fd - ga[idx]) <= 2e-5 * np.abs(ga).max()
+    fd = (loss(dd.with_(thickness=r0["t"] + h)) - loss(dd.with_(thickness=r0["t"] - h))) / (2 * h)
+    print("t", fd, gt, flush=True)
+    assert abs(fd - gt) <= 2e-5 * abs(gt)

@@ -168,3 +168,37 @@ def test_smooth_occupancy_culls_below_eps():
     # keeping the sub-eps voxels (no culling) only stiffens
     C_all, _ = hom.homogenize_stiffness(beta, NU)
     assert np.linalg.eigvalsh(C_all - C).min() > -1e-10 * np.abs(C).max()
+
+
+def test_culled_gradient_matches_finite_differences():
+    # brute force: central differences of the culled forward path (field ->
+    # logistic shell -> culled solve -> C^H, V) in a few positions and charge
+    # values against design_gradient_selective (no voxel crosses eps within h)
+    n, kappa = 8, 32.0
+    rng = np.random.default_rng(12)
+    pos = rng.random((4, 3))
+    q = np.array([1.0, -1.0, 0.7, -0.7])
+    F, G = fld.field_and_gradient(pos, q, n)
+    t = fld.thickness_for_volume(fld.distance(F, G), 0.3, kappa)
+    dLdC = rng.standard_normal((6, 6))
+    dLdV = -0.4
+    C, V, dpos, dq = sel.design_gradient_selective(pos, q, n, dLdC, dLdV, thickness=t, kappa=kappa)
+
+    def loss(p, qq):
+        Cp, info = sel.homogenize_design_selective(p, qq, n, thickness=t, kappa=kappa, rtol=1e-13)
+        return float(np.sum(dLdC * Cp) + dLdV * info["V"])
+
+    h = 1e-6
+    scale = max(np.abs(dpos).max(), np.abs(dq).max())
+    for j, c in ((0, 0), (1, 2), (3, 1)):
+        pp, pm = pos.copy(), pos.copy()
+        pp[j, c] += h
+        pm[j, c] -= h
+        fd = (loss(pp, q) - loss(pm, q)) / (2 * h)
+        assert abs(fd - dpos[j, c]) <= 2e-5 * scale, (j, c, fd, dpos[j, c])
+    for j in (0, 2):
+        qp, qm = q.copy(), q.copy()
+        qp[j] += h
+        qm[j] -= h
+        fd = (loss(pos, qp) - loss(pos, qm)) / (2 * h)
+        assert abs(fd - dq[j]) <= 2e-5 * scale, (j, fd, dq[j])
