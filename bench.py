@@ -241,7 +241,7 @@ def inverse_step(args):
         L.backward()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        print(f"inverse: step {step} {dt:.2f} s loss {float(L):.4e}", file=sys.stderr, flush=True)
+        print(f"inverse: step {step} {dt:.2f} s loss {float(L.detach()):.4e}", file=sys.stderr, flush=True)
         if step >= args.warmup:
             times.append(dt)
     ms = 1e3 * float(np.mean(times))
