@@ -71,8 +71,12 @@ extern "C" {
                                  multigrid V-cycle whose coarse levels are the Galerkin
                                  grids of the culled voxel operator where the grid
                                  coarsens (as for SHH_SOLVER_MG), else by Jacobi.  Any n.
-                                 Not served by the engine (SHH_UNSUPPORTED); shh_grad
-                                 differentiates the culled model                         */
+                                 Served by the engine like the other solvers; shh_grad
+                                 differentiates the culled model.  A load case whose
+                                 true residual has not fallen by 1% over 50 residual
+                                 recomputes stops with SHH_NOT_CONVERGED (the FP32
+                                 floor of a mixed solve on a poorly conditioned
+                                 culled design; SHH_PREC_FP64 reaches rtol there)        */
 #define SHH_SOLVER_SELECTIVE_JACOBI 4 /* the same culled system, always Jacobi-preconditioned */
 
 /* One design (Eq. (6)-(7) parameters and material). */
@@ -360,7 +364,9 @@ int32_t shh_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *hip_
 /* ---- serving engine: continuous batching ------------------------------
    Requests are admitted into slots while a free slot and enough arena memory
    exist (first fit), run together -- every CG phase is one launch over all
-   resident designs -- and leave when their six load cases have converged.
+   resident designs (one per solver group: dense and selective designs are
+   stepped as two batches) -- and leave when their six load cases have
+   converged.  A design's result does not depend on what else is resident.
    Admission happens at iteration boundaries inside shh_engine_step.
    d_arena: caller-owned device memory (e.g. a PyTorch uint8 tensor) of
    arena_bytes bytes, the engine's whole HBM budget; it must outlive the engine.

@@ -816,7 +816,6 @@ int32_t shh_engine_submit(shh_engine *eng, const shh_design *design, const shh_o
   SHH_TRY(normalize_opts(opts, &o));
   if (eng->prec >= 0 && o.precision != eng->prec) return SHH_INVALID_ARG;
   SHH_TRY(check_solver(design->n, &o));  // SHH_SOLVER_AUTO: multigrid or Jacobi for this grid
-  if (is_selective(o.solver)) return SHH_UNSUPPORTED;  // solved one design at a time
   size_t need = 0;
   SHH_TRY(shh_engine_footprint(design, &o, &need));
   if (need > eng->bytes - eng->header) return SHH_OVER_BUDGET;
@@ -879,32 +878,48 @@ static void engine_retire(shh_engine *eng, size_t idx) {
 
 int32_t shh_engine_step(shh_engine *eng, int32_t iters, int32_t *n_resident, int32_t *n_queued) {
   if (!eng || iters < 0) return SHH_INVALID_ARG;
-  std::vector<Slot *> fresh, failed;
+  std::vector<Slot *> fresh, failed, fresh_sel;
   SHH_TRY(engine_admit(eng, fresh));
+  // selective requests run their own solve (compact lists, culled hierarchy)
+  // beside the dense ones, one launch per step for all of them
+  for (size_t i = fresh.size(); i-- > 0;)
+    if (is_selective(fresh[i]->opts.solver)) {
+      fresh_sel.push_back(fresh[i]);
+      fresh.erase(fresh.begin() + i);
+    }
   // a request whose own setup fails completes with its status; the others go on
   SHH_TRY(eng->solver->start(fresh, &failed));
+  SHH_TRY(sel_start(fresh_sel, eng->st));
+  std::vector<Slot *> done;
+  for (Slot *s : fresh_sel)
+    if (s->finished) (s->status < 0 ? failed : done).push_back(s);  // setup failure, or all culled
   for (Slot *f : failed) {
     shh_result r;
     std::memset(&r, 0, sizeof(r));
     r.status = f->status;
     eng->completed.emplace_back(f->id, r);
   }
-  if (!failed.empty()) {
-    SHH_HIP(hipStreamSynchronize(eng->st));  // their memory may still be in use
-    for (size_t i = eng->resident.size(); i-- > 0;)
-      if (eng->resident[i]->finished) engine_retire(eng, i);
-  }
-  std::vector<Slot *> live;
-  for (auto &s : eng->resident) live.push_back(s.get());
-  if (!live.empty() && iters > 0) {
-    SHH_TRY(eng->solver->iterate(live, iters));
-    std::vector<Slot *> done;
-    SHH_TRY(eng->solver->poll(live, done));
-    for (Slot *d : done) {
-      shh_result r;
-      fill_result(*d, &r);
-      eng->completed.emplace_back(d->id, r);
+  std::vector<Slot *> live, live_sel;
+  for (auto &s : eng->resident)
+    if (!s->finished) (is_selective(s->opts.solver) ? live_sel : live).push_back(s.get());
+  if (iters > 0) {
+    if (!live.empty()) {
+      SHH_TRY(eng->solver->iterate(live, iters));
+      SHH_TRY(eng->solver->poll(live, done));
     }
+    if (!live_sel.empty()) {
+      SHH_TRY(sel_step(live_sel, iters, eng->st));
+      for (Slot *s : live_sel)
+        if (s->finished) done.push_back(s);
+    }
+  }
+  for (Slot *d : done) {
+    shh_result r;
+    fill_result(*d, &r);
+    eng->completed.emplace_back(d->id, r);
+  }
+  if (!failed.empty() || !done.empty()) {
+    SHH_HIP(hipStreamSynchronize(eng->st));  // their memory may still be in use
     for (size_t i = eng->resident.size(); i-- > 0;)
       if (eng->resident[i]->finished) engine_retire(eng, i);
   }

@@ -81,6 +81,7 @@ struct CgState {
   double ff[NRHS];        // ||f||^2
   double rel[NRHS];       // ||r|| / ||f|| last seen
   double rel_true[NRHS];  // ||f - K u|| / ||f|| at the last recompute
+  double rel_min[NRHS];   // selective multigrid CG: the smallest of those so far
   double mean[NRHS][3];   // mean of the recomputed residual per component
   int active[NRHS];       // 1 while load case k iterates
   int status[NRHS];
@@ -88,6 +89,7 @@ struct CgState {
   int pcur[NRHS];         // which of the two r, p, q buffer sets is current
   int mgpar[NRHS];        // multigrid CG: which p buffer holds the current direction
   int no_keep[NRHS];      // selective multigrid CG: restart after every replacement (set by a stall)
+  int stag[NRHS];         // selective CG: replacements since the true residual last fell by 1 %
   unsigned cnt[8];        // last-workgroup counters (0..5 per load case, 6, 7 misc)
   double V;               // volume fraction
   double t;               // half-thickness used

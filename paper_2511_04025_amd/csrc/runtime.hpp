@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <vector>
 
 #include "shellhom.h"
@@ -36,6 +37,8 @@ struct DesignCopy {
   int nfbv = 0;                 // the caller's charge count
 };
 
+struct SelHost;  // selective solve state of a slot (selsolve.cpp)
+
 struct Slot {
   DesignCopy design;
   shh_opts opts;
@@ -60,6 +63,7 @@ struct Slot {
   bool mg_restart = false;      // next iteration starts from z = V r, p = z
   bool mg_keep_dir = false;     // ... or, after a residual replacement, p = z + beta p
   int sel_active_nodes = 0;     // selective solve: active nodes
+  std::shared_ptr<SelHost> sel; // selective solve: descriptor and progress between steps
   bool timing = true;           // launch timing allowed (false: the no-allocation entry point)
 };
 
@@ -178,7 +182,12 @@ void profile_add(int kind, double ms);
 double now_ms();
 // the selective solve of slots whose culled moduli are in place (field setup
 // or given moduli): compaction, CG on the active nodes, C^H; the slots share
-// every launch (same precision and solver option)
+// every launch (same precision and solver option).  sel_start sets up a set
+// of slots (compaction, hierarchy, first residual); sel_step runs `iters`
+// iterations of the unfinished ones, checks those that stopped and finishes
+// them (C^H, status, s.finished); sel_solve runs both to the end.
+int sel_start(const std::vector<Slot *> &slots, hipStream_t st);
+int sel_step(const std::vector<Slot *> &slots, int iters, hipStream_t st);
 int sel_solve(const std::vector<Slot *> &slots, hipStream_t st);
 inline int sel_solve(Slot &s, hipStream_t st) { return sel_solve(std::vector<Slot *>{&s}, st); }
 // the selective solve's dL/dE_e (dense [n^3], zero on culled voxels) for the

@@ -798,6 +798,9 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch 
     st->alpha[k] = 0.0;
     st->beta[k] = 0.0;
     st->iters[k] = 0;
+    st->rel_min[k] = 1.0;
+    st->no_keep[k] = 0;
+    st->stag[k] = 0;
     if (sqrt(rr) <= S->ffloor) {  // zero load: u = 0
       st->active[k] = 0;
       st->status[k] = ST_CONVERGED;
@@ -809,7 +812,19 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch 
     }
   } else if (rmode == 1) {
     st->rr[k] = rr;
-    st->rel_true[k] = sqrt(rr / st->ff[k]);
+    const double rel = sqrt(rr / st->ff[k]);
+    // a true residual twice the smallest one so far: the kept directions
+    // have drifted; this case restarts after every replacement from now on
+    if (rel > 2.0 * st->rel_min[k]) st->no_keep[k] = 1;
+    // 50 replacements without a 1 % gain: the precision's floor is above the
+    // tolerance (FP32 vectors on a nearly singular culled system); stop
+    st->stag[k] = rel < 0.99 * st->rel_min[k] ? 0 : st->stag[k] + 1;
+    if (st->stag[k] >= 50) {
+      st->active[k] = 0;
+      st->status[k] = ST_MAXIT;
+    }
+    st->rel_min[k] = fmin(st->rel_min[k], rel);
+    st->rel_true[k] = rel;
   } else {
     st->rr[k] = rr;
     const double rel = sqrt(rr / st->ff[k]);
@@ -817,8 +832,8 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_scalar_kernel(const SelBatch 
     if (rel <= S->rtol) {
       st->active[k] = 0;
       st->status[k] = ST_CONVERGED;
-    } else if (st->status[k] != ST_BREAKDOWN && st->iters[k] < S->max_iter) {
-      st->active[k] = 1;  // the recursive residual was optimistic: resume
+    } else if (st->status[k] != ST_BREAKDOWN && st->status[k] != ST_MAXIT && st->iters[k] < S->max_iter) {
+      st->active[k] = 1;  // the recursive residual was optimistic, or the case stalled: resume
       st->status[k] = ST_RUNNING;
     } else if (st->status[k] != ST_BREAKDOWN) {
       st->active[k] = 0;

@@ -70,40 +70,55 @@ void element_forces(double lam, double mu, double (&f0)[NRHS][8][3]) {
       }
 }
 
-// One design of a batch: its host copy of the descriptor, the device copy,
-// and where it stands.
-struct SelSlot {
-  Slot *s = nullptr;
+}  // namespace
+
+// Where one design's selective solve stands, kept with its slot between the
+// steps of a batch call or of the engine: the host copy of the descriptor, the
+// device copy, the preconditioner, and the iteration and check counts.
+struct SelHost {
   SelDev h;
   SelDev *d = nullptr;
-  bool done = false;  // converged (true residual checked), or given up
-  int finals = 0;     // final residual checks so far
+  size_t aux = 0;        // bytes of the compact arrays in vectors 0-1
+  bool mg = false;       // multigrid-preconditioned (else Jacobi)
+  bool done = false;     // converged (true residual checked), or given up
+  int finals = 0;        // final residual checks so far
+  long long launched = 0;  // CG iterations launched
 };
 
-SelBatch batch_of(const std::vector<SelSlot *> &v) {
+namespace {
+
+SelHost &H(Slot *s) { return *s->sel; }
+
+SelBatch batch_of(const std::vector<Slot *> &v) {
   SelBatch B;
   std::memset(&B, 0, sizeof(B));
   B.count = int(v.size());
   for (size_t i = 0; i < v.size(); ++i) {
-    B.d[i] = v[i]->d;
-    B.prec = v[i]->h.prec;
-    B.parts_max = std::max(B.parts_max, v[i]->h.nparts);
-    B.chunks_max = std::max(B.chunks_max, v[i]->h.nchunks);
-    B.nn1_max = std::max(B.nn1_max, v[i]->h.nn1);
+    const SelHost &x = H(v[i]);
+    B.d[i] = x.d;
+    B.prec = x.h.prec;
+    B.parts_max = std::max(B.parts_max, x.h.nparts);
+    B.chunks_max = std::max(B.chunks_max, x.h.nchunks);
+    B.nn1_max = std::max(B.nn1_max, x.h.nn1);
   }
   return B;
-}
-
-std::vector<Slot *> slots_of(const std::vector<SelSlot *> &v) {
-  std::vector<Slot *> out;
-  for (SelSlot *x : v) out.push_back(x->s);
-  return out;
 }
 
 bool all_stopped(const CgState &c) {
   for (int k = 0; k < NRHS; ++k)
     if (c.active[k]) return false;
   return true;
+}
+
+// the slots in launches of at most SEL_MAXB
+template <typename F>
+int chunked(const std::vector<Slot *> &v, F fn) {
+  int rc;
+  for (size_t b0 = 0; b0 < v.size(); b0 += SEL_MAXB) {
+    const std::vector<Slot *> part(v.begin() + b0, v.begin() + std::min(v.size(), b0 + SEL_MAXB));
+    if ((rc = fn(part))) return rc;
+  }
+  return SHH_OK;
 }
 
 struct SelRun {
@@ -115,7 +130,11 @@ struct SelRun {
     int kind;
   };
   std::vector<Timed> timed;
+  SelRun(hipStream_t s, const std::vector<Slot *> &v) : st(s) {
+    timing = !v.empty() && v[0]->timing && profile_on();
+  }
   ~SelRun() {
+    (void)hipStreamSynchronize(st);
     resolve();
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
@@ -153,27 +172,29 @@ struct SelRun {
     }
     timed.clear();
   }
-  int read_state(const std::vector<SelSlot *> &v) {
-    for (SelSlot *x : v)
-      SEL_HIP(hipMemcpyAsync(&x->s->state, x->s->d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
+  int read_state(const std::vector<Slot *> &v) {
+    for (Slot *s : v) SEL_HIP(hipMemcpyAsync(&s->state, s->d_state, sizeof(CgState), hipMemcpyDeviceToHost, st));
     SEL_HIP(hipStreamSynchronize(st));
     resolve();
     return SHH_OK;
   }
-  void record(const std::vector<SelSlot *> &v, int k) {
-    for (SelSlot *x : v)
-      if (x->s->ev[k]) (void)hipEventRecord(x->s->ev[k], st);
+  void record(const std::vector<Slot *> &v, int k) {
+    for (Slot *s : v)
+      if (s->ev[k]) (void)hipEventRecord(s->ev[k], st);
   }
   // recompute r = f - K x64 for the cases of rmode (0 initial, 1 replacement, 2 final)
-  int residual(const SelBatch &B, int rmode) {
-    if (rmode != 0) SEL_HIP(sel_launch_fold(B, rmode == 2 ? 1 : 0, st));
-    int rc;
-    if ((rc = run_timed(SHH_PROF_SEL_RESID, [&] { return sel_launch_op(B, 10 + rmode, st); }))) return rc;
-    SEL_HIP(sel_launch_scalar(B, 100 + rmode, st));
-    SEL_HIP(sel_launch_finish(B, rmode, st));
-    SEL_HIP(sel_launch_scalar(B, rmode == 0 ? SSC_RESID_INIT : (rmode == 1 ? SSC_RESID_REPLACE : SSC_RESID_FINAL),
-                              st));
-    return SHH_OK;
+  int residual(const std::vector<Slot *> &v, int rmode) {
+    return chunked(v, [&](const std::vector<Slot *> &part) {
+      const SelBatch B = batch_of(part);
+      if (rmode != 0) SEL_HIP(sel_launch_fold(B, rmode == 2 ? 1 : 0, st));
+      int rc;
+      if ((rc = run_timed(SHH_PROF_SEL_RESID, [&] { return sel_launch_op(B, 10 + rmode, st); }))) return rc;
+      SEL_HIP(sel_launch_scalar(B, 100 + rmode, st));
+      SEL_HIP(sel_launch_finish(B, rmode, st));
+      SEL_HIP(sel_launch_scalar(
+          B, rmode == 0 ? SSC_RESID_INIT : (rmode == 1 ? SSC_RESID_REPLACE : SSC_RESID_FINAL), st));
+      return SHH_OK;
+    });
   }
   // multigrid-preconditioned CG (the V-cycle: a Chebyshev pre-smoothing of
   // the CG residual at the voxel level, restriction to level 1, the coarse
@@ -195,28 +216,32 @@ struct SelRun {
   }
   // z = V r of a new residual: a restart (beta = 0), or after a residual
   // replacement with the direction kept (SSC_MG_REPLACE)
-  int restart(const std::vector<SelSlot *> &v, int phase = SSC_MG_RESTART) {
-    const SelBatch B = batch_of(v);
-    int rc;
-    if ((rc = vcycle(B, slots_of(v), 1))) return rc;
-    SEL_HIP(sel_launch_scalar(B, phase, st));
-    return SHH_OK;
+  int restart(const std::vector<Slot *> &v, int phase = SSC_MG_RESTART) {
+    return chunked(v, [&](const std::vector<Slot *> &part) {
+      const SelBatch B = batch_of(part);
+      int rc;
+      if ((rc = vcycle(B, part, 1))) return rc;
+      SEL_HIP(sel_launch_scalar(B, phase, st));
+      return SHH_OK;
+    });
   }
-  int iteration(const std::vector<SelSlot *> &v, bool mg) {
-    const SelBatch B = batch_of(v);
-    int rc;
-    if (mg) {
-      if ((rc = run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_dir(B, st); }))) return rc;
-      if ((rc = run_timed(SHH_PROF_SEL_MG_PQ, [&] { return sel_launch_mg_op(B, SMO_PQ, st); }))) return rc;
-      SEL_HIP(sel_launch_scalar(B, SSC_MG_ALPHA, st));
-      if ((rc = vcycle(B, slots_of(v), 0))) return rc;
-      SEL_HIP(sel_launch_scalar(B, SSC_MG_BETA, st));
-    } else {
-      if ((rc = run_timed(SHH_PROF_SEL_OP, [&] { return sel_launch_op(B, SOP_PCG, st); }))) return rc;
-      SEL_HIP(sel_launch_scalar(B, SSC_ITER, st));
-      if ((rc = run_timed(SHH_PROF_SEL_UPDATE, [&] { return sel_launch_update(B, st); }))) return rc;
-    }
-    return SHH_OK;
+  int iteration(const std::vector<Slot *> &v, bool mg) {
+    return chunked(v, [&](const std::vector<Slot *> &part) {
+      const SelBatch B = batch_of(part);
+      int rc;
+      if (mg) {
+        if ((rc = run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_dir(B, st); }))) return rc;
+        if ((rc = run_timed(SHH_PROF_SEL_MG_PQ, [&] { return sel_launch_mg_op(B, SMO_PQ, st); }))) return rc;
+        SEL_HIP(sel_launch_scalar(B, SSC_MG_ALPHA, st));
+        if ((rc = vcycle(B, part, 0))) return rc;
+        SEL_HIP(sel_launch_scalar(B, SSC_MG_BETA, st));
+      } else {
+        if ((rc = run_timed(SHH_PROF_SEL_OP, [&] { return sel_launch_op(B, SOP_PCG, st); }))) return rc;
+        SEL_HIP(sel_launch_scalar(B, SSC_ITER, st));
+        if ((rc = run_timed(SHH_PROF_SEL_UPDATE, [&] { return sel_launch_update(B, st); }))) return rc;
+      }
+      return SHH_OK;
+    });
   }
 };
 
@@ -224,9 +249,9 @@ struct SelRun {
 // dense CG vector region (seven [6][3][n^3] vectors): the map, coordinates,
 // counts, moduli and diagonal in vectors 0-1, r, p, q, x in vectors 2, 3, 4,
 // 6, the partials in vector 5; the descriptor in the slot's small parameter
-// block.  Returns the bytes used in vectors 0-1.
-int describe(SelSlot &x, size_t &aux_used) {
-  Slot &s = *x.s;
+// block.
+int describe(Slot &s) {
+  SelHost &x = *s.sel;
   const Layout &L = s.lay;
   const SlotDev &sd = s.host;
   SelDev &h = x.h;
@@ -269,7 +294,7 @@ int describe(SelSlot &x, size_t &aux_used) {
   h.partials = (double *)(vec + 5 * vb);
   static_assert(sizeof(SelDev) <= 4096, "descriptor fits the parameter block");
   x.d = (SelDev *)(base + L.segs);
-  aux_used = off;
+  x.aux = off;
   return SHH_OK;
 }
 
@@ -277,8 +302,8 @@ int describe(SelSlot &x, size_t &aux_used) {
 // multigrid's three extra [n_a][18] vectors after the compact arrays in
 // vectors 0-1, then after the partials in vector 5 (Jacobi when a nearly full
 // design leaves no room for them).
-int place(SelSlot &x, size_t aux_used) {
-  Slot &s = *x.s;
+int place(Slot &s) {
+  SelHost &x = *s.sel;
   SelDev &h = x.h;
   const size_t ts = h.prec == SHH_PREC_FP64 ? 8 : 4;
   char *vec = s.base + s.lay.vec;
@@ -288,8 +313,8 @@ int place(SelSlot &x, size_t aux_used) {
   if (pbytes > vb || 22ull * h.nparts * sizeof(double) > vb) return SHH_WORKSPACE_TOO_SMALL;
   if (h.mg) {
     const size_t vbytes = al256((size_t)h.na * 3 * NRHS * ts);
-    char *arena[2] = {vec + aux_used, vec + 5 * vb + pbytes};
-    size_t room[2] = {2 * vb - aux_used, vb - pbytes};
+    char *arena[2] = {vec + x.aux, vec + 5 * vb + pbytes};
+    size_t room[2] = {2 * vb - x.aux, vb - pbytes};
     void **dst[3] = {&h.d1, &h.xv, &h.rv};
     for (void **v : dst) {
       const int a = room[0] >= vbytes ? 0 : (room[1] >= vbytes ? 1 : -1);
@@ -302,72 +327,14 @@ int place(SelSlot &x, size_t aux_used) {
       room[a] -= vbytes;
     }
   }
+  x.mg = h.mg != 0;
   return SHH_OK;
 }
 
-// the CG loop of one group of slots (one preconditioner), batched
-int run_group(SelRun &run, const std::vector<SelSlot *> &group, bool mg, const shh_opts &o) {
-  hipStream_t st = run.st;
-  int rc;
-  {
-    const SelBatch B = batch_of(group);
-    SEL_HIP(sel_launch_gather(B, st));
-    SEL_HIP(sel_launch_zero(B, st));
-    if ((rc = run.residual(B, 0))) return rc;
-    if (mg) {
-      if ((rc = run.restart(group))) return rc;
-    } else {
-      SEL_HIP(sel_launch_dir0(B, st));
-    }
-  }
-  run.record(group, 2);
-  const int R = group[0]->h.prec == SHH_PREC_MIXED ? o.recompute_every : 0;
-  const int check = std::max(1, o.check_every);
-  long long launched = 0;
-  const long long guard = 4LL * o.max_iter + 64LL * check + 1024;
-  if ((rc = run.read_state(group))) return rc;
-  for (SelSlot *x : group) x->done = false;
-  auto live_of = [&]() {
-    std::vector<SelSlot *> v;
-    for (SelSlot *x : group)
-      if (!x->done) v.push_back(x);
-    return v;
-  };
-  for (std::vector<SelSlot *> live = live_of(); !live.empty(); live = live_of()) {
-    // slots whose every load case has stopped: the true residual decides (a
-    // case whose recursive residual was optimistic resumes, at most 8 times)
-    std::vector<SelSlot *> stopped, running;
-    for (SelSlot *x : live) (all_stopped(x->s->state) ? stopped : running).push_back(x);
-    if (!stopped.empty()) {
-      if ((rc = run.residual(batch_of(stopped), 2))) return rc;
-      if ((rc = run.read_state(stopped))) return rc;
-      std::vector<SelSlot *> resumed;
-      for (SelSlot *x : stopped) {
-        ++x->finals;
-        if (all_stopped(x->s->state) || x->finals >= 8) x->done = true;
-        else resumed.push_back(x);
-      }
-      if (mg && !resumed.empty() && (rc = run.restart(resumed))) return rc;
-      for (SelSlot *x : resumed) running.push_back(x);
-    }
-    if (running.empty()) continue;
-    if (launched > guard) {
-      // given up: the true residual of what is left, as the status reports it
-      if ((rc = run.residual(batch_of(running), 2))) return rc;
-      for (SelSlot *x : running) x->done = true;
-      break;
-    }
-    for (int j = 0; j < check; ++j) {
-      if ((rc = run.iteration(running, mg))) return rc;
-      ++launched;
-      if (R > 0 && launched % R == 0) {
-        if ((rc = run.residual(batch_of(running), 1))) return rc;
-        if (mg && (rc = run.restart(running, SSC_MG_REPLACE))) return rc;  // z of the replaced residual
-      }
-    }
-    if ((rc = run.read_state(running))) return rc;
-  }
-  return SHH_OK;
+void finish(Slot &s, int status) {
+  s.status = status;
+  s.finished = true;
+  s.sel->done = true;
 }
 
 }  // namespace
@@ -378,131 +345,223 @@ int sel_energy_gradient(Slot &s, const double g21[21], double **d_gE, hipStream_
   // the compact lists and the FP64 solution of the forward call are still in
   // the workspace (save_for_backward); the descriptor is rebuilt from the
   // layout, n_a read back from the compaction counts
-  SelSlot x;
-  x.s = &s;
-  size_t aux = 0;
+  s.sel = std::make_shared<SelHost>();
   int rc;
-  if ((rc = describe(x, aux))) return rc;
+  if ((rc = describe(s))) return rc;
+  SelHost &x = *s.sel;
   SelDev &h = x.h;
   SEL_HIP(hipMemcpyAsync(&h.na, h.counts + h.nchunks, sizeof(int), hipMemcpyDeviceToHost, st));
   SEL_HIP(hipStreamSynchronize(st));
   h.nparts = std::max(1, (h.na + SEL_THREADS - 1) / SEL_THREADS);
   // dL/dE_e (n^3 doubles) and the weights after the compact arrays in vectors 0-1
   char *vec = s.base + s.lay.vec;
-  if (aux + al256(sizeof(double) * (size_t)h.nn) + 256 > 2 * s.lay.vec_bytes) return SHH_WORKSPACE_TOO_SMALL;
-  *d_gE = (double *)(vec + aux);
-  double *d_g21 = (double *)(vec + aux + al256(sizeof(double) * (size_t)h.nn));
+  if (x.aux + al256(sizeof(double) * (size_t)h.nn) + 256 > 2 * s.lay.vec_bytes) return SHH_WORKSPACE_TOO_SMALL;
+  *d_gE = (double *)(vec + x.aux);
+  double *d_g21 = (double *)(vec + x.aux + al256(sizeof(double) * (size_t)h.nn));
   SEL_HIP(hipMemcpyAsync(x.d, &h, sizeof(SelDev), hipMemcpyHostToDevice, st));
   SEL_HIP(hipMemcpyAsync(d_g21, g21, 21 * sizeof(double), hipMemcpyHostToDevice, st));
-  std::vector<SelSlot *> one{&x};
-  SEL_HIP(sel_launch_energy_sens(batch_of(one), h.nn, d_g21, *d_gE, st));
+  SEL_HIP(sel_launch_energy_sens(batch_of({&s}), h.nn, d_g21, *d_gE, st));
   // the weights' host copy must outlive the asynchronous upload
   SEL_HIP(hipStreamSynchronize(st));
   return SHH_OK;
 }
 
-int sel_solve(const std::vector<Slot *> &all, hipStream_t st) {
-  if (all.empty()) return SHH_OK;
+int sel_start(const std::vector<Slot *> &in, hipStream_t st) {
+  if (in.empty()) return SHH_OK;
+  SelRun run(st, in);
+  std::vector<Slot *> slots, mgc;
   int rc;
-  for (size_t b0 = 0; b0 < all.size(); b0 += SEL_MAXB) {
-    const std::vector<Slot *> part(all.begin() + b0, all.begin() + std::min(all.size(), b0 + SEL_MAXB));
-    SelRun run;
-    run.st = st;
-    run.timing = part[0]->timing && profile_on();
-    std::vector<SelSlot> xs(part.size());
-    std::vector<size_t> aux(part.size());
-    std::vector<Slot *> mgc;
-    for (size_t i = 0; i < part.size(); ++i) {
-      xs[i].s = part[i];
-      if ((rc = describe(xs[i], aux[i]))) return rc;
-      const Slot &s = *part[i];
-      if (s.opts.solver == SHH_SOLVER_SELECTIVE && s.lay.mg && mg_num_levels(s.host.n) >= 2) mgc.push_back(part[i]);
+  for (Slot *s : in) {
+    s->sel = std::make_shared<SelHost>();
+    if ((rc = describe(*s))) {
+      finish(*s, rc);
+      continue;
     }
-    // multigrid hierarchies of the culled operators (Galerkin levels from the
-    // culled moduli; their element matrices use the vector region as scratch,
-    // so they are built before the compaction writes there), batched
-    if (!mgc.empty()) {
-      std::vector<int> rcs;
-      if ((rc = mg_setup(mgc, st, &rcs))) return rc;
-      for (size_t j = 0; j < mgc.size(); ++j) {
-        if (rcs[j] != SHH_OK) continue;  // a failed estimate: Jacobi
-        for (SelSlot &x : xs)
-          if (x.s == mgc[j]) {
-            const MgDev &M = x.s->mg;
-            SelDev &h = x.h;
-            h.mg = 1;
-            h.inv_theta = M.lv[0].inv_theta;
-            h.c1 = M.lv[0].c1;
-            h.c2 = M.lv[0].c2;
-            h.n1 = M.lv[1].n;
-            h.nn1 = M.lv[1].nn;
-            h.b1 = M.lv[1].b;
-            h.x1 = M.lv[1].x;
-            h.d0 = M.lv[0].d;  // the dense level-0 direction buffer: [6][3][n^3] >= [n_a][18]
-          }
-      }
-    }
-    std::vector<SelSlot *> ptrs;
-    for (SelSlot &x : xs) ptrs.push_back(&x);
-    run.record(ptrs, 1);
-    for (SelSlot &x : xs) SEL_HIP(hipMemcpyAsync(x.d, &x.h, sizeof(SelDev), hipMemcpyHostToDevice, st));
-    SEL_HIP(sel_launch_compact(batch_of(ptrs), st));
-    std::vector<int> na(xs.size(), 0);
-    for (size_t i = 0; i < xs.size(); ++i)
-      SEL_HIP(hipMemcpyAsync(&na[i], xs[i].h.counts + xs[i].h.nchunks, sizeof(int), hipMemcpyDeviceToHost, st));
-    SEL_HIP(hipStreamSynchronize(st));
-    std::vector<SelSlot *> gm, gj, empty;
-    for (size_t i = 0; i < xs.size(); ++i) {
-      SelSlot &x = xs[i];
-      x.h.na = na[i];
-      x.s->sel_active_nodes = na[i];
-      if ((rc = place(x, aux[i]))) return rc;
-      SEL_HIP(hipMemcpyAsync(x.d, &x.h, sizeof(SelDev), hipMemcpyHostToDevice, st));
-      (na[i] == 0 ? empty : (x.h.mg ? gm : gj)).push_back(&x);
-    }
-    // everything culled: no stiffness, C^H = 0
-    if (!empty.empty() && (rc = run.read_state(empty))) return rc;
-    for (SelSlot *x : empty) {
-      Slot &s = *x->s;
-      for (int i = 0; i < 36; ++i) s.state.C[i] = 0.0;
-      for (int k = 0; k < NRHS; ++k) {
-        s.state.iters[k] = 0;
-        s.state.rel_true[k] = 0.0;
-        s.state.status[k] = ST_CONVERGED;
-      }
-      s.status = SHH_OK;
-      s.finished = true;
-    }
-    const shh_opts &o = part[0]->opts;
-    if (!gm.empty() && (rc = run_group(run, gm, true, o))) return rc;
-    if (!gj.empty() && (rc = run_group(run, gj, false, o))) return rc;
-    std::vector<SelSlot *> solved(gm);
-    solved.insert(solved.end(), gj.begin(), gj.end());
-    if (solved.empty()) continue;
-    run.record(solved, 3);
-    const SelBatch B = batch_of(solved);
-    SEL_HIP(sel_launch_fold(B, 1, st));
-    SEL_HIP(sel_launch_op(B, SOP_ENERGY, st));
-    SEL_HIP(sel_launch_scalar(B, SSC_ENERGY, st));
-    run.record(solved, 4);
-    if ((rc = run.read_state(solved))) return rc;
-    for (SelSlot *x : solved) {
-      Slot &s = *x->s;
-      float a = 0.f;
-      for (int k = 0; k < 4; ++k)
-        if (s.ev[k] && s.ev[k + 1] && hipEventElapsedTime(&a, s.ev[k], s.ev[k + 1]) == hipSuccess) s.ms[k] = a;
-      if (s.ev[0] && s.ev[4] && hipEventElapsedTime(&a, s.ev[0], s.ev[4]) == hipSuccess) s.ms[4] = a;
-      int status = SHH_OK;
-      for (int k = 0; k < NRHS; ++k) {
-        // a case still stalled after its restarts counts as broken down
-        if (s.state.status[k] == ST_BREAKDOWN || s.state.status[k] == ST_STALLED) status = SHH_BREAKDOWN;
-        else if (status == SHH_OK && s.state.status[k] != ST_CONVERGED) status = SHH_NOT_CONVERGED;
-      }
-      s.status = status;
-      s.finished = true;
+    slots.push_back(s);
+    if (s->opts.solver == SHH_SOLVER_SELECTIVE && s->lay.mg && mg_num_levels(s->host.n) >= 2) mgc.push_back(s);
+  }
+  // multigrid hierarchies of the culled operators (Galerkin levels from the
+  // culled moduli; their element matrices use the vector region as scratch,
+  // so they are built before the compaction writes there), batched
+  if (!mgc.empty()) {
+    std::vector<int> rcs;
+    if ((rc = mg_setup(mgc, st, &rcs))) return rc;
+    for (size_t j = 0; j < mgc.size(); ++j) {
+      if (rcs[j] != SHH_OK) continue;  // a failed estimate: Jacobi
+      const MgDev &M = mgc[j]->mg;
+      SelDev &h = H(mgc[j]).h;
+      h.mg = 1;
+      h.inv_theta = M.lv[0].inv_theta;
+      h.c1 = M.lv[0].c1;
+      h.c2 = M.lv[0].c2;
+      h.n1 = M.lv[1].n;
+      h.nn1 = M.lv[1].nn;
+      h.b1 = M.lv[1].b;
+      h.x1 = M.lv[1].x;
+      h.d0 = M.lv[0].d;  // the dense level-0 direction buffer: [6][3][n^3] >= [n_a][18]
     }
   }
+  run.record(slots, 1);
+  for (Slot *s : slots) SEL_HIP(hipMemcpyAsync(H(s).d, &H(s).h, sizeof(SelDev), hipMemcpyHostToDevice, st));
+  if ((rc = chunked(slots, [&](const std::vector<Slot *> &part) {
+         SEL_HIP(sel_launch_compact(batch_of(part), st));
+         return SHH_OK;
+       })))
+    return rc;
+  std::vector<int> na(slots.size(), 0);
+  for (size_t i = 0; i < slots.size(); ++i)
+    SEL_HIP(hipMemcpyAsync(&na[i], H(slots[i]).h.counts + H(slots[i]).h.nchunks, sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+  SEL_HIP(hipStreamSynchronize(st));
+  std::vector<Slot *> gm, gj, empty;
+  for (size_t i = 0; i < slots.size(); ++i) {
+    Slot *s = slots[i];
+    SelHost &x = H(s);
+    x.h.na = na[i];
+    s->sel_active_nodes = na[i];
+    if ((rc = place(*s))) {
+      finish(*s, rc);
+      continue;
+    }
+    SEL_HIP(hipMemcpyAsync(x.d, &x.h, sizeof(SelDev), hipMemcpyHostToDevice, st));
+    (na[i] == 0 ? empty : (x.mg ? gm : gj)).push_back(s);
+  }
+  // everything culled: no stiffness, C^H = 0
+  if (!empty.empty() && (rc = run.read_state(empty))) return rc;
+  for (Slot *s : empty) {
+    for (int i = 0; i < 36; ++i) s->state.C[i] = 0.0;
+    for (int k = 0; k < NRHS; ++k) {
+      s->state.iters[k] = 0;
+      s->state.rel_true[k] = 0.0;
+      s->state.status[k] = ST_CONVERGED;
+    }
+    finish(*s, SHH_OK);
+  }
+  for (const std::vector<Slot *> *g : {&gm, &gj}) {
+    if (g->empty()) continue;
+    if ((rc = chunked(*g, [&](const std::vector<Slot *> &part) {
+           const SelBatch B = batch_of(part);
+           SEL_HIP(sel_launch_gather(B, st));
+           SEL_HIP(sel_launch_zero(B, st));
+           return SHH_OK;
+         })))
+      return rc;
+    if ((rc = run.residual(*g, 0))) return rc;
+    if (g == &gm) {
+      if ((rc = run.restart(gm))) return rc;
+    } else if ((rc = chunked(gj, [&](const std::vector<Slot *> &part) {
+                  SEL_HIP(sel_launch_dir0(batch_of(part), st));
+                  return SHH_OK;
+                }))) {
+      return rc;
+    }
+  }
+  std::vector<Slot *> started(gm);
+  started.insert(started.end(), gj.begin(), gj.end());
+  run.record(started, 2);
+  return run.read_state(started);
+}
+
+int sel_step(const std::vector<Slot *> &in, int iters, hipStream_t st) {
+  std::vector<Slot *> live;
+  for (Slot *s : in)
+    if (s->sel && !s->sel->done) live.push_back(s);
+  if (live.empty()) return SHH_OK;
+  SelRun run(st, live);
+  int rc;
+  // iterate: each preconditioner's slots together; each slot replaces its
+  // residual by the FP64 one every R of its own iterations
+  for (const bool mg : {true, false}) {
+    std::vector<Slot *> g;
+    for (Slot *s : live)
+      if (H(s).mg == mg && !all_stopped(s->state)) g.push_back(s);
+    for (int j = 0; j < iters && !g.empty(); ++j) {
+      if ((rc = run.iteration(g, mg))) return rc;
+      std::vector<Slot *> due;
+      for (Slot *s : g) {
+        SelHost &x = H(s);
+        ++x.launched;
+        const int R = s->host.prec == SHH_PREC_MIXED ? s->opts.recompute_every : 0;
+        if (R > 0 && x.launched % R == 0) due.push_back(s);
+      }
+      if (!due.empty()) {
+        if ((rc = run.residual(due, 1))) return rc;
+        if (mg && (rc = run.restart(due, SSC_MG_REPLACE))) return rc;  // z of the replaced residual
+      }
+    }
+  }
+  if ((rc = run.read_state(live))) return rc;
+  // slots whose every load case has stopped: the true residual decides (a
+  // case whose recursive residual was optimistic, or that stalled, resumes
+  // from a restart, at most 8 times); a slot past the iteration guard stops
+  std::vector<Slot *> check, done;
+  for (Slot *s : live) {
+    const long long guard = 4LL * s->opts.max_iter + 64LL * std::max(1, s->opts.check_every) + 1024;
+    if (all_stopped(s->state) || H(s).launched > guard) check.push_back(s);
+  }
+  if (!check.empty()) {
+    if ((rc = run.residual(check, 2))) return rc;
+    if ((rc = run.read_state(check))) return rc;
+    std::vector<Slot *> resumed;
+    for (Slot *s : check) {
+      SelHost &x = H(s);
+      ++x.finals;
+      const long long guard = 4LL * s->opts.max_iter + 64LL * std::max(1, s->opts.check_every) + 1024;
+      if (all_stopped(s->state) || x.finals >= 8 || x.launched > guard) {
+        done.push_back(s);
+        continue;
+      }
+      // resume; the replacement schedule follows the device iteration count,
+      // so that the arithmetic does not depend on when the host polled
+      int m = 0;
+      for (int k = 0; k < NRHS; ++k) m = std::max(m, s->state.iters[k]);
+      x.launched = m;
+      resumed.push_back(s);
+    }
+    std::vector<Slot *> rmg;
+    for (Slot *s : resumed)
+      if (H(s).mg) rmg.push_back(s);
+    if (!rmg.empty() && (rc = run.restart(rmg))) return rc;
+  }
+  if (done.empty()) return SHH_OK;
+  // C^H of the finished slots
+  run.record(done, 3);
+  if ((rc = chunked(done, [&](const std::vector<Slot *> &part) {
+         const SelBatch B = batch_of(part);
+         SEL_HIP(sel_launch_fold(B, 1, st));
+         SEL_HIP(sel_launch_op(B, SOP_ENERGY, st));
+         SEL_HIP(sel_launch_scalar(B, SSC_ENERGY, st));
+         return SHH_OK;
+       })))
+    return rc;
+  run.record(done, 4);
+  if ((rc = run.read_state(done))) return rc;
+  for (Slot *s : done) {
+    float a = 0.f;
+    for (int k = 0; k < 4; ++k)
+      if (s->ev[k] && s->ev[k + 1] && hipEventElapsedTime(&a, s->ev[k], s->ev[k + 1]) == hipSuccess) s->ms[k] = a;
+    if (s->ev[0] && s->ev[4] && hipEventElapsedTime(&a, s->ev[0], s->ev[4]) == hipSuccess) s->ms[4] = a;
+    int status = SHH_OK;
+    for (int k = 0; k < NRHS; ++k) {
+      // a case still stalled after its restarts counts as broken down
+      if (s->state.status[k] == ST_BREAKDOWN || s->state.status[k] == ST_STALLED) status = SHH_BREAKDOWN;
+      else if (status == SHH_OK && s->state.status[k] != ST_CONVERGED) status = SHH_NOT_CONVERGED;
+    }
+    finish(*s, status);
+  }
   return SHH_OK;
+}
+
+int sel_solve(const std::vector<Slot *> &all, hipStream_t st) {
+  int rc;
+  if ((rc = sel_start(all, st))) return rc;
+  for (;;) {
+    std::vector<Slot *> live;
+    for (Slot *s : all)
+      if (!s->sel->done) live.push_back(s);
+    if (live.empty()) return SHH_OK;
+    if ((rc = sel_step(live, std::max(1, live[0]->opts.check_every), st))) return rc;
+  }
 }
 
 }  // namespace shh
