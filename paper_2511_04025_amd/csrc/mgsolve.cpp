@@ -34,7 +34,7 @@ hipError_t mg_launch_apply_case0(const MgBatch &B, int l, long long nn_max, int 
 bool mg_apply_wide(long long nn_max);
 hipError_t mg_launch_restrict(const MgBatch &B, int l, long long nn_coarse_max, int prec,
                               hipStream_t st);
-hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_fine_max, int prec, hipStream_t st);
+hipError_t mg_launch_prolong(const MgBatch &B, int l, long long nn_coarse_max, int prec, hipStream_t st);
 hipError_t mg_launch_coarsest(const MgBatch &B, int prec, hipStream_t st);
 hipError_t mg_launch_vec(const MgBatch &B, int l, int nchunks_max, int prec, hipStream_t st);
 hipError_t mg_launch_scalar(const MgBatch &B, int phase, hipStream_t st);
@@ -312,7 +312,7 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   if ((rc = te(SHH_PROF_MG_RESTRICT))) return rc;
   if ((rc = vcycle(smooth, l + 1, st, timer, apply0))) return rc;
   if ((rc = tb(l == 0))) return rc;
-  SHH_HIP(mg_launch_prolong(B, l, nn_max, prec, st));
+  SHH_HIP(mg_launch_prolong(B, l, nn_next_max, prec, st));
   if ((rc = te(SHH_PROF_MG_PROLONG))) return rc;
   // post-smoother
   if ((rc = app(MG_SRC_POST, MGE_POST)) || (rc = app(MG_SRC_LAST, MGE_LAST))) return rc;

@@ -258,7 +258,11 @@ __device__ __forceinline__ void block_of(const TE (&E)[8], TE lam, TE mu, TE (&A
 template <int RX, int RY, int RZ, typename TE, typename TV>
 __device__ __forceinline__ void accumulate(const TE (&E)[8], TE lam, TE mu, int j, const TV *u, int na,
                                            const unsigned act, TE (&q)[NRHS][3]) {
-  if (j < 0) return;  // a culled neighbour shares no stiffness with the node
+  // a culled neighbour shares no stiffness with the node.  (Reading row 0
+  // against a zero block instead of this branch, so that all 27 neighbours'
+  // loads form one block, measured 7 % slower: more registers, and the
+  // culled neighbours' loads still take issue slots.)
+  if (j < 0) return;
   TE A[3][3];
   block_of<RX, RY, RZ>(E, lam, mu, A);
   TE v[3 * NRHS];
@@ -1055,25 +1059,42 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_restrict_kernel(const SelB
   SelDev *S = B.d[blockIdx.y];
   const int n = S->n, n1 = S->n1;
   const long long nn1 = S->nn1;
-  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nn1) return;
-  const int X = int(I % n1), Y = int((I / n1) % n1), Z = int(I / ((long long)n1 * n1));
+  const unsigned I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= (unsigned)nn1) return;
+  const unsigned row = I / (unsigned)n1;  // 32-bit: n <= 512
+  const int X = int(I - row * (unsigned)n1), Y = int(row % (unsigned)n1), Z = int(row / (unsigned)n1);
   T acc[3 * NRHS];
 #pragma unroll
   for (int o = 0; o < 3 * NRHS; ++o) acc[o] = T(0);
   const T *rv = (const T *)S->rv;
-  for (int oz = -1; oz <= 1; ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        const int fx = wrap1(2 * X + ox, n), fy = wrap1(2 * Y + oy, n), fz = wrap1(2 * Z + oz, n);
-        const int j = S->map[((long long)fz * n + fy) * n + fx];
-        if (j < 0) continue;
-        const T w = T((ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0));
-        T v[3 * NRHS];
-        load_row(rv, j, v);
+  // the 27 map entries first, all in flight together
+  int jf[27];
+  bool any = false;
 #pragma unroll
-        for (int o = 0; o < 3 * NRHS; ++o) acc[o] += w * v[o];
-      }
+  for (int f = 0; f < 27; ++f) {
+    const int ox = f % 3 - 1, oy = (f / 3) % 3 - 1, oz = f / 9 - 1;
+    const int fx = wrap1(2 * X + ox, n), fy = wrap1(2 * Y + oy, n), fz = wrap1(2 * Z + oz, n);
+    jf[f] = S->map[((long long)fz * n + fy) * n + fx];
+  }
+#pragma unroll
+  for (int f = 0; f < 27; ++f) any = any || jf[f] >= 0;
+  // then the rows.  FP32: without a branch per fine node (a culled one reads
+  // row 0 at weight 0), so the loads of all 27 overlap (the transfer passes
+  // 6 % faster than with the branch); FP64 would not fit the registers that
+  // way and skips culled nodes by a branch.
+  constexpr bool STRAIGHT = sizeof(T) == 4;
+  if (any) {
+#pragma unroll
+    for (int f = 0; f < 27; ++f) {
+      if (!STRAIGHT && jf[f] < 0) continue;
+      const int ox = f % 3 - 1, oy = (f / 3) % 3 - 1, oz = f / 9 - 1;
+      const T w = jf[f] >= 0 ? T((ox ? 0.5 : 1.0) * (oy ? 0.5 : 1.0) * (oz ? 0.5 : 1.0)) : T(0);
+      T v[3 * NRHS];
+      load_row(rv, jf[f] >= 0 ? jf[f] : 0, v);
+#pragma unroll
+      for (int o = 0; o < 3 * NRHS; ++o) acc[o] += w * v[o];
+    }
+  }
   T *b1 = (T *)S->b1;
 #pragma unroll
   for (int o = 0; o < 3 * NRHS; ++o) b1[(long long)o * nn1 + I] = acc[o];
