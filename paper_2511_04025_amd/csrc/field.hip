@@ -9,6 +9,8 @@
 // workgroup contracts with the basis values of one z plane (a (2K+1)^2 plane
 // tensor in LDS) and then with its x and y basis values.  FP64 throughout, so
 // the hard threshold decides voxel for voxel like the FP64 oracle.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -148,39 +150,83 @@ __global__ __launch_bounds__(256) void distance_kernel(SlotDev *s) {
   }
 }
 
-// ---- hard step: k-th smallest distance by bisection over bit patterns --------
+// ---- hard step: k-th smallest distance by a 16-way search over bit patterns --
 // Non-negative doubles (and +inf) order like their bit patterns.  Two searches
-// run together: the k1-th and k2-th smallest values (1-based).  Each launch
-// halves both ranges; 64 launches finish any range.
+// run together: the k1-th and k2-th smallest values (1-based), each the
+// smallest pattern v with count(d <= v) >= k inside its range [lo, hi].  Each
+// launch counts the elements at or below 15 pivots splitting each range into
+// 16 parts and keeps the part that holds the answer; a range of width w
+// leaves at most w / 16 + 1, so 17 launches finish the 63-bit start.
+constexpr int SEL_WAYS = 16, SEL_LAUNCHES = 18;
+
+__device__ __forceinline__ unsigned long long sel_pivot(unsigned long long lo, unsigned long long w, int i) {
+  // lo + floor(w (i + 1) / 16) without overflow
+  return lo + (w / SEL_WAYS) * (i + 1) + ((w % SEL_WAYS) * (i + 1)) / SEL_WAYS;
+}
+
 __global__ __launch_bounds__(256) void select_count_kernel(SlotDev *s, long long k1, long long k2,
                                                            int nblocks) {
-  __shared__ double red[32];
+  constexpr int NP = SEL_WAYS - 1;
+  __shared__ double red[2 * NP * 16];
   __shared__ int lastflag;
   CgState *st = s->st;
-  const unsigned long long lo0 = st->sel_lo[0], hi0 = st->sel_hi[0];
-  const unsigned long long lo1 = st->sel_lo[1], hi1 = st->sel_hi[1];
-  const unsigned long long m0 = lo0 + ((hi0 - lo0) >> 1), m1 = lo1 + ((hi1 - lo1) >> 1);
+  const unsigned long long lo[2] = {st->sel_lo[0], st->sel_lo[1]};
+  const unsigned long long hi[2] = {st->sel_hi[0], st->sel_hi[1]};
+  if (lo[0] >= hi[0] && lo[1] >= hi[1]) return;  // both found (every workgroup sees the same)
+  unsigned long long m[2][NP];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) m[j][i] = sel_pivot(lo[j], hi[j] - lo[j], i);
+  unsigned c[2][NP];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) c[j][i] = 0u;
   const long long nn = s->nn;
-  double c[2] = {0.0, 0.0};
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn;
-       i += (long long)nblocks * blockDim.x) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(s->d[i]);
-    c[0] += (b <= m0) ? 1.0 : 0.0;
-    c[1] += (b <= m1) ? 1.0 : 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+       e += (long long)nblocks * blockDim.x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(s->d[e]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < NP; ++i) c[j][i] += b <= m[j][i] ? 1u : 0u;
   }
-  block_sum<2>(c, red, 256);
+  double v[2 * NP];  // exact: counts stay far below 2^53
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) v[j * NP + i] = double(c[j][i]);
+  block_sum<2 * NP>(v, red, 256);
   double *parts = s->partials;
-  if (threadIdx.x == 0) {
-    parts[4 * blockIdx.x + 0] = c[0];
-    parts[4 * blockIdx.x + 1] = c[1];
-  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < 2 * NP; ++i) parts[32 * blockIdx.x + i] = v[i];
   if (!arrive_last(&st->cnt[6], nblocks, &lastflag)) return;
-  double tot[2];
-  sum_partials<2>(parts, nblocks, tot, red, 256);
+  double tot[2 * NP];
+  sum_partials<2 * NP, 32>(parts, nblocks, tot, red, 256);
   if (threadIdx.x == 0) {
-    // smallest v with count(d <= v) >= k
-    if (lo0 < hi0) { if (tot[0] >= double(k1)) st->sel_hi[0] = m0; else st->sel_lo[0] = m0 + 1; }
-    if (lo1 < hi1) { if (tot[1] >= double(k2)) st->sel_hi[1] = m1; else st->sel_lo[1] = m1 + 1; }
+    const double kk[2] = {double(k1), double(k2)};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (lo[j] >= hi[j]) continue;
+      // the first pivot whose count reaches k bounds the answer from above;
+      // the pivot before it (or lo) from below
+      unsigned long long nlo = lo[j], nhi = hi[j];
+      bool found = false;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if (found) continue;
+        if (tot[j * NP + i] >= kk[j]) {
+          nhi = m[j][i];
+          found = true;
+        } else {
+          nlo = m[j][i] + 1;
+        }
+      }
+      st->sel_lo[j] = nlo;
+      st->sel_hi[j] = nhi;
+    }
     st->cnt[6] = 0;
   }
 }
@@ -394,10 +440,11 @@ hipError_t launch_field(SlotDev *d_slot, int n, int nb, hipStream_t st) {
 int reduce_blocks(long long nn) { return grid_for(nn, 1024); }
 
 hipError_t launch_select_hard(SlotDev *d_slot, long long nn, long long k, hipStream_t st) {
-  const int nbk = reduce_blocks(nn);
+  // 32 elements per thread: fewer partials for the last workgroup to sum
+  const int nbk = (int)std::max(1LL, std::min(2048LL, (nn + 8191) / 8192));
   const long long k1 = k <= 0 ? 1 : (k >= nn ? nn : k);
   const long long k2 = k <= 0 ? 1 : (k >= nn ? nn : k + 1);
-  for (int it = 0; it < 64; ++it) select_count_kernel<<<nbk, 256, 0, st>>>(d_slot, k1, k2, nbk);
+  for (int it = 0; it < SEL_LAUNCHES; ++it) select_count_kernel<<<nbk, 256, 0, st>>>(d_slot, k1, k2, nbk);
   select_finish_kernel<<<1, 1, 0, st>>>(d_slot, k);
   return hipGetLastError();
 }

@@ -786,9 +786,11 @@ __global__ __launch_bounds__(VEC_THREADS) void mg_power_reduce_kernel(MgBatch B,
 // the range equal to the pseudo-inverse), then invert in place by
 // Gauss-Jordan elimination (the matrix is symmetric positive definite, so no
 // pivoting).  FP64 throughout.
+// One workgroup per design of the batch (grid x).
 template <typename T>
-__global__ __launch_bounds__(1024) void mg_coarse_inverse_kernel(MgDev *mg) {
+__global__ __launch_bounds__(1024) void mg_coarse_inverse_kernel(MgBatch B) {
   __shared__ double red[16];
+  const MgDev *mg = B.mg[blockIdx.x];
   const MgLevel &L = mg->lv[mg->L];
   const int n = L.n, m = mg->ndof_c;
   const long long nn = L.nn;
@@ -886,9 +888,9 @@ hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec
   return hipGetLastError();
 }
 
-hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st) {
-  if (prec == 0) mg_coarse_inverse_kernel<double><<<1, 1024, 0, st>>>(d_mg);
-  else mg_coarse_inverse_kernel<float><<<1, 1024, 0, st>>>(d_mg);
+hipError_t mg_launch_coarse_inverse(const MgBatch &B, int prec, hipStream_t st) {
+  if (prec == 0) mg_coarse_inverse_kernel<double><<<B.count, 1024, 0, st>>>(B);
+  else mg_coarse_inverse_kernel<float><<<B.count, 1024, 0, st>>>(B);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ namespace shh {
 hipError_t mg_launch_elem1(const SlotDev *d_slot, const MgDev *d_mg, long long nn1, int prec, hipStream_t st);
 hipError_t mg_launch_elemc(const MgDev *d_mg, int l, long long nn_next, int prec, hipStream_t st);
 hipError_t mg_launch_stencil(const MgDev *d_mg, int l, long long nn, int prec, hipStream_t st);
-hipError_t mg_launch_coarse_inverse(MgDev *d_mg, int prec, hipStream_t st);
+hipError_t mg_launch_coarse_inverse(const MgBatch &B, int prec, hipStream_t st);
 // live = 1: skip the load cases whose CG has stopped (state read on the device)
 // ep: the Chebyshev sweep fused into the output stage (MGE_*)
 hipError_t mg_launch_apply(const MgBatch &B, int l, int src, long long nn_max, bool even, int prec,
@@ -373,8 +373,7 @@ int mg_setup_levels(Slot &s, hipStream_t st, double &bound0) {
   SHH_HIP(mg_launch_elem1(s.d_slot, s.d_mg, mg.lv[1].nn, prec, st));
   for (int l = 1; l + 1 < count; ++l) SHH_HIP(mg_launch_elemc(s.d_mg, l, mg.lv[l + 1].nn, prec, st));
   for (int l = 1; l < count; ++l) SHH_HIP(mg_launch_stencil(s.d_mg, l, mg.lv[l].nn, prec, st));
-  SHH_HIP(mg_launch_coarse_inverse(s.d_mg, prec, st));
-  return SHH_OK;
+  return SHH_OK;  // the coarsest inverse follows, batched over the slots (mg_setup)
 }
 
 // Chebyshev coefficients of every smoothing level from the estimates, and
@@ -442,6 +441,12 @@ int mg_setup(const std::vector<Slot *> &all, hipStream_t st, std::vector<int> *r
     max_l = std::max(max_l, all[i]->mg.L);
   }
   if (slots.empty()) return SHH_OK;
+  // the coarsest levels' dense inverses, one workgroup per slot (a launch
+  // per slot ran them one after another: 1.8 ms each)
+  for (size_t b0 = 0; b0 < slots.size(); b0 += MG_MAXB) {
+    const std::vector<Slot *> part(slots.begin() + b0, slots.begin() + std::min(slots.size(), b0 + MG_MAXB));
+    SHH_HIP(mg_launch_coarse_inverse(batch_of(part), prec, st));
+  }
   // lambda_max(D^-1 A) of every coarse smoothing level by power iteration
   // on load case 0, entirely on the device and batched over the slots that
   // have the level (phase 0 start, then per step: apply, phase 1 sweep,
