@@ -38,7 +38,7 @@ COPY_CEILING_GBS = 4912.5  # best of five 4 GiB copies (mean 4891.5)
 # the kernel sources it was measured on (digest), null otherwise.
 TRAFFIC = {
     "mg_apply1": {"ratio": 1.86, "sources": ["mg.hip", "mg.hpp", "common.hpp"],
-                  "sha256": "1ba9faa95210d1543ef07f0ccf390a15562eef7209d5ca3054c3efa59377e965"},
+                  "sha256": "b20e5e342f1a94c254682491eba9b68848346046830ec6ab92dfcfd0c5922969"},
 }
 
 
