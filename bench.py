@@ -55,19 +55,23 @@ def traffic_ratio(kind):
     return t["ratio"] if h.hexdigest() == t["sha256"] else None
 
 
-def family_bytes(results, n, R, solver):
+def family_bytes(results, n, R, solver, deg0=1):
     """Algorithmic HBM bytes per kernel family over the given results (FP32
     vectors, 12 B per node and load case per vector; a design's per-node data
     -- moduli, D^-1, coarse stencils -- counts once per iteration in which any
     of its load cases runs).  Only the work that each design's iteration
     counts imply is counted: restarted V-cycles after a residual replacement
     are not, so the figures are lower bounds.
-      multigrid voxel level, per (node, load case):
+      multigrid voxel level, per (node, load case), with the voxel level's
+      Chebyshev degree deg0 (the library's build option; 1 by default):
         direction pass  48 (z, p read; p, q written) + 4 E per node
-        pre-smoothing   48 (b staged; r, d1, x written) + 8 (E, D^-1) per node
-        r - K d1        36 (d1 staged, r read, r written) + 4
-        post-smoothing  36 (x staged, b read, r written) + 4
-        last sweep      48 (r staged; b, x read; x written) + 8
+        pre-smoothing   48 (b staged; r, d1, x written) + 8 (E, D^-1) per node;
+                        degree 1: 36 (b staged; r, x written) + 8
+        r - K d1        36 (d1 staged, r read, r written) + 4 (degree 2 only)
+        post-smoothing  36 (x staged, b read, r written) + 4 (degree 2 only)
+        last sweep      48 (r staged; b, x read; x written) + 8; degree 1 the
+                        one post-smoothing pass: 36 (x staged, b read, z
+                        written) + 8
         CG update       72 (x, p, b, q read; x, b written)
         restriction     12 fine read + 12 per coarse node written
         prolongation    24 fine read and written + 12 per coarse node read
@@ -87,7 +91,7 @@ def family_bytes(results, n, R, solver):
         multigrid-preconditioned, per iteration:
         q = K p         24 (p read, q written) + 12 (coordinate, map entry, modulus)
         smoothing       216 over the four fused operator passes (60 + 36 + 60 + 60)
-                        + 64 (16 per pass)
+                        + 64 (16 per pass); degree 1: 84 over two (48 + 36) + 32
         vectors         120 (CG update with D^-1 r: 84; p = z + beta p: 36) + 4
         transfers       36 per (active node, case) + 24 per (level-1 node, case)
                         + 4 per voxel (map) + 4 per active node (coordinate)
@@ -109,7 +113,10 @@ def family_bytes(results, n, R, solver):
                 out["sel_update"] += 84.0 * na * Ik + 4.0 * na * Im
             else:
                 out["sel_mg_pq"] += 24.0 * na * Ik + 12.0 * na * Im
-                out["sel_mg_smooth"] += 216.0 * na * Ik + 64.0 * na * Im
+                if deg0 == 1:
+                    out["sel_mg_smooth"] += 84.0 * na * Ik + 32.0 * na * Im
+                else:
+                    out["sel_mg_smooth"] += 216.0 * na * Ik + 64.0 * na * Im
                 out["sel_mg_vec"] += 120.0 * na * Ik + 4.0 * na * Im
                 out["sel_mg_transfer"] += (36.0 * na + 24.0 * nn1) * Ik + (4.0 * nn + 4.0 * na) * Im
             continue
@@ -118,10 +125,14 @@ def family_bytes(results, n, R, solver):
             out["cg_pass"] += 96.0 * nn * Ik + 8.0 * nn * Im
             continue
         out["mg_dir"] += 48.0 * nn * Ik + 4.0 * nn * Im
-        out["mg_step1"] += 48.0 * nn * Ik + 8.0 * nn * Im
-        out["mg_res"] += 36.0 * nn * Ik + 4.0 * nn * Im
-        out["mg_post"] += 36.0 * nn * Ik + 4.0 * nn * Im
-        out["mg_last"] += 48.0 * nn * Ik + 8.0 * nn * Im
+        if deg0 == 1:
+            out["mg_step1"] += 36.0 * nn * Ik + 8.0 * nn * Im
+            out["mg_last"] += 36.0 * nn * Ik + 8.0 * nn * Im
+        else:
+            out["mg_step1"] += 48.0 * nn * Ik + 8.0 * nn * Im
+            out["mg_res"] += 36.0 * nn * Ik + 4.0 * nn * Im
+            out["mg_post"] += 36.0 * nn * Ik + 4.0 * nn * Im
+            out["mg_last"] += 48.0 * nn * Ik + 8.0 * nn * Im
         out["mg_update"] += 72.0 * nn * Ik
         out["mg_restrict"] += (12.0 * nn + 12.0 * nn1) * Ik
         out["mg_prolong"] += (24.0 * nn + 12.0 * nn1) * Ik
@@ -420,7 +431,14 @@ def main():
     # per-family roofline: algorithmic bytes implied by the iteration counts
     # over the event-timed milliseconds of that family's launches
     R = args.recompute_every if args.recompute_every > 0 else (10 if args.solver == "selective" else 50)
-    fbytes = family_bytes(all_res, args.n, R, args.solver)
+    # the voxel level's smoothing degree, from the passes that ran: degree 2
+    # has the r - K d1 pass (dense) or two smoothing passes per transfer
+    # (selective)
+    if args.solver == "selective":
+        deg0 = 2 if fam["sel_mg_smooth"][0] > fam["sel_mg_transfer"][0] else 1
+    else:
+        deg0 = 2 if fam["mg_res"][0] > 0 else 1
+    fbytes = family_bytes(all_res, args.n, R, args.solver, deg0)
     kernels = {}
     for name, (nl, ms) in fam.items():
         if nl == 0:

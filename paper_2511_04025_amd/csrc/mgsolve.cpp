@@ -305,7 +305,11 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   };
   // pre-smoother (at the voxel level INIT also applies the pending CG
   // update); the second pass leaves r - A d1, the residual to restrict, in r
-  if ((rc = vec()) || (rc = app(MG_SRC_STEP1, MGE_STEP1)) || (rc = app(MG_SRC_RES, MGE_RES))) return rc;
+  // degree-1 smoothing at the voxel level: the first step alone (its r is
+  // the residual to restrict), and after the correction one pass that
+  // leaves z = x + D r / theta
+  const bool deg1 = l == 0 && SHH_MG_DEG0 == 1;
+  if ((rc = vec()) || (rc = app(MG_SRC_STEP1, MGE_STEP1)) || (!deg1 && (rc = app(MG_SRC_RES, MGE_RES)))) return rc;
   // coarse-grid correction
   if ((rc = tb(l == 0))) return rc;
   SHH_HIP(mg_launch_restrict(B, l, nn_next_max, prec, st));
@@ -315,6 +319,7 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
   SHH_HIP(mg_launch_prolong(B, l, nn_next_max, prec, st));
   if ((rc = te(SHH_PROF_MG_PROLONG))) return rc;
   // post-smoother
+  if (deg1) return app(MG_SRC_POST1, MGE_NONE);
   if ((rc = app(MG_SRC_POST, MGE_POST)) || (rc = app(MG_SRC_LAST, MGE_LAST))) return rc;
   return SHH_OK;
 }
@@ -404,6 +409,7 @@ int mg_setup_coefficients(Slot &s, const MgDev &est, double bound0, hipStream_t 
     W.inv_theta = 1.0 / theta;
     W.c1 = rho1 * rho0;
     W.c2 = 2.0 * rho1 / delta;
+    if (l == 0 && SHH_MG_DEG0 == 1) W.c1 = W.c2 = 0.0;  // one step: x = D b / theta
   }
   // the fused voxel-level sweeps read the coefficients from the slot
   h.mgc[0] = mg.lv[0].inv_theta;

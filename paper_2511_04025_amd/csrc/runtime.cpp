@@ -539,11 +539,13 @@ int Solver::iterate_mg(const std::vector<Slot *> &slots, int iters) {
   int rc;
   // voxel-level operator over all the given slots, one launch
   MgApply0 apply0 = [this](const std::vector<Slot *> &ss, int src) -> int {
-    static const Kind kinds[5] = {K_MG_DIR, K_MG_RES, K_MG_STEP1, K_MG_POST, K_MG_LAST};
-    static const int ops[5] = {SMG_DIR, SMG_RES, SMG_STEP1, SMG_POST, SMG_LAST};
-    static const int prof[5] = {SHH_PROF_MG_DIR, SHH_PROF_MG_RES, SHH_PROF_MG_STEP1, SHH_PROF_MG_POST,
-                                SHH_PROF_MG_LAST};
-    if (src < 0 || src > MG_SRC_LAST) return SHH_INVALID_ARG;
+    // (the degree-1 post-smoothing pass takes the last sweep's segments and
+    // profile kind: it replaces it)
+    static const Kind kinds[6] = {K_MG_DIR, K_MG_RES, K_MG_STEP1, K_MG_POST, K_MG_LAST, K_MG_LAST};
+    static const int ops[6] = {SMG_DIR, SMG_RES, SMG_STEP1, SMG_POST, SMG_LAST, SMG_POST1};
+    static const int prof[6] = {SHH_PROF_MG_DIR, SHH_PROF_MG_RES, SHH_PROF_MG_STEP1, SHH_PROF_MG_POST,
+                                SHH_PROF_MG_LAST, SHH_PROF_MG_LAST};
+    if (src < 0 || src > MG_SRC_POST1) return SHH_INVALID_ARG;
     LaunchArgs la;
     int r;
     // segments of the load cases still running at the last read-back; the

@@ -95,7 +95,7 @@ int mg_setup(const std::vector<Slot *> &slots, hipStream_t st, std::vector<int> 
 // p_j . q); r - K d for the stored Chebyshev direction (the residual the
 // restriction takes, in place of r); the operator fused with the Chebyshev
 // sweep after it (pre-smoother step 1, post-smoother steps 1 and 2)
-enum { MG_SRC_DIR = 0, MG_SRC_RES = 1, MG_SRC_STEP1 = 2, MG_SRC_POST = 3, MG_SRC_LAST = 4 };
+enum { MG_SRC_DIR = 0, MG_SRC_RES = 1, MG_SRC_STEP1 = 2, MG_SRC_POST = 3, MG_SRC_LAST = 4, MG_SRC_POST1 = 5 };
 class Solver;
 using MgApply0 = std::function<int(const std::vector<Slot *> &, int)>;
 // one multigrid-preconditioned CG iteration of every load case of the slots

@@ -927,7 +927,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(const SelBatch B
   if (!act) return;
   const T lam = (T)S->lam, mu = (T)S->mu;
   const T *in = (const T *)(MODE == SMO_PQ ? S->p : MODE == SMO_STEP1 ? S->d0 : MODE == SMO_RES ? S->d1
-                           : MODE == SMO_POST ? S->xv : S->d0);
+                           : (MODE == SMO_POST || MODE == SMO_POST1) ? S->xv : S->d0);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   T q[NRHS][3];
 #pragma unroll
@@ -967,7 +967,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(const SelBatch B
           x[o] = d0[o] + d1[o];
         }
       store_row((T *)S->rv, i, r1);
-      store_row((T *)S->d1, i, d1);
+      if constexpr (SHH_MG_DEG0 != 1) store_row((T *)S->d1, i, d1);  // degree 1: d1 = 0, unused
       store_row((T *)S->xv, i, x);
     } else if constexpr (MODE == SMO_RES) {
       T r[3 * NRHS];
@@ -995,6 +995,22 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(const SelBatch B
       store_row((T *)S->rv, i, r);
       store_row((T *)S->d0, i, d0);
       store_row((T *)S->d1, i, x);
+    } else if constexpr (MODE == SMO_POST1) {
+      // degree 1: z = x + D (b - K x) / theta into d1 (x is the operand),
+      // and the sums b . z, b . b
+      T b[3 * NRHS], x[3 * NRHS];
+      load_row((const T *)S->r, i, b);
+      load_row((const T *)S->xv, i, x);
+#pragma unroll
+      for (int k = 0; k < NRHS; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int o = 3 * k + c;
+          x[o] += it * dv * (b[o] - q[k][c]);
+          acc[k][0] += (double)b[o] * (double)x[o];
+          acc[k][1] += (double)b[o] * (double)b[o];
+        }
+      store_row((T *)S->d1, i, x);
     } else {  // SMO_LAST: z = x + d1 into xv, and the sums b . z, b . b
       T b[3 * NRHS], x[3 * NRHS], r[3 * NRHS], d0[3 * NRHS];
       load_row((const T *)S->r, i, b);
@@ -1014,7 +1030,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(const SelBatch B
       store_row((T *)S->xv, i, x);
     }
   }
-  if constexpr (MODE == SMO_PQ || MODE == SMO_LAST) {
+  if constexpr (MODE == SMO_PQ || MODE == SMO_LAST || MODE == SMO_POST1) {
     double *parts = S->partials;
     const int np = S->nparts;
 #pragma unroll
@@ -1081,7 +1097,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_dir_kernel(const SelBatch 
   for (int k = 0; k < NRHS; ++k) b[k] = (T)S->st->beta[k];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     T z[3 * NRHS], p[3 * NRHS];
-    load_row((const T *)S->xv, i, z);
+    load_row((const T *)(SHH_MG_DEG0 == 1 ? S->d1 : S->xv), i, z);  // where post-smoothing left z
     load_row((const T *)S->p, i, p);
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {
@@ -1329,6 +1345,7 @@ hipError_t sel_launch_mg_op(const SelBatch &B, int mode, hipStream_t st) {
     case SMO_STEP1: SEL_MG_OP(SMO_STEP1); break;
     case SMO_RES: SEL_MG_OP(SMO_RES); break;
     case SMO_POST: SEL_MG_OP(SMO_POST); break;
+    case SMO_POST1: SEL_MG_OP(SMO_POST1); break;
     default: SEL_MG_OP(SMO_LAST); break;
   }
 #undef SEL_MG_OP

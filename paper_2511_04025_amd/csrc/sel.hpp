@@ -76,7 +76,8 @@ enum { SOP_PCG = 0, SOP_RESID = 1, SOP_ENERGY = 2, SOP_APPLY = 3 };
 enum { SSC_ITER = 0, SSC_MEAN = 1, SSC_RESID_INIT = 2, SSC_RESID_REPLACE = 3, SSC_RESID_FINAL = 4,
        SSC_ENERGY = 5, SSC_MG_ALPHA = 6, SSC_MG_BETA = 7, SSC_MG_RESTART = 8, SSC_MG_REPLACE = 9 };
 // voxel-level passes of the multigrid-preconditioned solve (input vector -> epilogue)
-enum { SMO_PQ = 0, SMO_STEP1 = 1, SMO_RES = 2, SMO_POST = 3, SMO_LAST = 4 };
+enum { SMO_PQ = 0, SMO_STEP1 = 1, SMO_RES = 2, SMO_POST = 3, SMO_LAST = 4,
+       SMO_POST1 = 5 };  // POST1: degree-1 post-smoothing, z = x + D (b - K x) / theta
 
 // One launch covers up to SEL_MAXB slots (grid y = slot) of one precision.
 constexpr int SEL_MAXB = 16;

@@ -51,7 +51,7 @@
 namespace shh {
 
 enum { MODE_PCG = 0, MODE_RESID = 1, MODE_APPLY = 2, MODE_MGDIR = 3, MODE_MGSTEP1 = 4, MODE_MGPOST = 5,
-       MODE_MGLAST = 6, MODE_MGRES = 7 };
+       MODE_MGLAST = 6, MODE_MGRES = 7, MODE_MGPOST1 = 8 };
 
 #ifndef SHH_STENCIL_WAVES_PER_EU
 #define SHH_STENCIL_WAVES_PER_EU 1
@@ -162,7 +162,8 @@ void stencil_kernel(LaunchArgs la) {
   constexpr bool MGF = MODE >= MODE_MGSTEP1;  // a Chebyshev sweep fused behind the operator
   // operand staged as D^-1 v / theta (v = b or r: the direction is not stored)
   constexpr bool MG_SCALED = MODE == MODE_MGSTEP1 || MODE == MODE_MGLAST;
-  constexpr bool WITH_D = MODE == MODE_PCG || MG_SCALED;
+  constexpr bool MG_NEED_D = MG_SCALED || MODE == MODE_MGPOST1;  // D^-1 at the owned nodes
+  constexpr bool WITH_D = MODE == MODE_PCG || MG_NEED_D;
   const uint32_t dOff = WITH_D ? (uint32_t)((const char *)s->Dinv - Ebase) : 0u;
   const rsrc_t rE = make_rsrc(Ebase, WITH_D ? (uint64_t)dOff + (uint64_t)nn * SS : (uint64_t)nn * SC);
 
@@ -179,12 +180,15 @@ void stencil_kernel(LaunchArgs la) {
   // the outputs:
   //   STEP1: b (r[0]) staged as d0 = D b / theta;  r = b - q,
   //          d1 = c1 d0 + c2 D r, x = d0 + d1 -> r (q[1]), d1 (mgd), x (r[1])
+  //          (degree 1: r and x = d0 only)
   //   POST:  x (r[1]) staged as is; aux b;  r = b - q -> q[1]
   //   RES:   d1 (mgd) staged as is; aux r (q[1]);  r - q -> q[1] (the
   //          residual the restriction takes)
   //   LAST:  r (q[1]) staged as d = D r / theta; aux b, x;
   //          x + (1 + c1) d + c2 D (r - q) -> r[1], partials b . x, b . b
   //          (the post-smoother's x + d folded into the last update)
+  //   POST1 (degree-1 smoothing): x (r[1]) staged as is; aux b;
+  //          z = x + D (b - q) / theta -> mgd, partials b . z, b . b
   constexpr int NAUX = MODE == MODE_MGLAST ? 2 : 1;
   constexpr int NLOAD = MODE == MODE_MGSTEP1 ? 0 : NAUX;  // auxiliary vectors read
   rsrc_t rA, rB, rC, rR, rQ, rP, rX, rAux[NAUX];
@@ -203,6 +207,10 @@ void stencil_kernel(LaunchArgs la) {
       rA = make_rsrc((const TS *)(MODE == MODE_MGPOST ? s->r[1] : s->mgd) + vbase, vbytesS);
       rAux[0] = make_rsrc((const TS *)(MODE == MODE_MGPOST ? s->r[0] : s->q[1]) + vbase, vbytesS);
       rR = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
+    } else if constexpr (MODE == MODE_MGPOST1) {
+      rA = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+      rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
+      rX = make_rsrc((const TS *)s->mgd + vbase, vbytesS);
     } else {
       rA = make_rsrc((const TS *)s->q[1] + vbase, vbytesS);
       rAux[0] = make_rsrc((const TS *)s->r[0] + vbase, vbytesS);
@@ -211,7 +219,8 @@ void stencil_kernel(LaunchArgs la) {
     }
   } else if constexpr (MODE == MODE_MGDIR) {
     const int pc = st->mgpar[rhs];
-    rA = make_rsrc((const TS *)s->r[1] + vbase, vbytesS);
+    // z: the last post-smoothing pass leaves it in r[1] (degree 2) or mgd
+    rA = make_rsrc((const TS *)(SHH_MG_DEG0 == 1 ? s->mgd : s->r[1]) + vbase, vbytesS);
     rC = make_rsrc((const TS *)s->p[pc] + vbase, vbytesS);
     rP = make_rsrc((const TS *)s->p[pc ^ 1] + vbase, vbytesS);
     rQ = make_rsrc((const TS *)s->q[0] + vbase, vbytesS);
@@ -296,7 +305,7 @@ void stencil_kernel(LaunchArgs la) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = zero_x ? 0.0 : bload<TL>(rA, hoL[k], pz * SL + cL[c]);
       } else if constexpr (MGF) {
-        if constexpr (MG_SCALED) raw_d[k] = bload<TS>(rE, hoS[k], dOff + pz * SS);
+        if constexpr (MG_NEED_D) raw_d[k] = bload<TS>(rE, hoS[k], dOff + pz * SS);
 #pragma unroll
         for (int c = 0; c < 3; ++c) raw_a[k][c] = bload<TS>(rA, hoS[k], pz * SS + cS[c]);
         if (k == 0 && is_out && ownz) {
@@ -391,7 +400,7 @@ void stencil_kernel(LaunchArgs la) {
             own_p[b][c] = v[c];
             own_z[b][c] = (TC)raw_a[0][c];
           }
-          if constexpr (MG_SCALED) own_d[b] = (TC)raw_d[0];
+          if constexpr (MG_NEED_D) own_d[b] = (TC)raw_d[0];
 #pragma unroll
           for (int a = 0; a < NLOAD; ++a)
 #pragma unroll
@@ -489,7 +498,7 @@ void stencil_kernel(LaunchArgs la) {
         op[c] = own_p[b][c];
         oz[c] = own_z[b][c];
       }
-      if constexpr (MG_SCALED) od = own_d[b];
+      if constexpr (MG_NEED_D) od = own_d[b];
 #pragma unroll
       for (int a = 0; a < NLOAD; ++a)
 #pragma unroll
@@ -576,15 +585,29 @@ void stencil_kernel(LaunchArgs la) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const TC rv = oz[c] - qv[c];
-          const TC d1 = c1 * op[c] + c2 * od * rv;
           bstore<TS>((TS)rv, rR, ooff, pk + cS[c]);
-          bstore<TS>((TS)d1, rP, ooff, pk + cS[c]);
-          bstore<TS>((TS)(op[c] + d1), rX, ooff, pk + cS[c]);
+          if constexpr (SHH_MG_DEG0 == 1) {
+            bstore<TS>((TS)op[c], rX, ooff, pk + cS[c]);  // one step: x = d0
+          } else {
+            const TC d1 = c1 * op[c] + c2 * od * rv;
+            bstore<TS>((TS)d1, rP, ooff, pk + cS[c]);
+            bstore<TS>((TS)(op[c] + d1), rX, ooff, pk + cS[c]);
+          }
         }
       } else if constexpr (MODE == MODE_MGPOST || MODE == MODE_MGRES) {
         // oa[0] = b (POST) or r (RES)
 #pragma unroll
         for (int c = 0; c < 3; ++c) bstore<TS>((TS)(oa[0][c] - qv[c]), rR, ooff, pk + cS[c]);
+      } else if constexpr (MODE == MODE_MGPOST1) {
+        // op = x, oa = b
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const TC zv = op[c] + od * (oa[0][c] - qv[c]) * ith;
+          bstore<TS>((TS)zv, rX, ooff, pk + cS[c]);
+          const double b64 = (double)oa[0][c];
+          acc[0] += b64 * (double)zv;
+          acc[1] += b64 * b64;
+        }
       } else if constexpr (MODE == MODE_MGLAST) {
         // op = d, oz = r, oa = b, x
         const TC c1p = TC(1) + c1;
@@ -624,7 +647,7 @@ void stencil_kernel(LaunchArgs la) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) parts[i] = acc[i];
     }
-  } else if constexpr (MODE == MODE_MGLAST) {
+  } else if constexpr (MODE == MODE_MGLAST || MODE == MODE_MGPOST1) {
     double a2[2] = {acc[0], acc[1]};
     block_sum<2>(a2, red, STENCIL_THREADS);
     if (tid == 0) {
@@ -691,6 +714,7 @@ hipError_t launch_stencil_mg(const LaunchArgs &la, int prec, int op, hipStream_t
     case SMG_POST: launch_mg_mode<MODE_MGPOST>(la, prec, st); break;
     case SMG_LAST: launch_mg_mode<MODE_MGLAST>(la, prec, st); break;
     case SMG_RES: launch_mg_mode<MODE_MGRES>(la, prec, st); break;
+    case SMG_POST1: launch_mg_mode<MODE_MGPOST1>(la, prec, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
