@@ -37,8 +37,8 @@ COPY_CEILING_GBS = 4912.5  # best of five 4 GiB copies (mean 4891.5)
 # included, so the figure bounds HBM traffic from above.  It holds only for
 # the kernel sources it was measured on (digest), null otherwise.
 TRAFFIC = {
-    "mg_apply1": {"ratio": 1.86, "sources": ["mg.hip", "mg.hpp", "common.hpp"],
-                  "sha256": "b20e5e342f1a94c254682491eba9b68848346046830ec6ab92dfcfd0c5922969"},
+    "mg_apply1": {"ratio": 1.87, "sources": ["mg.hip", "mg.hpp", "common.hpp"],
+                  "sha256": "342e1898ca637c9ced735caecebeab95e1dae02597587e82e4452237dd0202e5"},
 }
 
 
@@ -210,6 +210,9 @@ def serving_trace(args):
     engine.close()
     L = np.array([lat[i] for i in range(len(designs))])
     bad = sum(1 for r in res.values() if r["status"] != 0)
+    # the requests that did not converge: (index, n, status, worst relative residual)
+    failed = [[int(i), int(designs[i].n), int(r["status"]), float(np.max(r["rel_res"]))]
+              for i, r in sorted(res.items()) if r["status"] != 0]
     by_n = {}
     for i, d in enumerate(designs):
         by_n.setdefault(d.n, []).append(L[i])
@@ -223,7 +226,7 @@ def serving_trace(args):
         "latency_p50_s": round(float(np.percentile(L, 50)), 4),
         "latency_p99_s": round(float(np.percentile(L, 99)), 4),
         "latency_p50_by_n": {str(k): round(float(np.percentile(v, 50)), 4) for k, v in sorted(by_n.items())},
-        "status_failures": bad, "wall_s": round(wall, 2)}))
+        "status_failures": bad, "failed_requests": failed, "wall_s": round(wall, 2)}))
 
 
 def inverse_step(args):
