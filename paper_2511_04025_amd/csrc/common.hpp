@@ -167,11 +167,16 @@ struct Segment {
 // Fused voxel-level passes of the multigrid-preconditioned CG (stencil kernel)
 enum { SMG_DIR = 0, SMG_STEP1 = 1, SMG_POST = 2, SMG_LAST = 3, SMG_RES = 4, SMG_POST1 = 5 };
 // Chebyshev degree of the voxel level's smoother (1 or 2; the coarse levels
-// take 2).  Degree 1 costs about 1 % more CG iterations at 128^3 and saves
-// two of the five voxel-level operator passes of an iteration (the served
-// multigrid path 20 % faster); 2 is kept as a build option.
+// take 2).  Dense multigrid (SHH_MG_DEG0): degree 1 costs about 1 % more CG
+// iterations at 128^3 and saves two of the five voxel-level operator passes
+// of an iteration (20 % faster).  Selective solve (SHH_SEL_DEG0): degree 2,
+// since with degree 1 the FP32 culled solve of some designs stalls above the
+// tolerance (FP64 converges).  The other degree is a build option.
 #ifndef SHH_MG_DEG0
 #define SHH_MG_DEG0 1
+#endif
+#ifndef SHH_SEL_DEG0
+#define SHH_SEL_DEG0 2
 #endif
 
 struct LaunchArgs {

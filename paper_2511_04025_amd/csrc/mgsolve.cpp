@@ -409,7 +409,9 @@ int mg_setup_coefficients(Slot &s, const MgDev &est, double bound0, hipStream_t 
     W.inv_theta = 1.0 / theta;
     W.c1 = rho1 * rho0;
     W.c2 = 2.0 * rho1 / delta;
-    if (l == 0 && SHH_MG_DEG0 == 1) W.c1 = W.c2 = 0.0;  // one step: x = D b / theta
+    // one step, x = D b / theta, where the voxel level smooths with degree 1
+    // (the selective solve takes these coefficients for its own voxel level)
+    if (l == 0 && (is_selective(s.opts.solver) ? SHH_SEL_DEG0 : SHH_MG_DEG0) == 1) W.c1 = W.c2 = 0.0;
   }
   // the fused voxel-level sweeps read the coefficients from the slot
   h.mgc[0] = mg.lv[0].inv_theta;

@@ -967,7 +967,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_op_kernel(const SelBatch B
           x[o] = d0[o] + d1[o];
         }
       store_row((T *)S->rv, i, r1);
-      if constexpr (SHH_MG_DEG0 != 1) store_row((T *)S->d1, i, d1);  // degree 1: d1 = 0, unused
+      if constexpr (SHH_SEL_DEG0 != 1) store_row((T *)S->d1, i, d1);  // degree 1: d1 = 0, unused
       store_row((T *)S->xv, i, x);
     } else if constexpr (MODE == SMO_RES) {
       T r[3 * NRHS];
@@ -1097,7 +1097,7 @@ __global__ __launch_bounds__(SEL_THREADS) void sel_mg_dir_kernel(const SelBatch 
   for (int k = 0; k < NRHS; ++k) b[k] = (T)S->st->beta[k];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += S->nparts * blockDim.x) {
     T z[3 * NRHS], p[3 * NRHS];
-    load_row((const T *)(SHH_MG_DEG0 == 1 ? S->d1 : S->xv), i, z);  // where post-smoothing left z
+    load_row((const T *)(SHH_SEL_DEG0 == 1 ? S->d1 : S->xv), i, z);  // where post-smoothing left z
     load_row((const T *)S->p, i, p);
 #pragma unroll
     for (int k = 0; k < NRHS; ++k) {

@@ -205,10 +205,10 @@ struct SelRun {
   int vcycle(const SelBatch &B, const std::vector<Slot *> &ss, int restart) {
     int rc;
     if ((rc = run_timed(SHH_PROF_SEL_MG_VEC, [&] { return sel_launch_mg_s1(B, restart, st); }))) return rc;
-    // degree-1 smoothing (SHH_MG_DEG0): one pass before the restriction and
-    // one after the prolongation
-    const std::vector<int> pre = SHH_MG_DEG0 == 1 ? std::vector<int>{SMO_STEP1} : std::vector<int>{SMO_STEP1, SMO_RES};
-    const std::vector<int> post = SHH_MG_DEG0 == 1 ? std::vector<int>{SMO_POST1} : std::vector<int>{SMO_POST, SMO_LAST};
+    // degree-1 smoothing (build option SHH_SEL_DEG0): one pass before the
+    // restriction and one after the prolongation
+    const std::vector<int> pre = SHH_SEL_DEG0 == 1 ? std::vector<int>{SMO_STEP1} : std::vector<int>{SMO_STEP1, SMO_RES};
+    const std::vector<int> post = SHH_SEL_DEG0 == 1 ? std::vector<int>{SMO_POST1} : std::vector<int>{SMO_POST, SMO_LAST};
     for (int m : pre)
       if ((rc = run_timed(SHH_PROF_SEL_MG_SMOOTH, [&] { return sel_launch_mg_op(B, m, st); }))) return rc;
     if ((rc = run_timed(SHH_PROF_SEL_MG_TRANSFER, [&] { return sel_launch_mg_restrict(B, st); }))) return rc;
