@@ -38,7 +38,7 @@ COPY_CEILING_GBS = 4912.5  # best of five 4 GiB copies (mean 4891.5)
 # the kernel sources it was measured on (digest), null otherwise.
 TRAFFIC = {
     "mg_apply1": {"ratio": 1.87, "sources": ["mg.hip", "mg.hpp", "common.hpp"],
-                  "sha256": "342e1898ca637c9ced735caecebeab95e1dae02597587e82e4452237dd0202e5"},
+                  "sha256": "722819f5a030965320042ddc7a7ee96a57fb468c25582d89fd867fff0140f3b0"},
 }
 
 
