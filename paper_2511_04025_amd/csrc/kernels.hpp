@@ -25,7 +25,7 @@ hipError_t launch_dinv(SlotDev *d_slot, long long nn, int prec, hipStream_t st);
 hipError_t launch_stencil_pcg(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_stencil_resid(const LaunchArgs &la, int prec, hipStream_t st);
 hipError_t launch_stencil_apply(const LaunchArgs &la, int prec, hipStream_t st);
-// multigrid voxel-level passes (op: SMG_DIR, SMG_STEP1, SMG_POST, SMG_LAST, SMG_RES)
+// multigrid voxel-level passes (op: SMG_DIR, SMG_STEP1, SMG_POST, SMG_LAST, SMG_RES, SMG_POST1)
 hipError_t launch_stencil_mg(const LaunchArgs &la, int prec, int op, hipStream_t st);
 
 // cg.hip (segments of (slot, load case, chunk); fold/zero use one case per slot)

@@ -304,10 +304,10 @@ int vcycle(const std::vector<Slot *> &slots, int l, hipStream_t st, Solver *time
     return te(SHH_PROF_MG_APPLY1);
   };
   // pre-smoother (at the voxel level INIT also applies the pending CG
-  // update); the second pass leaves r - A d1, the residual to restrict, in r
-  // degree-1 smoothing at the voxel level: the first step alone (its r is
-  // the residual to restrict), and after the correction one pass that
-  // leaves z = x + D r / theta
+  // update); with degree 2 the second pass leaves r - A d1, the residual to
+  // restrict, in r.  Degree-1 smoothing at the voxel level: the first step
+  // alone (its r is the residual to restrict), and after the correction one
+  // pass that leaves z = x + D r / theta
   const bool deg1 = l == 0 && SHH_MG_DEG0 == 1;
   if ((rc = vec()) || (rc = app(MG_SRC_STEP1, MGE_STEP1)) || (!deg1 && (rc = app(MG_SRC_RES, MGE_RES)))) return rc;
   // coarse-grid correction

@@ -704,8 +704,8 @@ static void launch_mg_mode(const LaunchArgs &la, int prec, hipStream_t st) {
 // Voxel-level passes of the multigrid-preconditioned CG, in the vector
 // precision: SMG_DIR the CG direction p_j = z + beta p_{j-1} (into the other
 // p buffer), q = K p_j and per-tile partials p_j . q; SMG_STEP1 / SMG_POST /
-// SMG_LAST the operator with the Chebyshev sweep that consumes its output
-// (LAST: per-tile partials b . x, b . b).
+// SMG_LAST / SMG_RES / SMG_POST1 the operator with the Chebyshev sweep that
+// consumes its output (LAST and POST1: per-tile partials b . z, b . b).
 hipError_t launch_stencil_mg(const LaunchArgs &la, int prec, int op, hipStream_t st) {
   if (la.total == 0) return hipSuccess;
   switch (op) {
